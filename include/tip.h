@@ -1,0 +1,172 @@
+/*
+ * tip.h -- Tr(A^-1) by hierarchical probing on toroidal lattices, MI355X (gfx950).
+ *
+ * C ABI of libtip.so.  Method: Stathopoulos, Laeuchli, Orginos, "Hierarchical
+ * probing for estimating the trace of the matrix inverse on toroidal lattices"
+ * (arXiv:1302.4018).  The library
+ *   1. generates probing vectors in-kernel from site indices: the hierarchical
+ *      lattice permutation (Sec. 3, Alg. 5 with the Red-Black order of Alg. 3 in
+ *      the closed form of Lemma 3.3), Hadamard columns in the order of
+ *      eq. HpermSequence read through eq. row-col-permutation, and the random
+ *      vector z0 of Sec. 4 (eq. removebias);
+ *   2. solves A x = z by conjugate gradients with a lattice stencil (Sec. 1.1.2:
+ *      quadratures through linear solves);
+ *   3. accumulates z^H x into the estimator (1/s) sum_m z_m^H A^-1 z_m
+ *      (Sec. 1, Hutchinson) reported at every s = 2^k (Sec. 1.1.4, and the
+ *      nesting Z(k-1) = Z(k)(:, 1:2^{k-1}) after eq. Hperm-recursive).
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * Lattice: ndim in 1..4, sides dims[0..ndim-1] = n_1..n_ndim, each a power of
+ *   two >= 1 (Sec. 3); V = prod n_j <= 2^31.  Sites are numbered
+ *   s = x_1 + n_1 (x_2 + n_2 (x_3 + n_3 x_4)).
+ * Operator: A = sum_e w_e L_e + diag(m(x)) (x) I_ncomp over the edges e = (x, x+mu)
+ *   of the torus (the shifted periodic Laplacian of Sec. 5), with
+ *     TIP_KIND_SCALAR    (ncomp = 1): L_e = [[1, -1], [-1, 1]];
+ *     TIP_KIND_COVARIANT (ncomp = 3): L_e = [[I, -U_mu(x)], [-U_mu(x)^H, I]],
+ *   i.e. (A x)(s) = (m(s) + sum_mu [w_mu(s) + w_mu(s-mu)]) x(s)
+ *                 - sum_mu [w_mu(s) U_mu(s) x(s+mu) + w_mu(s-mu) U_mu(s-mu)^H x(s-mu)].
+ *   A is Hermitian positive definite when every m(x) > 0.
+ * Right-hand sides: spatial probe m (0-based) and internal component c give
+ *   b_{m,c}(y, c') = delta_{c c'} z0(y, c) H(P(y), bitrev_L(m)), L = log2 V,
+ *   H(i, j) = (-1)^{popcount(i & j)} (eq. HadamardElements), P the location of
+ *   site y in the hierarchical permutation (Alg. 5; the bits of the first
+ *   active dimension are the most significant of each Red-Black index, and
+ *   earlier levels occupy more significant bits of P).
+ *   z0(y, c) uses counter n = y * ncomp + c of SplitMix64(seed) (state
+ *   seed + (n+1) * 0x9E3779B97F4A7C15, then the published 64-bit mix):
+ *   Z2: +1 / -1 from the top output bit; Z4: i^t, t = the top two bits.
+ * Memory: every pointer documented as "device" is caller-owned device memory
+ *   and is never freed by the library; "host" pointers likewise.  Complex
+ *   numbers are interleaved (re, im) float64 pairs.
+ * Streams: `stream` is a hipStream_t (NULL = the default stream).  All work of
+ *   a call is enqueued on that stream; calls that return synchronise it.
+ * Errors: no exception crosses the ABI.  Argument validation fails with
+ *   TIP_EINVAL before any output is written or any device work is enqueued;
+ *   tip_last_error() then returns a thread-local message.
+ */
+#ifndef TIP_H
+#define TIP_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  TIP_OK = 0,
+  TIP_EINVAL = -1,       /* invalid argument (nothing written)                   */
+  TIP_ENOMEM = -2,       /* device or host allocation failed                     */
+  TIP_ENOCONV = -3,      /* a solve hit max_iter (completed checkpoints written) */
+  TIP_EBREAKDOWN = -4,   /* CG breakdown: p^H A p <= 0 or not finite             */
+  TIP_EDEVICE = -5,      /* a HIP runtime call failed                            */
+  TIP_EUNSUPPORTED = -6  /* valid request this build does not implement          */
+} tip_status;
+
+enum { TIP_KIND_SCALAR = 0, TIP_KIND_COVARIANT = 1 };
+enum { TIP_MASK_DEFAULT = -1, TIP_MASK_NONE = 0, TIP_MASK_Z2 = 1, TIP_MASK_Z4 = 2 };
+enum { TIP_PREC_FP64 = 0 };
+
+/* Operator description.  Arrays are DEVICE pointers, read only. */
+typedef struct {
+  int32_t ndim;              /* 1..4                                              */
+  int64_t dims[4];           /* n_1..n_ndim, powers of two                         */
+  int32_t kind;              /* TIP_KIND_SCALAR or TIP_KIND_COVARIANT              */
+  double mass;               /* m(x) = mass when mass_field is NULL                */
+  const double* mass_field;  /* [V] m(x), or NULL                                  */
+  const double* coupling;    /* [ndim][V] w_mu(x) of edge x -> x+mu, or NULL (= 1) */
+  const double* links;       /* covariant: [ndim][V][3][3] complex128, row-major,
+                                (U x)_a = sum_b U[a][b] x_b; ignored for scalar    */
+} tip_operator;
+
+typedef struct {
+  int64_t n_vectors;    /* spatial probes s, 1 <= n_vectors <= V                   */
+  int64_t m_begin;      /* first probe solved; 0 for a fresh run (see quadratures) */
+  double tol;           /* accept a solve when ||b - A x||_2 <= tol ||b||_2, with the
+                           residual recomputed in FP64 (Sec. 1.1.2 stops on the
+                           residual; its square bounds the quadrature error)        */
+  int32_t max_iter;     /* CG iterations per solve; 0 = min(10 V ncomp, 2^20)      */
+  uint64_t seed;        /* seed of z0                                              */
+  int32_t mask;         /* TIP_MASK_*; DEFAULT = Z2 for scalar, Z4 for covariant   */
+  int32_t rhs_block;    /* right-hand sides solved together; 0 = library choice   */
+  int32_t precision;    /* TIP_PREC_FP64                                           */
+  void* stream;         /* hipStream_t or NULL                                     */
+  double* quadratures;  /* HOST [n_vectors][2] q_m = sum_c b_{m,c}^H x_{m,c}, or NULL.
+                           Entries [m_begin, n_vectors) are written.  When m_begin > 0
+                           entries [0, m_begin) must hold the q_m of an earlier call
+                           (same operator, seed, mask) and are read: this resumes a
+                           run, reusing earlier levels' quadratures.                */
+} tip_params;
+
+typedef struct {
+  int64_t solves;              /* right-hand sides solved by this call             */
+  int64_t total_iters;         /* CG iterations summed over those solves           */
+  int32_t max_iters;           /* largest iteration count of one solve             */
+  int32_t n_checkpoints_done;  /* leading estimates[] entries that are valid       */
+  double max_true_relres;      /* max ||b - A x|| / ||b|| over accepted solves     */
+  double seconds;              /* wall time of the call                            */
+  int64_t stencil_launches;    /* stencil-kernel launches (timed when profiling on) */
+  double stencil_seconds;      /* summed device time of those launches (hipEvents), 0 if off */
+  double stencil_bytes;        /* algorithmic HBM bytes of those launches          */
+} tip_stats;
+
+/* Number of estimates written by trace_inv_probe: floor(log2 n) + 1, plus one
+ * more (at s = n) when n is not a power of two. */
+int32_t tip_num_checkpoints(int64_t n_vectors);
+
+/* Tr(A^-1) estimates.  estimates: HOST [tip_num_checkpoints(n_vectors)][2];
+ * entry k is T = (1/s) sum_{m<s} q_m at s = 2^k (last entry at s = n_vectors),
+ * summed in m order with Neumaier compensation.  stats may be NULL.
+ * Builds a temporary operator handle (link repack) for the call.
+ * On TIP_ENOCONV / TIP_EBREAKDOWN the checkpoints completed before the first
+ * failing probe are written and stats->n_checkpoints_done says how many. */
+tip_status trace_inv_probe(const tip_operator* op, const tip_params* p,
+                           double* estimates, tip_stats* stats);
+
+/* Operator handle: validates op and repacks links/couplings into the kernels'
+ * layout in library-owned device memory (one time, on `stream`).  The caller's
+ * arrays are not referenced after tip_op_create returns. */
+typedef struct tip_op_s* tip_op_handle;
+tip_status tip_op_create(const tip_operator* op, void* stream, tip_op_handle* out);
+tip_status tip_op_destroy(tip_op_handle h);
+
+/* trace_inv_probe on a prepared handle (no repack inside the call). */
+tip_status trace_inv_probe_op(tip_op_handle h, const tip_params* p,
+                              double* estimates, tip_stats* stats);
+
+/* One solve A x = b_{m,comp} on a prepared handle, for checks of the solver
+ * and for callers that need the solution itself.  Uses tol, max_iter, seed,
+ * mask, precision and stream of p; its probe-count fields are ignored.
+ * x_out: DEVICE, [V][ncomp] complex128 when the solve is complex (covariant
+ * operator, or Z4 mask), else [V] float64.  q_out: HOST [2] = b^H x, or NULL.
+ * stats may be NULL.  Status as trace_inv_probe for a single solve. */
+tip_status tip_solve_probe(tip_op_handle h, const tip_params* p, int64_t m, int32_t comp,
+                           double* x_out, double* q_out, tip_stats* stats);
+
+/* y = A x for nrhs vectors.  x, y: DEVICE [nrhs][V][ncomp] complex128 for the
+ * covariant operator, [nrhs][V] float64 for the scalar one. */
+tip_status tip_apply_operator(const tip_operator* op, int32_t nrhs,
+                              const double* x, double* y, void* stream);
+
+/* P(x) of every site (Alg. 5): DEVICE uint32 [V]. */
+tip_status tip_hier_perm(int32_t ndim, const int64_t* dims, uint32_t* P_out, void* stream);
+
+/* Probing vectors b_{m,comp}(y, comp) = z0(y, comp) H(P(y), bitrev_L(m)) for
+ * m = m0 .. m0+count-1: DEVICE complex128 [count][V].  mask as in tip_params
+ * (DEFAULT resolves with ncomp: 1 -> Z2, 3 -> Z4). */
+tip_status tip_probe_vectors(int32_t ndim, const int64_t* dims, int32_t ncomp, int32_t mask,
+                             uint64_t seed, int64_t m0, int64_t count, int32_t comp,
+                             double* out, void* stream);
+
+/* Turn per-launch hipEvent timing of the stencil kernel on (1) or off (0). */
+void tip_set_profiling(int32_t on);
+
+/* Message for the last non-OK status returned on this thread. */
+const char* tip_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* TIP_H */

@@ -1,0 +1,301 @@
+"""Thin ctypes binding of libtip.so (argument marshalling only).
+
+Every entry point of ``include/tip.h`` has a Python function of the same name
+here.  Tensors are torch tensors on the current HIP device; the binding passes
+their data pointers and the current torch stream and does no arithmetic of
+its own.  Importing this module raises if the library has not been built:
+there is no CPU fallback.
+"""
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libtip.so")
+
+TIP_OK, TIP_EINVAL, TIP_ENOMEM, TIP_ENOCONV, TIP_EBREAKDOWN, TIP_EDEVICE, TIP_EUNSUPPORTED = 0, -1, -2, -3, -4, -5, -6
+STATUS_NAMES = {0: "TIP_OK", -1: "TIP_EINVAL", -2: "TIP_ENOMEM", -3: "TIP_ENOCONV", -4: "TIP_EBREAKDOWN",
+                -5: "TIP_EDEVICE", -6: "TIP_EUNSUPPORTED"}
+KIND_SCALAR, KIND_COVARIANT = 0, 1
+MASK_DEFAULT, MASK_NONE, MASK_Z2, MASK_Z4 = -1, 0, 1, 2
+PREC_FP64 = 0
+
+
+class tip_operator(ctypes.Structure):
+    _fields_ = [("ndim", ctypes.c_int32), ("dims", ctypes.c_int64 * 4), ("kind", ctypes.c_int32),
+                ("mass", ctypes.c_double), ("mass_field", ctypes.c_void_p), ("coupling", ctypes.c_void_p),
+                ("links", ctypes.c_void_p)]
+
+
+class tip_params(ctypes.Structure):
+    _fields_ = [("n_vectors", ctypes.c_int64), ("m_begin", ctypes.c_int64), ("tol", ctypes.c_double),
+                ("max_iter", ctypes.c_int32), ("seed", ctypes.c_uint64), ("mask", ctypes.c_int32),
+                ("rhs_block", ctypes.c_int32), ("precision", ctypes.c_int32), ("stream", ctypes.c_void_p),
+                ("quadratures", ctypes.POINTER(ctypes.c_double))]
+
+
+class tip_stats(ctypes.Structure):
+    _fields_ = [("solves", ctypes.c_int64), ("total_iters", ctypes.c_int64), ("max_iters", ctypes.c_int32),
+                ("n_checkpoints_done", ctypes.c_int32), ("max_true_relres", ctypes.c_double),
+                ("seconds", ctypes.c_double), ("stencil_launches", ctypes.c_int64),
+                ("stencil_seconds", ctypes.c_double), ("stencil_bytes", ctypes.c_double)]
+
+
+def _load():
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is not built: run `python -m paper_1302_4018_amd.build` "
+                           "(there is no CPU fallback)")
+    lib = ctypes.CDLL(LIB_PATH)
+    P = ctypes.POINTER
+    sig = {
+        "tip_num_checkpoints": (ctypes.c_int32, [ctypes.c_int64]),
+        "trace_inv_probe": (ctypes.c_int, [P(tip_operator), P(tip_params), P(ctypes.c_double), P(tip_stats)]),
+        "tip_op_create": (ctypes.c_int, [P(tip_operator), ctypes.c_void_p, P(ctypes.c_void_p)]),
+        "tip_op_destroy": (ctypes.c_int, [ctypes.c_void_p]),
+        "trace_inv_probe_op": (ctypes.c_int, [ctypes.c_void_p, P(tip_params), P(ctypes.c_double), P(tip_stats)]),
+        "tip_solve_probe": (ctypes.c_int, [ctypes.c_void_p, P(tip_params), ctypes.c_int64, ctypes.c_int32,
+                                           ctypes.c_void_p, P(ctypes.c_double), P(tip_stats)]),
+        "tip_apply_operator": (ctypes.c_int, [P(tip_operator), ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p,
+                                              ctypes.c_void_p]),
+        "tip_hier_perm": (ctypes.c_int, [ctypes.c_int32, P(ctypes.c_int64), ctypes.c_void_p, ctypes.c_void_p]),
+        "tip_probe_vectors": (ctypes.c_int, [ctypes.c_int32, P(ctypes.c_int64), ctypes.c_int32, ctypes.c_int32,
+                                             ctypes.c_uint64, ctypes.c_int64, ctypes.c_int64, ctypes.c_int32,
+                                             ctypes.c_void_p, ctypes.c_void_p]),
+        "tip_set_profiling": (None, [ctypes.c_int32]),
+        "tip_last_error": (ctypes.c_char_p, []),
+    }
+    for name, (res, args) in sig.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    return lib
+
+
+lib = _load()
+
+
+class TipError(RuntimeError):
+    def __init__(self, status, where):
+        msg = lib.tip_last_error().decode(errors="replace")
+        super().__init__(f"{where}: {STATUS_NAMES.get(status, status)}: {msg}")
+        self.status = status
+
+
+def _check(status, where):
+    if status != TIP_OK:
+        raise TipError(status, where)
+
+
+def _stream(stream):
+    """hipStream_t of a torch stream (default: the current one), or a raw handle."""
+    if isinstance(stream, int):
+        return ctypes.c_void_p(stream)
+    if stream is None:
+        import torch
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+def _ptr(t):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def _need_cuda(t, name):
+    if t is not None and (not t.is_cuda or not t.is_contiguous()):
+        raise ValueError(f"{name} must be a contiguous tensor on the GPU")
+
+
+class Operator:
+    """Operator description holding device tensors (see tip_operator)."""
+
+    def __init__(self, dims, kind, mass=0.0, mass_field=None, coupling=None, links=None):
+        import torch
+        self.dims = [int(n) for n in dims]
+        self.kind = int(kind)
+        self.mass = float(mass)
+        self.mass_field = mass_field
+        self.coupling = coupling
+        if links is not None and links.dtype == torch.complex128:
+            links = torch.view_as_real(links)
+        self.links = links
+        for t, n in ((mass_field, "mass_field"), (coupling, "coupling"), (links, "links")):
+            _need_cuda(t, n)
+
+    @property
+    def ncomp(self):
+        return 3 if self.kind == KIND_COVARIANT else 1
+
+    @property
+    def V(self):
+        v = 1
+        for n in self.dims:
+            v *= n
+        return v
+
+    def c_struct(self):
+        s = tip_operator()
+        s.ndim = len(self.dims)
+        for j, n in enumerate(self.dims):
+            s.dims[j] = n
+        s.kind = self.kind
+        s.mass = self.mass
+        s.mass_field = _ptr(self.mass_field)
+        s.coupling = _ptr(self.coupling)
+        s.links = _ptr(self.links)
+        return s
+
+
+def _params(n_vectors, tol, seed, mask, max_iter, rhs_block, m_begin, quadratures, stream, precision=PREC_FP64):
+    p = tip_params()
+    p.n_vectors = int(n_vectors)
+    p.m_begin = int(m_begin)
+    p.tol = float(tol)
+    p.max_iter = int(max_iter)
+    p.seed = int(seed) & ((1 << 64) - 1)
+    p.mask = int(mask)
+    p.rhs_block = int(rhs_block)
+    p.precision = int(precision)
+    p.stream = _stream(stream)
+    p.quadratures = quadratures.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+    return p
+
+
+def _stats_dict(st):
+    return {f: getattr(st, f) for f, _ in tip_stats._fields_}
+
+
+def tip_num_checkpoints(n_vectors):
+    return int(lib.tip_num_checkpoints(int(n_vectors)))
+
+
+def _run(fn, first, n_vectors, tol, seed, mask, max_iter, rhs_block, m_begin, quadratures, stream, raise_on_error,
+         precision=PREC_FP64):
+    nck = tip_num_checkpoints(n_vectors)
+    est = np.zeros((nck, 2), dtype=np.float64)
+    q = np.zeros((int(n_vectors), 2), dtype=np.float64)
+    if quadratures is not None:
+        q[:m_begin] = np.asarray(quadratures, dtype=np.complex128)[:m_begin].view(np.float64).reshape(-1, 2)
+    p = _params(n_vectors, tol, seed, mask, max_iter, rhs_block, m_begin, q, stream, precision)
+    st = tip_stats()
+    status = fn(first, ctypes.byref(p), est.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), ctypes.byref(st))
+    stats = _stats_dict(st)
+    stats["status"] = status
+    if raise_on_error:
+        _check(status, fn.__name__)
+    done = stats["n_checkpoints_done"]
+    est_c = est[:, 0] + 1j * est[:, 1]
+    return est_c[:done] if status != TIP_OK else est_c, q[:, 0] + 1j * q[:, 1], stats
+
+
+def trace_inv_probe(op, n_vectors, tol, seed, mask=MASK_DEFAULT, max_iter=0, rhs_block=0, m_begin=0,
+                    quadratures=None, stream=None, raise_on_error=True, precision=PREC_FP64):
+    """Estimates at s = 2^k (complex numpy), quadratures q_m (complex numpy), stats dict."""
+    s = op.c_struct()
+    return _run(lib.trace_inv_probe, ctypes.byref(s), n_vectors, tol, seed, mask, max_iter, rhs_block, m_begin,
+                quadratures, stream, raise_on_error, precision)
+
+
+class OpHandle:
+    """Prepared operator (tip_op_create / tip_op_destroy)."""
+
+    def __init__(self, op, stream=None):
+        self._h = ctypes.c_void_p()
+        s = op.c_struct()
+        _check(lib.tip_op_create(ctypes.byref(s), _stream(stream), ctypes.byref(self._h)), "tip_op_create")
+        self.op = op
+
+    def trace_inv_probe(self, n_vectors, tol, seed, mask=MASK_DEFAULT, max_iter=0, rhs_block=0, m_begin=0,
+                        quadratures=None, stream=None, raise_on_error=True, precision=PREC_FP64):
+        return _run(lib.trace_inv_probe_op, self._h, n_vectors, tol, seed, mask, max_iter, rhs_block, m_begin,
+                    quadratures, stream, raise_on_error, precision)
+
+    def solve_probe(self, m, comp, tol, seed, mask=MASK_DEFAULT, max_iter=0, stream=None, precision=PREC_FP64):
+        """x = A^-1 b_{m,comp} (torch tensor on the GPU), q = b^H x, stats."""
+        import torch
+        op = self.op
+        complex_solve = op.kind == KIND_COVARIANT or mask == MASK_Z4
+        shape = (op.V, op.ncomp, 2) if complex_solve else (op.V,)
+        x = torch.empty(shape, dtype=torch.float64, device="cuda")
+        q = np.zeros(2)
+        p = _params(1, tol, seed, mask, max_iter, 1, 0, np.zeros((1, 2)), stream, precision)
+        st = tip_stats()
+        _check(lib.tip_solve_probe(self._h, ctypes.byref(p), int(m), int(comp), _ptr(x),
+                                   q.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), ctypes.byref(st)),
+               "tip_solve_probe")
+        return (torch.view_as_complex(x) if complex_solve else x), complex(q[0], q[1]), _stats_dict(st)
+
+    def close(self):
+        if self._h:
+            _check(lib.tip_op_destroy(self._h), "tip_op_destroy")
+            self._h = ctypes.c_void_p()
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def trace_inv_probe_op(handle, *args, **kwargs):
+    return handle.trace_inv_probe(*args, **kwargs)
+
+
+def tip_solve_probe(handle, *args, **kwargs):
+    return handle.solve_probe(*args, **kwargs)
+
+
+def tip_op_create(op, stream=None):
+    return OpHandle(op, stream)
+
+
+def tip_op_destroy(handle):
+    handle.close()
+
+
+def tip_apply_operator(op, x, stream=None):
+    """y = A x; x is [nrhs, V, 3] complex128 (covariant) or [nrhs, V] float64 (scalar) on the GPU."""
+    import torch
+    _need_cuda(x, "x")
+    xr = torch.view_as_real(x) if x.is_complex() else x
+    y = torch.empty_like(xr)
+    s = op.c_struct()
+    _check(lib.tip_apply_operator(ctypes.byref(s), int(x.shape[0]), _ptr(xr), _ptr(y), _stream(stream)),
+           "tip_apply_operator")
+    return torch.view_as_complex(y) if x.is_complex() else y
+
+
+def tip_hier_perm(dims, stream=None):
+    """P(x) for every site as an int32 tensor (values < 2^31)."""
+    import torch
+    V = int(np.prod(dims))
+    out = torch.empty(V, dtype=torch.int32, device="cuda")
+    d = (ctypes.c_int64 * 4)(*[int(n) for n in dims])
+    _check(lib.tip_hier_perm(len(dims), d, _ptr(out), _stream(stream)), "tip_hier_perm")
+    return out
+
+
+def tip_probe_vectors(dims, ncomp, mask, seed, m0, count, comp, stream=None):
+    """b_{m,comp} restricted to component comp, m = m0..m0+count-1: complex128 [count, V]."""
+    import torch
+    V = int(np.prod(dims))
+    out = torch.empty((int(count), V, 2), dtype=torch.float64, device="cuda")
+    d = (ctypes.c_int64 * 4)(*[int(n) for n in dims])
+    _check(lib.tip_probe_vectors(len(dims), d, int(ncomp), int(mask), int(seed) & ((1 << 64) - 1), int(m0),
+                                 int(count), int(comp), _ptr(out), _stream(stream)), "tip_probe_vectors")
+    return torch.view_as_complex(out)
+
+
+def tip_set_profiling(on):
+    lib.tip_set_profiling(1 if on else 0)
+
+
+def tip_last_error():
+    return lib.tip_last_error().decode(errors="replace")

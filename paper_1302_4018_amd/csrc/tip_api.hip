@@ -1,0 +1,667 @@
+// Host side of libtip: the C ABI declared in include/tip.h.
+//
+// trace_inv_probe_op drives the hot path.  Right-hand sides (spatial probe m,
+// internal component c) are solved B at a time.  For each block the kernels
+// generate b in place, run CG with per-RHS scalars kept on the device, and
+// confirm convergence on the true FP64 residual; the host only polls one
+// counter every few iterations.  Quadratures are then combined per probe and
+// summed in probe order with Neumaier compensation into the estimates at
+// s = 2^k.
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/tip.h"
+#include "tip_launch.h"
+
+using namespace tip;
+
+namespace {
+
+thread_local std::string g_err;
+int g_profiling = 0;
+
+tip_status fail(tip_status st, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return st;
+}
+
+#define TIP_HIP(call)                                                                             \
+  do {                                                                                            \
+    hipError_t e_ = (call);                                                                       \
+    if (e_ != hipSuccess) return fail(TIP_EDEVICE, "%s failed: %s", #call, hipGetErrorString(e_)); \
+  } while (0)
+
+bool is_pow2(int64_t n) { return n >= 1 && (n & (n - 1)) == 0; }
+int ilog2(int64_t n) { int k = 0; while ((int64_t(1) << k) < n) ++k; return k; }
+
+tip_status make_geom(int32_t ndim, const int64_t* dims, int ncomp, Geom* g) {
+  if (ndim < 1 || ndim > kMaxDim) return fail(TIP_EINVAL, "ndim = %d, expected 1..4", ndim);
+  if (!dims) return fail(TIP_EINVAL, "dims is NULL");
+  std::memset(g, 0, sizeof *g);
+  g->ndim = ndim;
+  g->ncomp = ncomp;
+  int64_t V = 1;
+  int shift = 0;
+  for (int j = 0; j < ndim; ++j) {
+    if (!is_pow2(dims[j])) return fail(TIP_EINVAL, "dims[%d] = %lld is not a power of two >= 1", j, (long long)dims[j]);
+    const int k = ilog2(dims[j]);
+    g->logn[j] = k;
+    g->shift[j] = shift;
+    shift += k;
+    g->nlevels = std::max(g->nlevels, k);
+    V *= dims[j];
+    if (V > (int64_t(1) << 31)) return fail(TIP_EINVAL, "lattice volume exceeds 2^31 sites");
+  }
+  g->V = (uint32_t)V;
+  g->L = shift;
+  return TIP_OK;
+}
+
+struct DevBuf {
+  void* p = nullptr;
+  size_t n = 0;
+  ~DevBuf() { if (p) (void)hipFree(p); }
+  hipError_t ensure(size_t bytes) {
+    if (bytes <= n) return hipSuccess;
+    if (p) { (void)hipFree(p); p = nullptr; n = 0; }
+    hipError_t e = hipMalloc(&p, bytes);
+    if (e == hipSuccess) n = bytes;
+    return e;
+  }
+};
+
+struct HostPinned {
+  void* p = nullptr;
+  size_t n = 0;
+  ~HostPinned() { if (p) (void)hipHostFree(p); }
+  hipError_t ensure(size_t bytes) {
+    if (bytes <= n) return hipSuccess;
+    if (p) { (void)hipHostFree(p); p = nullptr; n = 0; }
+    hipError_t e = hipHostMalloc(&p, bytes, hipHostMallocDefault);
+    if (e == hipSuccess) n = bytes;
+    return e;
+  }
+};
+
+}  // namespace
+
+struct tip_op_s {
+  Geom geom{};                 // ncomp filled from kind
+  int kind = 0;
+  double mass = 0.0;
+  DevBuf links, mass_field, coupling;
+  bool has_mass_field = false, has_coupling = false;
+  // workspace, grown on demand
+  DevBuf vec, partial, scal;
+  HostPinned host;
+  std::vector<hipEvent_t> events;
+
+  OpDev dev() const {
+    OpDev o;
+    o.kind = kind;
+    o.mass = mass;
+    o.mass_field = has_mass_field ? (const double*)mass_field.p : nullptr;
+    o.coupling = has_coupling ? (const double*)coupling.p : nullptr;
+    o.links = kind == 1 ? (const double*)links.p : nullptr;
+    return o;
+  }
+  ~tip_op_s() {
+    for (hipEvent_t e : events) (void)hipEventDestroy(e);
+  }
+};
+
+namespace {
+
+tip_status validate_op(const tip_operator* op, Geom* g) {
+  if (!op) return fail(TIP_EINVAL, "operator is NULL");
+  if (op->kind != TIP_KIND_SCALAR && op->kind != TIP_KIND_COVARIANT)
+    return fail(TIP_EINVAL, "unknown operator kind %d", op->kind);
+  tip_status st = make_geom(op->ndim, op->dims, op->kind == TIP_KIND_COVARIANT ? 3 : 1, g);
+  if (st != TIP_OK) return st;
+  if (op->kind == TIP_KIND_COVARIANT && !op->links) return fail(TIP_EINVAL, "covariant operator needs links");
+  if (!op->mass_field && !std::isfinite(op->mass)) return fail(TIP_EINVAL, "mass is not finite");
+  return TIP_OK;
+}
+
+tip_status create_handle(const tip_operator* op, hipStream_t st, tip_op_s** out) {
+  Geom g;
+  tip_status s = validate_op(op, &g);
+  if (s != TIP_OK) return s;
+  tip_op_s* h = new (std::nothrow) tip_op_s();
+  if (!h) return fail(TIP_ENOMEM, "out of host memory");
+  h->geom = g;
+  h->kind = op->kind;
+  h->mass = op->mass;
+  const size_t V = g.V;
+  auto bail = [&](tip_status code) { delete h; return code; };
+  if (op->mass_field) {
+    if (h->mass_field.ensure(V * sizeof(double)) != hipSuccess) return bail(fail(TIP_ENOMEM, "hipMalloc mass_field"));
+    if (hipMemcpyAsync(h->mass_field.p, op->mass_field, V * sizeof(double), hipMemcpyDeviceToDevice, st) != hipSuccess)
+      return bail(fail(TIP_EDEVICE, "copy of mass_field failed"));
+    h->has_mass_field = true;
+  }
+  if (op->coupling) {
+    const size_t n = (size_t)g.ndim * V * sizeof(double);
+    if (h->coupling.ensure(n) != hipSuccess) return bail(fail(TIP_ENOMEM, "hipMalloc coupling"));
+    if (hipMemcpyAsync(h->coupling.p, op->coupling, n, hipMemcpyDeviceToDevice, st) != hipSuccess)
+      return bail(fail(TIP_EDEVICE, "copy of coupling failed"));
+    h->has_coupling = true;
+  }
+  if (op->kind == TIP_KIND_COVARIANT) {
+    const size_t n = (size_t)g.ndim * 9 * V * sizeof(double2);
+    if (h->links.ensure(n) != hipSuccess) return bail(fail(TIP_ENOMEM, "hipMalloc links (%zu bytes)", n));
+    if (launch_repack_links(g, (const double2*)op->links, (double2*)h->links.p, st) != hipSuccess)
+      return bail(fail(TIP_EDEVICE, "link repack launch failed"));
+  }
+  if (hipStreamSynchronize(st) != hipSuccess) return bail(fail(TIP_EDEVICE, "operator setup failed on the device"));
+  *out = h;
+  return TIP_OK;
+}
+
+// Neumaier running sum.
+struct Compensated {
+  double s = 0.0, c = 0.0;
+  void add(double v) {
+    const double t = s + v;
+    if (std::fabs(s) >= std::fabs(v)) c += (s - t) + v;
+    else c += (v - t) + s;
+    s = t;
+  }
+  double value() const { return s + c; }
+};
+
+int num_checkpoints(int64_t n) {
+  if (n < 1) return 0;
+  int k = 0;
+  while ((int64_t(1) << (k + 1)) <= n) ++k;
+  return k + 1 + (is_pow2(n) ? 0 : 1);
+}
+
+int64_t checkpoint_size(int64_t n, int idx) {
+  const int npow = num_checkpoints(n) - (is_pow2(n) ? 0 : 1);
+  return idx < npow ? (int64_t(1) << idx) : n;
+}
+
+struct Plan {
+  Elem elem;
+  int mask;
+  int R;      // right-hand sides per thread in the stencil
+  int B;      // right-hand sides per block (multiple of R)
+  int gx;     // site workgroups
+  size_t esz; // bytes per vector element
+};
+
+// Common validation of the solve parameters; resolves the mask.
+tip_status check_params(const tip_op_s* h, const tip_params* p, int* mask_out) {
+  if (!p) return fail(TIP_EINVAL, "params is NULL");
+  const int64_t V = h->geom.V;
+  if (p->n_vectors < 1 || p->n_vectors > V)
+    return fail(TIP_EINVAL, "n_vectors = %lld must be in [1, V = %lld]", (long long)p->n_vectors, (long long)V);
+  if (p->m_begin < 0 || p->m_begin > p->n_vectors)
+    return fail(TIP_EINVAL, "m_begin = %lld must be in [0, n_vectors]", (long long)p->m_begin);
+  if (!(p->tol > 0.0) || !std::isfinite(p->tol)) return fail(TIP_EINVAL, "tol must be positive and finite");
+  if (p->max_iter < 0) return fail(TIP_EINVAL, "max_iter must be >= 0");
+  if (p->rhs_block < 0) return fail(TIP_EINVAL, "rhs_block must be >= 0");
+  if (p->precision != TIP_PREC_FP64) return fail(TIP_EUNSUPPORTED, "precision %d is not available", p->precision);
+  int mask = p->mask;
+  if (mask == TIP_MASK_DEFAULT) mask = h->kind == TIP_KIND_COVARIANT ? TIP_MASK_Z4 : TIP_MASK_Z2;
+  if (mask < TIP_MASK_NONE || mask > TIP_MASK_Z4) return fail(TIP_EINVAL, "unknown mask %d", p->mask);
+  *mask_out = mask;
+  return TIP_OK;
+}
+
+// CG over blocks of right-hand sides on one prepared operator.
+struct Solver {
+  tip_op_s* h;
+  const tip_params* p;
+  hipStream_t st;
+  Plan pl;
+  int max_iter, max_restarts = 8;
+  double tol2;
+  size_t vbytes, pstride, nscal;
+  void *X, *Rv, *Pv, *Ap;
+  double* part;
+  CgScalars sc;
+  int* ran_dev;
+  double *h_q, *h_relres2;
+  int *h_state, *h_iters, *h_active, *h_ran;
+  OpDev od;
+  double mv_bytes;
+  int predicted = 8;
+  // stencil accounting
+  int64_t stencil_launches = 0;
+  double stencil_seconds = 0.0, stencil_bytes = 0.0;
+  struct Timed { hipEvent_t a, b; };
+  size_t ev_used = 0;
+
+  hipError_t next_event(hipEvent_t* e) {
+    if (ev_used == h->events.size()) {
+      hipEvent_t ne;
+      hipError_t r = hipEventCreate(&ne);
+      if (r != hipSuccess) return r;
+      h->events.push_back(ne);
+    }
+    *e = h->events[ev_used++];
+    return hipSuccess;
+  }
+
+  tip_status setup(tip_op_s* handle, const tip_params* params, int mask, int64_t n_rhs) {
+    h = handle;
+    p = params;
+    st = (hipStream_t)p->stream;
+    const Geom& g = h->geom;
+    const int64_t V = g.V;
+    const int ncomp = g.ncomp;
+    pl.mask = mask;
+    pl.elem = (h->kind == TIP_KIND_COVARIANT || mask == TIP_MASK_Z4) ? Elem::kComplex : Elem::kReal;
+    pl.esz = pl.elem == Elem::kReal ? sizeof(double) : sizeof(double2);
+    pl.gx = (int)((V + kBlock - 1) / kBlock);
+    pl.R = pl.gx < 64 ? 1 : 4;
+    if (p->rhs_block > 0) {
+      pl.B = (int)std::min<int64_t>(p->rhs_block, std::max<int64_t>(n_rhs, 1));
+    } else {
+      const int gy = std::max(1, (2048 + pl.gx - 1) / pl.gx);
+      pl.B = (int)std::min<int64_t>((int64_t)pl.R * gy, std::max<int64_t>(n_rhs, 1));
+    }
+    // keep the four CG vectors of a block within 32 GiB
+    while (pl.B > 1 && 4.0 * pl.B * ncomp * (double)V * pl.esz > 32.0 * (1ull << 30)) pl.B /= 2;
+    if (pl.B < pl.R) pl.R = pl.B >= 4 ? 4 : (pl.B >= 2 ? 2 : 1);
+    pl.B = (pl.B + pl.R - 1) / pl.R * pl.R;
+    max_iter = p->max_iter > 0 ? p->max_iter : (int)std::min<int64_t>(10 * V * ncomp, 1 << 20);
+    tol2 = p->tol * p->tol;
+
+    vbytes = (size_t)pl.B * ncomp * V * pl.esz;   // one CG vector of the block
+    pstride = (size_t)pl.B * pl.gx;
+    nscal = (size_t)pl.B;
+    if (h->vec.ensure(4 * vbytes) != hipSuccess)
+      return fail(TIP_ENOMEM, "hipMalloc of %zu bytes of CG vectors failed", 4 * vbytes);
+    if (h->partial.ensure(3 * pstride * sizeof(double)) != hipSuccess) return fail(TIP_ENOMEM, "hipMalloc partials");
+    const size_t scal_bytes = nscal * (7 * sizeof(double) + 3 * sizeof(int)) + 64 + kMaxChunk * sizeof(int);
+    if (h->scal.ensure(scal_bytes) != hipSuccess) return fail(TIP_ENOMEM, "hipMalloc scalars");
+    const size_t host_bytes = nscal * (3 * sizeof(double) + 2 * sizeof(int)) + 64 + kMaxChunk * sizeof(int);
+    if (h->host.ensure(host_bytes) != hipSuccess) return fail(TIP_ENOMEM, "hipHostMalloc");
+
+    char* vb = (char*)h->vec.p;
+    X = vb;
+    Rv = vb + vbytes;
+    Pv = vb + 2 * vbytes;
+    Ap = vb + 3 * vbytes;
+    part = (double*)h->partial.p;
+    double* d = (double*)h->scal.p;
+    sc.rho = d;
+    sc.alpha = d + nscal;
+    sc.beta = d + 2 * nscal;
+    sc.bnorm2 = d + 3 * nscal;
+    sc.relres2 = d + 4 * nscal;
+    sc.q = d + 5 * nscal;            // 2 * nscal
+    int* iv = (int*)(d + 7 * nscal);
+    sc.state = iv;
+    sc.iters = iv + nscal;
+    sc.restarts = iv + 2 * nscal;
+    sc.active = iv + 3 * nscal;
+    ran_dev = sc.active + 16;
+    char* hb = (char*)h->host.p;
+    h_q = (double*)hb;
+    h_relres2 = h_q + 2 * nscal;
+    h_state = (int*)(h_relres2 + nscal);
+    h_iters = h_state + nscal;
+    h_active = h_iters + nscal;
+    h_ran = h_active + 16;
+
+    od = h->dev();
+    // Algorithmic bytes of one stencil launch: every operand read or written once.
+    const double groups = pl.B / pl.R;
+    double per_group = 0.0;
+    if (h->kind == TIP_KIND_COVARIANT) per_group += (double)g.ndim * 9 * 16 * V;
+    if (h->has_coupling) per_group += (double)g.ndim * 8 * V;
+    if (h->has_mass_field) per_group += 8.0 * V;
+    mv_bytes = groups * per_group + 2.0 * pl.B * ncomp * V * pl.esz;
+    return TIP_OK;
+  }
+
+  static constexpr int kMaxChunk = 4096;
+
+  // Solve right-hand sides rhs0 .. rhs0+nb-1; x stays in X.  Fills the host
+  // mirrors h_q, h_relres2, h_state, h_iters for those nb right-hand sides.
+  tip_status solve_block(int64_t rhs0, int nb) {
+    const Geom& g = h->geom;
+    TIP_HIP(launch_scalars_init(sc, nb, pl.B, (double)g.V, p->tol >= 1.0 ? 1 : 0, st));
+    TIP_HIP(launch_init(g, pl.elem, pl.B, rhs0, nb, p->seed, pl.mask, X, Rv, Pv, st));
+    bool first_chunk = true;
+    std::vector<Timed> window;
+    for (;;) {
+      // CG iterations, polled every `chunk` iterations
+      for (;;) {
+        const int chunk = first_chunk ? std::min(kMaxChunk, std::max(1, predicted - 1)) : 2;
+        first_chunk = false;
+        window.clear();
+        ev_used = 0;
+        TIP_HIP(hipMemsetAsync(ran_dev, 0, chunk * sizeof(int), st));
+        for (int it = 0; it < chunk; ++it) {
+          Timed tv{};
+          if (g_profiling) {
+            TIP_HIP(next_event(&tv.a));
+            TIP_HIP(next_event(&tv.b));
+            TIP_HIP(hipEventRecord(tv.a, st));
+          }
+          TIP_HIP(launch_matvec(od, g, pl.elem, pl.R, pl.B, Pv, Ap, part, sc.active, ran_dev + it, st));
+          if (g_profiling) {
+            TIP_HIP(hipEventRecord(tv.b, st));
+            window.push_back(tv);
+          }
+          TIP_HIP(launch_reduce_alpha(sc, pl.B, part, pl.gx, st));
+          TIP_HIP(launch_update(g, pl.elem, pl.B, sc, X, Rv, Pv, Ap, part + pstride, st));
+          TIP_HIP(launch_reduce_beta(sc, pl.B, part + pstride, pl.gx, tol2, max_iter, st));
+          TIP_HIP(launch_direction(g, pl.elem, pl.B, sc, Rv, Pv, st));
+        }
+        // launches issued after every RHS of the block stopped return at once;
+        // the kernel's ran flag tells the working launches apart
+        TIP_HIP(hipMemcpyAsync(h_ran, ran_dev, chunk * sizeof(int), hipMemcpyDeviceToHost, st));
+        TIP_HIP(hipMemcpyAsync(h_active, sc.active, sizeof(int), hipMemcpyDeviceToHost, st));
+        TIP_HIP(hipStreamSynchronize(st));
+        for (int i = 0; i < chunk; ++i) {
+          if (!h_ran[i]) continue;
+          ++stencil_launches;
+          stencil_bytes += mv_bytes;
+          if (g_profiling) {
+            float ms = 0.f;
+            TIP_HIP(hipEventElapsedTime(&ms, window[i].a, window[i].b));
+            stencil_seconds += ms * 1e-3;
+          }
+        }
+        if (*h_active == 0) break;
+      }
+      // true residual: accept, or restart CG from x
+      TIP_HIP(launch_true_residual(od, g, pl.elem, pl.R, pl.B, rhs0, nb, p->seed, pl.mask, X, Rv, Pv, part, pstride,
+                                   st));
+      TIP_HIP(launch_reduce_true(sc, pl.B, part, pl.gx, pstride, tol2, max_iter, max_restarts, st));
+      TIP_HIP(hipMemcpyAsync(h_active, sc.active, sizeof(int), hipMemcpyDeviceToHost, st));
+      TIP_HIP(hipStreamSynchronize(st));
+      if (*h_active == 0) break;
+    }
+    TIP_HIP(hipMemcpyAsync(h_q, sc.q, 2 * nb * sizeof(double), hipMemcpyDeviceToHost, st));
+    TIP_HIP(hipMemcpyAsync(h_relres2, sc.relres2, nb * sizeof(double), hipMemcpyDeviceToHost, st));
+    TIP_HIP(hipMemcpyAsync(h_state, sc.state, nb * sizeof(int), hipMemcpyDeviceToHost, st));
+    TIP_HIP(hipMemcpyAsync(h_iters, sc.iters, nb * sizeof(int), hipMemcpyDeviceToHost, st));
+    TIP_HIP(hipStreamSynchronize(st));
+    int blk_max = 0;
+    for (int j = 0; j < nb; ++j) blk_max = std::max(blk_max, h_iters[j]);
+    predicted = std::max(1, blk_max);
+    return TIP_OK;
+  }
+
+  void fill_stats(tip_stats* stats) const {
+    stats->stencil_launches = stencil_launches;
+    stats->stencil_seconds = g_profiling ? stencil_seconds : 0.0;
+    stats->stencil_bytes = stencil_bytes;
+  }
+};
+
+}  // namespace
+
+extern "C" {
+
+int32_t tip_num_checkpoints(int64_t n_vectors) { return num_checkpoints(n_vectors); }
+
+const char* tip_last_error(void) { return g_err.c_str(); }
+
+void tip_set_profiling(int32_t on) { g_profiling = on ? 1 : 0; }
+
+tip_status tip_op_create(const tip_operator* op, void* stream, tip_op_handle* out) {
+  if (!out) return fail(TIP_EINVAL, "out is NULL");
+  tip_op_s* h = nullptr;
+  tip_status s = create_handle(op, (hipStream_t)stream, &h);
+  if (s == TIP_OK) *out = h;
+  return s;
+}
+
+tip_status tip_op_destroy(tip_op_handle h) {
+  if (!h) return fail(TIP_EINVAL, "handle is NULL");
+  (void)hipDeviceSynchronize();
+  delete h;
+  return TIP_OK;
+}
+
+tip_status trace_inv_probe_op(tip_op_handle h, const tip_params* p, double* estimates, tip_stats* stats) {
+  const auto t_start = std::chrono::steady_clock::now();
+  if (!h) return fail(TIP_EINVAL, "handle is NULL");
+  if (!estimates) return fail(TIP_EINVAL, "estimates is NULL");
+  int mask = 0;
+  tip_status s = check_params(h, p, &mask);
+  if (s != TIP_OK) return s;
+  if (p->m_begin > 0 && !p->quadratures) return fail(TIP_EINVAL, "m_begin > 0 needs the earlier quadratures");
+  const int ncomp = h->geom.ncomp;
+  const int64_t probes = p->n_vectors - p->m_begin;
+  const int64_t n_rhs = probes * ncomp;
+  Solver sv;
+  s = sv.setup(h, p, mask, n_rhs);
+  if (s != TIP_OK) return s;
+
+  std::vector<double> qre((size_t)n_rhs, 0.0), qim((size_t)n_rhs, 0.0), rhs_relres((size_t)n_rhs, 0.0);
+  std::vector<int> rhs_state((size_t)n_rhs, kPadding), rhs_iters((size_t)n_rhs, 0);
+  int64_t first_bad_rhs = -1;
+  tip_status bad_status = TIP_OK;
+  for (int64_t blk0 = 0; blk0 < n_rhs && first_bad_rhs < 0; blk0 += sv.pl.B) {
+    const int nb = (int)std::min<int64_t>(sv.pl.B, n_rhs - blk0);
+    s = sv.solve_block(p->m_begin * ncomp + blk0, nb);
+    if (s != TIP_OK) return s;
+    for (int j = 0; j < nb; ++j) {
+      const size_t k = (size_t)(blk0 + j);
+      qre[k] = sv.h_q[2 * j];
+      qim[k] = sv.h_q[2 * j + 1];
+      rhs_state[k] = sv.h_state[j];
+      rhs_iters[k] = sv.h_iters[j];
+      rhs_relres[k] = std::sqrt(sv.h_relres2[j]);
+      if (sv.h_state[j] != kAccepted && first_bad_rhs < 0) {
+        first_bad_rhs = (int64_t)k;
+        bad_status = sv.h_state[j] == kBreakdown ? TIP_EBREAKDOWN : TIP_ENOCONV;
+      }
+    }
+  }
+
+  // ---- quadratures per probe, compensated sums, checkpoints ---------------
+  const int64_t n = p->n_vectors;
+  const int64_t good_probes = first_bad_rhs < 0 ? probes : first_bad_rhs / ncomp;
+  const int64_t m_end = p->m_begin + good_probes;      // probes [0, m_end) are valid
+  std::vector<double> q_all_re((size_t)m_end), q_all_im((size_t)m_end);
+  for (int64_t m = 0; m < p->m_begin; ++m) {
+    q_all_re[m] = p->quadratures[2 * m];
+    q_all_im[m] = p->quadratures[2 * m + 1];
+  }
+  for (int64_t m = p->m_begin; m < m_end; ++m) {
+    double re = 0.0, im = 0.0;
+    for (int c = 0; c < ncomp; ++c) {
+      re += qre[(size_t)((m - p->m_begin) * ncomp + c)];
+      im += qim[(size_t)((m - p->m_begin) * ncomp + c)];
+    }
+    q_all_re[m] = re;
+    q_all_im[m] = im;
+  }
+  if (p->quadratures)
+    for (int64_t m = p->m_begin; m < m_end; ++m) {
+      p->quadratures[2 * m] = q_all_re[m];
+      p->quadratures[2 * m + 1] = q_all_im[m];
+    }
+  const int nck = num_checkpoints(n);
+  int done = 0;
+  {
+    Compensated sre, sim;
+    int64_t m = 0;
+    for (int k = 0; k < nck; ++k) {
+      const int64_t sz = checkpoint_size(n, k);
+      if (sz > m_end) break;
+      for (; m < sz; ++m) {
+        sre.add(q_all_re[m]);
+        sim.add(q_all_im[m]);
+      }
+      estimates[2 * k] = sre.value() / (double)sz;
+      estimates[2 * k + 1] = sim.value() / (double)sz;
+      done = k + 1;
+    }
+  }
+
+  if (stats) {
+    std::memset(stats, 0, sizeof *stats);
+    double mx_rr = 0.0;
+    int64_t tot = 0;
+    int mx_it = 0, solved = 0;
+    for (int64_t k = 0; k < n_rhs; ++k) {
+      if (rhs_state[k] == kPadding) continue;
+      ++solved;
+      tot += rhs_iters[k];
+      mx_it = std::max(mx_it, rhs_iters[k]);
+      if (rhs_state[k] == kAccepted) mx_rr = std::max(mx_rr, rhs_relres[k]);
+    }
+    stats->solves = solved;
+    stats->total_iters = tot;
+    stats->max_iters = mx_it;
+    stats->n_checkpoints_done = done;
+    stats->max_true_relres = mx_rr;
+    sv.fill_stats(stats);
+    stats->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t_start).count();
+  }
+  if (first_bad_rhs >= 0) {
+    const int64_t bad_m = p->m_begin + first_bad_rhs / ncomp;
+    return fail(bad_status, "solve of probe %lld component %d %s", (long long)bad_m, (int)(first_bad_rhs % ncomp),
+                bad_status == TIP_EBREAKDOWN ? "broke down (p^H A p <= 0)" : "did not converge within max_iter");
+  }
+  return TIP_OK;
+}
+
+tip_status tip_solve_probe(tip_op_handle h, const tip_params* p, int64_t m, int32_t comp, double* x_out,
+                           double* q_out, tip_stats* stats) {
+  const auto t_start = std::chrono::steady_clock::now();
+  if (!h) return fail(TIP_EINVAL, "handle is NULL");
+  if (!p) return fail(TIP_EINVAL, "params is NULL");
+  tip_params one = *p;           // one right-hand side; probe-count fields do not apply
+  one.n_vectors = 1;
+  one.m_begin = 0;
+  one.rhs_block = 1;
+  int mask = 0;
+  tip_status s = check_params(h, &one, &mask);
+  if (s != TIP_OK) return s;
+  const Geom& g = h->geom;
+  if (m < 0 || m >= (int64_t)g.V) return fail(TIP_EINVAL, "probe %lld outside [0, V)", (long long)m);
+  if (comp < 0 || comp >= g.ncomp) return fail(TIP_EINVAL, "comp = %d out of range", comp);
+  if (!x_out) return fail(TIP_EINVAL, "x_out is NULL");
+  Solver sv;
+  s = sv.setup(h, &one, mask, 1);
+  if (s != TIP_OK) return s;
+  s = sv.solve_block(m * g.ncomp + comp, 1);
+  if (s != TIP_OK) return s;
+  TIP_HIP(launch_layout(g, sv.pl.elem, 1, sv.X, x_out, false, sv.st));
+  TIP_HIP(hipStreamSynchronize(sv.st));
+  if (q_out) {
+    q_out[0] = sv.h_q[0];
+    q_out[1] = sv.h_q[1];
+  }
+  if (stats) {
+    std::memset(stats, 0, sizeof *stats);
+    stats->solves = 1;
+    stats->total_iters = sv.h_iters[0];
+    stats->max_iters = sv.h_iters[0];
+    stats->max_true_relres = std::sqrt(sv.h_relres2[0]);
+    sv.fill_stats(stats);
+    stats->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t_start).count();
+  }
+  if (sv.h_state[0] == kBreakdown) return fail(TIP_EBREAKDOWN, "solve broke down (p^H A p <= 0)");
+  if (sv.h_state[0] != kAccepted) return fail(TIP_ENOCONV, "solve did not converge within max_iter");
+  return TIP_OK;
+}
+
+tip_status trace_inv_probe(const tip_operator* op, const tip_params* p, double* estimates, tip_stats* stats) {
+  if (!p) return fail(TIP_EINVAL, "params is NULL");
+  if (!estimates) return fail(TIP_EINVAL, "estimates is NULL");
+  Geom g;
+  tip_status s = validate_op(op, &g);
+  if (s != TIP_OK) return s;
+  if (p->n_vectors < 1 || p->n_vectors > (int64_t)g.V)
+    return fail(TIP_EINVAL, "n_vectors = %lld must be in [1, V = %u]", (long long)p->n_vectors, g.V);
+  tip_op_s* h = nullptr;
+  s = create_handle(op, (hipStream_t)p->stream, &h);
+  if (s != TIP_OK) return s;
+  s = trace_inv_probe_op(h, p, estimates, stats);
+  const std::string msg = g_err;
+  (void)hipStreamSynchronize((hipStream_t)p->stream);
+  delete h;
+  g_err = msg;
+  return s;
+}
+
+tip_status tip_apply_operator(const tip_operator* op, int32_t nrhs, const double* x, double* y, void* stream) {
+  Geom g;
+  tip_status s = validate_op(op, &g);
+  if (s != TIP_OK) return s;
+  if (nrhs < 1 || nrhs > 65535) return fail(TIP_EINVAL, "nrhs = %d must be in [1, 65535]", nrhs);
+  if (!x || !y) return fail(TIP_EINVAL, "x or y is NULL");
+  hipStream_t st = (hipStream_t)stream;
+  tip_op_s* h = nullptr;
+  s = create_handle(op, st, &h);
+  if (s != TIP_OK) return s;
+  const Elem elem = op->kind == TIP_KIND_COVARIANT ? Elem::kComplex : Elem::kReal;
+  const size_t esz = elem == Elem::kReal ? sizeof(double) : sizeof(double2);
+  const size_t bytes = (size_t)nrhs * g.ncomp * g.V * esz;
+  tip_status ret = TIP_OK;
+  do {
+    if (h->vec.ensure(2 * bytes) != hipSuccess) { ret = fail(TIP_ENOMEM, "hipMalloc apply buffers"); break; }
+    char* in = (char*)h->vec.p;
+    char* out = in + bytes;
+    if (launch_layout(g, elem, nrhs, x, in, true, st) != hipSuccess) { ret = fail(TIP_EDEVICE, "layout launch"); break; }
+    if (launch_matvec(h->dev(), g, elem, 1, nrhs, in, out, nullptr, nullptr, nullptr, st) != hipSuccess) {
+      ret = fail(TIP_EDEVICE, "stencil launch failed");
+      break;
+    }
+    if (launch_layout(g, elem, nrhs, out, y, false, st) != hipSuccess) { ret = fail(TIP_EDEVICE, "layout launch"); break; }
+    if (hipStreamSynchronize(st) != hipSuccess) { ret = fail(TIP_EDEVICE, "apply failed on the device"); break; }
+  } while (0);
+  delete h;
+  return ret;
+}
+
+tip_status tip_hier_perm(int32_t ndim, const int64_t* dims, uint32_t* P_out, void* stream) {
+  Geom g;
+  tip_status s = make_geom(ndim, dims, 1, &g);
+  if (s != TIP_OK) return s;
+  if (!P_out) return fail(TIP_EINVAL, "P_out is NULL");
+  hipStream_t st = (hipStream_t)stream;
+  TIP_HIP(launch_hier_perm(g, P_out, st));
+  TIP_HIP(hipStreamSynchronize(st));
+  return TIP_OK;
+}
+
+tip_status tip_probe_vectors(int32_t ndim, const int64_t* dims, int32_t ncomp, int32_t mask, uint64_t seed,
+                             int64_t m0, int64_t count, int32_t comp, double* out, void* stream) {
+  if (ncomp != 1 && ncomp != 3) return fail(TIP_EINVAL, "ncomp = %d, expected 1 or 3", ncomp);
+  Geom g;
+  tip_status s = make_geom(ndim, dims, ncomp, &g);
+  if (s != TIP_OK) return s;
+  if (mask == TIP_MASK_DEFAULT) mask = ncomp == 1 ? TIP_MASK_Z2 : TIP_MASK_Z4;
+  if (mask < TIP_MASK_NONE || mask > TIP_MASK_Z4) return fail(TIP_EINVAL, "unknown mask %d", mask);
+  if (comp < 0 || comp >= ncomp) return fail(TIP_EINVAL, "comp = %d out of range", comp);
+  if (m0 < 0 || count < 0 || m0 + count > (int64_t)g.V) return fail(TIP_EINVAL, "probe range outside [0, V)");
+  if (!out && count > 0) return fail(TIP_EINVAL, "out is NULL");
+  hipStream_t st = (hipStream_t)stream;
+  for (int64_t done = 0; done < count; done += 65535) {
+    const int c = (int)std::min<int64_t>(65535, count - done);
+    TIP_HIP(launch_probe_vectors(g, seed, mask, m0 + done, c, comp, (double2*)out + (size_t)done * g.V, st));
+  }
+  TIP_HIP(hipStreamSynchronize(st));
+  return TIP_OK;
+}
+
+}  // extern "C"

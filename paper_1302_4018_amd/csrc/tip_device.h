@@ -1,0 +1,176 @@
+// Device-side building blocks shared by the HIP kernels of libtip.
+//
+// Lattice geometry, the hierarchical permutation of Sec. 3 (Alg. 5 with the
+// Red-Black order in the closed form of Lemma 3.3), the probing-vector entry
+// of eq. row-col-permutation, the bias mask of Sec. 4 and small complex
+// helpers.  Everything here is computed per site from its index; nothing is
+// tabulated in memory.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace tip {
+
+constexpr int kMaxDim = 4;
+constexpr int kBlock = 256;        // threads per workgroup (4 wave64)
+constexpr int kMaxLevels = 31;
+
+// Per-call lattice description, passed by value to every kernel.
+struct Geom {
+  int32_t ndim;
+  int32_t ncomp;
+  uint32_t V;
+  int32_t L;                 // sum_j k_j = log2 V
+  int32_t nlevels;           // max_j k_j
+  int32_t logn[kMaxDim];     // k_j
+  int32_t shift[kMaxDim];    // log2 of the site-index stride of dimension j
+};
+
+__device__ __forceinline__ uint32_t coord(uint32_t s, const Geom& g, int mu) {
+  return (s >> g.shift[mu]) & ((1u << g.logn[mu]) - 1u);
+}
+
+// s + mu_hat and s - mu_hat with periodic wrap.
+__device__ __forceinline__ uint32_t nbr_fwd(uint32_t s, const Geom& g, int mu) {
+  const uint32_t n = 1u << g.logn[mu];
+  const uint32_t stride = 1u << g.shift[mu];
+  return coord(s, g, mu) == n - 1u ? s - (n - 1u) * stride : s + stride;
+}
+__device__ __forceinline__ uint32_t nbr_bwd(uint32_t s, const Geom& g, int mu) {
+  const uint32_t n = 1u << g.logn[mu];
+  const uint32_t stride = 1u << g.shift[mu];
+  return coord(s, g, mu) == 0u ? s + (n - 1u) * stride : s - stride;
+}
+
+// Location of site s in the hierarchical permutation (Sec. 3.3, Alg. 5).
+// Level m (0-based here) gathers bit m of every dimension that still has one,
+// first dimension most significant, and appends its Red-Black position
+// RB_a(i) = floor(i/2) + parity(i) 2^{a-1} (Lemma 3.3 with c_a(i) = parity of
+// the one-bits of i, which is what c_j = [c_{j-1}, not c_{j-1}] unrolls to).
+// The Theorem of Sec. 3.3 makes the a-dimensional table the one to use when
+// only a dimensions are active, so no d-dimensional table is needed.
+__device__ __forceinline__ uint32_t hier_perm(uint32_t s, const Geom& g) {
+  uint32_t x[kMaxDim];
+#pragma unroll
+  for (int mu = 0; mu < kMaxDim; ++mu) x[mu] = mu < g.ndim ? coord(s, g, mu) : 0u;
+  uint32_t loc = 0;
+  for (int m = 0; m < g.nlevels; ++m) {
+    uint32_t idx = 0;
+    int a = 0;
+#pragma unroll
+    for (int mu = 0; mu < kMaxDim; ++mu) {
+      if (mu < g.ndim && m < g.logn[mu]) {
+        idx = (idx << 1) | ((x[mu] >> m) & 1u);
+        ++a;
+      }
+    }
+    const uint32_t rb = (idx >> 1) | ((uint32_t)(__popc(idx) & 1) << (a - 1));
+    loc = (loc << a) | rb;
+  }
+  return loc;
+}
+
+// Column of the Hadamard matrix used by probe m: eq. HpermSequence is the
+// L-bit reversal of m.
+__device__ __forceinline__ uint32_t hadamard_column(uint32_t m, int L) {
+  return L == 0 ? 0u : (__brev(m) >> (32 - L));
+}
+
+// H(P, col) = (-1)^{popcount(P & col)} (eq. HadamardElements), as +1 / -1.
+__device__ __forceinline__ double hadamard_sign(uint32_t P, uint32_t col) {
+  return (__popc(P & col) & 1) ? -1.0 : 1.0;
+}
+
+// Output n of SplitMix64(seed) (Steele, Lea & Flood 2014): the generator's
+// state after n+1 steps is seed + (n+1) * gamma; the output mixes that state.
+__device__ __forceinline__ uint64_t splitmix64_at(uint64_t seed, uint64_t n) {
+  uint64_t z = seed + (n + 1ull) * 0x9E3779B97F4A7C15ull;
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  return z ^ (z >> 31);
+}
+
+enum MaskKind { kMaskNone = 0, kMaskZ2 = 1, kMaskZ4 = 2 };
+
+// Entry (s, comp) of the probing right-hand side b_{m,comp} = z0 .* z_m:
+// (re, im), each exactly 0 or +-1.
+__device__ __forceinline__ double2 probe_value(uint32_t s, uint32_t P, uint32_t col, int comp,
+                                               const Geom& g, uint64_t seed, int mask) {
+  const double h = hadamard_sign(P, col);
+  if (mask == kMaskNone) return make_double2(h, 0.0);
+  const uint64_t u = splitmix64_at(seed, (uint64_t)s * (uint64_t)g.ncomp + (uint64_t)comp);
+  if (mask == kMaskZ2) return make_double2((u >> 63) ? -h : h, 0.0);
+  switch ((int)(u >> 62)) {            // i^t
+    case 0: return make_double2(h, 0.0);
+    case 1: return make_double2(0.0, h);
+    case 2: return make_double2(-h, 0.0);
+    default: return make_double2(0.0, -h);
+  }
+}
+
+// ---- complex helpers (double2 = re, im) ----------------------------------
+__device__ __forceinline__ double2 cadd(double2 a, double2 b) { return make_double2(a.x + b.x, a.y + b.y); }
+__device__ __forceinline__ double2 csub(double2 a, double2 b) { return make_double2(a.x - b.x, a.y - b.y); }
+__device__ __forceinline__ double2 cscale(double a, double2 b) { return make_double2(a * b.x, a * b.y); }
+// acc + u * v
+__device__ __forceinline__ double2 cfma(double2 u, double2 v, double2 acc) {
+  acc.x = fma(u.x, v.x, acc.x);
+  acc.x = fma(-u.y, v.y, acc.x);
+  acc.y = fma(u.x, v.y, acc.y);
+  acc.y = fma(u.y, v.x, acc.y);
+  return acc;
+}
+// acc + conj(u) * v
+__device__ __forceinline__ double2 cfma_conj(double2 u, double2 v, double2 acc) {
+  acc.x = fma(u.x, v.x, acc.x);
+  acc.x = fma(u.y, v.y, acc.x);
+  acc.y = fma(u.x, v.y, acc.y);
+  acc.y = fma(-u.y, v.x, acc.y);
+  return acc;
+}
+
+// Generic element helpers for real (double) and complex (double2) vectors.
+__device__ __forceinline__ double axpy(double a, double x, double y) { return fma(a, x, y); }
+__device__ __forceinline__ double2 axpy(double a, double2 x, double2 y) {
+  return make_double2(fma(a, x.x, y.x), fma(a, x.y, y.y));
+}
+__device__ __forceinline__ double norm2(double a) { return a * a; }
+__device__ __forceinline__ double norm2(double2 a) { return fma(a.x, a.x, a.y * a.y); }
+// Re(conj(a) b)
+__device__ __forceinline__ double redot(double a, double b) { return a * b; }
+__device__ __forceinline__ double redot(double2 a, double2 b) { return fma(a.x, b.x, a.y * b.y); }
+// Im(conj(a) b)
+__device__ __forceinline__ double imdot(double, double) { return 0.0; }
+__device__ __forceinline__ double imdot(double2 a, double2 b) { return fma(a.x, b.y, -a.y * b.x); }
+template <class T> __device__ __forceinline__ T zero();
+template <> __device__ __forceinline__ double zero<double>() { return 0.0; }
+template <> __device__ __forceinline__ double2 zero<double2>() { return make_double2(0.0, 0.0); }
+template <class T> __device__ __forceinline__ T from_c(double2 v);
+template <> __device__ __forceinline__ double from_c<double>(double2 v) { return v.x; }
+template <> __device__ __forceinline__ double2 from_c<double2>(double2 v) { return v; }
+
+// Sum of N per-thread values over a 256-thread workgroup; thread 0 gets the
+// totals.  Wave64 butterfly first, then the 4 wave results through LDS; the
+// order is fixed, so results are reproducible run to run.
+template <int N>
+__device__ __forceinline__ void block_sum(double (&v)[N], double* lds /* [N][4] */) {
+#pragma unroll
+  for (int i = 0; i < N; ++i) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v[i] += __shfl_down(v[i], off, 64);
+  }
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  __syncthreads();   // lds may still be read by thread 0 from a previous call
+  if (lane == 0) {
+#pragma unroll
+    for (int i = 0; i < N; ++i) lds[i * 4 + wave] = v[i];
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int i = 0; i < N; ++i) v[i] = (lds[i * 4 + 0] + lds[i * 4 + 1]) + (lds[i * 4 + 2] + lds[i * 4 + 3]);
+  }
+}
+
+}  // namespace tip

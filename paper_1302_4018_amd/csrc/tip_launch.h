@@ -1,0 +1,64 @@
+// Internal interface between the host driver (tip_api.hip) and the kernels
+// (tip_kernels.hip).  Not part of the public C ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "tip_device.h"
+
+namespace tip {
+
+enum class Elem { kReal, kComplex };
+
+// Per right-hand-side CG state codes.
+enum : int { kActive = 0, kFrozen = 1, kAccepted = 2, kBreakdown = 3, kNoConv = 4, kPadding = 5 };
+
+// Operator as the kernels see it (device pointers, kernel layouts).
+struct OpDev {
+  int kind;                    // 0 scalar, 1 covariant
+  double mass;
+  const double* mass_field;    // [V] or null
+  const double* coupling;      // [ndim][V] or null
+  const double* links;         // [ndim][9][V] double2 (covariant)
+};
+
+// Per right-hand-side CG scalars, device arrays of length B (q: 2B).
+struct CgScalars {
+  double* rho;
+  double* alpha;
+  double* beta;
+  double* bnorm2;
+  double* relres2;
+  double* q;
+  int* state;
+  int* iters;
+  int* restarts;
+  int* active;                 // number of right-hand sides still iterating
+};
+
+hipError_t launch_matvec(const OpDev& op, const Geom& g, Elem elem, int R, int B, const void* in, void* out,
+                         double* partial, const int* active, int* ran, hipStream_t st);
+hipError_t launch_true_residual(const OpDev& op, const Geom& g, Elem elem, int R, int B, int64_t rhs0, int nb,
+                                uint64_t seed, int mask, const void* x, void* r, void* p, double* partial,
+                                size_t pstride, hipStream_t st);
+hipError_t launch_init(const Geom& g, Elem elem, int B, int64_t rhs0, int nb, uint64_t seed, int mask, void* x,
+                       void* r, void* p, hipStream_t st);
+hipError_t launch_update(const Geom& g, Elem elem, int B, const CgScalars& sc, void* x, void* r, const void* p,
+                         const void* Ap, double* partial, hipStream_t st);
+hipError_t launch_direction(const Geom& g, Elem elem, int B, const CgScalars& sc, const void* r, void* p,
+                            hipStream_t st);
+hipError_t launch_scalars_init(const CgScalars& sc, int nb, int B, double bnorm2, int start_frozen, hipStream_t st);
+hipError_t launch_reduce_alpha(const CgScalars& sc, int B, const double* partial, int gx, hipStream_t st);
+hipError_t launch_reduce_beta(const CgScalars& sc, int B, const double* partial, int gx, double tol2, int max_iter,
+                              hipStream_t st);
+hipError_t launch_reduce_true(const CgScalars& sc, int B, const double* partial, int gx, size_t pstride, double tol2,
+                              int max_iter, int max_restarts, hipStream_t st);
+hipError_t launch_hier_perm(const Geom& g, uint32_t* out, hipStream_t st);
+hipError_t launch_probe_vectors(const Geom& g, uint64_t seed, int mask, int64_t m0, int count, int comp, double2* out,
+                                hipStream_t st);
+hipError_t launch_repack_links(const Geom& g, const double2* src, double2* dst, hipStream_t st);
+hipError_t launch_layout(const Geom& g, Elem elem, int n, const void* src, void* dst, bool to_comp_major,
+                         hipStream_t st);
+
+}  // namespace tip

@@ -22,3 +22,22 @@ def read_golden(name):
             if line:
                 rows.append([float(t) if ("." in t or "e" in t) else int(t) for t in line.split()])
     return rows
+
+
+def gpu_binding():
+    """The HIP binding, or skip when this machine has no GPU.  A missing
+    library is an error, never a skip."""
+    import pytest
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU on this machine")
+    from paper_1302_4018_amd import binding
+    return binding
+
+
+def to_dev(a):
+    import torch
+    return None if a is None else torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+import numpy as np  # noqa: E402  (used by to_dev)
