@@ -15,6 +15,7 @@
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <new>
 #include <string>
@@ -200,11 +201,64 @@ int64_t checkpoint_size(int64_t n, int idx) {
 struct Plan {
   Elem elem;
   int mask;
-  int R;      // right-hand sides per thread in the stencil
-  int B;      // right-hand sides per block (multiple of R)
-  int gx;     // site workgroups
-  size_t esz; // bytes per vector element
+  int B, logB; // right-hand sides per block (power of two <= 64), one per lane
+  size_t esz;  // bytes per vector element
+  TileMap tm;  // generic site kernels
+  MarchMap mm; // marching stencil (valid when use_march)
+  bool use_march;
 };
+
+bool env_off(const char* name) {
+  const char* e = std::getenv(name);
+  return e && e[0] == '0';
+}
+
+TileMap make_tilemap(const Geom& g, int logB) {
+  TileMap tm{};
+  tm.logB = logB;
+  tm.TS = kBlock >> logB;
+  const int64_t V = g.V, ntiles = (V + tm.TS - 1) / tm.TS;
+  tm.grid = (uint32_t)ntiles;
+  // XCD-aware order: whole tiles, a tile count divisible by the XCD count and
+  // whole planes of the last dimension per XCD chunk (TIP_TILE_ORDER=0: off).
+  const int64_t n_last = int64_t(1) << g.logn[g.ndim - 1];
+  if (!env_off("TIP_TILE_ORDER") && V % tm.TS == 0 && ntiles % kNumXcd == 0 && ntiles % n_last == 0) {
+    const int64_t P = ntiles / n_last, C = ntiles / kNumXcd;
+    if (C % P == 0) {
+      tm.pc = (int32_t)(C / P);
+      tm.P = (int32_t)P;
+    }
+  }
+  return tm;
+}
+
+// Marching stencil map, or false when the geometry does not fit it
+// (TIP_MARCH=0 turns it off; TIP_MARCH_TC fixes the chunk length).
+bool make_marchmap(const Geom& g, int logB, MarchMap* mm) {
+  if (env_off("TIP_MARCH") || g.ndim < 2) return false;
+  const int nt = 1 << g.logn[g.ndim - 1];
+  if (nt < 2) return false;
+  const int TS = kBlock >> logB;
+  const uint32_t V3 = g.V / (uint32_t)nt;
+  if (V3 % (uint32_t)TS != 0) return false;
+  mm->logB = logB;
+  mm->TS = TS;
+  mm->V3 = V3;
+  mm->Q = (int32_t)(V3 / TS);
+  mm->nt = nt;
+  int Tc = nt;
+  if (const char* e = std::getenv("TIP_MARCH_TC")) {
+    const int v = std::atoi(e);
+    if (v >= 1 && v <= nt && (v & (v - 1)) == 0) Tc = v;
+  } else {
+    while (Tc > 1 && (int64_t)mm->Q * (nt / Tc) < 2048) Tc /= 2;
+  }
+  mm->Tc = Tc;
+  mm->xcd_order = !env_off("TIP_TILE_ORDER") && mm->Q % kNumXcd == 0;
+  mm->lds_links = !env_off("TIP_LDS_LINKS") && TS <= 64;
+  mm->grid = (uint32_t)mm->Q * (uint32_t)(nt / Tc);
+  return true;
+}
 
 // Common validation of the solve parameters; resolves the mask.
 tip_status check_params(const tip_op_s* h, const tip_params* p, int* mask_out) {
@@ -233,8 +287,9 @@ struct Solver {
   Plan pl;
   int max_iter, max_restarts = 8;
   double tol2;
-  size_t vbytes, pstride, nscal;
-  void *X, *Rv, *Pv, *Ap;
+  size_t vbytes, pstride, nscal, nelem;
+  int gx_m, gx_u, gx_t;       // partials per rhs written by matvec, update, true residual
+  void *X, *Rv, *Pv, *W;
   double* part;
   CgScalars sc;
   int* ran_dev;
@@ -248,6 +303,7 @@ struct Solver {
   double stencil_seconds = 0.0, stencil_bytes = 0.0;
   struct Timed { hipEvent_t a, b; };
   size_t ev_used = 0;
+  static constexpr int kMaxChunk = 4096;
 
   hipError_t next_event(hipEvent_t* e) {
     if (ev_used == h->events.size()) {
@@ -260,7 +316,7 @@ struct Solver {
     return hipSuccess;
   }
 
-  tip_status setup(tip_op_s* handle, const tip_params* params, int mask, int64_t n_rhs) {
+  tip_status setup(tip_op_s* handle, const tip_params* params, int mask) {
     h = handle;
     p = params;
     st = (hipStream_t)p->stream;
@@ -270,28 +326,39 @@ struct Solver {
     pl.mask = mask;
     pl.elem = (h->kind == TIP_KIND_COVARIANT || mask == TIP_MASK_Z4) ? Elem::kComplex : Elem::kReal;
     pl.esz = pl.elem == Elem::kReal ? sizeof(double) : sizeof(double2);
-    pl.gx = (int)((V + kBlock - 1) / kBlock);
-    pl.R = pl.gx < 64 ? 1 : 4;
+    // block size: a power of two <= 64; 16 shares each link among 16 solves;
+    // small lattices take more right-hand sides per block to fill the GPU.
+    // B depends only on the operator and rhs_block, so a right-hand side is
+    // solved with the same arithmetic whichever block it falls in (resumed
+    // runs reproduce uninterrupted ones bit for bit).
+    int B = 1;
     if (p->rhs_block > 0) {
-      pl.B = (int)std::min<int64_t>(p->rhs_block, std::max<int64_t>(n_rhs, 1));
+      while (B < p->rhs_block && B < 64) B *= 2;
     } else {
-      const int gy = std::max(1, (2048 + pl.gx - 1) / pl.gx);
-      pl.B = (int)std::min<int64_t>((int64_t)pl.R * gy, std::max<int64_t>(n_rhs, 1));
+      B = 16;
+      while (B < 64 && V * B < (int64_t(1) << 18)) B *= 2;
     }
     // keep the four CG vectors of a block within 32 GiB
-    while (pl.B > 1 && 4.0 * pl.B * ncomp * (double)V * pl.esz > 32.0 * (1ull << 30)) pl.B /= 2;
-    if (pl.B < pl.R) pl.R = pl.B >= 4 ? 4 : (pl.B >= 2 ? 2 : 1);
-    pl.B = (pl.B + pl.R - 1) / pl.R * pl.R;
+    while (B > 1 && 4.0 * B * ncomp * (double)V * pl.esz > 32.0 * (1ull << 30)) B /= 2;
+    pl.B = B;
+    pl.logB = 0;
+    while ((1 << pl.logB) < B) ++pl.logB;
+    pl.tm = make_tilemap(g, pl.logB);
+    pl.use_march = make_marchmap(g, pl.logB, &pl.mm);
     max_iter = p->max_iter > 0 ? p->max_iter : (int)std::min<int64_t>(10 * V * ncomp, 1 << 20);
     tol2 = p->tol * p->tol;
 
-    vbytes = (size_t)pl.B * ncomp * V * pl.esz;   // one CG vector of the block
-    pstride = (size_t)pl.B * pl.gx;
-    nscal = (size_t)pl.B;
+    nelem = (size_t)B * ncomp * V;
+    vbytes = nelem * pl.esz;                      // one CG vector of the block
+    gx_m = (int)(pl.use_march ? pl.mm.grid : pl.tm.grid);
+    gx_u = (int)update_grid(nelem);
+    gx_t = (int)pl.tm.grid;
+    pstride = (size_t)B * std::max(gx_m, std::max(gx_u, gx_t));
+    nscal = (size_t)B;
     if (h->vec.ensure(4 * vbytes) != hipSuccess)
       return fail(TIP_ENOMEM, "hipMalloc of %zu bytes of CG vectors failed", 4 * vbytes);
     if (h->partial.ensure(3 * pstride * sizeof(double)) != hipSuccess) return fail(TIP_ENOMEM, "hipMalloc partials");
-    const size_t scal_bytes = nscal * (7 * sizeof(double) + 3 * sizeof(int)) + 64 + kMaxChunk * sizeof(int);
+    const size_t scal_bytes = nscal * (8 * sizeof(double) + 3 * sizeof(int)) + 64 + kMaxChunk * sizeof(int);
     if (h->scal.ensure(scal_bytes) != hipSuccess) return fail(TIP_ENOMEM, "hipMalloc scalars");
     const size_t host_bytes = nscal * (3 * sizeof(double) + 2 * sizeof(int)) + 64 + kMaxChunk * sizeof(int);
     if (h->host.ensure(host_bytes) != hipSuccess) return fail(TIP_ENOMEM, "hipHostMalloc");
@@ -300,16 +367,17 @@ struct Solver {
     X = vb;
     Rv = vb + vbytes;
     Pv = vb + 2 * vbytes;
-    Ap = vb + 3 * vbytes;
+    W = vb + 3 * vbytes;
     part = (double*)h->partial.p;
     double* d = (double*)h->scal.p;
     sc.rho = d;
     sc.alpha = d + nscal;
-    sc.beta = d + 2 * nscal;
-    sc.bnorm2 = d + 3 * nscal;
-    sc.relres2 = d + 4 * nscal;
-    sc.q = d + 5 * nscal;            // 2 * nscal
-    int* iv = (int*)(d + 7 * nscal);
+    sc.xalpha = d + 2 * nscal;
+    sc.beta = d + 3 * nscal;
+    sc.bnorm2 = d + 4 * nscal;
+    sc.relres2 = d + 5 * nscal;
+    sc.q = d + 6 * nscal;            // 2 * nscal
+    int* iv = (int*)(d + 8 * nscal);
     sc.state = iv;
     sc.iters = iv + nscal;
     sc.restarts = iv + 2 * nscal;
@@ -324,28 +392,29 @@ struct Solver {
     h_ran = h_active + 16;
 
     od = h->dev();
-    // Algorithmic bytes of one stencil launch: every operand read or written once.
-    const double groups = pl.B / pl.R;
-    double per_group = 0.0;
-    if (h->kind == TIP_KIND_COVARIANT) per_group += (double)g.ndim * 9 * 16 * V;
-    if (h->has_coupling) per_group += (double)g.ndim * 8 * V;
-    if (h->has_mass_field) per_group += 8.0 * V;
-    mv_bytes = groups * per_group + 2.0 * pl.B * ncomp * V * pl.esz;
+    // Algorithmic bytes of one stencil launch: per site, each link, coupling
+    // and mass read once (shared by the B right-hand sides), p read and
+    // w = A p written once per right-hand side.
+    double per_site = 0.0;
+    if (h->kind == TIP_KIND_COVARIANT) per_site += (double)g.ndim * 9 * 16;
+    if (h->has_coupling) per_site += (double)g.ndim * 8;
+    if (h->has_mass_field) per_site += 8.0;
+    mv_bytes = per_site * V + 2.0 * (double)vbytes;
     return TIP_OK;
   }
-
-  static constexpr int kMaxChunk = 4096;
 
   // Solve right-hand sides rhs0 .. rhs0+nb-1; x stays in X.  Fills the host
   // mirrors h_q, h_relres2, h_state, h_iters for those nb right-hand sides.
   tip_status solve_block(int64_t rhs0, int nb) {
     const Geom& g = h->geom;
+    const MarchMap* mm = pl.use_march ? &pl.mm : nullptr;
     TIP_HIP(launch_scalars_init(sc, nb, pl.B, (double)g.V, p->tol >= 1.0 ? 1 : 0, st));
-    TIP_HIP(launch_init(g, pl.elem, pl.B, rhs0, nb, p->seed, pl.mask, X, Rv, Pv, st));
+    TIP_HIP(launch_init(g, pl.elem, pl.logB, rhs0, nb, p->seed, pl.mask, X, Rv, Pv, st));
     bool first_chunk = true;
     std::vector<Timed> window;
     for (;;) {
-      // CG iterations, polled every `chunk` iterations
+      // CG iterations, polled every `chunk` iterations; launches issued after
+      // every rhs of the block stopped return at once (ran flag stays 0)
       for (;;) {
         const int chunk = first_chunk ? std::min(kMaxChunk, std::max(1, predicted - 1)) : 2;
         first_chunk = false;
@@ -359,18 +428,16 @@ struct Solver {
             TIP_HIP(next_event(&tv.b));
             TIP_HIP(hipEventRecord(tv.a, st));
           }
-          TIP_HIP(launch_matvec(od, g, pl.elem, pl.R, pl.B, Pv, Ap, part, sc.active, ran_dev + it, st));
+          TIP_HIP(launch_stencil(od, g, pl.tm, mm, pl.elem, sc.state, sc.active, Pv, W, part, ran_dev + it, st));
           if (g_profiling) {
             TIP_HIP(hipEventRecord(tv.b, st));
             window.push_back(tv);
           }
-          TIP_HIP(launch_reduce_alpha(sc, pl.B, part, pl.gx, st));
-          TIP_HIP(launch_update(g, pl.elem, pl.B, sc, X, Rv, Pv, Ap, part + pstride, st));
-          TIP_HIP(launch_reduce_beta(sc, pl.B, part + pstride, pl.gx, tol2, max_iter, st));
-          TIP_HIP(launch_direction(g, pl.elem, pl.B, sc, Rv, Pv, st));
+          TIP_HIP(launch_reduce_alpha(sc, pl.B, part, gx_m, st));
+          TIP_HIP(launch_update_r(nelem, pl.logB, pl.elem, sc, Rv, W, part + pstride, st));
+          TIP_HIP(launch_reduce_beta(sc, pl.B, part + pstride, gx_u, tol2, max_iter, st));
+          TIP_HIP(launch_direction(nelem, pl.logB, pl.elem, sc, X, Rv, Pv, st));
         }
-        // launches issued after every RHS of the block stopped return at once;
-        // the kernel's ran flag tells the working launches apart
         TIP_HIP(hipMemcpyAsync(h_ran, ran_dev, chunk * sizeof(int), hipMemcpyDeviceToHost, st));
         TIP_HIP(hipMemcpyAsync(h_active, sc.active, sizeof(int), hipMemcpyDeviceToHost, st));
         TIP_HIP(hipStreamSynchronize(st));
@@ -387,9 +454,9 @@ struct Solver {
         if (*h_active == 0) break;
       }
       // true residual: accept, or restart CG from x
-      TIP_HIP(launch_true_residual(od, g, pl.elem, pl.R, pl.B, rhs0, nb, p->seed, pl.mask, X, Rv, Pv, part, pstride,
-                                   st));
-      TIP_HIP(launch_reduce_true(sc, pl.B, part, pl.gx, pstride, tol2, max_iter, max_restarts, st));
+      TIP_HIP(launch_true_residual(od, g, pl.tm, pl.elem, sc.state, rhs0, nb, p->seed, pl.mask, X, Rv, Pv, part,
+                                   pstride, st));
+      TIP_HIP(launch_reduce_true(sc, pl.B, part, gx_t, pstride, tol2, max_iter, max_restarts, st));
       TIP_HIP(hipMemcpyAsync(h_active, sc.active, sizeof(int), hipMemcpyDeviceToHost, st));
       TIP_HIP(hipStreamSynchronize(st));
       if (*h_active == 0) break;
@@ -449,7 +516,7 @@ tip_status trace_inv_probe_op(tip_op_handle h, const tip_params* p, double* esti
   const int64_t probes = p->n_vectors - p->m_begin;
   const int64_t n_rhs = probes * ncomp;
   Solver sv;
-  s = sv.setup(h, p, mask, n_rhs);
+  s = sv.setup(h, p, mask);
   if (s != TIP_OK) return s;
 
   std::vector<double> qre((size_t)n_rhs, 0.0), qim((size_t)n_rhs, 0.0), rhs_relres((size_t)n_rhs, 0.0);
@@ -560,11 +627,11 @@ tip_status tip_solve_probe(tip_op_handle h, const tip_params* p, int64_t m, int3
   if (comp < 0 || comp >= g.ncomp) return fail(TIP_EINVAL, "comp = %d out of range", comp);
   if (!x_out) return fail(TIP_EINVAL, "x_out is NULL");
   Solver sv;
-  s = sv.setup(h, &one, mask, 1);
+  s = sv.setup(h, &one, mask);
   if (s != TIP_OK) return s;
   s = sv.solve_block(m * g.ncomp + comp, 1);
   if (s != TIP_OK) return s;
-  TIP_HIP(launch_layout(g, sv.pl.elem, 1, sv.X, x_out, false, sv.st));
+  TIP_HIP(launch_layout(g, sv.pl.elem, sv.X, x_out, false, sv.st));
   TIP_HIP(hipStreamSynchronize(sv.st));
   if (q_out) {
     q_out[0] = sv.h_q[0];
@@ -607,7 +674,7 @@ tip_status tip_apply_operator(const tip_operator* op, int32_t nrhs, const double
   Geom g;
   tip_status s = validate_op(op, &g);
   if (s != TIP_OK) return s;
-  if (nrhs < 1 || nrhs > 65535) return fail(TIP_EINVAL, "nrhs = %d must be in [1, 65535]", nrhs);
+  if (nrhs < 1) return fail(TIP_EINVAL, "nrhs = %d must be >= 1", nrhs);
   if (!x || !y) return fail(TIP_EINVAL, "x or y is NULL");
   hipStream_t st = (hipStream_t)stream;
   tip_op_s* h = nullptr;
@@ -615,20 +682,21 @@ tip_status tip_apply_operator(const tip_operator* op, int32_t nrhs, const double
   if (s != TIP_OK) return s;
   const Elem elem = op->kind == TIP_KIND_COVARIANT ? Elem::kComplex : Elem::kReal;
   const size_t esz = elem == Elem::kReal ? sizeof(double) : sizeof(double2);
-  const size_t bytes = (size_t)nrhs * g.ncomp * g.V * esz;
+  const size_t bytes = (size_t)g.ncomp * g.V * esz;       // one vector
+  const TileMap tm = make_tilemap(g, 0);
   tip_status ret = TIP_OK;
-  do {
-    if (h->vec.ensure(2 * bytes) != hipSuccess) { ret = fail(TIP_ENOMEM, "hipMalloc apply buffers"); break; }
+  if (h->vec.ensure(2 * bytes) != hipSuccess) ret = fail(TIP_ENOMEM, "hipMalloc apply buffers");
+  for (int k = 0; k < nrhs && ret == TIP_OK; ++k) {
     char* in = (char*)h->vec.p;
     char* out = in + bytes;
-    if (launch_layout(g, elem, nrhs, x, in, true, st) != hipSuccess) { ret = fail(TIP_EDEVICE, "layout launch"); break; }
-    if (launch_matvec(h->dev(), g, elem, 1, nrhs, in, out, nullptr, nullptr, nullptr, st) != hipSuccess) {
-      ret = fail(TIP_EDEVICE, "stencil launch failed");
-      break;
-    }
-    if (launch_layout(g, elem, nrhs, out, y, false, st) != hipSuccess) { ret = fail(TIP_EDEVICE, "layout launch"); break; }
-    if (hipStreamSynchronize(st) != hipSuccess) { ret = fail(TIP_EDEVICE, "apply failed on the device"); break; }
-  } while (0);
+    const char* xk = (const char*)x + k * bytes;
+    char* yk = (char*)y + k * bytes;
+    if (launch_layout(g, elem, xk, in, true, st) != hipSuccess ||
+        launch_stencil(h->dev(), g, tm, nullptr, elem, nullptr, nullptr, in, out, nullptr, nullptr, st) != hipSuccess ||
+        launch_layout(g, elem, out, yk, false, st) != hipSuccess)
+      ret = fail(TIP_EDEVICE, "apply launch failed");
+  }
+  if (ret == TIP_OK && hipStreamSynchronize(st) != hipSuccess) ret = fail(TIP_EDEVICE, "apply failed on the device");
   delete h;
   return ret;
 }

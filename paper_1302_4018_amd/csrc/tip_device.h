@@ -27,6 +27,8 @@ struct Geom {
   int32_t shift[kMaxDim];    // log2 of the site-index stride of dimension j
 };
 
+constexpr int kNumXcd = 8;   // MI355X: 8 XCDs, each with its own L2
+
 __device__ __forceinline__ uint32_t coord(uint32_t s, const Geom& g, int mu) {
   return (s >> g.shift[mu]) & ((1u << g.logn[mu]) - 1u);
 }
@@ -151,7 +153,7 @@ template <> __device__ __forceinline__ double from_c<double>(double2 v) { return
 template <> __device__ __forceinline__ double2 from_c<double2>(double2 v) { return v; }
 
 // Sum of N per-thread values over a 256-thread workgroup; thread 0 gets the
-// totals.  Wave64 butterfly first, then the 4 wave results through LDS; the
+// totals.  A shuffle tree inside each wave64 first, then the 4 wave results through LDS; the
 // order is fixed, so results are reproducible run to run.
 template <int N>
 __device__ __forceinline__ void block_sum(double (&v)[N], double* lds /* [N][4] */) {

@@ -1,20 +1,33 @@
 // HIP kernels of libtip for gfx950 (MI355X).
 //
 // Data layout in HBM (site index s = x1 + n1 (x2 + n2 (x3 + n3 x4))):
-//   vectors   [B][ncomp][V] of T (T = double for real scalar problems,
-//             double2 = (re, im) otherwise): one coalesced 8/16-byte word per
-//             lane for every (rhs, component);
-//   links     [ndim][9][V] double2: element (a, b) of U_mu(s) at
-//             [mu][3a+b][s], so a wave reads each matrix element of 64
-//             consecutive sites as one contiguous 1 KiB run;
+//   vectors   a block of B right-hand sides (B a power of two <= 64) is one
+//             array [ncomp][V][B] of T (T = double for real scalar problems,
+//             double2 = (re, im) otherwise): right-hand side fastest.  A
+//             thread owns one (site, rhs) pair, the B lanes of a site are
+//             adjacent, so a wave reads 64/B sites x B rhs as one contiguous
+//             1 KiB (or 512 B) run and every per-site operand (links,
+//             couplings, mass) is one address shared by B lanes;
+//   links     [ndim][9][V] double2: element (a, b) of U_mu(s) at [mu][3a+b][s];
 //   coupling  [ndim][V] double, mass_field [V] double (caller layout).
-// Workgroups are 256 threads; blockIdx.x tiles sites, blockIdx.y selects a
-// group of R right-hand sides that one thread carries in registers, so each
-// link is read once per R right-hand sides.
 //
+// The stencil marches along the last lattice dimension ("t"): a workgroup
+// owns a tile of 256/B sites of the other dimensions and a chunk of t values.
+// Each t-link is read once and used twice (forward hop of t, and the
+// backward hop of t+1, carried in registers), x(t-1), x(t), x(t+1) stay in
+// registers, and tiles are ordered so that one XCD keeps a contiguous slab
+// of tiles in flight (neighbour loads then hit its own L2).
+//
+// CG (Hestenes-Stiefel, per right-hand side j) uses three passes per
+// iteration, with one-workgroup-per-RHS reductions in between:
+//   matvec:  w = A p, partial p^H w            -> alpha = rho / p^H w
+//   update:  r -= alpha w, partial ||r||^2     -> beta = rho' / rho
+//   direct:  x += alpha p; p = r + beta p
 // All reductions are two-stage and deterministic: each workgroup writes one
-// partial per right-hand side, a second kernel sums the partials in a fixed
+// partial per right-hand side and a second kernel sums them in a fixed
 // order.  No floating-point atomics are used.
+
+#include <algorithm>
 
 #include "tip_device.h"
 #include "tip_launch.h"
@@ -22,342 +35,482 @@
 namespace tip {
 
 // ---------------------------------------------------------------------------
-// Stencils: hop(s) = sum_mu [w_mu(s) U_mu(s) x(s+mu) + w_mu(s-mu) U_mu(s-mu)^H x(s-mu)],
-// diag(s) = m(s) + sum_mu [w_mu(s) + w_mu(s-mu)],  (A x)(s) = diag(s) x(s) - hop(s).
+// Operator policies and small helpers
 // ---------------------------------------------------------------------------
 
-template <int R>
-__device__ __forceinline__ void cov_hop(const Geom& g, uint32_t s, const double2* __restrict__ U,
-                                        const double* __restrict__ w, const double2* __restrict__ in,
-                                        double2 (&hop)[R][3], double& diag) {
+struct CovOp {                         // 3 complex components, links U_mu
+  using T = double2;
+  static constexpr int NC = 3;
+  const double2* __restrict__ U;
+};
+
+template <class TT>
+struct ScalarOp {                      // 1 component, real or complex vectors
+  using T = TT;
+  static constexpr int NC = 1;
+};
+
+// y = U x and y = U^H x for a 3x3 complex matrix u[3a+b].
+__device__ __forceinline__ void mul_u(const double2 (&u)[9], const double2 (&x)[3], double2 (&y)[3]) {
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    double2 t = make_double2(0.0, 0.0);
+#pragma unroll
+    for (int b = 0; b < 3; ++b) t = cfma(u[3 * a + b], x[b], t);
+    y[a] = t;
+  }
+}
+__device__ __forceinline__ void mul_uh(const double2 (&u)[9], const double2 (&x)[3], double2 (&y)[3]) {
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    double2 t = make_double2(0.0, 0.0);
+#pragma unroll
+    for (int b = 0; b < 3; ++b) t = cfma_conj(u[3 * b + a], x[b], t);
+    y[a] = t;
+  }
+}
+
+__device__ __forceinline__ void load_link(const CovOp& op, size_t V, int mu, uint32_t s, double2 (&u)[9]) {
+  const double2* Um = op.U + (size_t)mu * 9 * V;
+#pragma unroll
+  for (int e = 0; e < 9; ++e) u[e] = Um[(size_t)e * V + s];
+}
+
+// x at (site s, rhs lane j) for all components: in[(c V + s) B + j]
+template <class T, int NC>
+__device__ __forceinline__ void load_vec(const T* __restrict__ in, size_t V, int logB, uint32_t s, int j, T (&x)[NC]) {
+#pragma unroll
+  for (int c = 0; c < NC; ++c) x[c] = in[((((size_t)c * V + s)) << logB) + j];
+}
+template <class T, int NC>
+__device__ __forceinline__ void store_vec(T* __restrict__ out, size_t V, int logB, uint32_t s, int j, const T (&x)[NC]) {
+#pragma unroll
+  for (int c = 0; c < NC; ++c) out[((((size_t)c * V + s)) << logB) + j] = x[c];
+}
+
+// One hop term h = U x (fwd) or U^H x (bwd) for the operator policy.
+template <class Op>
+__device__ __forceinline__ void hop_term(const Op&, size_t, int, uint32_t, bool,
+                                         const typename Op::T (&x)[Op::NC], typename Op::T (&h)[Op::NC]) {
+  h[0] = x[0];
+}
+__device__ __forceinline__ void hop_term(const CovOp& op, size_t V, int mu, uint32_t s_link, bool backward,
+                                         const double2 (&x)[3], double2 (&h)[3]) {
+  double2 u[9];
+  load_link(op, V, mu, s_link, u);
+  if (backward) mul_uh(u, x, h);
+  else mul_u(u, x, h);
+}
+
+// acc += wgt * h
+template <class T, int NC>
+__device__ __forceinline__ void add_weighted(double wgt, const T (&h)[NC], T (&acc)[NC]) {
+#pragma unroll
+  for (int c = 0; c < NC; ++c) acc[c] = axpy(wgt, h[c], acc[c]);
+}
+
+// Sum per right-hand side over a 256-thread workgroup whose lane l holds rhs
+// l mod B: a shuffle tree inside each wave down to B lanes, then the four
+// wave results through LDS.  Threads tid < B end with the totals of rhs tid.
+template <int N>
+__device__ __forceinline__ void seg_sum(double (&v)[N], int B, double* lds /* [N][4][64] */) {
+#pragma unroll
+  for (int i = 0; i < N; ++i)
+    for (int off = 32; off >= B; off >>= 1) v[i] += __shfl_down(v[i], off, 64);
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  __syncthreads();
+  if (lane < B) {
+#pragma unroll
+    for (int i = 0; i < N; ++i) lds[(i * 4 + wave) * 64 + lane] = v[i];
+  }
+  __syncthreads();
+  if ((int)threadIdx.x < B) {
+    const int t = threadIdx.x;
+#pragma unroll
+    for (int i = 0; i < N; ++i)
+      v[i] = (lds[(i * 4 + 0) * 64 + t] + lds[(i * 4 + 1) * 64 + t]) +
+             (lds[(i * 4 + 2) * 64 + t] + lds[(i * 4 + 3) * 64 + t]);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Site tiles: a workgroup owns TS = 256/B sites x B right-hand sides.
+// ---------------------------------------------------------------------------
+
+// First site of tile b in the generic (one site per thread) kernels.
+// Workgroups are dispatched round-robin over the XCDs (b mod 8), so tile b
+// and tile b+1 land on different L2 caches.  When the geometry allows, XCD k
+// instead gets a contiguous chunk of pc planes of the last (slowest)
+// dimension and walks it with that dimension innermost, so the +-mu
+// neighbours a tile needs were fetched into the same L2 by tiles dispatched
+// shortly before it.  The map is a bijection of the tiles; it changes only
+// which workgroup computes which sites, never the arithmetic of a site.
+__device__ __forceinline__ uint32_t tile_first_site(uint32_t b, const TileMap& tm) {
+  if (tm.pc == 0) return b * (uint32_t)tm.TS;
+  const uint32_t xcd = b % kNumXcd, slot = b / kNumXcd;
+  const uint32_t t_local = slot % (uint32_t)tm.pc, q = slot / (uint32_t)tm.pc;
+  return ((xcd * (uint32_t)tm.pc + t_local) * (uint32_t)tm.P + q) * (uint32_t)tm.TS;
+}
+
+// Stencil at one (site, rhs): y = diag x(s) - sum_mu [w_mu(s) U_mu(s) x(s+mu)
+// + w_mu(s-mu) U_mu(s-mu)^H x(s-mu)], with the hop terms summed in the order
+// mu = 0..ndim-1, forward before backward (the marching kernel keeps it).
+template <class Op>
+__device__ __forceinline__ void stencil_site(const Op& op, const Geom& g, int logB, uint32_t s, int j,
+                                             const double* __restrict__ mass_field, double mass,
+                                             const double* __restrict__ w, const typename Op::T* __restrict__ in,
+                                             typename Op::T (&xs)[Op::NC], typename Op::T (&y)[Op::NC]) {
+  using T = typename Op::T;
+  constexpr int NC = Op::NC;
   const size_t V = g.V;
+  T hop[NC];
 #pragma unroll
-  for (int r = 0; r < R; ++r)
-#pragma unroll
-    for (int a = 0; a < 3; ++a) hop[r][a] = make_double2(0.0, 0.0);
+  for (int c = 0; c < NC; ++c) hop[c] = zero<T>();
+  double diag = mass_field ? mass_field[s] : mass;
   for (int mu = 0; mu < g.ndim; ++mu) {
     const uint32_t sf = nbr_fwd(s, g, mu);
     const uint32_t sb = nbr_bwd(s, g, mu);
     const double wf = w ? w[(size_t)mu * V + s] : 1.0;
     const double wb = w ? w[(size_t)mu * V + sb] : 1.0;
     diag += wf + wb;
-    const double2* Um = U + (size_t)mu * 9 * V;
-    {
-      double2 u[9];
-#pragma unroll
-      for (int e = 0; e < 9; ++e) u[e] = Um[(size_t)e * V + s];
-#pragma unroll
-      for (int r = 0; r < R; ++r) {
-        double2 xv[3];
-#pragma unroll
-        for (int b = 0; b < 3; ++b) xv[b] = in[((size_t)r * 3 + b) * V + sf];
-#pragma unroll
-        for (int a = 0; a < 3; ++a) {
-          double2 t = make_double2(0.0, 0.0);
-#pragma unroll
-          for (int b = 0; b < 3; ++b) t = cfma(u[3 * a + b], xv[b], t);
-          hop[r][a].x = fma(wf, t.x, hop[r][a].x);
-          hop[r][a].y = fma(wf, t.y, hop[r][a].y);
-        }
-      }
-    }
-    {
-      double2 u[9];
-#pragma unroll
-      for (int e = 0; e < 9; ++e) u[e] = Um[(size_t)e * V + sb];
-#pragma unroll
-      for (int r = 0; r < R; ++r) {
-        double2 xv[3];
-#pragma unroll
-        for (int b = 0; b < 3; ++b) xv[b] = in[((size_t)r * 3 + b) * V + sb];
-#pragma unroll
-        for (int a = 0; a < 3; ++a) {
-          double2 t = make_double2(0.0, 0.0);
-#pragma unroll
-          for (int b = 0; b < 3; ++b) t = cfma_conj(u[3 * b + a], xv[b], t);
-          hop[r][a].x = fma(wb, t.x, hop[r][a].x);
-          hop[r][a].y = fma(wb, t.y, hop[r][a].y);
-        }
-      }
-    }
+    T xn[NC], h[NC];
+    load_vec<T, NC>(in, V, logB, sf, j, xn);
+    hop_term(op, V, mu, s, false, xn, h);
+    add_weighted<T, NC>(wf, h, hop);
+    load_vec<T, NC>(in, V, logB, sb, j, xn);
+    hop_term(op, V, mu, sb, true, xn, h);
+    add_weighted<T, NC>(wb, h, hop);
   }
+  load_vec<T, NC>(in, V, logB, s, j, xs);
+#pragma unroll
+  for (int c = 0; c < NC; ++c) y[c] = axpy(diag, xs[c], axpy(-1.0, hop[c], zero<T>()));
 }
 
-template <class T, int R>
-__device__ __forceinline__ void scalar_hop(const Geom& g, uint32_t s, const double* __restrict__ w,
-                                           const T* __restrict__ in, T (&hop)[R], double& diag) {
-  const size_t V = g.V;
-#pragma unroll
-  for (int r = 0; r < R; ++r) hop[r] = zero<T>();
-  for (int mu = 0; mu < g.ndim; ++mu) {
-    const uint32_t sf = nbr_fwd(s, g, mu);
-    const uint32_t sb = nbr_bwd(s, g, mu);
-    const double wf = w ? w[(size_t)mu * V + s] : 1.0;
-    const double wb = w ? w[(size_t)mu * V + sb] : 1.0;
-    diag += wf + wb;
-#pragma unroll
-    for (int r = 0; r < R; ++r) {
-      hop[r] = axpy(wf, in[(size_t)r * V + sf], hop[r]);
-      hop[r] = axpy(wb, in[(size_t)r * V + sb], hop[r]);
-    }
-  }
-}
+// ---------------------------------------------------------------------------
+// Stencil kernels
+// ---------------------------------------------------------------------------
 
-// out = A in for R right-hand sides per thread; partial[j][bx] = Re(in_j^H out_j)
-// summed over the workgroup's sites (p^H A p in CG).  partial may be null.
-template <int R>
-__global__ __launch_bounds__(kBlock) void k_cov_matvec(Geom g, const double2* __restrict__ U,
-                                                       const double* __restrict__ mass_field, double mass,
-                                                       const double* __restrict__ w,
-                                                       const double2* __restrict__ in,
-                                                       double2* __restrict__ out,
-                                                       double* __restrict__ partial,
-                                                       const int* __restrict__ active, int* __restrict__ ran) {
+// Generic stencil, one (site, rhs) per thread: out = A in for lanes whose rhs
+// is live (state == kActive, or every lane when state is null); partial[j][bx]
+// = Re(in_j^H out_j) over the tile.
+template <class Op>
+__global__ __launch_bounds__(kBlock) void k_stencil(Geom g, TileMap tm, Op op, const double* __restrict__ mass_field,
+                                                    double mass, const double* __restrict__ w, const int* __restrict__ state,
+                                                    const int* __restrict__ active, const typename Op::T* __restrict__ in,
+                                                    typename Op::T* __restrict__ out, double* __restrict__ partial,
+                                                    int* __restrict__ ran) {
+  using T = typename Op::T;
+  constexpr int NC = Op::NC;
   if (active && *active == 0) return;
-  if (ran && blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x == 0) *ran = 1;
-  __shared__ double lds[R * 4];
-  const uint32_t s = blockIdx.x * kBlock + threadIdx.x;
-  const size_t V = g.V;
-  const size_t off = (size_t)blockIdx.y * R * 3 * V;
-  in += off;
-  out += off;
-  double dot[R];
+  if (ran && blockIdx.x == 0 && threadIdx.x == 0) *ran = 1;
+  __shared__ double lds[4 * 64];
+  const int B = 1 << tm.logB;
+  const int j = threadIdx.x & (B - 1);
+  const uint32_t s = tile_first_site(blockIdx.x, tm) + (threadIdx.x >> tm.logB);
+  double dot[1] = {0.0};
+  if (s < g.V && (!state || state[j] == kActive)) {
+    T xs[NC], y[NC];
+    stencil_site(op, g, tm.logB, s, j, mass_field, mass, w, in, xs, y);
+    store_vec<T, NC>(out, g.V, tm.logB, s, j, y);
 #pragma unroll
-  for (int r = 0; r < R; ++r) dot[r] = 0.0;
-  if (s < g.V) {
-    double2 hop[R][3];
-    double diag = mass_field ? mass_field[s] : mass;
-    cov_hop<R>(g, s, U, w, in, hop, diag);
-#pragma unroll
-    for (int r = 0; r < R; ++r) {
-#pragma unroll
-      for (int a = 0; a < 3; ++a) {
-        const size_t i = ((size_t)r * 3 + a) * V + s;
-        const double2 x = in[i];
-        double2 y;
-        y.x = fma(diag, x.x, -hop[r][a].x);
-        y.y = fma(diag, x.y, -hop[r][a].y);
-        out[i] = y;
-        dot[r] += redot(x, y);
-      }
-    }
+    for (int c = 0; c < NC; ++c) dot[0] += redot(xs[c], y[c]);
   }
   if (partial) {
-    block_sum<R>(dot, lds);
-    if (threadIdx.x == 0) {
-#pragma unroll
-      for (int r = 0; r < R; ++r) partial[(size_t)(blockIdx.y * R + r) * gridDim.x + blockIdx.x] = dot[r];
-    }
+    seg_sum<1>(dot, B, lds);
+    if ((int)threadIdx.x < B) partial[(size_t)threadIdx.x * gridDim.x + blockIdx.x] = dot[0];
   }
 }
 
-template <class T, int R>
-__global__ __launch_bounds__(kBlock) void k_scalar_matvec(Geom g, const double* __restrict__ mass_field,
-                                                          double mass, const double* __restrict__ w,
-                                                          const T* __restrict__ in, T* __restrict__ out,
-                                                          double* __restrict__ partial,
-                                                          const int* __restrict__ active, int* __restrict__ ran) {
+// Marching stencil (ndim >= 2): workgroup b owns spatial tile q (TS sites of
+// the first ndim-1 dimensions, V3 = V / n_t sites per t-plane) and the t
+// values [c Tc, (c+1) Tc).  Same arithmetic, same summation order as
+// stencil_site.
+//
+// kLdsLinks (covariant operator): at every t the workgroup first copies the
+// links its TS sites use -- the forward link of every dimension and the
+// backward link U_mu(s-mu) of every marched-over dimension -- into LDS with
+// one coalesced 16-byte load per element, then the B lanes of a site read
+// them from there.  Without it every lane would fetch the 3x3 matrices
+// itself, so the L1 would deliver each link B times.
+template <class Op, bool kLdsLinks, int kLogB = -1, int kHasW = -1>
+__global__ __launch_bounds__(kBlock) void k_stencil_march(Geom g, MarchMap mm, Op op,
+                                                          const double* __restrict__ mass_field, double mass,
+                                                          const double* __restrict__ w, const int* __restrict__ state,
+                                                          const int* __restrict__ active,
+                                                          const typename Op::T* __restrict__ in,
+                                                          typename Op::T* __restrict__ out,
+                                                          double* __restrict__ partial, int* __restrict__ ran) {
+  using T = typename Op::T;
+  constexpr int NC = Op::NC;
   if (active && *active == 0) return;
-  if (ran && blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x == 0) *ran = 1;
-  __shared__ double lds[R * 4];
-  const uint32_t s = blockIdx.x * kBlock + threadIdx.x;
-  const size_t V = g.V;
-  const size_t off = (size_t)blockIdx.y * R * V;
-  in += off;
-  out += off;
-  double dot[R];
-#pragma unroll
-  for (int r = 0; r < R; ++r) dot[r] = 0.0;
-  if (s < g.V) {
-    T hop[R];
-    double diag = mass_field ? mass_field[s] : mass;
-    scalar_hop<T, R>(g, s, w, in, hop, diag);
-#pragma unroll
-    for (int r = 0; r < R; ++r) {
-      const size_t i = (size_t)r * V + s;
-      const T x = in[i];
-      const T y = axpy(diag, x, axpy(-1.0, hop[r], zero<T>()));
-      out[i] = y;
-      dot[r] += redot(x, y);
+  if (ran && blockIdx.x == 0 && threadIdx.x == 0) *ran = 1;
+  __shared__ double lds[4 * 64];
+  extern __shared__ double2 lds_links[];           // [2 ndim - 1][9][TS] when kLdsLinks
+  // kLogB >= 0 / kHasW >= 0 fix the block size / the presence of couplings at
+  // compile time (LDS offsets become immediates, unit weights disappear)
+  const int logB = kLogB >= 0 ? kLogB : mm.logB;
+  const int B = 1 << logB;
+  const int TS = kBlock >> logB;
+  if (kHasW == 0) w = nullptr;
+  const int j = threadIdx.x & (B - 1);
+  const int si = threadIdx.x >> logB;
+  uint32_t q, chunk;
+  {
+    const uint32_t b = blockIdx.x;
+    if (mm.xcd_order) {
+      const uint32_t per = (uint32_t)mm.Q / kNumXcd;      // spatial tiles per XCD
+      const uint32_t xcd = b % kNumXcd, slot = b / kNumXcd;
+      q = xcd * per + slot % per;
+      chunk = slot / per;
+    } else {
+      q = b % (uint32_t)mm.Q;
+      chunk = b / (uint32_t)mm.Q;
     }
   }
-  if (partial) {
-    block_sum<R>(dot, lds);
-    if (threadIdx.x == 0) {
-#pragma unroll
-      for (int r = 0; r < R; ++r) partial[(size_t)(blockIdx.y * R + r) * gridDim.x + blockIdx.x] = dot[r];
+  const uint32_t s3_first = q * (uint32_t)TS;
+  const uint32_t s3 = s3_first + (uint32_t)si;
+  const size_t V = g.V;
+  const uint32_t V3 = mm.V3;
+  const int nt = mm.nt;
+  const int mt = g.ndim - 1;                      // marching dimension
+  const bool live = !state || state[j] == kActive;
+  const int t0 = (int)chunk * mm.Tc;
+  double dot[1] = {0.0};
+  T carry[NC], xc[NC];
+  double wprev = 1.0;
+  if (live) {
+    // prologue: x(t0-1) and the link from t0-1 give the backward t hop of t0
+    const int tp = t0 == 0 ? nt - 1 : t0 - 1;
+    const uint32_t sp = s3 + V3 * (uint32_t)tp;
+    T xp[NC];
+    load_vec<T, NC>(in, V, logB, sp, j, xp);
+    hop_term(op, V, mt, sp, true, xp, carry);
+    wprev = w ? w[(size_t)mt * V + sp] : 1.0;
+    load_vec<T, NC>(in, V, logB, s3 + V3 * (uint32_t)t0, j, xc);
+  }
+  for (int t = t0; t < t0 + mm.Tc; ++t) {
+    const uint32_t s = s3 + V3 * (uint32_t)t;
+    if constexpr (kLdsLinks) {
+      // every thread helps to stage the tile's links, live or not
+      const int nitems = (2 * g.ndim - 1) * 9 * TS;
+      __syncthreads();
+      for (int it = threadIdx.x; it < nitems; it += kBlock) {
+        const int site = it & (TS - 1);
+        const int es = it >> (8 - logB);          // it / TS
+        const int e = es % 9;
+        const int slot = es / 9;
+        const uint32_t ss = s3_first + (uint32_t)site + V3 * (uint32_t)t;
+        const int mu = slot < g.ndim ? slot : slot - g.ndim;
+        const uint32_t sl = slot < g.ndim ? ss : nbr_bwd(ss, g, mu);
+        lds_links[it] = op.U[((size_t)mu * 9 + e) * V + sl];
+      }
+      __syncthreads();
     }
+    if (!live) continue;
+    const uint32_t sn = s3 + V3 * (uint32_t)(t + 1 == nt ? 0 : t + 1);
+    T hop[NC];
+#pragma unroll
+    for (int c = 0; c < NC; ++c) hop[c] = zero<T>();
+    double diag = mass_field ? mass_field[s] : mass;
+    for (int mu = 0; mu < mt; ++mu) {
+      const uint32_t sf = nbr_fwd(s, g, mu);
+      const uint32_t sb = nbr_bwd(s, g, mu);
+      const double wf = w ? w[(size_t)mu * V + s] : 1.0;
+      const double wb = w ? w[(size_t)mu * V + sb] : 1.0;
+      diag += wf + wb;
+      T xn[NC], h[NC];
+      load_vec<T, NC>(in, V, logB, sf, j, xn);
+      if constexpr (kLdsLinks) {
+        double2 u[9];
+#pragma unroll
+        for (int e = 0; e < 9; ++e) u[e] = lds_links[(mu * 9 + e) * TS + si];
+        mul_u(u, xn, h);
+      } else {
+        hop_term(op, V, mu, s, false, xn, h);
+      }
+      add_weighted<T, NC>(wf, h, hop);
+      load_vec<T, NC>(in, V, logB, sb, j, xn);
+      if constexpr (kLdsLinks) {
+        double2 u[9];
+#pragma unroll
+        for (int e = 0; e < 9; ++e) u[e] = lds_links[((g.ndim + mu) * 9 + e) * TS + si];
+        mul_uh(u, xn, h);
+      } else {
+        hop_term(op, V, mu, sb, true, xn, h);
+      }
+      add_weighted<T, NC>(wb, h, hop);
+    }
+    // t direction: forward hop with the link of s, backward hop carried
+    const double wt = w ? w[(size_t)mt * V + s] : 1.0;
+    diag += wt + wprev;
+    T xn[NC], h[NC];
+    load_vec<T, NC>(in, V, logB, sn, j, xn);
+    if constexpr (NC == 3) {
+      double2 u[9];
+      if constexpr (kLdsLinks) {
+#pragma unroll
+        for (int e = 0; e < 9; ++e) u[e] = lds_links[(mt * 9 + e) * TS + si];
+      } else {
+        load_link(op, V, mt, s, u);
+      }
+      mul_u(u, xn, h);
+      add_weighted<T, NC>(wt, h, hop);
+      add_weighted<T, NC>(wprev, carry, hop);
+      mul_uh(u, xc, carry);                    // backward hop of t+1
+    } else {
+      add_weighted<T, NC>(wt, xn, hop);
+      add_weighted<T, NC>(wprev, carry, hop);
+      carry[0] = xc[0];
+    }
+    wprev = wt;
+    T y[NC];
+#pragma unroll
+    for (int c = 0; c < NC; ++c) {
+      y[c] = axpy(diag, xc[c], axpy(-1.0, hop[c], zero<T>()));
+      dot[0] += redot(xc[c], y[c]);
+    }
+    store_vec<T, NC>(out, V, logB, s, j, y);
+#pragma unroll
+    for (int c = 0; c < NC; ++c) xc[c] = xn[c];
+  }
+  if (partial) {
+    seg_sum<1>(dot, B, lds);
+    if ((int)threadIdx.x < B) partial[(size_t)threadIdx.x * gridDim.x + blockIdx.x] = dot[0];
   }
 }
 
 // ---------------------------------------------------------------------------
-// CG passes.  RHS j of the block is global right-hand side rhs0 + j, i.e.
-// spatial probe m = (rhs0 + j) / ncomp and component c = (rhs0 + j) % ncomp.
+// CG vector passes over the flat block [ncomp][V][B]: element i has rhs i mod B.
 // ---------------------------------------------------------------------------
 
-// x = 0, r = p = b_j (generated from the site index), zero for padding RHS.
+// r -= alpha w for active right-hand sides; partial = ||r||^2.  Grid-stride:
+// the stride is a multiple of 256, so a thread always meets the same rhs and
+// the number of partials per rhs is the (moderate) grid size.
 template <class T>
-__global__ __launch_bounds__(kBlock) void k_init(Geom g, int64_t rhs0, int nb, uint64_t seed, int mask,
-                                                 T* __restrict__ x, T* __restrict__ r, T* __restrict__ p) {
-  const uint32_t s = blockIdx.x * kBlock + threadIdx.x;
-  if (s >= g.V) return;
-  const int j = blockIdx.y;
-  const size_t V = g.V;
-  const uint32_t P = hier_perm(s, g);
-  const int64_t rg = rhs0 + j;
-  const int cj = (int)(rg % g.ncomp);
-  const uint32_t col = hadamard_column((uint32_t)(rg / g.ncomp), g.L);
-  for (int c = 0; c < g.ncomp; ++c) {
-    const size_t i = ((size_t)j * g.ncomp + c) * V + s;
-    T b = zero<T>();
-    if (j < nb && c == cj) b = from_c<T>(probe_value(s, P, col, c, g, seed, mask));
-    x[i] = zero<T>();
-    r[i] = b;
-    p[i] = b;
-  }
-}
-
-// x += alpha p; r -= alpha Ap; partial = ||r||^2  (active right-hand sides only)
-template <class T>
-__global__ __launch_bounds__(kBlock) void k_update(Geom g, const CgScalars sc, T* __restrict__ x,
-                                                   T* __restrict__ r, const T* __restrict__ p,
-                                                   const T* __restrict__ Ap, double* __restrict__ partial) {
-  const int j = blockIdx.y;
-  if (*sc.active == 0 || sc.state[j] != kActive) return;
-  __shared__ double lds[4];
-  const uint32_t s = blockIdx.x * kBlock + threadIdx.x;
-  const size_t V = g.V;
-  const double a = sc.alpha[j];
+__global__ __launch_bounds__(kBlock) void k_update_r(size_t n, int logB, const CgScalars sc, T* __restrict__ r,
+                                                     const T* __restrict__ Ap, double* __restrict__ partial) {
+  __shared__ double lds[4 * 64];
+  const int B = 1 << logB;
+  const int j = threadIdx.x & (B - 1);
   double acc[1] = {0.0};
-  if (s < g.V) {
-    for (int c = 0; c < g.ncomp; ++c) {
-      const size_t i = ((size_t)j * g.ncomp + c) * V + s;
-      x[i] = axpy(a, p[i], x[i]);
+  if (sc.state[j] == kActive) {
+    const double a = sc.alpha[j];
+    const size_t stride = (size_t)gridDim.x * kBlock;
+    size_t i = (size_t)blockIdx.x * kBlock + threadIdx.x;
+    for (; i + 3 * stride < n; i += 4 * stride) {      // four independent loads in flight
+      T rr[4], ww[4];
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        rr[k] = r[i + k * stride];
+        ww[k] = Ap[i + k * stride];
+      }
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        rr[k] = axpy(-a, ww[k], rr[k]);
+        r[i + k * stride] = rr[k];
+        acc[0] += norm2(rr[k]);
+      }
+    }
+    for (; i < n; i += stride) {
       const T ri = axpy(-a, Ap[i], r[i]);
       r[i] = ri;
       acc[0] += norm2(ri);
     }
   }
-  block_sum<1>(acc, lds);
-  if (threadIdx.x == 0) partial[(size_t)j * gridDim.x + blockIdx.x] = acc[0];
+  seg_sum<1>(acc, B, lds);
+  if ((int)threadIdx.x < B) partial[(size_t)threadIdx.x * gridDim.x + blockIdx.x] = acc[0];
 }
 
-// p = r + beta p  (active right-hand sides only)
+// x += xalpha p (the update of this iteration, also for a rhs that just
+// converged); p = r + beta p for right-hand sides still iterating.
 template <class T>
-__global__ __launch_bounds__(kBlock) void k_direction(Geom g, const CgScalars sc, const T* __restrict__ r,
-                                                      T* __restrict__ p) {
-  const int j = blockIdx.y;
-  if (*sc.active == 0 || sc.state[j] != kActive) return;
-  const uint32_t s = blockIdx.x * kBlock + threadIdx.x;
+__global__ __launch_bounds__(kBlock) void k_direction(size_t n, int logB, const CgScalars sc, T* __restrict__ x,
+                                                      const T* __restrict__ r, T* __restrict__ p) {
+  const int B = 1 << logB;
+  const size_t i = (size_t)blockIdx.x * kBlock + threadIdx.x;
+  const int j = threadIdx.x & (B - 1);
+  if (i >= n) return;
+  const double a = sc.xalpha[j];
+  const bool live = sc.state[j] == kActive;
+  if (a == 0.0 && !live) return;
+  const T pi = p[i];
+  if (a != 0.0) x[i] = axpy(a, pi, x[i]);
+  if (live) p[i] = axpy(sc.beta[j], pi, r[i]);
+}
+
+// ---------------------------------------------------------------------------
+// Right-hand sides, initial state and the true residual.  Lane j of the block
+// is global right-hand side rhs0 + j: spatial probe m = (rhs0 + j) / ncomp,
+// component c = (rhs0 + j) % ncomp.
+// ---------------------------------------------------------------------------
+
+template <class T, int NC>
+__device__ __forceinline__ void rhs_at(const Geom& g, uint32_t s, uint32_t P, int64_t rhs0, int j, int nb,
+                                       uint64_t seed, int mask, T (&b)[NC]) {
+#pragma unroll
+  for (int c = 0; c < NC; ++c) b[c] = zero<T>();
+  if (j >= nb) return;
+  const int64_t rg = rhs0 + j;
+  const int cj = (int)(rg % NC);
+  const uint32_t col = hadamard_column((uint32_t)(rg / NC), g.L);
+  const T v = from_c<T>(probe_value(s, P, col, cj, g, seed, mask));
+#pragma unroll
+  for (int c = 0; c < NC; ++c)
+    if (c == cj) b[c] = v;
+}
+
+// x = 0, r = p = b for every lane (zero for padding lanes j >= nb).
+template <class T, int NC>
+__global__ __launch_bounds__(kBlock) void k_init(Geom g, int logB, int64_t rhs0, int nb, uint64_t seed, int mask,
+                                                 T* __restrict__ x, T* __restrict__ r, T* __restrict__ p) {
+  const int B = 1 << logB;
+  const int j = threadIdx.x & (B - 1);
+  const uint32_t s = blockIdx.x * (kBlock >> logB) + (threadIdx.x >> logB);
   if (s >= g.V) return;
-  const size_t V = g.V;
-  const double b = sc.beta[j];
-  for (int c = 0; c < g.ncomp; ++c) {
-    const size_t i = ((size_t)j * g.ncomp + c) * V + s;
-    p[i] = axpy(b, p[i], r[i]);
-  }
+  T b[NC], z[NC];
+  rhs_at<T, NC>(g, s, hier_perm(s, g), rhs0, j, nb, seed, mask, b);
+#pragma unroll
+  for (int c = 0; c < NC; ++c) z[c] = zero<T>();
+  store_vec<T, NC>(x, g.V, logB, s, j, z);
+  store_vec<T, NC>(r, g.V, logB, s, j, b);
+  store_vec<T, NC>(p, g.V, logB, s, j, b);
 }
 
-// True residual: rt = b - A x in FP64, with b regenerated; r = p = rt.
-// partial[0] = ||rt||^2, partial[1], partial[2] = Re, Im of b^H x.
-template <int R>
-__global__ __launch_bounds__(kBlock) void k_cov_true_residual(Geom g, const double2* __restrict__ U,
-                                                              const double* __restrict__ mass_field, double mass,
-                                                              const double* __restrict__ w, int64_t rhs0, int nb,
-                                                              uint64_t seed, int mask,
-                                                              const double2* __restrict__ x,
-                                                              double2* __restrict__ r, double2* __restrict__ p,
-                                                              double* __restrict__ partial, size_t pstride) {
-  __shared__ double lds[3 * R * 4];
-  const uint32_t s = blockIdx.x * kBlock + threadIdx.x;
-  const size_t V = g.V;
-  const int j0 = blockIdx.y * R;
-  const size_t off = (size_t)j0 * 3 * V;
-  double acc[3 * R];
+// For lanes in state kFrozen: rt = b - A x in FP64 with b regenerated;
+// r = p = rt.  partial[k] (k = 0, 1, 2): ||rt||^2, Re b^H x, Im b^H x.
+template <class Op>
+__global__ __launch_bounds__(kBlock) void k_true_residual(Geom g, TileMap tm, Op op,
+                                                          const double* __restrict__ mass_field, double mass,
+                                                          const double* __restrict__ w, const int* __restrict__ state,
+                                                          int64_t rhs0, int nb, uint64_t seed, int mask,
+                                                          const typename Op::T* __restrict__ x,
+                                                          typename Op::T* __restrict__ r, typename Op::T* __restrict__ p,
+                                                          double* __restrict__ partial, size_t pstride) {
+  using T = typename Op::T;
+  constexpr int NC = Op::NC;
+  __shared__ double lds[3 * 4 * 64];
+  const int B = 1 << tm.logB;
+  const int j = threadIdx.x & (B - 1);
+  const uint32_t s = tile_first_site(blockIdx.x, tm) + (threadIdx.x >> tm.logB);
+  double acc[3] = {0.0, 0.0, 0.0};
+  if (s < g.V && state[j] == kFrozen) {
+    T xs[NC], ax[NC], b[NC], rt[NC];
+    stencil_site(op, g, tm.logB, s, j, mass_field, mass, w, x, xs, ax);
+    rhs_at<T, NC>(g, s, hier_perm(s, g), rhs0, j, nb, seed, mask, b);
 #pragma unroll
-  for (int i = 0; i < 3 * R; ++i) acc[i] = 0.0;
-  if (s < g.V) {
-    double2 hop[R][3];
-    double diag = mass_field ? mass_field[s] : mass;
-    cov_hop<R>(g, s, U, w, x + off, hop, diag);
-    const uint32_t P = hier_perm(s, g);
-#pragma unroll
-    for (int rr = 0; rr < R; ++rr) {
-      const int j = j0 + rr;
-      const int64_t rg = rhs0 + j;
-      const int cj = (int)(rg % 3);
-      const uint32_t col = hadamard_column((uint32_t)(rg / 3), g.L);
-      const double2 bval = j < nb ? probe_value(s, P, col, cj, g, seed, mask) : make_double2(0.0, 0.0);
-#pragma unroll
-      for (int a = 0; a < 3; ++a) {
-        const size_t i = ((size_t)j * 3 + a) * V + s;
-        const double2 xv = x[i];
-        const double2 b = a == cj ? bval : make_double2(0.0, 0.0);
-        double2 rt;
-        rt.x = b.x - fma(diag, xv.x, -hop[rr][a].x);
-        rt.y = b.y - fma(diag, xv.y, -hop[rr][a].y);
-        r[i] = rt;
-        p[i] = rt;
-        acc[3 * rr + 0] += norm2(rt);
-        acc[3 * rr + 1] += redot(b, xv);
-        acc[3 * rr + 2] += imdot(b, xv);
-      }
+    for (int c = 0; c < NC; ++c) {
+      rt[c] = axpy(-1.0, ax[c], b[c]);
+      acc[0] += norm2(rt[c]);
+      acc[1] += redot(b[c], xs[c]);
+      acc[2] += imdot(b[c], xs[c]);
     }
+    store_vec<T, NC>(r, g.V, tm.logB, s, j, rt);
+    store_vec<T, NC>(p, g.V, tm.logB, s, j, rt);
   }
-  block_sum<3 * R>(acc, lds);
-  if (threadIdx.x == 0) {
+  seg_sum<3>(acc, B, lds);
+  if ((int)threadIdx.x < B) {
 #pragma unroll
-    for (int rr = 0; rr < R; ++rr)
-#pragma unroll
-      for (int k = 0; k < 3; ++k)
-        partial[k * pstride + (size_t)(j0 + rr) * gridDim.x + blockIdx.x] = acc[3 * rr + k];
-  }
-}
-
-template <class T, int R>
-__global__ __launch_bounds__(kBlock) void k_scalar_true_residual(Geom g, const double* __restrict__ mass_field,
-                                                                 double mass, const double* __restrict__ w,
-                                                                 int64_t rhs0, int nb, uint64_t seed, int mask,
-                                                                 const T* __restrict__ x, T* __restrict__ r,
-                                                                 T* __restrict__ p, double* __restrict__ partial,
-                                                                 size_t pstride) {
-  __shared__ double lds[3 * R * 4];
-  const uint32_t s = blockIdx.x * kBlock + threadIdx.x;
-  const size_t V = g.V;
-  const int j0 = blockIdx.y * R;
-  const size_t off = (size_t)j0 * V;
-  double acc[3 * R];
-#pragma unroll
-  for (int i = 0; i < 3 * R; ++i) acc[i] = 0.0;
-  if (s < g.V) {
-    T hop[R];
-    double diag = mass_field ? mass_field[s] : mass;
-    scalar_hop<T, R>(g, s, w, x + off, hop, diag);
-    const uint32_t P = hier_perm(s, g);
-#pragma unroll
-    for (int rr = 0; rr < R; ++rr) {
-      const int j = j0 + rr;
-      const int64_t rg = rhs0 + j;
-      const uint32_t col = hadamard_column((uint32_t)rg, g.L);
-      const T b = j < nb ? from_c<T>(probe_value(s, P, col, 0, g, seed, mask)) : zero<T>();
-      const size_t i = (size_t)j * V + s;
-      const T xv = x[i];
-      const T ax = axpy(diag, xv, axpy(-1.0, hop[rr], zero<T>()));
-      const T rt = axpy(-1.0, ax, b);
-      r[i] = rt;
-      p[i] = rt;
-      acc[3 * rr + 0] += norm2(rt);
-      acc[3 * rr + 1] += redot(b, xv);
-      acc[3 * rr + 2] += imdot(b, xv);
-    }
-  }
-  block_sum<3 * R>(acc, lds);
-  if (threadIdx.x == 0) {
-#pragma unroll
-    for (int rr = 0; rr < R; ++rr)
-#pragma unroll
-      for (int k = 0; k < 3; ++k)
-        partial[k * pstride + (size_t)(j0 + rr) * gridDim.x + blockIdx.x] = acc[3 * rr + k];
+    for (int k = 0; k < 3; ++k) partial[k * pstride + (size_t)threadIdx.x * gridDim.x + blockIdx.x] = acc[k];
   }
 }
 
@@ -382,6 +535,7 @@ __global__ void k_scalars_init(CgScalars sc, int nb, int B, double bnorm2, int s
   sc.bnorm2[j] = valid ? bnorm2 : 0.0;
   sc.rho[j] = valid ? bnorm2 : 0.0;
   sc.alpha[j] = 0.0;
+  sc.xalpha[j] = 0.0;
   sc.beta[j] = 0.0;
   sc.iters[j] = 0;
   sc.restarts[j] = 0;
@@ -393,30 +547,30 @@ __global__ void k_scalars_init(CgScalars sc, int nb, int B, double bnorm2, int s
 // alpha = rho / p^H A p; breakdown when p^H A p is not positive and finite.
 __global__ __launch_bounds__(kBlock) void k_reduce_alpha(CgScalars sc, const double* __restrict__ partial, int gx) {
   const int j = blockIdx.x;
-  if (*sc.active == 0) return;
+  if (*sc.active == 0 || sc.state[j] != kActive) return;     // uniform per workgroup
   const double pAp = sum_partials(partial + (size_t)j * gx, gx);
   if (threadIdx.x != 0) return;
-  if (sc.state[j] != kActive) {
-    sc.alpha[j] = 0.0;
-    return;
-  }
   if (!(pAp > 0.0) || !isfinite(pAp)) {
     sc.state[j] = kBreakdown;
-    sc.alpha[j] = 0.0;
     atomicSub(sc.active, 1);
     return;
   }
   sc.alpha[j] = sc.rho[j] / pAp;
 }
 
-// rho' = ||r||^2; beta = rho'/rho; freeze on the recursive residual, or stop at max_iter.
+// rho' = ||r||^2; beta = rho'/rho; freeze on the recursive residual, or stop
+// at max_iter.  xalpha = the x update the direction pass applies this
+// iteration (alpha for a rhs that iterated, 0 otherwise).
 __global__ __launch_bounds__(kBlock) void k_reduce_beta(CgScalars sc, const double* __restrict__ partial, int gx,
                                                         double tol2, int max_iter) {
   const int j = blockIdx.x;
-  if (*sc.active == 0) return;
-  if (sc.state[j] != kActive) return;        // uniform per workgroup
+  if (sc.state[j] != kActive) {                // uniform per workgroup
+    if (threadIdx.x == 0) sc.xalpha[j] = 0.0;
+    return;
+  }
   const double rho_new = sum_partials(partial + (size_t)j * gx, gx);
   if (threadIdx.x != 0) return;
+  sc.xalpha[j] = sc.alpha[j];
   const int it = sc.iters[j] + 1;
   sc.iters[j] = it;
   sc.beta[j] = rho_new / sc.rho[j];
@@ -433,10 +587,12 @@ __global__ __launch_bounds__(kBlock) void k_reduce_beta(CgScalars sc, const doub
   }
 }
 
-// Accept a frozen solve when its true residual passes, else restart CG from x.
+// Accept a frozen solve when its true residual passes, else restart CG from x
+// (r and p already hold the true residual).
 __global__ __launch_bounds__(kBlock) void k_reduce_true(CgScalars sc, const double* __restrict__ partial, int gx,
                                                         size_t pstride, double tol2, int max_iter, int max_restarts) {
   const int j = blockIdx.x;
+  if (threadIdx.x == 0) sc.xalpha[j] = 0.0;
   if (sc.state[j] != kFrozen) return;
   const double rt2 = sum_partials(partial + (size_t)j * gx, gx);
   const double qre = sum_partials(partial + pstride + (size_t)j * gx, gx);
@@ -486,143 +642,120 @@ __global__ __launch_bounds__(kBlock) void k_repack_links(Geom g, const double2* 
   for (int e = 0; e < 9; ++e) dst[((size_t)mu * 9 + e) * V + s] = src[((size_t)mu * V + s) * 9 + e];
 }
 
-// [n][V][nc] <-> [n][nc][V]
+// one vector: [V][nc] <-> [nc][V]
 template <class T>
 __global__ __launch_bounds__(kBlock) void k_site_major_to_comp_major(Geom g, const T* __restrict__ src,
                                                                      T* __restrict__ dst) {
   const uint32_t s = blockIdx.x * kBlock + threadIdx.x;
   if (s >= g.V) return;
-  const size_t V = g.V, j = blockIdx.y, nc = g.ncomp;
-  for (size_t c = 0; c < nc; ++c) dst[(j * nc + c) * V + s] = src[(j * V + s) * nc + c];
+  const size_t V = g.V, nc = g.ncomp;
+  for (size_t c = 0; c < nc; ++c) dst[c * V + s] = src[s * nc + c];
 }
 template <class T>
 __global__ __launch_bounds__(kBlock) void k_comp_major_to_site_major(Geom g, const T* __restrict__ src,
                                                                      T* __restrict__ dst) {
   const uint32_t s = blockIdx.x * kBlock + threadIdx.x;
   if (s >= g.V) return;
-  const size_t V = g.V, j = blockIdx.y, nc = g.ncomp;
-  for (size_t c = 0; c < nc; ++c) dst[(j * V + s) * nc + c] = src[(j * nc + c) * V + s];
+  const size_t V = g.V, nc = g.ncomp;
+  for (size_t c = 0; c < nc; ++c) dst[s * nc + c] = src[c * V + s];
 }
 
 // ---------------------------------------------------------------------------
 // Host-side launchers.
 // ---------------------------------------------------------------------------
 
-static inline dim3 site_grid(const Geom& g, unsigned y) { return dim3((g.V + kBlock - 1) / kBlock, y); }
+static inline unsigned cdiv(size_t a, size_t b) { return (unsigned)((a + b - 1) / b); }
 
-hipError_t launch_matvec(const OpDev& op, const Geom& g, Elem elem, int R, int B, const void* in, void* out,
-                         double* partial, const int* active, int* ran, hipStream_t st) {
-  const dim3 grid = site_grid(g, B / R);
-  if (op.kind == 1) {
-    const double2* U = (const double2*)op.links;
-    const double2* x = (const double2*)in;
-    double2* y = (double2*)out;
-    switch (R) {
-      case 1: k_cov_matvec<1><<<grid, kBlock, 0, st>>>(g, U, op.mass_field, op.mass, op.coupling, x, y, partial, active, ran); break;
-      case 2: k_cov_matvec<2><<<grid, kBlock, 0, st>>>(g, U, op.mass_field, op.mass, op.coupling, x, y, partial, active, ran); break;
-      case 4: k_cov_matvec<4><<<grid, kBlock, 0, st>>>(g, U, op.mass_field, op.mass, op.coupling, x, y, partial, active, ran); break;
-      case 8: k_cov_matvec<8><<<grid, kBlock, 0, st>>>(g, U, op.mass_field, op.mass, op.coupling, x, y, partial, active, ran); break;
-      default: return hipErrorInvalidValue;
-    }
-  } else if (elem == Elem::kReal) {
-    const double* x = (const double*)in;
-    double* y = (double*)out;
-    switch (R) {
-      case 1: k_scalar_matvec<double, 1><<<grid, kBlock, 0, st>>>(g, op.mass_field, op.mass, op.coupling, x, y, partial, active, ran); break;
-      case 2: k_scalar_matvec<double, 2><<<grid, kBlock, 0, st>>>(g, op.mass_field, op.mass, op.coupling, x, y, partial, active, ran); break;
-      case 4: k_scalar_matvec<double, 4><<<grid, kBlock, 0, st>>>(g, op.mass_field, op.mass, op.coupling, x, y, partial, active, ran); break;
-      case 8: k_scalar_matvec<double, 8><<<grid, kBlock, 0, st>>>(g, op.mass_field, op.mass, op.coupling, x, y, partial, active, ran); break;
-      default: return hipErrorInvalidValue;
-    }
-  } else {
-    const double2* x = (const double2*)in;
-    double2* y = (double2*)out;
-    switch (R) {
-      case 1: k_scalar_matvec<double2, 1><<<grid, kBlock, 0, st>>>(g, op.mass_field, op.mass, op.coupling, x, y, partial, active, ran); break;
-      case 2: k_scalar_matvec<double2, 2><<<grid, kBlock, 0, st>>>(g, op.mass_field, op.mass, op.coupling, x, y, partial, active, ran); break;
-      case 4: k_scalar_matvec<double2, 4><<<grid, kBlock, 0, st>>>(g, op.mass_field, op.mass, op.coupling, x, y, partial, active, ran); break;
-      case 8: k_scalar_matvec<double2, 8><<<grid, kBlock, 0, st>>>(g, op.mass_field, op.mass, op.coupling, x, y, partial, active, ran); break;
-      default: return hipErrorInvalidValue;
-    }
-  }
+size_t march_lds_bytes(const Geom& g, const MarchMap& mm) {
+  return (size_t)(2 * g.ndim - 1) * 9 * mm.TS * sizeof(double2);
+}
+
+// Calls f(op_policy) for the operator / element combination.
+template <class F>
+static hipError_t dispatch(const OpDev& od, Elem elem, F&& f) {
+  if (od.kind == 1) f(CovOp{(const double2*)od.links});
+  else if (elem == Elem::kReal) f(ScalarOp<double>{});
+  else f(ScalarOp<double2>{});
   return hipGetLastError();
 }
 
-hipError_t launch_true_residual(const OpDev& op, const Geom& g, Elem elem, int R, int B, int64_t rhs0, int nb,
-                                uint64_t seed, int mask, const void* x, void* r, void* p, double* partial,
-                                size_t pstride, hipStream_t st) {
-  const dim3 grid = site_grid(g, B / R);
-  if (op.kind == 1) {
-    const double2* U = (const double2*)op.links;
-    auto X = (const double2*)x;
-    auto Rr = (double2*)r;
-    auto Pp = (double2*)p;
-#define TIP_TR(RR) k_cov_true_residual<RR><<<grid, kBlock, 0, st>>>(g, U, op.mass_field, op.mass, op.coupling, rhs0, nb, seed, mask, X, Rr, Pp, partial, pstride)
-    switch (R) {
-      case 1: TIP_TR(1); break;
-      case 2: TIP_TR(2); break;
-      case 4: TIP_TR(4); break;
-      case 8: TIP_TR(8); break;
-      default: return hipErrorInvalidValue;
+hipError_t launch_stencil(const OpDev& od, const Geom& g, const TileMap& tm, const MarchMap* mm, Elem elem,
+                          const int* state, const int* active, const void* in, void* out, double* partial, int* ran,
+                          hipStream_t st) {
+  return dispatch(od, elem, [&](auto op) {
+    using Op = decltype(op);
+    using T = typename Op::T;
+    if constexpr (Op::NC == 3) {
+      if (mm && mm->lds_links) {
+        const size_t lds = march_lds_bytes(g, *mm);
+        auto go = [&](auto kern) {
+          kern<<<mm->grid, kBlock, lds, st>>>(g, *mm, op, od.mass_field, od.mass, od.coupling, state, active,
+                                              (const T*)in, (T*)out, partial, ran);
+        };
+        const bool hw = od.coupling != nullptr;
+        switch (mm->logB * 2 + (hw ? 1 : 0)) {
+          case 4: go(k_stencil_march<Op, true, 2, 0>); break;
+          case 5: go(k_stencil_march<Op, true, 2, 1>); break;
+          case 6: go(k_stencil_march<Op, true, 3, 0>); break;
+          case 7: go(k_stencil_march<Op, true, 3, 1>); break;
+          case 8: go(k_stencil_march<Op, true, 4, 0>); break;
+          case 9: go(k_stencil_march<Op, true, 4, 1>); break;
+          default: go(k_stencil_march<Op, true>); break;
+        }
+        return;
+      }
     }
-#undef TIP_TR
-  } else if (elem == Elem::kReal) {
-    auto X = (const double*)x;
-    auto Rr = (double*)r;
-    auto Pp = (double*)p;
-#define TIP_TR(RR) k_scalar_true_residual<double, RR><<<grid, kBlock, 0, st>>>(g, op.mass_field, op.mass, op.coupling, rhs0, nb, seed, mask, X, Rr, Pp, partial, pstride)
-    switch (R) {
-      case 1: TIP_TR(1); break;
-      case 2: TIP_TR(2); break;
-      case 4: TIP_TR(4); break;
-      case 8: TIP_TR(8); break;
-      default: return hipErrorInvalidValue;
-    }
-#undef TIP_TR
-  } else {
-    auto X = (const double2*)x;
-    auto Rr = (double2*)r;
-    auto Pp = (double2*)p;
-#define TIP_TR(RR) k_scalar_true_residual<double2, RR><<<grid, kBlock, 0, st>>>(g, op.mass_field, op.mass, op.coupling, rhs0, nb, seed, mask, X, Rr, Pp, partial, pstride)
-    switch (R) {
-      case 1: TIP_TR(1); break;
-      case 2: TIP_TR(2); break;
-      case 4: TIP_TR(4); break;
-      case 8: TIP_TR(8); break;
-      default: return hipErrorInvalidValue;
-    }
-#undef TIP_TR
-  }
-  return hipGetLastError();
+    if (mm)
+      k_stencil_march<Op, false><<<mm->grid, kBlock, 0, st>>>(g, *mm, op, od.mass_field, od.mass, od.coupling, state,
+                                                              active, (const T*)in, (T*)out, partial, ran);
+    else
+      k_stencil<Op><<<tm.grid, kBlock, 0, st>>>(g, tm, op, od.mass_field, od.mass, od.coupling, state, active,
+                                                (const T*)in, (T*)out, partial, ran);
+  });
 }
 
-hipError_t launch_init(const Geom& g, Elem elem, int B, int64_t rhs0, int nb, uint64_t seed, int mask, void* x,
+hipError_t launch_true_residual(const OpDev& od, const Geom& g, const TileMap& tm, Elem elem, const int* state,
+                                int64_t rhs0, int nb, uint64_t seed, int mask, const void* x, void* r, void* p,
+                                double* partial, size_t pstride, hipStream_t st) {
+  return dispatch(od, elem, [&](auto op) {
+    using Op = decltype(op);
+    using T = typename Op::T;
+    k_true_residual<Op><<<tm.grid, kBlock, 0, st>>>(g, tm, op, od.mass_field, od.mass, od.coupling, state, rhs0, nb,
+                                                    seed, mask, (const T*)x, (T*)r, (T*)p, partial, pstride);
+  });
+}
+
+hipError_t launch_init(const Geom& g, Elem elem, int logB, int64_t rhs0, int nb, uint64_t seed, int mask, void* x,
                        void* r, void* p, hipStream_t st) {
-  const dim3 grid = site_grid(g, B);
-  if (elem == Elem::kReal)
-    k_init<double><<<grid, kBlock, 0, st>>>(g, rhs0, nb, seed, mask, (double*)x, (double*)r, (double*)p);
+  const unsigned grid = cdiv(g.V, (size_t)(kBlock >> logB));
+  if (g.ncomp == 3)
+    k_init<double2, 3><<<grid, kBlock, 0, st>>>(g, logB, rhs0, nb, seed, mask, (double2*)x, (double2*)r, (double2*)p);
+  else if (elem == Elem::kReal)
+    k_init<double, 1><<<grid, kBlock, 0, st>>>(g, logB, rhs0, nb, seed, mask, (double*)x, (double*)r, (double*)p);
   else
-    k_init<double2><<<grid, kBlock, 0, st>>>(g, rhs0, nb, seed, mask, (double2*)x, (double2*)r, (double2*)p);
+    k_init<double2, 1><<<grid, kBlock, 0, st>>>(g, logB, rhs0, nb, seed, mask, (double2*)x, (double2*)r, (double2*)p);
   return hipGetLastError();
 }
 
-hipError_t launch_update(const Geom& g, Elem elem, int B, const CgScalars& sc, void* x, void* r, const void* p,
-                         const void* Ap, double* partial, hipStream_t st) {
-  const dim3 grid = site_grid(g, B);
+unsigned update_grid(size_t n) { return std::min<unsigned>(cdiv(n, kBlock), 8192u); }
+
+hipError_t launch_update_r(size_t n, int logB, Elem elem, const CgScalars& sc, void* r, const void* Ap,
+                           double* partial, hipStream_t st) {
+  const unsigned grid = update_grid(n);
   if (elem == Elem::kReal)
-    k_update<double><<<grid, kBlock, 0, st>>>(g, sc, (double*)x, (double*)r, (const double*)p, (const double*)Ap, partial);
+    k_update_r<double><<<grid, kBlock, 0, st>>>(n, logB, sc, (double*)r, (const double*)Ap, partial);
   else
-    k_update<double2><<<grid, kBlock, 0, st>>>(g, sc, (double2*)x, (double2*)r, (const double2*)p, (const double2*)Ap, partial);
+    k_update_r<double2><<<grid, kBlock, 0, st>>>(n, logB, sc, (double2*)r, (const double2*)Ap, partial);
   return hipGetLastError();
 }
 
-hipError_t launch_direction(const Geom& g, Elem elem, int B, const CgScalars& sc, const void* r, void* p,
+hipError_t launch_direction(size_t n, int logB, Elem elem, const CgScalars& sc, void* x, const void* r, void* p,
                             hipStream_t st) {
-  const dim3 grid = site_grid(g, B);
+  const unsigned grid = cdiv(n, kBlock);
   if (elem == Elem::kReal)
-    k_direction<double><<<grid, kBlock, 0, st>>>(g, sc, (const double*)r, (double*)p);
+    k_direction<double><<<grid, kBlock, 0, st>>>(n, logB, sc, (double*)x, (const double*)r, (double*)p);
   else
-    k_direction<double2><<<grid, kBlock, 0, st>>>(g, sc, (const double2*)r, (double2*)p);
+    k_direction<double2><<<grid, kBlock, 0, st>>>(n, logB, sc, (double2*)x, (const double2*)r, (double2*)p);
   return hipGetLastError();
 }
 
@@ -649,24 +782,23 @@ hipError_t launch_reduce_true(const CgScalars& sc, int B, const double* partial,
 }
 
 hipError_t launch_hier_perm(const Geom& g, uint32_t* out, hipStream_t st) {
-  k_hier_perm<<<site_grid(g, 1), kBlock, 0, st>>>(g, out);
+  k_hier_perm<<<cdiv(g.V, kBlock), kBlock, 0, st>>>(g, out);
   return hipGetLastError();
 }
 
 hipError_t launch_probe_vectors(const Geom& g, uint64_t seed, int mask, int64_t m0, int count, int comp, double2* out,
                                 hipStream_t st) {
-  k_probe_vectors<<<site_grid(g, count), kBlock, 0, st>>>(g, seed, mask, m0, comp, out);
+  k_probe_vectors<<<dim3(cdiv(g.V, kBlock), count), kBlock, 0, st>>>(g, seed, mask, m0, comp, out);
   return hipGetLastError();
 }
 
 hipError_t launch_repack_links(const Geom& g, const double2* src, double2* dst, hipStream_t st) {
-  k_repack_links<<<site_grid(g, g.ndim), kBlock, 0, st>>>(g, src, dst);
+  k_repack_links<<<dim3(cdiv(g.V, kBlock), g.ndim), kBlock, 0, st>>>(g, src, dst);
   return hipGetLastError();
 }
 
-hipError_t launch_layout(const Geom& g, Elem elem, int n, const void* src, void* dst, bool to_comp_major,
-                         hipStream_t st) {
-  const dim3 grid = site_grid(g, n);
+hipError_t launch_layout(const Geom& g, Elem elem, const void* src, void* dst, bool to_comp_major, hipStream_t st) {
+  const unsigned grid = cdiv(g.V, kBlock);
   if (elem == Elem::kReal) {
     if (to_comp_major) k_site_major_to_comp_major<double><<<grid, kBlock, 0, st>>>(g, (const double*)src, (double*)dst);
     else k_comp_major_to_site_major<double><<<grid, kBlock, 0, st>>>(g, (const double*)src, (double*)dst);

@@ -27,6 +27,7 @@ struct OpDev {
 struct CgScalars {
   double* rho;
   double* alpha;
+  double* xalpha;              // x update the direction pass applies this iteration
   double* beta;
   double* bnorm2;
   double* relres2;
@@ -37,16 +38,42 @@ struct CgScalars {
   int* active;                 // number of right-hand sides still iterating
 };
 
-hipError_t launch_matvec(const OpDev& op, const Geom& g, Elem elem, int R, int B, const void* in, void* out,
-                         double* partial, const int* active, int* ran, hipStream_t st);
-hipError_t launch_true_residual(const OpDev& op, const Geom& g, Elem elem, int R, int B, int64_t rhs0, int nb,
-                                uint64_t seed, int mask, const void* x, void* r, void* p, double* partial,
-                                size_t pstride, hipStream_t st);
-hipError_t launch_init(const Geom& g, Elem elem, int B, int64_t rhs0, int nb, uint64_t seed, int mask, void* x,
+// Generic site kernels: workgroup b owns TS = 256/B sites (tile_first_site).
+struct TileMap {
+  int32_t logB;
+  int32_t TS;
+  int32_t pc, P;               // XCD-aware order, pc = 0 for plain order
+  uint32_t grid;
+};
+
+// Marching stencil: workgroup -> (spatial tile of TS sites, chunk of Tc t values).
+struct MarchMap {
+  int32_t logB;
+  int32_t TS;
+  uint32_t V3;                 // sites per plane of the marching dimension
+  int32_t Q;                   // spatial tiles, V3 / TS
+  int32_t nt, Tc;
+  int32_t xcd_order;
+  int32_t lds_links;           // stage links in LDS (covariant, TS <= 64)
+  uint32_t grid;               // Q * nt / Tc
+};
+
+// Dynamic LDS of the marching stencil when it stages links.
+size_t march_lds_bytes(const Geom& g, const MarchMap& mm);
+
+hipError_t launch_stencil(const OpDev& op, const Geom& g, const TileMap& tm, const MarchMap* mm, Elem elem,
+                          const int* state, const int* active, const void* in, void* out, double* partial, int* ran,
+                          hipStream_t st);
+hipError_t launch_true_residual(const OpDev& op, const Geom& g, const TileMap& tm, Elem elem, const int* state,
+                                int64_t rhs0, int nb, uint64_t seed, int mask, const void* x, void* r, void* p,
+                                double* partial, size_t pstride, hipStream_t st);
+hipError_t launch_init(const Geom& g, Elem elem, int logB, int64_t rhs0, int nb, uint64_t seed, int mask, void* x,
                        void* r, void* p, hipStream_t st);
-hipError_t launch_update(const Geom& g, Elem elem, int B, const CgScalars& sc, void* x, void* r, const void* p,
-                         const void* Ap, double* partial, hipStream_t st);
-hipError_t launch_direction(const Geom& g, Elem elem, int B, const CgScalars& sc, const void* r, void* p,
+// Workgroups of the update pass (= partials per right-hand side).
+unsigned update_grid(size_t n);
+hipError_t launch_update_r(size_t n, int logB, Elem elem, const CgScalars& sc, void* r, const void* Ap,
+                           double* partial, hipStream_t st);
+hipError_t launch_direction(size_t n, int logB, Elem elem, const CgScalars& sc, void* x, const void* r, void* p,
                             hipStream_t st);
 hipError_t launch_scalars_init(const CgScalars& sc, int nb, int B, double bnorm2, int start_frozen, hipStream_t st);
 hipError_t launch_reduce_alpha(const CgScalars& sc, int B, const double* partial, int gx, hipStream_t st);
@@ -58,7 +85,6 @@ hipError_t launch_hier_perm(const Geom& g, uint32_t* out, hipStream_t st);
 hipError_t launch_probe_vectors(const Geom& g, uint64_t seed, int mask, int64_t m0, int count, int comp, double2* out,
                                 hipStream_t st);
 hipError_t launch_repack_links(const Geom& g, const double2* src, double2* dst, hipStream_t st);
-hipError_t launch_layout(const Geom& g, Elem elem, int n, const void* src, void* dst, bool to_comp_major,
-                         hipStream_t st);
+hipError_t launch_layout(const Geom& g, Elem elem, const void* src, void* dst, bool to_comp_major, hipStream_t st);
 
 }  // namespace tip
