@@ -6,6 +6,9 @@ site, Haar-random U(3) links, mass field m(x) = 0.1 + 0.02 clip(xi, +-3),
 Z4 mask; 256 spatial probes x 3 diluted components = 768 CG solves to a true
 relative residual of 1e-10 (FP64).  One step is one trace_inv_probe call over
 all 768 right-hand sides, with the operator already resident on the GPU.
+The headline value is the FP64 solver; the mixed-precision solver (FP32 CG,
+FP64 reliable updates, same FP64 true-residual acceptance) is timed beside
+it and reported under "mixed_precision".
 
 Prints one JSON line: solves/s, the stencil kernel's achieved HBM bandwidth
 against the MI355X peak (hipEvent timing of every stencil launch inside the
@@ -107,6 +110,9 @@ def main():
     ap.add_argument("--cpu-iters", type=int, default=40)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true")
+    ap.add_argument("--precision", choices=["both", "fp64", "mixed"], default="both",
+                    help="FP64 is the headline value; 'both' adds the mixed-precision solver beside it")
+    ap.add_argument("--reliable-delta", type=float, default=0.0)
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -139,41 +145,69 @@ def main():
     repack_s = time.perf_counter() - t
     log(f"operator handle (link repack) {repack_s * 1e3:.1f} ms")
 
-    tip.tip_set_profiling(True)
     n_rhs = args.n_vectors * 3
-    for w in range(args.warmup):
-        est, q, st = handle.trace_inv_probe(args.n_vectors, args.tol, args.seed, rhs_block=args.rhs_block)
-        log(f"warmup {w}: {st['seconds']:.3f} s, {st['total_iters'] / st['solves']:.2f} it/solve, "
-            f"T_s={est[-1].real:.10f}")
+    kernel_names = {tip.PREC_FP64: "k_stencil_march<CovOp<double2>>", tip.PREC_MIXED: "k_stencil_march<CovOp<float2>>"}
 
-    tot = {"launches": 0, "seconds": 0.0, "bytes": 0.0, "iters": 0, "solves": 0, "relres": 0.0}
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for k in range(args.steps):
-        est, q, st = handle.trace_inv_probe(args.n_vectors, args.tol, args.seed, rhs_block=args.rhs_block)
-        tot["launches"] += st["stencil_launches"]
-        tot["seconds"] += st["stencil_seconds"]
-        tot["bytes"] += st["stencil_bytes"]
-        tot["iters"] += st["total_iters"]
-        tot["solves"] += st["solves"]
-        tot["relres"] = max(tot["relres"], st["max_true_relres"])
-        log(f"step {k}: {st['seconds']:.3f} s, {st['solves']} solves, max rel.res {st['max_true_relres']:.2e}")
-    torch.cuda.synchronize()
-    elapsed = time.perf_counter() - t0
-    tip.tip_set_profiling(False)
-    handle.close()
-
-    value = n_rhs * args.steps / elapsed
-    iters_per_solve = tot["iters"] / max(tot["solves"], 1)
-    avg_launch_s = tot["seconds"] / max(tot["launches"], 1)
-    bytes_per_launch = tot["bytes"] / max(tot["launches"], 1)
-    achieved = bytes_per_launch / avg_launch_s / 1e9 if avg_launch_s > 0 else 0.0
-    kernel_name = "k_cov_matvec"
-    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": measured_traffic(kernel_name),
-                "kernel": kernel_name, "alg_bytes_per_launch": bytes_per_launch,
+    def timed(precision):
+        """W warmup calls, then K timed calls of the whole path at one precision."""
+        tip.tip_set_profiling(True)
+        kw = dict(rhs_block=args.rhs_block, precision=precision, reliable_delta=args.reliable_delta)
+        for w in range(args.warmup):
+            est, q, st = handle.trace_inv_probe(args.n_vectors, args.tol, args.seed, **kw)
+            log(f"[{precision}] warmup {w}: {st['seconds']:.3f} s, {st['total_iters'] / st['solves']:.2f} it/solve")
+        tot = {"launches": 0, "seconds": 0.0, "bytes": 0.0, "iters": 0, "solves": 0, "relres": 0.0, "ru": 0,
+               "bound": 0.0}
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for k in range(args.steps):
+            est, q, st = handle.trace_inv_probe(args.n_vectors, args.tol, args.seed, **kw)
+            tot["launches"] += st["stencil_launches"]
+            tot["seconds"] += st["stencil_seconds"]
+            tot["bytes"] += st["stencil_bytes"]
+            tot["iters"] += st["total_iters"]
+            tot["solves"] += st["solves"]
+            tot["ru"] += st["reliable_updates"]
+            tot["relres"] = max(tot["relres"], st["max_true_relres"])
+            tot["bound"] = max(tot["bound"], st["max_quad_err_bound"])
+            log(f"[{precision}] step {k}: {st['seconds']:.3f} s, {st['solves']} solves, "
+                f"max rel.res {st['max_true_relres']:.2e}")
+        torch.cuda.synchronize()
+        elapsed = time.perf_counter() - t0
+        tip.tip_set_profiling(False)
+        avg_launch_s = tot["seconds"] / max(tot["launches"], 1)
+        bytes_per_launch = tot["bytes"] / max(tot["launches"], 1)
+        achieved = bytes_per_launch / avg_launch_s / 1e9 if avg_launch_s > 0 else 0.0
+        name = kernel_names[precision]
+        roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": measured_traffic(name),
+                "kernel": name, "alg_bytes_per_launch": bytes_per_launch,
                 "avg_launch_us": round(avg_launch_s * 1e6, 2), "launches": tot["launches"]}
+        return {"value": n_rhs * args.steps / elapsed, "elapsed": elapsed, "roofline": roof, "est": est,
+                "iters_per_solve": tot["iters"] / max(tot["solves"], 1), "max_true_relres": tot["relres"],
+                "reliable_updates_per_step": tot["ru"] / args.steps, "max_quad_err_bound": tot["bound"]}
+
+    precisions = {"fp64": [tip.PREC_FP64], "mixed": [tip.PREC_MIXED],
+                  "both": [tip.PREC_FP64, tip.PREC_MIXED]}[args.precision]
+    res = {pr: timed(pr) for pr in precisions}
+    handle.close()
+    main_pr = precisions[0]
+    main = res[main_pr]
+    value = main["value"]
+    elapsed = main["elapsed"]
+    iters_per_solve = main["iters_per_solve"]
+    roofline = main["roofline"]
+    est = main["est"]
     log(f"T_k estimates: {[round(float(v.real), 6) for v in est]}")
+    mixed = None
+    if tip.PREC_MIXED in res and main_pr != tip.PREC_MIXED:
+        m = res[tip.PREC_MIXED]
+        mixed = {"value": round(m["value"], 2), "unit": "solves/s", "ms_per_step": round(m["elapsed"] / args.steps * 1e3, 2),
+                 "speedup_vs_fp64": round(m["value"] / value, 3), "dtype": "f32 CG + f64 reliable updates",
+                 "iters_per_solve": round(m["iters_per_solve"], 2),
+                 "reliable_updates_per_solve": round(m["reliable_updates_per_step"] / n_rhs, 2),
+                 "max_true_relres": m["max_true_relres"], "max_quad_err_bound": m["max_quad_err_bound"],
+                 "max_rel_diff_estimates_vs_fp64": float(np.max(np.abs(m["est"] - est) / np.abs(est))),
+                 "roofline": m["roofline"]}
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -181,13 +215,14 @@ def main():
 
     out = {"metric": METRIC, "value": round(value, 2), "unit": "solves/s", "n_gpus": 1, "steps": args.steps,
            "warmup": args.warmup, "ms_per_step": round(elapsed / args.steps * 1e3, 2), "higher_is_better": True,
-           "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+           "scaling": "weak", "vs_baseline": None,
+           "dtype": "f64" if main_pr == tip.PREC_FP64 else "f32 CG + f64 reliable updates", "data": "synthetic",
            "config": {"workload": "4D 32^4 covariant Laplacian x3 (Haar U(3) links, m(x)=0.1+0.02clip(xi)), "
                                   f"{args.n_vectors} hierarchical probes x 3 = {n_rhs} CG solves, tol {args.tol:g}",
                       "lattice": DIMS, "n_vectors": args.n_vectors, "rhs_per_step": n_rhs, "tol": args.tol,
                       "mask": "Z4", "iters_per_solve": round(iters_per_solve, 2),
-                      "max_true_relres": tot["relres"], "repack_ms": round(repack_s * 1e3, 2)},
-           "roofline": roofline, "cpu_baseline": cpu}
+                      "max_true_relres": main["max_true_relres"], "repack_ms": round(repack_s * 1e3, 2)},
+           "roofline": roofline, "cpu_baseline": cpu, "mixed_precision": mixed}
     print(json.dumps(out), flush=True)
 
 

@@ -66,7 +66,16 @@ typedef enum {
 
 enum { TIP_KIND_SCALAR = 0, TIP_KIND_COVARIANT = 1 };
 enum { TIP_MASK_DEFAULT = -1, TIP_MASK_NONE = 0, TIP_MASK_Z2 = 1, TIP_MASK_Z4 = 2 };
-enum { TIP_PREC_FP64 = 0 };
+/* Precision of the CG solves.  FP64: vectors, links and arithmetic in FP64.
+ * MIXED: CG vectors and links stored and combined in FP32, with FP64 kept for
+ * the solution x, the CG scalars, reliable updates (the residual recomputed
+ * from x with the FP64 operator whenever the FP32 residual has fallen by
+ * reliable_delta; Sleijpen & van der Vorst 1996) and the final true-residual
+ * test, so a solve is accepted on the same FP64 criterion as in FP64 mode.
+ * MIXED reports the variational quadrature 2 Re(b^H x) - x^H A x = b^H x + x^H r,
+ * whose error r^H A^-1 r <= ||r||^2 / lambda_min is second order in the
+ * residual. */
+enum { TIP_PREC_FP64 = 0, TIP_PREC_MIXED = 1 };
 
 /* Operator description.  Arrays are DEVICE pointers, read only. */
 typedef struct {
@@ -90,13 +99,15 @@ typedef struct {
   uint64_t seed;        /* seed of z0                                              */
   int32_t mask;         /* TIP_MASK_*; DEFAULT = Z2 for scalar, Z4 for covariant   */
   int32_t rhs_block;    /* right-hand sides solved together; 0 = library choice   */
-  int32_t precision;    /* TIP_PREC_FP64                                           */
+  int32_t precision;    /* TIP_PREC_FP64 or TIP_PREC_MIXED                         */
   void* stream;         /* hipStream_t or NULL                                     */
   double* quadratures;  /* HOST [n_vectors][2] q_m = sum_c b_{m,c}^H x_{m,c}, or NULL.
                            Entries [m_begin, n_vectors) are written.  When m_begin > 0
                            entries [0, m_begin) must hold the q_m of an earlier call
                            (same operator, seed, mask) and are read: this resumes a
                            run, reusing earlier levels' quadratures.                */
+  double reliable_delta; /* MIXED: reliable update when the FP32 residual norm has
+                            fallen by this factor since the last one; 0 = 0.01     */
 } tip_params;
 
 typedef struct {
@@ -109,6 +120,10 @@ typedef struct {
   int64_t stencil_launches;    /* stencil-kernel launches (timed when profiling on) */
   double stencil_seconds;      /* summed device time of those launches (hipEvents), 0 if off */
   double stencil_bytes;        /* algorithmic HBM bytes of those launches          */
+  int64_t reliable_updates;    /* MIXED: reliable updates done (all right-hand sides) */
+  double max_quad_err_bound;   /* max over solves of ||b - A x||^2 / lambda_lb, with
+                                  lambda_lb = min m(x) (valid when every coupling is
+                                  >= 0, NaN otherwise): bounds each quadrature's error */
 } tip_stats;
 
 /* Number of estimates written by trace_inv_probe: floor(log2 n) + 1, plus one

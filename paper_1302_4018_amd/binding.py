@@ -20,7 +20,7 @@ STATUS_NAMES = {0: "TIP_OK", -1: "TIP_EINVAL", -2: "TIP_ENOMEM", -3: "TIP_ENOCON
                 -5: "TIP_EDEVICE", -6: "TIP_EUNSUPPORTED"}
 KIND_SCALAR, KIND_COVARIANT = 0, 1
 MASK_DEFAULT, MASK_NONE, MASK_Z2, MASK_Z4 = -1, 0, 1, 2
-PREC_FP64 = 0
+PREC_FP64, PREC_MIXED = 0, 1
 
 
 class tip_operator(ctypes.Structure):
@@ -33,14 +33,15 @@ class tip_params(ctypes.Structure):
     _fields_ = [("n_vectors", ctypes.c_int64), ("m_begin", ctypes.c_int64), ("tol", ctypes.c_double),
                 ("max_iter", ctypes.c_int32), ("seed", ctypes.c_uint64), ("mask", ctypes.c_int32),
                 ("rhs_block", ctypes.c_int32), ("precision", ctypes.c_int32), ("stream", ctypes.c_void_p),
-                ("quadratures", ctypes.POINTER(ctypes.c_double))]
+                ("quadratures", ctypes.POINTER(ctypes.c_double)), ("reliable_delta", ctypes.c_double)]
 
 
 class tip_stats(ctypes.Structure):
     _fields_ = [("solves", ctypes.c_int64), ("total_iters", ctypes.c_int64), ("max_iters", ctypes.c_int32),
                 ("n_checkpoints_done", ctypes.c_int32), ("max_true_relres", ctypes.c_double),
                 ("seconds", ctypes.c_double), ("stencil_launches", ctypes.c_int64),
-                ("stencil_seconds", ctypes.c_double), ("stencil_bytes", ctypes.c_double)]
+                ("stencil_seconds", ctypes.c_double), ("stencil_bytes", ctypes.c_double),
+                ("reliable_updates", ctypes.c_int64), ("max_quad_err_bound", ctypes.c_double)]
 
 
 def _load():
@@ -147,7 +148,8 @@ class Operator:
         return s
 
 
-def _params(n_vectors, tol, seed, mask, max_iter, rhs_block, m_begin, quadratures, stream, precision=PREC_FP64):
+def _params(n_vectors, tol, seed, mask, max_iter, rhs_block, m_begin, quadratures, stream, precision=PREC_FP64,
+            reliable_delta=0.0):
     p = tip_params()
     p.n_vectors = int(n_vectors)
     p.m_begin = int(m_begin)
@@ -159,6 +161,7 @@ def _params(n_vectors, tol, seed, mask, max_iter, rhs_block, m_begin, quadrature
     p.precision = int(precision)
     p.stream = _stream(stream)
     p.quadratures = quadratures.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+    p.reliable_delta = float(reliable_delta)
     return p
 
 
@@ -171,13 +174,13 @@ def tip_num_checkpoints(n_vectors):
 
 
 def _run(fn, first, n_vectors, tol, seed, mask, max_iter, rhs_block, m_begin, quadratures, stream, raise_on_error,
-         precision=PREC_FP64):
+         precision=PREC_FP64, reliable_delta=0.0):
     nck = tip_num_checkpoints(n_vectors)
     est = np.zeros((nck, 2), dtype=np.float64)
     q = np.zeros((int(n_vectors), 2), dtype=np.float64)
     if quadratures is not None:
         q[:m_begin] = np.asarray(quadratures, dtype=np.complex128)[:m_begin].view(np.float64).reshape(-1, 2)
-    p = _params(n_vectors, tol, seed, mask, max_iter, rhs_block, m_begin, q, stream, precision)
+    p = _params(n_vectors, tol, seed, mask, max_iter, rhs_block, m_begin, q, stream, precision, reliable_delta)
     st = tip_stats()
     status = fn(first, ctypes.byref(p), est.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), ctypes.byref(st))
     stats = _stats_dict(st)
@@ -190,11 +193,11 @@ def _run(fn, first, n_vectors, tol, seed, mask, max_iter, rhs_block, m_begin, qu
 
 
 def trace_inv_probe(op, n_vectors, tol, seed, mask=MASK_DEFAULT, max_iter=0, rhs_block=0, m_begin=0,
-                    quadratures=None, stream=None, raise_on_error=True, precision=PREC_FP64):
+                    quadratures=None, stream=None, raise_on_error=True, precision=PREC_FP64, reliable_delta=0.0):
     """Estimates at s = 2^k (complex numpy), quadratures q_m (complex numpy), stats dict."""
     s = op.c_struct()
     return _run(lib.trace_inv_probe, ctypes.byref(s), n_vectors, tol, seed, mask, max_iter, rhs_block, m_begin,
-                quadratures, stream, raise_on_error, precision)
+                quadratures, stream, raise_on_error, precision, reliable_delta)
 
 
 class OpHandle:
@@ -207,11 +210,12 @@ class OpHandle:
         self.op = op
 
     def trace_inv_probe(self, n_vectors, tol, seed, mask=MASK_DEFAULT, max_iter=0, rhs_block=0, m_begin=0,
-                        quadratures=None, stream=None, raise_on_error=True, precision=PREC_FP64):
+                        quadratures=None, stream=None, raise_on_error=True, precision=PREC_FP64, reliable_delta=0.0):
         return _run(lib.trace_inv_probe_op, self._h, n_vectors, tol, seed, mask, max_iter, rhs_block, m_begin,
-                    quadratures, stream, raise_on_error, precision)
+                    quadratures, stream, raise_on_error, precision, reliable_delta)
 
-    def solve_probe(self, m, comp, tol, seed, mask=MASK_DEFAULT, max_iter=0, stream=None, precision=PREC_FP64):
+    def solve_probe(self, m, comp, tol, seed, mask=MASK_DEFAULT, max_iter=0, stream=None, precision=PREC_FP64,
+                    reliable_delta=0.0):
         """x = A^-1 b_{m,comp} (torch tensor on the GPU), q = b^H x, stats."""
         import torch
         op = self.op
@@ -219,7 +223,7 @@ class OpHandle:
         shape = (op.V, op.ncomp, 2) if complex_solve else (op.V,)
         x = torch.empty(shape, dtype=torch.float64, device="cuda")
         q = np.zeros(2)
-        p = _params(1, tol, seed, mask, max_iter, 1, 0, np.zeros((1, 2)), stream, precision)
+        p = _params(1, tol, seed, mask, max_iter, 1, 0, np.zeros((1, 2)), stream, precision, reliable_delta)
         st = tip_stats()
         _check(lib.tip_solve_probe(self._h, ctypes.byref(p), int(m), int(comp), _ptr(x),
                                    q.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), ctypes.byref(st)),

@@ -106,19 +106,23 @@ struct tip_op_s {
   int kind = 0;
   double mass = 0.0;
   DevBuf links, mass_field, coupling;
-  bool has_mass_field = false, has_coupling = false;
+  DevBuf links32;              // single-precision copy, made on first mixed-precision use
+  bool has_mass_field = false, has_coupling = false, has_links32 = false;
+  // lower bound of the spectrum: A = sum_e w_e L_e + diag(m) with L_e PSD, so
+  // lambda_min >= min m(x) whenever every w_e >= 0 (NaN when not known)
+  double lambda_lb = 0.0;
   // workspace, grown on demand
   DevBuf vec, partial, scal;
   HostPinned host;
   std::vector<hipEvent_t> events;
 
-  OpDev dev() const {
+  OpDev dev(bool single = false) const {
     OpDev o;
     o.kind = kind;
     o.mass = mass;
     o.mass_field = has_mass_field ? (const double*)mass_field.p : nullptr;
     o.coupling = has_coupling ? (const double*)coupling.p : nullptr;
-    o.links = kind == 1 ? (const double*)links.p : nullptr;
+    o.links = kind == 1 ? (const double*)(single ? links32.p : links.p) : nullptr;
     return o;
   }
   ~tip_op_s() {
@@ -170,6 +174,22 @@ tip_status create_handle(const tip_operator* op, hipStream_t st, tip_op_s** out)
       return bail(fail(TIP_EDEVICE, "link repack launch failed"));
   }
   if (hipStreamSynchronize(st) != hipSuccess) return bail(fail(TIP_EDEVICE, "operator setup failed on the device"));
+  {
+    double lb = op->mass;
+    if (op->mass_field) {
+      std::vector<double> m(V);
+      if (hipMemcpy(m.data(), op->mass_field, V * sizeof(double), hipMemcpyDeviceToHost) != hipSuccess)
+        return bail(fail(TIP_EDEVICE, "reading mass_field failed"));
+      lb = *std::min_element(m.begin(), m.end());
+    }
+    if (op->coupling) {
+      std::vector<double> w((size_t)g.ndim * V);
+      if (hipMemcpy(w.data(), op->coupling, w.size() * sizeof(double), hipMemcpyDeviceToHost) != hipSuccess)
+        return bail(fail(TIP_EDEVICE, "reading coupling failed"));
+      if (*std::min_element(w.begin(), w.end()) < 0.0) lb = std::nan("");
+    }
+    h->lambda_lb = lb;
+  }
   *out = h;
   return TIP_OK;
 }
@@ -271,7 +291,10 @@ tip_status check_params(const tip_op_s* h, const tip_params* p, int* mask_out) {
   if (!(p->tol > 0.0) || !std::isfinite(p->tol)) return fail(TIP_EINVAL, "tol must be positive and finite");
   if (p->max_iter < 0) return fail(TIP_EINVAL, "max_iter must be >= 0");
   if (p->rhs_block < 0) return fail(TIP_EINVAL, "rhs_block must be >= 0");
-  if (p->precision != TIP_PREC_FP64) return fail(TIP_EUNSUPPORTED, "precision %d is not available", p->precision);
+  if (p->precision != TIP_PREC_FP64 && p->precision != TIP_PREC_MIXED)
+    return fail(TIP_EINVAL, "unknown precision %d", p->precision);
+  if (!(p->reliable_delta >= 0.0 && p->reliable_delta < 1.0))
+    return fail(TIP_EINVAL, "reliable_delta must be in [0, 1)");
   int mask = p->mask;
   if (mask == TIP_MASK_DEFAULT) mask = h->kind == TIP_KIND_COVARIANT ? TIP_MASK_Z4 : TIP_MASK_Z2;
   if (mask < TIP_MASK_NONE || mask > TIP_MASK_Z4) return fail(TIP_EINVAL, "unknown mask %d", p->mask);
@@ -280,24 +303,31 @@ tip_status check_params(const tip_op_s* h, const tip_params* p, int* mask_out) {
 }
 
 // CG over blocks of right-hand sides on one prepared operator.
+//   FP64:  x, r, p, w in FP64; one FP64 true-residual check per solve.
+//   mixed: x in FP64; correction xh, r, p, w in FP32 with FP32 links; FP64
+//          reliable updates whenever the FP32 residual has fallen by delta,
+//          and the same FP64 true-residual check at the end.
 struct Solver {
   tip_op_s* h;
   const tip_params* p;
   hipStream_t st;
   Plan pl;
+  bool mixed = false;
+  Prec prec = Prec::kF64;
   int max_iter, max_restarts = 8;
-  double tol2;
-  size_t vbytes, pstride, nscal, nelem;
+  double tol2, delta2 = 0.0;
+  size_t vbytes, vbytes64, pstride, nscal, nelem;
   int gx_m, gx_u, gx_t;       // partials per rhs written by matvec, update, true residual
-  void *X, *Rv, *Pv, *W;
+  void *X, *Rv, *Pv, *W, *XH; // FP64 path: X, Rv, Pv, W; mixed: X (FP64) + XH, Rv, Pv, W (FP32)
   double* part;
   CgScalars sc;
   int* ran_dev;
   double *h_q, *h_relres2;
   int *h_state, *h_iters, *h_active, *h_ran;
-  OpDev od;
+  OpDev od, od64;
   double mv_bytes;
   int predicted = 8;
+  int64_t reliable_updates = 0;
   // stencil accounting
   int64_t stencil_launches = 0;
   double stencil_seconds = 0.0, stencil_bytes = 0.0;
@@ -320,12 +350,15 @@ struct Solver {
     h = handle;
     p = params;
     st = (hipStream_t)p->stream;
+    mixed = p->precision == TIP_PREC_MIXED;
+    prec = mixed ? Prec::kF32 : Prec::kF64;
     const Geom& g = h->geom;
     const int64_t V = g.V;
     const int ncomp = g.ncomp;
     pl.mask = mask;
     pl.elem = (h->kind == TIP_KIND_COVARIANT || mask == TIP_MASK_Z4) ? Elem::kComplex : Elem::kReal;
-    pl.esz = pl.elem == Elem::kReal ? sizeof(double) : sizeof(double2);
+    const size_t esz64 = pl.elem == Elem::kReal ? sizeof(double) : sizeof(double2);
+    pl.esz = mixed ? esz64 / 2 : esz64;
     // block size: a power of two <= 64; 16 shares each link among 16 solves;
     // small lattices take more right-hand sides per block to fill the GPU.
     // B depends only on the operator and rhs_block, so a right-hand side is
@@ -338,8 +371,8 @@ struct Solver {
       B = 16;
       while (B < 64 && V * B < (int64_t(1) << 18)) B *= 2;
     }
-    // keep the four CG vectors of a block within 32 GiB
-    while (B > 1 && 4.0 * B * ncomp * (double)V * pl.esz > 32.0 * (1ull << 30)) B /= 2;
+    // keep the CG vectors of a block within 32 GiB
+    while (B > 1 && 4.5 * B * ncomp * (double)V * esz64 > 32.0 * (1ull << 30)) B /= 2;
     pl.B = B;
     pl.logB = 0;
     while ((1 << pl.logB) < B) ++pl.logB;
@@ -347,69 +380,108 @@ struct Solver {
     pl.use_march = make_marchmap(g, pl.logB, &pl.mm);
     max_iter = p->max_iter > 0 ? p->max_iter : (int)std::min<int64_t>(10 * V * ncomp, 1 << 20);
     tol2 = p->tol * p->tol;
+    if (mixed) {
+      const double d = p->reliable_delta > 0.0 ? p->reliable_delta : 0.01;
+      delta2 = d * d;
+    }
 
     nelem = (size_t)B * ncomp * V;
     vbytes = nelem * pl.esz;                      // one CG vector of the block
+    vbytes64 = nelem * esz64;
     gx_m = (int)(pl.use_march ? pl.mm.grid : pl.tm.grid);
     gx_u = (int)update_grid(nelem);
     gx_t = (int)pl.tm.grid;
     pstride = (size_t)B * std::max(gx_m, std::max(gx_u, gx_t));
     nscal = (size_t)B;
-    if (h->vec.ensure(4 * vbytes) != hipSuccess)
-      return fail(TIP_ENOMEM, "hipMalloc of %zu bytes of CG vectors failed", 4 * vbytes);
-    if (h->partial.ensure(3 * pstride * sizeof(double)) != hipSuccess) return fail(TIP_ENOMEM, "hipMalloc partials");
-    const size_t scal_bytes = nscal * (8 * sizeof(double) + 3 * sizeof(int)) + 64 + kMaxChunk * sizeof(int);
+    const size_t vec_total = mixed ? vbytes64 + 4 * vbytes : 4 * vbytes;
+    if (h->vec.ensure(vec_total) != hipSuccess)
+      return fail(TIP_ENOMEM, "hipMalloc of %zu bytes of CG vectors failed", vec_total);
+    if (h->partial.ensure(5 * pstride * sizeof(double)) != hipSuccess) return fail(TIP_ENOMEM, "hipMalloc partials");
+    const size_t scal_bytes = nscal * (9 * sizeof(double) + 4 * sizeof(int)) + 128 + kMaxChunk * sizeof(int);
     if (h->scal.ensure(scal_bytes) != hipSuccess) return fail(TIP_ENOMEM, "hipMalloc scalars");
-    const size_t host_bytes = nscal * (3 * sizeof(double) + 2 * sizeof(int)) + 64 + kMaxChunk * sizeof(int);
+    const size_t host_bytes = nscal * (3 * sizeof(double) + 2 * sizeof(int)) + 128 + kMaxChunk * sizeof(int);
     if (h->host.ensure(host_bytes) != hipSuccess) return fail(TIP_ENOMEM, "hipHostMalloc");
+    if (mixed && h->kind == TIP_KIND_COVARIANT && !h->has_links32) {
+      const size_t n = (size_t)g.ndim * 9 * V;
+      if (h->links32.ensure(n * sizeof(float2)) != hipSuccess) return fail(TIP_ENOMEM, "hipMalloc FP32 links");
+      TIP_HIP(launch_cast_links(n, (const double2*)h->links.p, (float2*)h->links32.p, st));
+      h->has_links32 = true;
+    }
 
     char* vb = (char*)h->vec.p;
     X = vb;
-    Rv = vb + vbytes;
-    Pv = vb + 2 * vbytes;
-    W = vb + 3 * vbytes;
+    if (mixed) {
+      XH = vb + vbytes64;
+      Rv = vb + vbytes64 + vbytes;
+      Pv = vb + vbytes64 + 2 * vbytes;
+      W = vb + vbytes64 + 3 * vbytes;
+    } else {
+      XH = nullptr;
+      Rv = vb + vbytes;
+      Pv = vb + 2 * vbytes;
+      W = vb + 3 * vbytes;
+    }
     part = (double*)h->partial.p;
     double* d = (double*)h->scal.p;
     sc.rho = d;
     sc.alpha = d + nscal;
     sc.xalpha = d + 2 * nscal;
     sc.beta = d + 3 * nscal;
-    sc.bnorm2 = d + 4 * nscal;
-    sc.relres2 = d + 5 * nscal;
-    sc.q = d + 6 * nscal;            // 2 * nscal
-    int* iv = (int*)(d + 8 * nscal);
+    sc.rho_ref = d + 4 * nscal;
+    sc.bnorm2 = d + 5 * nscal;
+    sc.relres2 = d + 6 * nscal;
+    sc.q = d + 7 * nscal;            // 2 * nscal
+    int* iv = (int*)(d + 9 * nscal);
     sc.state = iv;
     sc.iters = iv + nscal;
     sc.restarts = iv + 2 * nscal;
-    sc.active = iv + 3 * nscal;
-    ran_dev = sc.active + 16;
+    sc.ru = iv + 3 * nscal;
+    sc.active = iv + 4 * nscal;
+    sc.n_ru = sc.active + 1;
+    sc.ru_count = sc.active + 2;
+    ran_dev = sc.active + 32;
     char* hb = (char*)h->host.p;
     h_q = (double*)hb;
     h_relres2 = h_q + 2 * nscal;
     h_state = (int*)(h_relres2 + nscal);
     h_iters = h_state + nscal;
-    h_active = h_iters + nscal;
-    h_ran = h_active + 16;
+    h_active = h_iters + nscal;      // [0] active, [2] reliable updates of the block
+    h_ran = h_active + 32;
 
-    od = h->dev();
+    od = h->dev(mixed);
+    od64 = h->dev(false);
     // Algorithmic bytes of one stencil launch: per site, each link, coupling
     // and mass read once (shared by the B right-hand sides), p read and
     // w = A p written once per right-hand side.
     double per_site = 0.0;
-    if (h->kind == TIP_KIND_COVARIANT) per_site += (double)g.ndim * 9 * 16;
+    if (h->kind == TIP_KIND_COVARIANT) per_site += (double)g.ndim * 9 * 2 * (mixed ? 4 : 8);
     if (h->has_coupling) per_site += (double)g.ndim * 8;
     if (h->has_mass_field) per_site += 8.0;
     mv_bytes = per_site * V + 2.0 * (double)vbytes;
     return TIP_OK;
   }
 
-  // Solve right-hand sides rhs0 .. rhs0+nb-1; x stays in X.  Fills the host
-  // mirrors h_q, h_relres2, h_state, h_iters for those nb right-hand sides.
+  // Reliable updates of flagged right-hand sides (mode 0, enqueued after
+  // every iteration; the kernels return at once when none is pending) or the
+  // final check of frozen ones (mode 1) in the mixed solver.
+  tip_status reliable(int64_t rhs0, int nb, int mode) {
+    const Geom& g = h->geom;
+    TIP_HIP(launch_ru_accumulate(nelem, pl.logB, pl.elem, sc, mode, X, XH, st));
+    TIP_HIP(launch_ru_residual(od64, g, pl.tm, pl.elem, sc, mode, rhs0, nb, p->seed, pl.mask, X, Rv, Pv, part,
+                               pstride, st));
+    TIP_HIP(launch_reduce_ru(sc, pl.B, part, (int)ru_grid(pl.tm), pstride, mode, tol2, max_iter, max_restarts, st));
+    return TIP_OK;
+  }
+
+  // Solve right-hand sides rhs0 .. rhs0+nb-1; x (FP64) stays in X.  Fills the
+  // host mirrors h_q, h_relres2, h_state, h_iters for those nb right-hand sides.
   tip_status solve_block(int64_t rhs0, int nb) {
     const Geom& g = h->geom;
     const MarchMap* mm = pl.use_march ? &pl.mm : nullptr;
     TIP_HIP(launch_scalars_init(sc, nb, pl.B, (double)g.V, p->tol >= 1.0 ? 1 : 0, st));
-    TIP_HIP(launch_init(g, pl.elem, pl.logB, rhs0, nb, p->seed, pl.mask, X, Rv, Pv, st));
+    if (mixed) TIP_HIP(launch_init_mixed(g, pl.elem, pl.logB, rhs0, nb, p->seed, pl.mask, X, XH, Rv, Pv, st));
+    else TIP_HIP(launch_init(g, pl.elem, pl.logB, rhs0, nb, p->seed, pl.mask, X, Rv, Pv, st));
+    void* xdir = mixed ? XH : X;     // vector the direction pass updates
     bool first_chunk = true;
     std::vector<Timed> window;
     for (;;) {
@@ -428,15 +500,19 @@ struct Solver {
             TIP_HIP(next_event(&tv.b));
             TIP_HIP(hipEventRecord(tv.a, st));
           }
-          TIP_HIP(launch_stencil(od, g, pl.tm, mm, pl.elem, sc.state, sc.active, Pv, W, part, ran_dev + it, st));
+          TIP_HIP(launch_stencil(od, g, pl.tm, mm, pl.elem, prec, sc.state, sc.active, Pv, W, part, ran_dev + it, st));
           if (g_profiling) {
             TIP_HIP(hipEventRecord(tv.b, st));
             window.push_back(tv);
           }
           TIP_HIP(launch_reduce_alpha(sc, pl.B, part, gx_m, st));
-          TIP_HIP(launch_update_r(nelem, pl.logB, pl.elem, sc, Rv, W, part + pstride, st));
-          TIP_HIP(launch_reduce_beta(sc, pl.B, part + pstride, gx_u, tol2, max_iter, st));
-          TIP_HIP(launch_direction(nelem, pl.logB, pl.elem, sc, X, Rv, Pv, st));
+          TIP_HIP(launch_update_r(nelem, pl.logB, pl.elem, prec, sc, Rv, W, part + pstride, st));
+          TIP_HIP(launch_reduce_beta(sc, pl.B, part + pstride, gx_u, tol2, max_iter, delta2, st));
+          TIP_HIP(launch_direction(nelem, pl.logB, pl.elem, prec, sc, xdir, Rv, Pv, st));
+          if (mixed) {
+            tip_status s = reliable(rhs0, nb, 0);
+            if (s != TIP_OK) return s;
+          }
         }
         TIP_HIP(hipMemcpyAsync(h_ran, ran_dev, chunk * sizeof(int), hipMemcpyDeviceToHost, st));
         TIP_HIP(hipMemcpyAsync(h_active, sc.active, sizeof(int), hipMemcpyDeviceToHost, st));
@@ -451,21 +527,28 @@ struct Solver {
             stencil_seconds += ms * 1e-3;
           }
         }
-        if (*h_active == 0) break;
+        if (h_active[0] == 0) break;
       }
-      // true residual: accept, or restart CG from x
-      TIP_HIP(launch_true_residual(od, g, pl.tm, pl.elem, sc.state, rhs0, nb, p->seed, pl.mask, X, Rv, Pv, part,
-                                   pstride, st));
-      TIP_HIP(launch_reduce_true(sc, pl.B, part, gx_t, pstride, tol2, max_iter, max_restarts, st));
+      // FP64 true residual: accept, or restart CG from x
+      if (mixed) {
+        tip_status s = reliable(rhs0, nb, 1);
+        if (s != TIP_OK) return s;
+      } else {
+        TIP_HIP(launch_true_residual(od, g, pl.tm, pl.elem, sc.state, rhs0, nb, p->seed, pl.mask, X, Rv, Pv, part,
+                                     pstride, st));
+        TIP_HIP(launch_reduce_true(sc, pl.B, part, gx_t, pstride, tol2, max_iter, max_restarts, st));
+      }
       TIP_HIP(hipMemcpyAsync(h_active, sc.active, sizeof(int), hipMemcpyDeviceToHost, st));
       TIP_HIP(hipStreamSynchronize(st));
-      if (*h_active == 0) break;
+      if (h_active[0] == 0) break;
     }
     TIP_HIP(hipMemcpyAsync(h_q, sc.q, 2 * nb * sizeof(double), hipMemcpyDeviceToHost, st));
     TIP_HIP(hipMemcpyAsync(h_relres2, sc.relres2, nb * sizeof(double), hipMemcpyDeviceToHost, st));
     TIP_HIP(hipMemcpyAsync(h_state, sc.state, nb * sizeof(int), hipMemcpyDeviceToHost, st));
     TIP_HIP(hipMemcpyAsync(h_iters, sc.iters, nb * sizeof(int), hipMemcpyDeviceToHost, st));
+    TIP_HIP(hipMemcpyAsync(h_active + 2, sc.ru_count, sizeof(int), hipMemcpyDeviceToHost, st));
     TIP_HIP(hipStreamSynchronize(st));
+    reliable_updates += h_active[2];
     int blk_max = 0;
     for (int j = 0; j < nb; ++j) blk_max = std::max(blk_max, h_iters[j]);
     predicted = std::max(1, blk_max);
@@ -476,6 +559,7 @@ struct Solver {
     stats->stencil_launches = stencil_launches;
     stats->stencil_seconds = g_profiling ? stencil_seconds : 0.0;
     stats->stencil_bytes = stencil_bytes;
+    stats->reliable_updates = reliable_updates;
   }
 };
 
@@ -599,6 +683,8 @@ tip_status trace_inv_probe_op(tip_op_handle h, const tip_params* p, double* esti
     stats->max_iters = mx_it;
     stats->n_checkpoints_done = done;
     stats->max_true_relres = mx_rr;
+    // error of one quadrature: r^H A^-1 r <= ||r||^2 / lambda_min, ||b||^2 = V
+    stats->max_quad_err_bound = mx_rr * mx_rr * (double)h->geom.V / h->lambda_lb;
     sv.fill_stats(stats);
     stats->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t_start).count();
   }
@@ -643,6 +729,7 @@ tip_status tip_solve_probe(tip_op_handle h, const tip_params* p, int64_t m, int3
     stats->total_iters = sv.h_iters[0];
     stats->max_iters = sv.h_iters[0];
     stats->max_true_relres = std::sqrt(sv.h_relres2[0]);
+    stats->max_quad_err_bound = sv.h_relres2[0] * (double)g.V / h->lambda_lb;
     sv.fill_stats(stats);
     stats->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t_start).count();
   }
@@ -692,7 +779,7 @@ tip_status tip_apply_operator(const tip_operator* op, int32_t nrhs, const double
     const char* xk = (const char*)x + k * bytes;
     char* yk = (char*)y + k * bytes;
     if (launch_layout(g, elem, xk, in, true, st) != hipSuccess ||
-        launch_stencil(h->dev(), g, tm, nullptr, elem, nullptr, nullptr, in, out, nullptr, nullptr, st) != hipSuccess ||
+        launch_stencil(h->dev(), g, tm, nullptr, elem, Prec::kF64, nullptr, nullptr, in, out, nullptr, nullptr, st) != hipSuccess ||
         launch_layout(g, elem, out, yk, false, st) != hipSuccess)
       ret = fail(TIP_EDEVICE, "apply launch failed");
   }

@@ -132,7 +132,25 @@ __device__ __forceinline__ double2 cfma_conj(double2 u, double2 v, double2 acc) 
   return acc;
 }
 
-// Generic element helpers for real (double) and complex (double2) vectors.
+// FP32 complex helpers (single-precision storage and arithmetic).
+__device__ __forceinline__ float2 cfma(float2 u, float2 v, float2 acc) {
+  acc.x = fmaf(u.x, v.x, acc.x);
+  acc.x = fmaf(-u.y, v.y, acc.x);
+  acc.y = fmaf(u.x, v.y, acc.y);
+  acc.y = fmaf(u.y, v.x, acc.y);
+  return acc;
+}
+__device__ __forceinline__ float2 cfma_conj(float2 u, float2 v, float2 acc) {
+  acc.x = fmaf(u.x, v.x, acc.x);
+  acc.x = fmaf(u.y, v.y, acc.x);
+  acc.y = fmaf(u.x, v.y, acc.y);
+  acc.y = fmaf(-u.y, v.x, acc.y);
+  return acc;
+}
+
+// Generic element helpers for real (double, float) and complex (double2,
+// float2) vectors.  Scalars are passed in double and applied in the vector's
+// own precision; dot products and norms are always returned in double.
 __device__ __forceinline__ double axpy(double a, double x, double y) { return fma(a, x, y); }
 __device__ __forceinline__ double2 axpy(double a, double2 x, double2 y) {
   return make_double2(fma(a, x.x, y.x), fma(a, x.y, y.y));
@@ -145,12 +163,39 @@ __device__ __forceinline__ double redot(double2 a, double2 b) { return fma(a.x, 
 // Im(conj(a) b)
 __device__ __forceinline__ double imdot(double, double) { return 0.0; }
 __device__ __forceinline__ double imdot(double2 a, double2 b) { return fma(a.x, b.y, -a.y * b.x); }
+__device__ __forceinline__ float axpy(double a, float x, float y) { return fmaf((float)a, x, y); }
+__device__ __forceinline__ float2 axpy(double a, float2 x, float2 y) {
+  const float af = (float)a;
+  return make_float2(fmaf(af, x.x, y.x), fmaf(af, x.y, y.y));
+}
+__device__ __forceinline__ double norm2(float a) { return (double)a * (double)a; }
+__device__ __forceinline__ double norm2(float2 a) { return fma((double)a.x, (double)a.x, (double)a.y * (double)a.y); }
+__device__ __forceinline__ double redot(float a, float b) { return (double)a * (double)b; }
+__device__ __forceinline__ double redot(float2 a, float2 b) {
+  return fma((double)a.x, (double)b.x, (double)a.y * (double)b.y);
+}
+__device__ __forceinline__ double imdot(float, float) { return 0.0; }
+__device__ __forceinline__ double imdot(float2 a, float2 b) {
+  return fma((double)a.x, (double)b.y, -(double)a.y * (double)b.x);
+}
 template <class T> __device__ __forceinline__ T zero();
 template <> __device__ __forceinline__ double zero<double>() { return 0.0; }
 template <> __device__ __forceinline__ double2 zero<double2>() { return make_double2(0.0, 0.0); }
+template <> __device__ __forceinline__ float zero<float>() { return 0.0f; }
+template <> __device__ __forceinline__ float2 zero<float2>() { return make_float2(0.0f, 0.0f); }
+// exact values (probes) or FP64 vectors converted to the vector type
 template <class T> __device__ __forceinline__ T from_c(double2 v);
 template <> __device__ __forceinline__ double from_c<double>(double2 v) { return v.x; }
 template <> __device__ __forceinline__ double2 from_c<double2>(double2 v) { return v; }
+template <> __device__ __forceinline__ float from_c<float>(double2 v) { return (float)v.x; }
+template <> __device__ __forceinline__ float2 from_c<float2>(double2 v) { return make_float2((float)v.x, (float)v.y); }
+__device__ __forceinline__ double2 to_c(double v) { return make_double2(v, 0.0); }
+__device__ __forceinline__ double2 to_c(double2 v) { return v; }
+__device__ __forceinline__ double2 to_c(float v) { return make_double2((double)v, 0.0); }
+__device__ __forceinline__ double2 to_c(float2 v) { return make_double2((double)v.x, (double)v.y); }
+// element of an FP64 vector converted to the single-precision type
+__device__ __forceinline__ float to_single(double v) { return (float)v; }
+__device__ __forceinline__ float2 to_single(double2 v) { return make_float2((float)v.x, (float)v.y); }
 
 // Sum of N per-thread values over a 256-thread workgroup; thread 0 gets the
 // totals.  A shuffle tree inside each wave64 first, then the 4 wave results through LDS; the

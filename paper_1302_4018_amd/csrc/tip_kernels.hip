@@ -34,14 +34,17 @@
 
 namespace tip {
 
+extern __shared__ __align__(16) unsigned char tip_dyn_lds[];
+
 // ---------------------------------------------------------------------------
 // Operator policies and small helpers
 // ---------------------------------------------------------------------------
 
-struct CovOp {                         // 3 complex components, links U_mu
-  using T = double2;
+template <class C>
+struct CovOp {                         // 3 complex components, links U_mu (C = double2 or float2)
+  using T = C;
   static constexpr int NC = 3;
-  const double2* __restrict__ U;
+  const C* __restrict__ U;
 };
 
 template <class TT>
@@ -51,27 +54,30 @@ struct ScalarOp {                      // 1 component, real or complex vectors
 };
 
 // y = U x and y = U^H x for a 3x3 complex matrix u[3a+b].
-__device__ __forceinline__ void mul_u(const double2 (&u)[9], const double2 (&x)[3], double2 (&y)[3]) {
+template <class C>
+__device__ __forceinline__ void mul_u(const C (&u)[9], const C (&x)[3], C (&y)[3]) {
 #pragma unroll
   for (int a = 0; a < 3; ++a) {
-    double2 t = make_double2(0.0, 0.0);
+    C t = zero<C>();
 #pragma unroll
     for (int b = 0; b < 3; ++b) t = cfma(u[3 * a + b], x[b], t);
     y[a] = t;
   }
 }
-__device__ __forceinline__ void mul_uh(const double2 (&u)[9], const double2 (&x)[3], double2 (&y)[3]) {
+template <class C>
+__device__ __forceinline__ void mul_uh(const C (&u)[9], const C (&x)[3], C (&y)[3]) {
 #pragma unroll
   for (int a = 0; a < 3; ++a) {
-    double2 t = make_double2(0.0, 0.0);
+    C t = zero<C>();
 #pragma unroll
     for (int b = 0; b < 3; ++b) t = cfma_conj(u[3 * b + a], x[b], t);
     y[a] = t;
   }
 }
 
-__device__ __forceinline__ void load_link(const CovOp& op, size_t V, int mu, uint32_t s, double2 (&u)[9]) {
-  const double2* Um = op.U + (size_t)mu * 9 * V;
+template <class C>
+__device__ __forceinline__ void load_link(const CovOp<C>& op, size_t V, int mu, uint32_t s, C (&u)[9]) {
+  const C* Um = op.U + (size_t)mu * 9 * V;
 #pragma unroll
   for (int e = 0; e < 9; ++e) u[e] = Um[(size_t)e * V + s];
 }
@@ -94,9 +100,10 @@ __device__ __forceinline__ void hop_term(const Op&, size_t, int, uint32_t, bool,
                                          const typename Op::T (&x)[Op::NC], typename Op::T (&h)[Op::NC]) {
   h[0] = x[0];
 }
-__device__ __forceinline__ void hop_term(const CovOp& op, size_t V, int mu, uint32_t s_link, bool backward,
-                                         const double2 (&x)[3], double2 (&h)[3]) {
-  double2 u[9];
+template <class C>
+__device__ __forceinline__ void hop_term(const CovOp<C>& op, size_t V, int mu, uint32_t s_link, bool backward,
+                                         const C (&x)[3], C (&h)[3]) {
+  C u[9];
   load_link(op, V, mu, s_link, u);
   if (backward) mul_uh(u, x, h);
   else mul_u(u, x, h);
@@ -245,7 +252,8 @@ __global__ __launch_bounds__(kBlock) void k_stencil_march(Geom g, MarchMap mm, O
   if (active && *active == 0) return;
   if (ran && blockIdx.x == 0 && threadIdx.x == 0) *ran = 1;
   __shared__ double lds[4 * 64];
-  extern __shared__ double2 lds_links[];           // [2 ndim - 1][9][TS] when kLdsLinks
+  // [2 ndim - 1][9][TS] link elements when kLdsLinks
+  T* lds_links = reinterpret_cast<T*>(tip_dyn_lds);
   // kLogB >= 0 / kHasW >= 0 fix the block size / the presence of couplings at
   // compile time (LDS offsets become immediates, unit weights disappear)
   const int logB = kLogB >= 0 ? kLogB : mm.logB;
@@ -321,7 +329,7 @@ __global__ __launch_bounds__(kBlock) void k_stencil_march(Geom g, MarchMap mm, O
       T xn[NC], h[NC];
       load_vec<T, NC>(in, V, logB, sf, j, xn);
       if constexpr (kLdsLinks) {
-        double2 u[9];
+        T u[9];
 #pragma unroll
         for (int e = 0; e < 9; ++e) u[e] = lds_links[(mu * 9 + e) * TS + si];
         mul_u(u, xn, h);
@@ -331,7 +339,7 @@ __global__ __launch_bounds__(kBlock) void k_stencil_march(Geom g, MarchMap mm, O
       add_weighted<T, NC>(wf, h, hop);
       load_vec<T, NC>(in, V, logB, sb, j, xn);
       if constexpr (kLdsLinks) {
-        double2 u[9];
+        T u[9];
 #pragma unroll
         for (int e = 0; e < 9; ++e) u[e] = lds_links[((g.ndim + mu) * 9 + e) * TS + si];
         mul_uh(u, xn, h);
@@ -346,7 +354,7 @@ __global__ __launch_bounds__(kBlock) void k_stencil_march(Geom g, MarchMap mm, O
     T xn[NC], h[NC];
     load_vec<T, NC>(in, V, logB, sn, j, xn);
     if constexpr (NC == 3) {
-      double2 u[9];
+      T u[9];
       if constexpr (kLdsLinks) {
 #pragma unroll
         for (int e = 0; e < 9; ++e) u[e] = lds_links[(mt * 9 + e) * TS + si];
@@ -528,7 +536,11 @@ __device__ __forceinline__ double sum_partials(const double* __restrict__ part, 
 
 __global__ void k_scalars_init(CgScalars sc, int nb, int B, double bnorm2, int start_frozen) {
   const int j = blockIdx.x * blockDim.x + threadIdx.x;
-  if (j == 0) *sc.active = start_frozen ? 0 : nb;
+  if (j == 0) {
+    *sc.active = start_frozen ? 0 : nb;
+    *sc.n_ru = 0;
+    *sc.ru_count = 0;
+  }
   if (j >= B) return;
   const bool valid = j < nb;
   sc.state[j] = valid ? (start_frozen ? kFrozen : kActive) : kPadding;
@@ -537,6 +549,8 @@ __global__ void k_scalars_init(CgScalars sc, int nb, int B, double bnorm2, int s
   sc.alpha[j] = 0.0;
   sc.xalpha[j] = 0.0;
   sc.beta[j] = 0.0;
+  sc.rho_ref[j] = valid ? bnorm2 : 0.0;
+  sc.ru[j] = 0;
   sc.iters[j] = 0;
   sc.restarts[j] = 0;
   sc.relres2[j] = 0.0;
@@ -562,7 +576,7 @@ __global__ __launch_bounds__(kBlock) void k_reduce_alpha(CgScalars sc, const dou
 // at max_iter.  xalpha = the x update the direction pass applies this
 // iteration (alpha for a rhs that iterated, 0 otherwise).
 __global__ __launch_bounds__(kBlock) void k_reduce_beta(CgScalars sc, const double* __restrict__ partial, int gx,
-                                                        double tol2, int max_iter) {
+                                                        double tol2, int max_iter, double delta2) {
   const int j = blockIdx.x;
   if (sc.state[j] != kActive) {                // uniform per workgroup
     if (threadIdx.x == 0) sc.xalpha[j] = 0.0;
@@ -584,6 +598,9 @@ __global__ __launch_bounds__(kBlock) void k_reduce_beta(CgScalars sc, const doub
   } else if (it >= max_iter) {
     sc.state[j] = kNoConv;
     atomicSub(sc.active, 1);
+  } else if (rho_new < delta2 * sc.rho_ref[j] && sc.ru[j] == 0) {
+    sc.ru[j] = 1;                              // ask for a reliable update
+    atomicAdd(sc.n_ru, 1);
   }
 }
 
@@ -611,6 +628,160 @@ __global__ __launch_bounds__(kBlock) void k_reduce_true(CgScalars sc, const doub
   } else {
     sc.state[j] = kNoConv;
   }
+}
+
+// ---------------------------------------------------------------------------
+// Mixed precision: CG in FP32 (links and vectors stored and combined in
+// single precision) with FP64 reliable updates (Sleijpen & van der Vorst,
+// Computing 56 (1996) 141): when the FP32 recursive residual has fallen by
+// the factor delta since the last update, x (FP64) absorbs the FP32
+// correction and the residual is recomputed from x with the FP64 operator.
+// The final acceptance is the same FP64 true-residual test as in plain FP64.
+// Lanes are selected by mode: 0 = flagged for a reliable update and still
+// iterating, 1 = frozen (final check).
+// ---------------------------------------------------------------------------
+
+template <class T> struct SingleOf;
+template <> struct SingleOf<double> { using type = float; };
+template <> struct SingleOf<double2> { using type = float2; };
+
+__device__ __forceinline__ bool ru_selected(const CgScalars& sc, int mode, int j) {
+  return mode == 0 ? (sc.ru[j] != 0 && sc.state[j] == kActive) : sc.state[j] == kFrozen;
+}
+
+// x64 = 0, xh = 0, rh = ph = b (exact in single precision).
+template <class T64, class T32, int NC>
+__global__ __launch_bounds__(kBlock) void k_init_mixed(Geom g, int logB, int64_t rhs0, int nb, uint64_t seed,
+                                                       int mask, T64* __restrict__ x, T32* __restrict__ xh,
+                                                       T32* __restrict__ rh, T32* __restrict__ ph) {
+  const int B = 1 << logB;
+  const int j = threadIdx.x & (B - 1);
+  const uint32_t s = blockIdx.x * (kBlock >> logB) + (threadIdx.x >> logB);
+  if (s >= g.V) return;
+  T32 b[NC], z[NC];
+  T64 z64[NC];
+  rhs_at<T32, NC>(g, s, hier_perm(s, g), rhs0, j, nb, seed, mask, b);
+#pragma unroll
+  for (int c = 0; c < NC; ++c) {
+    z[c] = zero<T32>();
+    z64[c] = zero<T64>();
+  }
+  store_vec<T64, NC>(x, g.V, logB, s, j, z64);
+  store_vec<T32, NC>(xh, g.V, logB, s, j, z);
+  store_vec<T32, NC>(rh, g.V, logB, s, j, b);
+  store_vec<T32, NC>(ph, g.V, logB, s, j, b);
+}
+
+// x64 += xh, xh = 0 for the selected lanes (flat [ncomp][V][B] elements,
+// grid-stride with a stride that is a multiple of 256).  Mode 0 runs after
+// every CG iteration and returns at once when no update is pending.
+template <class T64, class T32>
+__global__ __launch_bounds__(kBlock) void k_ru_accumulate(size_t n, int logB, const CgScalars sc, int mode,
+                                                          T64* __restrict__ x, T32* __restrict__ xh) {
+  if (mode == 0 && *sc.n_ru == 0) return;
+  const int B = 1 << logB;
+  const int j = threadIdx.x & (B - 1);
+  if (!ru_selected(sc, mode, j)) return;
+  const size_t stride = (size_t)gridDim.x * kBlock;
+  for (size_t i = (size_t)blockIdx.x * kBlock + threadIdx.x; i < n; i += stride) {
+    x[i] = axpy(1.0, from_c<T64>(to_c(xh[i])), x[i]);
+    xh[i] = zero<T32>();
+  }
+}
+
+// r = b - A x with the FP64 operator for the selected lanes; rh = r rounded
+// to single; in mode 1 also ph = rh (restart direction).  partial[k] for
+// k = 0..4: ||r||^2, Re b^H x, Im b^H x, Re x^H r, Im x^H r.
+template <class Op64, class T32>
+__global__ __launch_bounds__(kBlock) void k_ru_residual(Geom g, TileMap tm, Op64 op,
+                                                        const double* __restrict__ mass_field, double mass,
+                                                        const double* __restrict__ w, const CgScalars sc, int mode,
+                                                        int64_t rhs0, int nb, uint64_t seed, int mask,
+                                                        const typename Op64::T* __restrict__ x, T32* __restrict__ rh,
+                                                        T32* __restrict__ ph, double* __restrict__ partial,
+                                                        size_t pstride) {
+  using T = typename Op64::T;
+  constexpr int NC = Op64::NC;
+  if (mode == 0 && *sc.n_ru == 0) return;
+  __shared__ double lds[5 * 4 * 64];
+  const int B = 1 << tm.logB;
+  const int j = threadIdx.x & (B - 1);
+  double acc[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+  if (ru_selected(sc, mode, j)) {
+    // grid-stride over the tiles: one partial per workgroup
+    for (uint32_t tile = blockIdx.x; tile < tm.grid; tile += gridDim.x) {
+      const uint32_t s = tile_first_site(tile, tm) + (threadIdx.x >> tm.logB);
+      if (s >= g.V) continue;
+      T xs[NC], ax[NC], b[NC];
+      T32 r32[NC];
+      stencil_site(op, g, tm.logB, s, j, mass_field, mass, w, x, xs, ax);
+      rhs_at<T, NC>(g, s, hier_perm(s, g), rhs0, j, nb, seed, mask, b);
+#pragma unroll
+      for (int c = 0; c < NC; ++c) {
+        const T rt = axpy(-1.0, ax[c], b[c]);
+        acc[0] += norm2(rt);
+        acc[1] += redot(b[c], xs[c]);
+        acc[2] += imdot(b[c], xs[c]);
+        acc[3] += redot(xs[c], rt);
+        acc[4] += imdot(xs[c], rt);
+        r32[c] = to_single(rt);
+      }
+      store_vec<T32, NC>(rh, g.V, tm.logB, s, j, r32);
+      if (mode == 1) store_vec<T32, NC>(ph, g.V, tm.logB, s, j, r32);
+    }
+  }
+  seg_sum<5>(acc, B, lds);
+  if ((int)threadIdx.x < B) {
+#pragma unroll
+    for (int k = 0; k < 5; ++k) partial[k * pstride + (size_t)threadIdx.x * gridDim.x + blockIdx.x] = acc[k];
+  }
+}
+
+// Mode 0: the recursive residual restarts from the true one.  Mode 1: accept
+// with the variational quadrature b^H x + x^H r = 2 Re(b^H x) - x^H A x, whose
+// error r^H A^-1 r is second order in the residual, or restart CG from x.
+__global__ __launch_bounds__(kBlock) void k_reduce_ru(CgScalars sc, const double* __restrict__ partial, int gx,
+                                                      size_t pstride, int mode, double tol2, int max_iter,
+                                                      int max_restarts) {
+  const int j = blockIdx.x;
+  if (mode == 0 && *sc.n_ru == 0) return;
+  if (!ru_selected(sc, mode, j)) return;      // uniform per workgroup
+  double v[5];
+#pragma unroll
+  for (int k = 0; k < 5; ++k) v[k] = sum_partials(partial + k * pstride + (size_t)j * gx, gx);
+  if (threadIdx.x != 0) return;
+  const double rt2 = v[0];
+  if (sc.ru[j]) {
+    sc.ru[j] = 0;
+    atomicSub(sc.n_ru, 1);
+  }
+  if (mode == 0) {
+    sc.rho[j] = rt2;
+    sc.rho_ref[j] = rt2;
+    atomicAdd(sc.ru_count, 1);
+    return;
+  }
+  sc.relres2[j] = rt2 / sc.bnorm2[j];
+  if (rt2 <= tol2 * sc.bnorm2[j]) {
+    sc.state[j] = kAccepted;
+    sc.q[2 * j] = v[1] + v[3];
+    sc.q[2 * j + 1] = v[2] + v[4];
+  } else if (sc.restarts[j] < max_restarts && sc.iters[j] < max_iter && isfinite(rt2)) {
+    sc.state[j] = kActive;
+    sc.rho[j] = rt2;
+    sc.rho_ref[j] = rt2;
+    sc.restarts[j] += 1;
+    atomicAdd(sc.active, 1);
+  } else {
+    sc.state[j] = kNoConv;
+  }
+}
+
+// FP64 links [ndim][9][V] -> single-precision copy, same layout.
+__global__ __launch_bounds__(kBlock) void k_cast_links(size_t n, const double2* __restrict__ src,
+                                                       float2* __restrict__ dst) {
+  const size_t i = (size_t)blockIdx.x * kBlock + threadIdx.x;
+  if (i < n) dst[i] = make_float2((float)src[i].x, (float)src[i].y);
 }
 
 // ---------------------------------------------------------------------------
@@ -666,28 +837,56 @@ __global__ __launch_bounds__(kBlock) void k_comp_major_to_site_major(Geom g, con
 
 static inline unsigned cdiv(size_t a, size_t b) { return (unsigned)((a + b - 1) / b); }
 
-size_t march_lds_bytes(const Geom& g, const MarchMap& mm) {
-  return (size_t)(2 * g.ndim - 1) * 9 * mm.TS * sizeof(double2);
+size_t march_lds_bytes(const Geom& g, const MarchMap& mm, Prec prec) {
+  return (size_t)(2 * g.ndim - 1) * 9 * mm.TS * (prec == Prec::kF64 ? sizeof(double2) : sizeof(float2));
 }
 
-// Calls f(op_policy) for the operator / element combination.
+// Calls f(op_policy) for the operator / element / precision combination.
 template <class F>
-static hipError_t dispatch(const OpDev& od, Elem elem, F&& f) {
-  if (od.kind == 1) f(CovOp{(const double2*)od.links});
+static hipError_t dispatch(const OpDev& od, Elem elem, Prec prec, F&& f) {
+  if (prec == Prec::kF64) {
+    if (od.kind == 1) f(CovOp<double2>{(const double2*)od.links});
+    else if (elem == Elem::kReal) f(ScalarOp<double>{});
+    else f(ScalarOp<double2>{});
+  } else {
+    if (od.kind == 1) f(CovOp<float2>{(const float2*)od.links});
+    else if (elem == Elem::kReal) f(ScalarOp<float>{});
+    else f(ScalarOp<float2>{});
+  }
+  return hipGetLastError();
+}
+
+// FP64 operators only (true residual, reliable updates).
+template <class F>
+static hipError_t dispatch64(const OpDev& od, Elem elem, F&& f) {
+  if (od.kind == 1) f(CovOp<double2>{(const double2*)od.links});
   else if (elem == Elem::kReal) f(ScalarOp<double>{});
   else f(ScalarOp<double2>{});
   return hipGetLastError();
 }
 
-hipError_t launch_stencil(const OpDev& od, const Geom& g, const TileMap& tm, const MarchMap* mm, Elem elem,
+// Calls f(T) with a value of the vector element type.
+template <class F>
+static hipError_t by_elem(Elem elem, Prec prec, F&& f) {
+  if (prec == Prec::kF64) {
+    if (elem == Elem::kReal) f(double{});
+    else f(double2{});
+  } else {
+    if (elem == Elem::kReal) f(float{});
+    else f(float2{});
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_stencil(const OpDev& od, const Geom& g, const TileMap& tm, const MarchMap* mm, Elem elem, Prec prec,
                           const int* state, const int* active, const void* in, void* out, double* partial, int* ran,
                           hipStream_t st) {
-  return dispatch(od, elem, [&](auto op) {
+  return dispatch(od, elem, prec, [&](auto op) {
     using Op = decltype(op);
     using T = typename Op::T;
     if constexpr (Op::NC == 3) {
       if (mm && mm->lds_links) {
-        const size_t lds = march_lds_bytes(g, *mm);
+        const size_t lds = march_lds_bytes(g, *mm, prec);
         auto go = [&](auto kern) {
           kern<<<mm->grid, kBlock, lds, st>>>(g, *mm, op, od.mass_field, od.mass, od.coupling, state, active,
                                               (const T*)in, (T*)out, partial, ran);
@@ -717,7 +916,7 @@ hipError_t launch_stencil(const OpDev& od, const Geom& g, const TileMap& tm, con
 hipError_t launch_true_residual(const OpDev& od, const Geom& g, const TileMap& tm, Elem elem, const int* state,
                                 int64_t rhs0, int nb, uint64_t seed, int mask, const void* x, void* r, void* p,
                                 double* partial, size_t pstride, hipStream_t st) {
-  return dispatch(od, elem, [&](auto op) {
+  return dispatch64(od, elem, [&](auto op) {
     using Op = decltype(op);
     using T = typename Op::T;
     k_true_residual<Op><<<tm.grid, kBlock, 0, st>>>(g, tm, op, od.mass_field, od.mass, od.coupling, state, rhs0, nb,
@@ -738,24 +937,72 @@ hipError_t launch_init(const Geom& g, Elem elem, int logB, int64_t rhs0, int nb,
 }
 
 unsigned update_grid(size_t n) { return std::min<unsigned>(cdiv(n, kBlock), 8192u); }
+unsigned ru_grid(const TileMap& tm) { return std::min<unsigned>(tm.grid, 4096u); }
 
-hipError_t launch_update_r(size_t n, int logB, Elem elem, const CgScalars& sc, void* r, const void* Ap,
+hipError_t launch_update_r(size_t n, int logB, Elem elem, Prec prec, const CgScalars& sc, void* r, const void* Ap,
                            double* partial, hipStream_t st) {
   const unsigned grid = update_grid(n);
-  if (elem == Elem::kReal)
-    k_update_r<double><<<grid, kBlock, 0, st>>>(n, logB, sc, (double*)r, (const double*)Ap, partial);
+  return by_elem(elem, prec, [&](auto tv) {
+    using T = decltype(tv);
+    k_update_r<T><<<grid, kBlock, 0, st>>>(n, logB, sc, (T*)r, (const T*)Ap, partial);
+  });
+}
+
+hipError_t launch_direction(size_t n, int logB, Elem elem, Prec prec, const CgScalars& sc, void* x, const void* r,
+                            void* p, hipStream_t st) {
+  const unsigned grid = cdiv(n, kBlock);
+  return by_elem(elem, prec, [&](auto tv) {
+    using T = decltype(tv);
+    k_direction<T><<<grid, kBlock, 0, st>>>(n, logB, sc, (T*)x, (const T*)r, (T*)p);
+  });
+}
+
+hipError_t launch_init_mixed(const Geom& g, Elem elem, int logB, int64_t rhs0, int nb, uint64_t seed, int mask,
+                             void* x64, void* xh, void* rh, void* ph, hipStream_t st) {
+  const unsigned grid = cdiv(g.V, (size_t)(kBlock >> logB));
+  if (g.ncomp == 3)
+    k_init_mixed<double2, float2, 3><<<grid, kBlock, 0, st>>>(g, logB, rhs0, nb, seed, mask, (double2*)x64,
+                                                              (float2*)xh, (float2*)rh, (float2*)ph);
+  else if (elem == Elem::kReal)
+    k_init_mixed<double, float, 1><<<grid, kBlock, 0, st>>>(g, logB, rhs0, nb, seed, mask, (double*)x64, (float*)xh,
+                                                            (float*)rh, (float*)ph);
   else
-    k_update_r<double2><<<grid, kBlock, 0, st>>>(n, logB, sc, (double2*)r, (const double2*)Ap, partial);
+    k_init_mixed<double2, float2, 1><<<grid, kBlock, 0, st>>>(g, logB, rhs0, nb, seed, mask, (double2*)x64,
+                                                              (float2*)xh, (float2*)rh, (float2*)ph);
   return hipGetLastError();
 }
 
-hipError_t launch_direction(size_t n, int logB, Elem elem, const CgScalars& sc, void* x, const void* r, void* p,
-                            hipStream_t st) {
-  const unsigned grid = cdiv(n, kBlock);
+hipError_t launch_ru_accumulate(size_t n, int logB, Elem elem, const CgScalars& sc, int mode, void* x64, void* xh,
+                                hipStream_t st) {
+  const unsigned grid = update_grid(n);
   if (elem == Elem::kReal)
-    k_direction<double><<<grid, kBlock, 0, st>>>(n, logB, sc, (double*)x, (const double*)r, (double*)p);
+    k_ru_accumulate<double, float><<<grid, kBlock, 0, st>>>(n, logB, sc, mode, (double*)x64, (float*)xh);
   else
-    k_direction<double2><<<grid, kBlock, 0, st>>>(n, logB, sc, (double2*)x, (const double2*)r, (double2*)p);
+    k_ru_accumulate<double2, float2><<<grid, kBlock, 0, st>>>(n, logB, sc, mode, (double2*)x64, (float2*)xh);
+  return hipGetLastError();
+}
+
+hipError_t launch_ru_residual(const OpDev& od64, const Geom& g, const TileMap& tm, Elem elem, const CgScalars& sc,
+                              int mode, int64_t rhs0, int nb, uint64_t seed, int mask, const void* x64, void* rh,
+                              void* ph, double* partial, size_t pstride, hipStream_t st) {
+  return dispatch64(od64, elem, [&](auto op) {
+    using Op = decltype(op);
+    using T = typename Op::T;
+    using T32 = typename SingleOf<T>::type;
+    k_ru_residual<Op, T32><<<ru_grid(tm), kBlock, 0, st>>>(g, tm, op, od64.mass_field, od64.mass, od64.coupling, sc, mode,
+                                                       rhs0, nb, seed, mask, (const T*)x64, (T32*)rh, (T32*)ph,
+                                                       partial, pstride);
+  });
+}
+
+hipError_t launch_reduce_ru(const CgScalars& sc, int B, const double* partial, int gx, size_t pstride, int mode,
+                            double tol2, int max_iter, int max_restarts, hipStream_t st) {
+  k_reduce_ru<<<B, kBlock, 0, st>>>(sc, partial, gx, pstride, mode, tol2, max_iter, max_restarts);
+  return hipGetLastError();
+}
+
+hipError_t launch_cast_links(size_t n, const double2* src, float2* dst, hipStream_t st) {
+  k_cast_links<<<cdiv(n, kBlock), kBlock, 0, st>>>(n, src, dst);
   return hipGetLastError();
 }
 
@@ -770,8 +1017,8 @@ hipError_t launch_reduce_alpha(const CgScalars& sc, int B, const double* partial
 }
 
 hipError_t launch_reduce_beta(const CgScalars& sc, int B, const double* partial, int gx, double tol2, int max_iter,
-                              hipStream_t st) {
-  k_reduce_beta<<<B, kBlock, 0, st>>>(sc, partial, gx, tol2, max_iter);
+                              double delta2, hipStream_t st) {
+  k_reduce_beta<<<B, kBlock, 0, st>>>(sc, partial, gx, tol2, max_iter, delta2);
   return hipGetLastError();
 }
 

@@ -10,6 +10,7 @@
 namespace tip {
 
 enum class Elem { kReal, kComplex };
+enum class Prec { kF64, kF32 };            // storage and arithmetic of the CG vectors and links
 
 // Per right-hand-side CG state codes.
 enum : int { kActive = 0, kFrozen = 1, kAccepted = 2, kBreakdown = 3, kNoConv = 4, kPadding = 5 };
@@ -29,6 +30,7 @@ struct CgScalars {
   double* alpha;
   double* xalpha;              // x update the direction pass applies this iteration
   double* beta;
+  double* rho_ref;             // residual norm^2 at the last reliable update (mixed precision)
   double* bnorm2;
   double* relres2;
   double* q;
@@ -36,6 +38,9 @@ struct CgScalars {
   int* iters;
   int* restarts;
   int* active;                 // number of right-hand sides still iterating
+  int* ru;                     // reliable update requested (mixed precision)
+  int* n_ru;                   // number of such right-hand sides
+  int* ru_count;               // reliable updates done in the block
 };
 
 // Generic site kernels: workgroup b owns TS = 256/B sites (tile_first_site).
@@ -59,10 +64,10 @@ struct MarchMap {
 };
 
 // Dynamic LDS of the marching stencil when it stages links.
-size_t march_lds_bytes(const Geom& g, const MarchMap& mm);
+size_t march_lds_bytes(const Geom& g, const MarchMap& mm, Prec prec);
 
 hipError_t launch_stencil(const OpDev& op, const Geom& g, const TileMap& tm, const MarchMap* mm, Elem elem,
-                          const int* state, const int* active, const void* in, void* out, double* partial, int* ran,
+                          Prec prec, const int* state, const int* active, const void* in, void* out, double* partial, int* ran,
                           hipStream_t st);
 hipError_t launch_true_residual(const OpDev& op, const Geom& g, const TileMap& tm, Elem elem, const int* state,
                                 int64_t rhs0, int nb, uint64_t seed, int mask, const void* x, void* r, void* p,
@@ -71,14 +76,27 @@ hipError_t launch_init(const Geom& g, Elem elem, int logB, int64_t rhs0, int nb,
                        void* r, void* p, hipStream_t st);
 // Workgroups of the update pass (= partials per right-hand side).
 unsigned update_grid(size_t n);
-hipError_t launch_update_r(size_t n, int logB, Elem elem, const CgScalars& sc, void* r, const void* Ap,
+// Workgroups of the reliable-update residual pass (= its partials per rhs).
+unsigned ru_grid(const TileMap& tm);
+hipError_t launch_update_r(size_t n, int logB, Elem elem, Prec prec, const CgScalars& sc, void* r, const void* Ap,
                            double* partial, hipStream_t st);
-hipError_t launch_direction(size_t n, int logB, Elem elem, const CgScalars& sc, void* x, const void* r, void* p,
-                            hipStream_t st);
+hipError_t launch_direction(size_t n, int logB, Elem elem, Prec prec, const CgScalars& sc, void* x, const void* r,
+                            void* p, hipStream_t st);
+// mixed precision (FP32 CG, FP64 reliable updates); mode 0 = flagged lanes, 1 = frozen lanes
+hipError_t launch_init_mixed(const Geom& g, Elem elem, int logB, int64_t rhs0, int nb, uint64_t seed, int mask,
+                             void* x64, void* xh, void* rh, void* ph, hipStream_t st);
+hipError_t launch_ru_accumulate(size_t n, int logB, Elem elem, const CgScalars& sc, int mode, void* x64, void* xh,
+                                hipStream_t st);
+hipError_t launch_ru_residual(const OpDev& od64, const Geom& g, const TileMap& tm, Elem elem, const CgScalars& sc,
+                              int mode, int64_t rhs0, int nb, uint64_t seed, int mask, const void* x64, void* rh,
+                              void* ph, double* partial, size_t pstride, hipStream_t st);
+hipError_t launch_reduce_ru(const CgScalars& sc, int B, const double* partial, int gx, size_t pstride, int mode,
+                            double tol2, int max_iter, int max_restarts, hipStream_t st);
+hipError_t launch_cast_links(size_t n, const double2* src, float2* dst, hipStream_t st);
 hipError_t launch_scalars_init(const CgScalars& sc, int nb, int B, double bnorm2, int start_frozen, hipStream_t st);
 hipError_t launch_reduce_alpha(const CgScalars& sc, int B, const double* partial, int gx, hipStream_t st);
 hipError_t launch_reduce_beta(const CgScalars& sc, int B, const double* partial, int gx, double tol2, int max_iter,
-                              hipStream_t st);
+                              double delta2, hipStream_t st);
 hipError_t launch_reduce_true(const CgScalars& sc, int B, const double* partial, int gx, size_t pstride, double tol2,
                               int max_iter, int max_restarts, hipStream_t st);
 hipError_t launch_hier_perm(const Geom& g, uint32_t* out, hipStream_t st);

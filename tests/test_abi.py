@@ -45,7 +45,9 @@ int main(void) {
   printf("tip_stats %zu\\n", sizeof(tip_stats));
   P(tip_operator, dims) P(tip_operator, kind) P(tip_operator, mass) P(tip_operator, links)
   P(tip_params, tol) P(tip_params, seed) P(tip_params, mask) P(tip_params, stream) P(tip_params, quadratures)
+  P(tip_params, reliable_delta)
   P(tip_stats, max_true_relres) P(tip_stats, stencil_launches) P(tip_stats, stencil_bytes)
+  P(tip_stats, reliable_updates) P(tip_stats, max_quad_err_bound)
   return 0;
 }
 """)

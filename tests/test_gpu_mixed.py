@@ -1,0 +1,98 @@
+"""Mixed precision (FP32 CG vectors and links, FP64 reliable updates and
+final true-residual test, variational quadrature): parity with the FP64
+oracle at the same 1e-10 bar as the FP64 path."""
+
+import numpy as np
+import pytest
+
+from conftest import gpu_binding, to_dev
+from oracle import exact
+from oracle.estimator import trace_inv_probe as oracle_trace
+from oracle.mask import MASK_Z2, MASK_Z4
+from oracle.operators import Operator as OracleOp
+from paper_1302_4018_amd import inputs
+
+pytestmark = pytest.mark.gpu
+REL = 1e-10
+
+
+def _rel(a, b):
+    return float(np.max(np.abs(np.asarray(a) - np.asarray(b)) / np.maximum(np.abs(np.asarray(b)), 1e-300)))
+
+
+def _ops(tip, dims, kind, mass=0.1, coupled=False, field=False, seed=0):
+    w = inputs.couplings(dims, seed=seed + 1) if coupled else None
+    mf = inputs.mass_field(dims, seed=seed + 2) if field else None
+    U = inputs.haar_links(dims, seed=seed + 3) if kind == 1 else None
+    orc = OracleOp(dims, kind, mass=mass, mass_field=mf, coupling=w, links=U)
+    gop = tip.Operator(dims, kind, mass=mass, mass_field=to_dev(mf), coupling=to_dev(w), links=to_dev(U))
+    return orc, gop
+
+
+@pytest.mark.parametrize("dims,kind,mass,coupled,n,tol,mask", [
+    ([16, 16], 0, 0.1, False, 256, 1e-12, MASK_Z2),          # C1, all vectors
+    ([32, 32, 32], 0, 0.05, True, 16, 1e-10, MASK_Z2),       # C2 subset
+    ([16, 16, 16, 16], 1, 0.1, False, 4, 1e-10, MASK_Z4),    # C3 subset
+    ([8, 8], 0, 0.3, True, 64, 1e-12, MASK_Z4),              # complex scalar path
+])
+def test_mixed_matches_oracle(dims, kind, mass, coupled, n, tol, mask):
+    tip = gpu_binding()
+    orc, gop = _ops(tip, dims, kind, mass=mass, coupled=coupled)
+    est, q, st = tip.trace_inv_probe(gop, n, tol, 4018, mask=mask, precision=tip.PREC_MIXED)
+    est_o, q_o, _ = oracle_trace(orc, n, tol, 4018, mask)
+    assert _rel(est, est_o) <= REL
+    assert _rel(q, q_o) <= REL
+    assert st["max_true_relres"] <= tol
+    assert st["reliable_updates"] > 0
+    # the reported bound covers the difference to the FP64 oracle's quadratures
+    assert np.all(np.abs(q - q_o) <= 2 * st["max_quad_err_bound"] + 1e-13 * np.abs(q_o))
+
+
+def test_mixed_exact_recovery_with_fields():
+    tip = gpu_binding()
+    orc, gop = _ops(tip, [4, 4, 4, 4], 1, coupled=True, field=True, seed=21)
+    est, q, st = tip.trace_inv_probe(gop, orc.V, 1e-12, 5, precision=tip.PREC_MIXED)
+    tr = exact.dense_trace_inverse(orc.dense())
+    assert abs(est[-1] - tr) <= 1e-10 * abs(tr)
+
+
+@pytest.mark.parametrize("delta", [0.5, 0.1, 0.01, 1e-3])
+def test_reliable_delta_only_changes_cost(delta):
+    tip = gpu_binding()
+    orc, gop = _ops(tip, [8, 8, 8, 8], 1, field=True, seed=4)
+    est64, q64, _ = tip.trace_inv_probe(gop, 8, 1e-10, 9)
+    est, q, st = tip.trace_inv_probe(gop, 8, 1e-10, 9, precision=tip.PREC_MIXED, reliable_delta=delta)
+    assert _rel(q, q64) <= REL
+    assert st["max_true_relres"] <= 1e-10
+
+
+def test_mixed_solve_probe_and_errors():
+    tip = gpu_binding()
+    orc, gop = _ops(tip, [8, 4, 4], 1, coupled=True, field=True, seed=7)
+    with tip.OpHandle(gop) as h:
+        x64, q64, _ = h.solve_probe(2, 1, 1e-12, 3)
+        x32, q32, st = h.solve_probe(2, 1, 1e-12, 3, precision=tip.PREC_MIXED)
+        assert np.linalg.norm((x32 - x64).cpu().numpy()) <= 1e-9 * np.linalg.norm(x64.cpu().numpy())
+        assert abs(q32 - q64) <= 1e-10 * abs(q64)
+        est, q, st = h.trace_inv_probe(4, 1e-12, 3, precision=tip.PREC_MIXED, max_iter=2, raise_on_error=False)
+        assert st["status"] == tip.TIP_ENOCONV
+        with pytest.raises(tip.TipError):
+            h.trace_inv_probe(4, 1e-12, 3, precision=7)
+        with pytest.raises(tip.TipError):
+            h.trace_inv_probe(4, 1e-12, 3, precision=tip.PREC_MIXED, reliable_delta=1.5)
+
+
+def test_mixed_full_size_matches_fp64():
+    """32^4 covariant workload (benchmark configuration): mixed and FP64
+    quadratures agree far below the solver tolerance."""
+    tip = gpu_binding()
+    dims = [32, 32, 32, 32]
+    U = inputs.haar_links(dims)
+    mf = inputs.mass_field(dims)
+    gop = tip.Operator(dims, 1, mass_field=to_dev(mf), links=to_dev(U))
+    with tip.OpHandle(gop) as h:
+        est64, q64, st64 = h.trace_inv_probe(8, 1e-10, 4018)
+        est32, q32, st32 = h.trace_inv_probe(8, 1e-10, 4018, precision=tip.PREC_MIXED)
+    assert _rel(q32, q64) <= REL
+    assert _rel(est32, est64) <= REL
+    assert st32["max_true_relres"] <= 1e-10
