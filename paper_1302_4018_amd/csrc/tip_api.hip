@@ -276,6 +276,12 @@ bool make_marchmap(const Geom& g, int logB, MarchMap* mm) {
   mm->Tc = Tc;
   mm->xcd_order = !env_off("TIP_TILE_ORDER") && mm->Q % kNumXcd == 0;
   mm->lds_links = !env_off("TIP_LDS_LINKS") && TS <= 64;
+  // the 4-D specialised kernel addresses every array with 32-bit byte
+  // offsets: 3 components x V x B x 16 bytes and the links must fit in 4 GiB
+  const double vec_bytes = 3.0 * g.V * (double)(1 << logB) * 16.0;
+  const double link_bytes = 4.0 * 9.0 * g.V * 16.0;
+  mm->spec4 = !env_off("TIP_SPEC4") && g.ndim == 4 && logB >= 2 && logB <= 5 && vec_bytes < 4294967296.0 &&
+              link_bytes < 4294967296.0;
   mm->grid = (uint32_t)mm->Q * (uint32_t)(nt / Tc);
   return true;
 }
@@ -359,7 +365,7 @@ struct Solver {
     pl.elem = (h->kind == TIP_KIND_COVARIANT || mask == TIP_MASK_Z4) ? Elem::kComplex : Elem::kReal;
     const size_t esz64 = pl.elem == Elem::kReal ? sizeof(double) : sizeof(double2);
     pl.esz = mixed ? esz64 / 2 : esz64;
-    // block size: a power of two <= 64; 16 shares each link among 16 solves;
+    // block size: a power of two <= 64; 32 shares each link among 32 solves;
     // small lattices take more right-hand sides per block to fill the GPU.
     // B depends only on the operator and rhs_block, so a right-hand side is
     // solved with the same arithmetic whichever block it falls in (resumed
@@ -368,7 +374,7 @@ struct Solver {
     if (p->rhs_block > 0) {
       while (B < p->rhs_block && B < 64) B *= 2;
     } else {
-      B = 16;
+      B = 32;
       while (B < 64 && V * B < (int64_t(1) << 18)) B *= 2;
     }
     // keep the CG vectors of a block within 32 GiB

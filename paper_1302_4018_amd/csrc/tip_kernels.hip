@@ -387,6 +387,168 @@ __global__ __launch_bounds__(kBlock) void k_stencil_march(Geom g, MarchMap mm, O
   }
 }
 
+// 4-D covariant marching stencil, specialised: the three marched-over
+// dimensions are unrolled, each thread's spatial neighbour offsets are fixed
+// for the whole march (its x, y, z never change), and every global access is
+// a kernel-argument base plus a 32-bit byte offset (the host checks that all
+// arrays fit), so the loop body is the 3x3 complex algebra plus little
+// address arithmetic.  Same arithmetic and summation order as stencil_site.
+template <class C>
+__device__ __forceinline__ C ld_off(const C* __restrict__ base, uint32_t byte_off) {
+  return *reinterpret_cast<const C*>(reinterpret_cast<const char*>(base) + byte_off);
+}
+template <class C>
+__device__ __forceinline__ void st_off(C* __restrict__ base, uint32_t byte_off, C v) {
+  *reinterpret_cast<C*>(reinterpret_cast<char*>(base) + byte_off) = v;
+}
+__device__ __forceinline__ double ld_offd(const double* __restrict__ base, uint32_t byte_off) {
+  return *reinterpret_cast<const double*>(reinterpret_cast<const char*>(base) + byte_off);
+}
+
+template <class C, int LOGB, bool HASW>
+__global__ __launch_bounds__(kBlock) void k_stencil_march4(Geom g, MarchMap mm, const C* __restrict__ U,
+                                                           const double* __restrict__ mass_field, double mass,
+                                                           const double* __restrict__ w,
+                                                           const int* __restrict__ state,
+                                                           const int* __restrict__ active, const C* __restrict__ in,
+                                                           C* __restrict__ out, double* __restrict__ partial,
+                                                           int* __restrict__ ran) {
+  constexpr int B = 1 << LOGB;
+  constexpr int TS = kBlock >> LOGB;
+  constexpr int SZ = (int)sizeof(C);
+  constexpr int NSLOT = 7;                        // 4 forward links + 3 backward (x, y, z)
+  if (active && *active == 0) return;
+  if (ran && blockIdx.x == 0 && threadIdx.x == 0) *ran = 1;
+  __shared__ double lds[4 * 64];
+  C* lds_links = reinterpret_cast<C*>(tip_dyn_lds);   // [7][9][TS]
+  const int j = threadIdx.x & (B - 1);
+  const int si = threadIdx.x >> LOGB;
+  uint32_t q, chunk;
+  {
+    const uint32_t b = blockIdx.x;
+    if (mm.xcd_order) {
+      const uint32_t per = (uint32_t)mm.Q / kNumXcd;
+      const uint32_t xcd = b % kNumXcd, slot = b / kNumXcd;
+      q = xcd * per + slot % per;
+      chunk = slot / per;
+    } else {
+      q = b % (uint32_t)mm.Q;
+      chunk = b / (uint32_t)mm.Q;
+    }
+  }
+  const uint32_t V = g.V;
+  const uint32_t V3 = mm.V3;
+  const uint32_t s3_first = q * (uint32_t)TS;
+  const uint32_t s3 = s3_first + (uint32_t)si;
+  const uint32_t cstride = (V << LOGB) * SZ;      // bytes between components
+  const uint32_t lstride = V * SZ;                // bytes between link elements
+  // fixed spatial neighbour offsets (in sites) of this thread
+  int32_t dfw[3], dbw[3];
+#pragma unroll
+  for (int mu = 0; mu < 3; ++mu) {
+    const uint32_t n = 1u << g.logn[mu], stride = 1u << g.shift[mu];
+    const uint32_t x = (s3 >> g.shift[mu]) & (n - 1u);
+    dfw[mu] = x == n - 1u ? -(int32_t)((n - 1u) * stride) : (int32_t)stride;
+    dbw[mu] = x == 0u ? (int32_t)((n - 1u) * stride) : -(int32_t)stride;
+  }
+  auto vec_off = [&](uint32_t site) -> uint32_t { return ((site << LOGB) + (uint32_t)j) * SZ; };
+  const bool live = !state || state[j] == kActive;
+  const int nt = mm.nt;
+  const int t0 = (int)chunk * mm.Tc;
+  double dot[1] = {0.0};
+  C carry[3], xc[3];
+  double wprev = 1.0;
+  if (live) {
+    const int tp = t0 == 0 ? nt - 1 : t0 - 1;
+    const uint32_t sp = s3 + V3 * (uint32_t)tp;
+    C u[9], xp[3];
+#pragma unroll
+    for (int e = 0; e < 9; ++e) u[e] = ld_off(U, (27u + (uint32_t)e) * lstride + sp * SZ);
+#pragma unroll
+    for (int c = 0; c < 3; ++c) xp[c] = ld_off(in, c * cstride + vec_off(sp));
+    mul_uh(u, xp, carry);
+    if constexpr (HASW) wprev = ld_offd(w, (3u * V + sp) * 8u);
+#pragma unroll
+    for (int c = 0; c < 3; ++c) xc[c] = ld_off(in, c * cstride + vec_off(s3 + V3 * (uint32_t)t0));
+  }
+  for (int t = t0; t < t0 + mm.Tc; ++t) {
+    const uint32_t s = s3 + V3 * (uint32_t)t;
+    // stage the tile's links: slots 0..3 forward U_mu(s), 4..6 backward U_mu(s - mu)
+    __syncthreads();
+    for (int it = threadIdx.x; it < NSLOT * 9 * TS; it += kBlock) {
+      const int site = it & (TS - 1);
+      const int es = it >> (8 - LOGB);
+      const int e = es % 9;
+      const int slot = es / 9;
+      const uint32_t ss = s3_first + (uint32_t)site + V3 * (uint32_t)t;
+      uint32_t sl = ss;
+      int mu = slot;
+      if (slot >= 4) {
+        mu = slot - 4;
+        const uint32_t n = 1u << g.logn[mu], stride = 1u << g.shift[mu];
+        sl = ((ss >> g.shift[mu]) & (n - 1u)) == 0u ? ss + (n - 1u) * stride : ss - stride;
+      }
+      lds_links[it] = ld_off(U, ((uint32_t)mu * 9u + (uint32_t)e) * lstride + sl * SZ);
+    }
+    __syncthreads();
+    if (!live) continue;
+    const uint32_t sn = s3 + V3 * (uint32_t)(t + 1 == nt ? 0 : t + 1);
+    C hop[3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) hop[c] = zero<C>();
+    double diag = mass_field ? ld_offd(mass_field, s * 8u) : mass;
+#pragma unroll
+    for (int mu = 0; mu < 3; ++mu) {
+      const uint32_t sf = (uint32_t)((int32_t)s + dfw[mu]);
+      const uint32_t sb = (uint32_t)((int32_t)s + dbw[mu]);
+      double wf = 1.0, wb = 1.0;
+      if constexpr (HASW) {
+        wf = ld_offd(w, ((uint32_t)mu * V + s) * 8u);
+        wb = ld_offd(w, ((uint32_t)mu * V + sb) * 8u);
+      }
+      diag += wf + wb;
+      C xn[3], h[3], u[9];
+#pragma unroll
+      for (int c = 0; c < 3; ++c) xn[c] = ld_off(in, c * cstride + vec_off(sf));
+#pragma unroll
+      for (int e = 0; e < 9; ++e) u[e] = lds_links[(mu * 9 + e) * TS + si];
+      mul_u(u, xn, h);
+      add_weighted<C, 3>(wf, h, hop);
+#pragma unroll
+      for (int c = 0; c < 3; ++c) xn[c] = ld_off(in, c * cstride + vec_off(sb));
+#pragma unroll
+      for (int e = 0; e < 9; ++e) u[e] = lds_links[((4 + mu) * 9 + e) * TS + si];
+      mul_uh(u, xn, h);
+      add_weighted<C, 3>(wb, h, hop);
+    }
+    double wt = 1.0;
+    if constexpr (HASW) wt = ld_offd(w, (3u * V + s) * 8u);
+    diag += wt + wprev;
+    C xn[3], h[3], u[9];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) xn[c] = ld_off(in, c * cstride + vec_off(sn));
+#pragma unroll
+    for (int e = 0; e < 9; ++e) u[e] = lds_links[(3 * 9 + e) * TS + si];
+    mul_u(u, xn, h);
+    add_weighted<C, 3>(wt, h, hop);
+    add_weighted<C, 3>(wprev, carry, hop);
+    mul_uh(u, xc, carry);
+    wprev = wt;
+    C y[3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+      y[c] = axpy(diag, xc[c], axpy(-1.0, hop[c], zero<C>()));
+      dot[0] += redot(xc[c], y[c]);
+      st_off(out, c * cstride + vec_off(s), y[c]);
+      xc[c] = xn[c];
+    }
+  }
+  if (partial) {
+    seg_sum<1>(dot, B, lds);
+    if ((int)threadIdx.x < B) partial[(size_t)threadIdx.x * gridDim.x + blockIdx.x] = dot[0];
+  }
+}
+
 // ---------------------------------------------------------------------------
 // CG vector passes over the flat block [ncomp][V][B]: element i has rhs i mod B.
 // ---------------------------------------------------------------------------
@@ -885,6 +1047,25 @@ hipError_t launch_stencil(const OpDev& od, const Geom& g, const TileMap& tm, con
     using Op = decltype(op);
     using T = typename Op::T;
     if constexpr (Op::NC == 3) {
+      if (mm && mm->lds_links && mm->spec4) {
+        const size_t lds = march_lds_bytes(g, *mm, prec);
+        const bool hw = od.coupling != nullptr;
+        auto go4 = [&](auto kern) {
+          kern<<<mm->grid, kBlock, lds, st>>>(g, *mm, op.U, od.mass_field, od.mass, od.coupling, state, active,
+                                              (const T*)in, (T*)out, partial, ran);
+        };
+        switch (mm->logB * 2 + (hw ? 1 : 0)) {
+          case 4: go4(k_stencil_march4<T, 2, false>); return;
+          case 5: go4(k_stencil_march4<T, 2, true>); return;
+          case 6: go4(k_stencil_march4<T, 3, false>); return;
+          case 7: go4(k_stencil_march4<T, 3, true>); return;
+          case 8: go4(k_stencil_march4<T, 4, false>); return;
+          case 9: go4(k_stencil_march4<T, 4, true>); return;
+          case 10: go4(k_stencil_march4<T, 5, false>); return;
+          case 11: go4(k_stencil_march4<T, 5, true>); return;
+          default: break;
+        }
+      }
       if (mm && mm->lds_links) {
         const size_t lds = march_lds_bytes(g, *mm, prec);
         auto go = [&](auto kern) {

@@ -60,6 +60,7 @@ struct MarchMap {
   int32_t nt, Tc;
   int32_t xcd_order;
   int32_t lds_links;           // stage links in LDS (covariant, TS <= 64)
+  int32_t spec4;               // 4-D specialised kernel (32-bit offsets fit, 4 <= B <= 32)
   uint32_t grid;               // Q * nt / Tc
 };
 
