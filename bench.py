@@ -32,6 +32,9 @@ HBM_PEAK_GBS = 8000.0
 METRIC = "probing-vector solves/sec (4D 32^4, rel.res 1e-10) + stencil HBM GB/s vs peak"
 KERNEL_SOURCES = ["paper_1302_4018_amd/csrc/tip_kernels.hip", "paper_1302_4018_amd/csrc/tip_device.h"]
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "stencil_traffic.json")
+# the dominant kernel: the 4-D marching stencil on FP64 complex 3-vectors
+STENCIL_FP64 = "k_stencil_march4<HIP_vector_type<double, 2u>"
+STENCIL_FP32 = "k_stencil_march4<HIP_vector_type<float, 2u>"
 
 
 def log(*a):
@@ -57,6 +60,42 @@ def measured_traffic(kernel_name):
     if t.get("source_sha256") != kernel_source_hash() or t.get("kernel") != kernel_name:
         return None
     return t.get("traffic_bytes_per_launch")
+
+
+def write_traffic(fetch_csv, write_csv, kernel_match, command):
+    """Derive HBM bytes per stencil launch from two rocprofv3 --pmc runs (FETCH_SIZE,
+    then WRITE_SIZE, each taken with --copy-calibration) and store them with the
+    hash of the kernel sources.  Each counter is scaled by what it reads for the
+    plain 1 GiB device copy of the same run (read 2^30 bytes, written 2^30 bytes)."""
+    import csv
+
+    def per_launch(path, counter):
+        copies, vals = [], []
+        with open(path) as f:
+            for row in csv.DictReader(f):
+                if row["Counter_Name"] != counter:
+                    continue
+                v = float(row["Counter_Value"])
+                if "copyBuffer" in row["Kernel_Name"]:
+                    copies.append(v)
+                elif kernel_match in row["Kernel_Name"]:
+                    vals.append(v)
+        if not vals or not copies:
+            raise SystemExit(f"{path}: no {counter} rows for {kernel_match!r} or for the calibration copy")
+        top = max(copies)
+        calib = [c for c in copies if c > 0.9 * top]
+        scale = float(1 << 30) / (1024.0 * sum(calib) / len(calib))
+        return sum(vals) / len(vals), scale, len(vals)
+
+    fk, fs, nf = per_launch(fetch_csv, "FETCH_SIZE")
+    wk, ws, nw = per_launch(write_csv, "WRITE_SIZE")
+    out = {"kernel": kernel_match, "source_sha256": kernel_source_hash(),
+           "fetch_kib_per_launch": fk, "fetch_scale": fs, "write_kib_per_launch": wk, "write_scale": ws,
+           "launches": [nf, nw], "traffic_bytes_per_launch": 1024.0 * (fk * fs + wk * ws), "command": command}
+    with open(TRAFFIC_FILE, "w") as f:
+        json.dump(out, f, indent=1)
+        f.write("\n")
+    print(json.dumps(out))
 
 
 def cpu_baseline(U, mf, seed, tol, iters_per_solve, n_iter):
@@ -113,7 +152,14 @@ def main():
     ap.add_argument("--precision", choices=["both", "fp64", "mixed"], default="both",
                     help="FP64 is the headline value; 'both' adds the mixed-precision solver beside it")
     ap.add_argument("--reliable-delta", type=float, default=0.0)
+    ap.add_argument("--traffic-from", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"),
+                    help="write the stencil's measured HBM bytes per launch from two rocprofv3 --pmc "
+                         "counter_collection.csv files, then exit (no GPU work)")
+    ap.add_argument("--traffic-command", default="", help="command recorded with --traffic-from")
     args = ap.parse_args()
+    if args.traffic_from:
+        write_traffic(args.traffic_from[0], args.traffic_from[1], STENCIL_FP64, args.traffic_command)
+        return
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -146,7 +192,7 @@ def main():
     log(f"operator handle (link repack) {repack_s * 1e3:.1f} ms")
 
     n_rhs = args.n_vectors * 3
-    kernel_names = {tip.PREC_FP64: "k_stencil_march<CovOp<double2>>", tip.PREC_MIXED: "k_stencil_march<CovOp<float2>>"}
+    kernel_names = {tip.PREC_FP64: STENCIL_FP64, tip.PREC_MIXED: STENCIL_FP32}
 
     def timed(precision):
         """W warmup calls, then K timed calls of the whole path at one precision."""

@@ -150,6 +150,25 @@ tip_status tip_op_destroy(tip_op_handle h);
 tip_status trace_inv_probe_op(tip_op_handle h, const tip_params* p,
                               double* estimates, tip_stats* stats);
 
+/* trace_inv_probe_op plus the gradient of the last estimate, T = (1/s) sum_{m<s} q_m
+ * at s = n_vectors, with respect to the operator's parameters, the probes held
+ * fixed.  Differentiating the Hutchinson estimator of Sec. 1 with
+ * d(A^-1) = -A^-1 (dA) A^-1, and using that A is Hermitian (the adjoint solves
+ * are the forward solves x_{m,c} = A^-1 b_{m,c}):
+ *   grad_mass[y]           = dT/dm(y)    = -(1/s) sum_{m<s,c} ||x_{m,c}(y)||^2
+ *   grad_coupling[mu][y]   = dT/dw_mu(y) = -(1/s) sum_{m<s,c} ||x_{m,c}(y) - U_mu(y) x_{m,c}(y+mu)||^2
+ * (U = 1 for the scalar operator).  This is the exact derivative of the
+ * estimate up to the solver tolerance; for s = V and no mask it is the exact
+ * -Tr(A^-1 (dA) A^-1).  With a NULL mass_field (coupling) the entries are the
+ * derivatives with respect to a per-site mass (coupling) at the uniform value.
+ * grad_mass: DEVICE float64 [V] or NULL; grad_coupling: DEVICE float64 [ndim][V]
+ * or NULL; not both NULL.  Both are overwritten; on a status other than TIP_OK
+ * their contents are unspecified.  p->m_begin must be 0 (TIP_EINVAL otherwise).
+ * The sums over probes are taken block by block in a fixed order, so results
+ * are reproducible run to run. */
+tip_status trace_inv_probe_grad(tip_op_handle h, const tip_params* p, double* estimates,
+                                double* grad_mass, double* grad_coupling, tip_stats* stats);
+
 /* One solve A x = b_{m,comp} on a prepared handle, for checks of the solver
  * and for callers that need the solution itself.  Uses tol, max_iter, seed,
  * mask, precision and stream of p; its probe-count fields are ignored.

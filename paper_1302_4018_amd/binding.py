@@ -56,6 +56,8 @@ def _load():
         "tip_op_create": (ctypes.c_int, [P(tip_operator), ctypes.c_void_p, P(ctypes.c_void_p)]),
         "tip_op_destroy": (ctypes.c_int, [ctypes.c_void_p]),
         "trace_inv_probe_op": (ctypes.c_int, [ctypes.c_void_p, P(tip_params), P(ctypes.c_double), P(tip_stats)]),
+        "trace_inv_probe_grad": (ctypes.c_int, [ctypes.c_void_p, P(tip_params), P(ctypes.c_double),
+                                                ctypes.c_void_p, ctypes.c_void_p, P(tip_stats)]),
         "tip_solve_probe": (ctypes.c_int, [ctypes.c_void_p, P(tip_params), ctypes.c_int64, ctypes.c_int32,
                                            ctypes.c_void_p, P(ctypes.c_double), P(tip_stats)]),
         "tip_apply_operator": (ctypes.c_int, [P(tip_operator), ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p,
@@ -214,6 +216,25 @@ class OpHandle:
         return _run(lib.trace_inv_probe_op, self._h, n_vectors, tol, seed, mask, max_iter, rhs_block, m_begin,
                     quadratures, stream, raise_on_error, precision, reliable_delta)
 
+    def trace_inv_probe_grad(self, n_vectors, tol, seed, mask=MASK_DEFAULT, max_iter=0, rhs_block=0, stream=None,
+                             precision=PREC_FP64, reliable_delta=0.0, mass=True, coupling=True):
+        """Estimates, quadratures, dT/dm [V] and dT/dw [ndim, V] of the last estimate
+        (float64 tensors on the GPU, or None where not asked for), stats."""
+        import torch
+        op = self.op
+        gm = torch.empty(op.V, dtype=torch.float64, device="cuda") if mass else None
+        gw = torch.empty((len(op.dims), op.V), dtype=torch.float64, device="cuda") if coupling else None
+        nck = tip_num_checkpoints(n_vectors)
+        est = np.zeros((nck, 2), dtype=np.float64)
+        q = np.zeros((int(n_vectors), 2), dtype=np.float64)
+        p = _params(n_vectors, tol, seed, mask, max_iter, rhs_block, 0, q, stream, precision, reliable_delta)
+        st = tip_stats()
+        _check(lib.trace_inv_probe_grad(self._h, ctypes.byref(p), est.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                        _ptr(gm) if gm is not None else None,
+                                        _ptr(gw) if gw is not None else None, ctypes.byref(st)),
+               "trace_inv_probe_grad")
+        return est[:, 0] + 1j * est[:, 1], q[:, 0] + 1j * q[:, 1], gm, gw, _stats_dict(st)
+
     def solve_probe(self, m, comp, tol, seed, mask=MASK_DEFAULT, max_iter=0, stream=None, precision=PREC_FP64,
                     reliable_delta=0.0):
         """x = A^-1 b_{m,comp} (torch tensor on the GPU), q = b^H x, stats."""
@@ -250,6 +271,10 @@ class OpHandle:
 
 def trace_inv_probe_op(handle, *args, **kwargs):
     return handle.trace_inv_probe(*args, **kwargs)
+
+
+def trace_inv_probe_grad(handle, *args, **kwargs):
+    return handle.trace_inv_probe_grad(*args, **kwargs)
 
 
 def tip_solve_probe(handle, *args, **kwargs):

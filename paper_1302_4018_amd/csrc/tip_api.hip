@@ -594,7 +594,15 @@ tip_status tip_op_destroy(tip_op_handle h) {
   return TIP_OK;
 }
 
-tip_status trace_inv_probe_op(tip_op_handle h, const tip_params* p, double* estimates, tip_stats* stats) {
+}  // extern "C"
+
+namespace {
+
+// The probing run behind trace_inv_probe_op and trace_inv_probe_grad; grad_mass
+// and grad_coupling (device, or NULL) receive the gradient of the estimate at
+// s = n_vectors, accumulated block by block from the solutions in the workspace.
+tip_status run_probe(tip_op_handle h, const tip_params* p, double* estimates, double* grad_mass,
+                     double* grad_coupling, tip_stats* stats) {
   const auto t_start = std::chrono::steady_clock::now();
   if (!h) return fail(TIP_EINVAL, "handle is NULL");
   if (!estimates) return fail(TIP_EINVAL, "estimates is NULL");
@@ -602,12 +610,17 @@ tip_status trace_inv_probe_op(tip_op_handle h, const tip_params* p, double* esti
   tip_status s = check_params(h, p, &mask);
   if (s != TIP_OK) return s;
   if (p->m_begin > 0 && !p->quadratures) return fail(TIP_EINVAL, "m_begin > 0 needs the earlier quadratures");
+  const bool want_grad = grad_mass || grad_coupling;
+  if (want_grad && p->m_begin != 0) return fail(TIP_EINVAL, "the gradient needs every solve: m_begin must be 0");
   const int ncomp = h->geom.ncomp;
   const int64_t probes = p->n_vectors - p->m_begin;
   const int64_t n_rhs = probes * ncomp;
   Solver sv;
   s = sv.setup(h, p, mask);
   if (s != TIP_OK) return s;
+  const size_t V = h->geom.V;
+  if (grad_mass) TIP_HIP(launch_fill(V, grad_mass, 0.0, sv.st));
+  if (grad_coupling) TIP_HIP(launch_fill((size_t)h->geom.ndim * V, grad_coupling, 0.0, sv.st));
 
   std::vector<double> qre((size_t)n_rhs, 0.0), qim((size_t)n_rhs, 0.0), rhs_relres((size_t)n_rhs, 0.0);
   std::vector<int> rhs_state((size_t)n_rhs, kPadding), rhs_iters((size_t)n_rhs, 0);
@@ -617,6 +630,8 @@ tip_status trace_inv_probe_op(tip_op_handle h, const tip_params* p, double* esti
     const int nb = (int)std::min<int64_t>(sv.pl.B, n_rhs - blk0);
     s = sv.solve_block(p->m_begin * ncomp + blk0, nb);
     if (s != TIP_OK) return s;
+    if (want_grad)
+      TIP_HIP(launch_grad_accum(sv.od64, h->geom, sv.pl.elem, sv.pl.logB, nb, sv.X, grad_mass, grad_coupling, sv.st));
     for (int j = 0; j < nb; ++j) {
       const size_t k = (size_t)(blk0 + j);
       qre[k] = sv.h_q[2 * j];
@@ -694,12 +709,32 @@ tip_status trace_inv_probe_op(tip_op_handle h, const tip_params* p, double* esti
     sv.fill_stats(stats);
     stats->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t_start).count();
   }
+  if (want_grad && first_bad_rhs < 0) {
+    const double f = -1.0 / (double)n;
+    if (grad_mass) TIP_HIP(launch_scale(V, grad_mass, f, sv.st));
+    if (grad_coupling) TIP_HIP(launch_scale((size_t)h->geom.ndim * V, grad_coupling, f, sv.st));
+    TIP_HIP(hipStreamSynchronize(sv.st));
+  }
   if (first_bad_rhs >= 0) {
     const int64_t bad_m = p->m_begin + first_bad_rhs / ncomp;
     return fail(bad_status, "solve of probe %lld component %d %s", (long long)bad_m, (int)(first_bad_rhs % ncomp),
                 bad_status == TIP_EBREAKDOWN ? "broke down (p^H A p <= 0)" : "did not converge within max_iter");
   }
   return TIP_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+tip_status trace_inv_probe_op(tip_op_handle h, const tip_params* p, double* estimates, tip_stats* stats) {
+  return run_probe(h, p, estimates, nullptr, nullptr, stats);
+}
+
+tip_status trace_inv_probe_grad(tip_op_handle h, const tip_params* p, double* estimates, double* grad_mass,
+                                double* grad_coupling, tip_stats* stats) {
+  if (!grad_mass && !grad_coupling) return fail(TIP_EINVAL, "grad_mass and grad_coupling are both NULL");
+  return run_probe(h, p, estimates, grad_mass, grad_coupling, stats);
 }
 
 tip_status tip_solve_probe(tip_op_handle h, const tip_params* p, int64_t m, int32_t comp, double* x_out,

@@ -947,6 +947,72 @@ __global__ __launch_bounds__(kBlock) void k_cast_links(size_t n, const double2* 
 }
 
 // ---------------------------------------------------------------------------
+// Gradient of the estimate with respect to the mass field and the couplings.
+// T = (1/s) sum_j b_j^H A^-1 b_j, so with the probes fixed
+// dT/dtheta = -(1/s) sum_j b_j^H A^-1 (dA/dtheta) A^-1 b_j = -(1/s) sum_j x_j^H (dA/dtheta) x_j
+// (A Hermitian: the adjoint solves are the forward ones).  dA/dm(x) is the
+// identity on site x; dA/dw_mu(x) is the edge Laplacian L_e of e = (x, x+mu),
+// whose quadratic form is ||x(x) - U_mu(x) x(x+mu)||^2.  One pass per block
+// adds the raw sums sum_j x_j^H (dA/dtheta) x_j; the B lanes of a site are
+// summed with shuffles and written by one lane, so there are no atomics.
+// ---------------------------------------------------------------------------
+
+template <class Op>
+__global__ __launch_bounds__(kBlock) void k_grad_accum(Geom g, int logB, int nb, Op op,
+                                                       const typename Op::T* __restrict__ x,
+                                                       double* __restrict__ gm, double* __restrict__ gw) {
+  using T = typename Op::T;
+  constexpr int NC = Op::NC;
+  const int B = 1 << logB;
+  const int j = threadIdx.x & (B - 1);
+  const uint32_t s = blockIdx.x * (kBlock >> logB) + (threadIdx.x >> logB);
+  if (s >= g.V) return;                                  // whole site groups leave together
+  const size_t V = g.V;
+  T xs[NC];
+  load_vec<T, NC>(x, V, logB, s, j, xs);
+  const bool use = j < nb;
+  double vm = 0.0;
+#pragma unroll
+  for (int c = 0; c < NC; ++c) vm += norm2(xs[c]);
+  double vw[kMaxDim] = {0.0, 0.0, 0.0, 0.0};
+  if (gw) {
+    for (int mu = 0; mu < g.ndim; ++mu) {
+      T xf[NC], h[NC];
+      load_vec<T, NC>(x, V, logB, nbr_fwd(s, g, mu), j, xf);
+      hop_term(op, V, mu, s, false, xf, h);          // U_mu(s) x(s+mu)
+      double acc = 0.0;
+#pragma unroll
+      for (int c = 0; c < NC; ++c) acc += norm2(axpy(-1.0, h[c], xs[c]));
+      vw[mu] = acc;
+    }
+  }
+  if (!use) {
+    vm = 0.0;
+    for (int mu = 0; mu < kMaxDim; ++mu) vw[mu] = 0.0;
+  }
+  for (int off = B >> 1; off > 0; off >>= 1) {
+    vm += __shfl_down(vm, off, 64);
+#pragma unroll
+    for (int mu = 0; mu < kMaxDim; ++mu) vw[mu] += __shfl_down(vw[mu], off, 64);
+  }
+  if (j == 0) {
+    if (gm) gm[s] += vm;
+    if (gw)
+      for (int mu = 0; mu < g.ndim; ++mu) gw[(size_t)mu * V + s] += vw[mu];
+  }
+}
+
+__global__ __launch_bounds__(kBlock) void k_scale(size_t n, double* __restrict__ a, double f) {
+  const size_t i = (size_t)blockIdx.x * kBlock + threadIdx.x;
+  if (i < n) a[i] *= f;
+}
+
+__global__ __launch_bounds__(kBlock) void k_fill(size_t n, double* __restrict__ a, double v) {
+  const size_t i = (size_t)blockIdx.x * kBlock + threadIdx.x;
+  if (i < n) a[i] = v;
+}
+
+// ---------------------------------------------------------------------------
 // Generator entry points and layout conversion.
 // ---------------------------------------------------------------------------
 
@@ -1179,6 +1245,26 @@ hipError_t launch_ru_residual(const OpDev& od64, const Geom& g, const TileMap& t
 hipError_t launch_reduce_ru(const CgScalars& sc, int B, const double* partial, int gx, size_t pstride, int mode,
                             double tol2, int max_iter, int max_restarts, hipStream_t st) {
   k_reduce_ru<<<B, kBlock, 0, st>>>(sc, partial, gx, pstride, mode, tol2, max_iter, max_restarts);
+  return hipGetLastError();
+}
+
+hipError_t launch_grad_accum(const OpDev& od64, const Geom& g, Elem elem, int logB, int nb, const void* x, double* gm,
+                             double* gw, hipStream_t st) {
+  const unsigned grid = cdiv(g.V, (size_t)(kBlock >> logB));
+  return dispatch64(od64, elem, [&](auto op) {
+    using Op = decltype(op);
+    using T = typename Op::T;
+    k_grad_accum<Op><<<grid, kBlock, 0, st>>>(g, logB, nb, op, (const T*)x, gm, gw);
+  });
+}
+
+hipError_t launch_scale(size_t n, double* a, double f, hipStream_t st) {
+  k_scale<<<cdiv(n, kBlock), kBlock, 0, st>>>(n, a, f);
+  return hipGetLastError();
+}
+
+hipError_t launch_fill(size_t n, double* a, double v, hipStream_t st) {
+  k_fill<<<cdiv(n, kBlock), kBlock, 0, st>>>(n, a, v);
   return hipGetLastError();
 }
 

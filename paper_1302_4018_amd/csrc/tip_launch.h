@@ -94,6 +94,11 @@ hipError_t launch_ru_residual(const OpDev& od64, const Geom& g, const TileMap& t
 hipError_t launch_reduce_ru(const CgScalars& sc, int B, const double* partial, int gx, size_t pstride, int mode,
                             double tol2, int max_iter, int max_restarts, hipStream_t st);
 hipError_t launch_cast_links(size_t n, const double2* src, float2* dst, hipStream_t st);
+// gradient: gm[s] += sum_j ||x_j(s)||^2, gw[mu][s] += sum_j ||x_j(s) - U_mu(s) x_j(s+mu)||^2 over lanes j < nb
+hipError_t launch_grad_accum(const OpDev& od64, const Geom& g, Elem elem, int logB, int nb, const void* x, double* gm,
+                             double* gw, hipStream_t st);
+hipError_t launch_scale(size_t n, double* a, double f, hipStream_t st);
+hipError_t launch_fill(size_t n, double* a, double v, hipStream_t st);
 hipError_t launch_scalars_init(const CgScalars& sc, int nb, int B, double bnorm2, int start_frozen, hipStream_t st);
 hipError_t launch_reduce_alpha(const CgScalars& sc, int B, const double* partial, int gx, hipStream_t st);
 hipError_t launch_reduce_beta(const CgScalars& sc, int B, const double* partial, int gx, double tol2, int max_iter,

@@ -1,0 +1,130 @@
+"""Pins for the oracle's gradient of the trace estimate with respect to the
+mass field and the edge couplings.
+
+* Closed forms on constant-coefficient tori: the Fourier modes diagonalise
+  A = m + sum_mu D_mu with D_mu(k) = 4 sin^2(pi k_mu / n_mu), so
+  dTr(A^-1)/dm(y) = -(1/V) sum_k lambda(k)^-2 at every site and
+  dTr(A^-1)/dw_mu(y) = -(1/V) sum_k D_mu(k) lambda(k)^-2 on every mu-edge.
+* Gauge covariance: pure-gauge links give the scalar values times 3.
+* Homogeneity: A is linear in (m, w), T_s is homogeneous of degree -1, so
+  sum m dT/dm + sum w dT/dw = -T_s for every s (Euler).
+* Central finite differences of Tr(A^-1) (dense inverse) and of T_s
+  (partial-sum identity with the perturbed dense inverse, no solve).
+* Exact recovery: at s = V the probe gradient equals the dense one.
+"""
+
+import numpy as np
+import pytest
+
+from oracle import exact, mask
+from oracle.gradient import dense_trace_inverse_grad, trace_inv_probe_grad
+from oracle.hierperm import hier_perm
+from oracle.lattice import total_levels, volume
+from oracle.operators import Operator
+from paper_1302_4018_amd import inputs
+
+
+def _free_closed_forms(dims, m):
+    """(-(1/V) sum lambda^-2, [-(1/V) sum D_mu lambda^-2 for each mu])."""
+    grids = np.meshgrid(*[np.arange(n) for n in dims], indexing="ij")
+    D = [4.0 * np.sin(np.pi * k / n) ** 2 for k, n in zip(grids, dims)]
+    lam = m + sum(D)
+    V = volume(dims)
+    return -np.sum(lam ** -2.0) / V, [-np.sum(d / lam ** 2) / V for d in D]
+
+
+@pytest.mark.parametrize("dims,m", [([8, 8], 0.1), ([4, 8, 2], 0.3), ([16], 0.05)])
+def test_dense_grad_free_closed_form(dims, m):
+    op = Operator(dims, 0, mass=m)
+    gm, gw = dense_trace_inverse_grad(op)
+    cm, cw = _free_closed_forms(dims, m)
+    assert np.allclose(gm, cm, rtol=1e-11, atol=0)
+    for mu in range(len(dims)):
+        assert np.allclose(gw[mu], cw[mu], rtol=1e-11, atol=0)
+    # the per-site values sum to -Tr(A^-2)
+    assert abs(gm.sum() + exact.free_trace_power(dims, m, -2)) <= 1e-11 * abs(gm.sum())
+
+
+def test_dense_grad_pure_gauge_is_three_scalar_copies():
+    dims = [2, 4, 2]
+    g = inputs.random_site_unitaries(volume(dims), seed=70)
+    U = exact.pure_gauge_links(g, dims)
+    gm_c, gw_c = dense_trace_inverse_grad(Operator(dims, 1, mass=0.2, links=U))
+    gm_s, gw_s = dense_trace_inverse_grad(Operator(dims, 0, mass=0.2))
+    assert np.allclose(gm_c, 3 * gm_s, rtol=1e-11, atol=0)
+    assert np.allclose(gw_c, 3 * gw_s, rtol=1e-11, atol=0)
+
+
+def _fields(dims, kind, seed):
+    mf = inputs.mass_field(dims, m0=0.3, sigma=0.05, seed=seed)
+    w = inputs.couplings(dims, seed=seed + 1)
+    U = inputs.haar_links(dims, seed=seed + 2) if kind == 1 else None
+    return mf, w, U
+
+
+@pytest.mark.parametrize("kind", [0, 1])
+def test_dense_grad_euler_and_finite_differences(kind):
+    dims = [2, 4, 2]
+    mf, w, U = _fields(dims, kind, 80)
+    op = Operator(dims, kind, mass_field=mf, coupling=w, links=U)
+    gm, gw = dense_trace_inverse_grad(op)
+    tr = exact.dense_trace_inverse(op.dense()).real
+    assert abs(np.dot(mf, gm) + np.sum(w * gw) + tr) <= 1e-12 * tr
+    h = 1e-4
+    for y in [0, 5, 13]:
+        d = np.zeros_like(mf)
+        d[y] = h
+        tp = exact.dense_trace_inverse(Operator(dims, kind, mass_field=mf + d, coupling=w, links=U).dense()).real
+        tm = exact.dense_trace_inverse(Operator(dims, kind, mass_field=mf - d, coupling=w, links=U).dense()).real
+        assert abs((tp - tm) / (2 * h) - gm[y]) <= 1e-7 * abs(gm[y])
+    for mu, y in [(0, 3), (1, 9), (2, 14)]:
+        d = np.zeros_like(w)
+        d[mu, y] = h
+        tp = exact.dense_trace_inverse(Operator(dims, kind, mass_field=mf, coupling=w + d, links=U).dense()).real
+        tm = exact.dense_trace_inverse(Operator(dims, kind, mass_field=mf, coupling=w - d, links=U).dense()).real
+        assert abs((tp - tm) / (2 * h) - gw[mu, y]) <= 1e-7 * abs(gw[mu, y])
+
+
+@pytest.mark.parametrize("dims,kind,mk", [([4, 4], 0, mask.MASK_Z2), ([2, 2, 4, 2], 1, mask.MASK_Z4),
+                                          ([2, 4, 2], 1, mask.MASK_NONE)])
+def test_probe_grad_exact_at_s_equals_V(dims, kind, mk):
+    mf, w, U = _fields(dims, kind, 90)
+    op = Operator(dims, kind, mass_field=mf, coupling=w, links=U)
+    T, gm, gw, _ = trace_inv_probe_grad(op, op.V, 1e-13, 11, mk)
+    dm, dw = dense_trace_inverse_grad(op)
+    assert abs(T - exact.dense_trace_inverse(op.dense())) <= 1e-10 * abs(T)
+    assert np.max(np.abs(gm - dm)) <= 1e-9 * np.max(np.abs(dm))
+    assert np.max(np.abs(gw - dw)) <= 1e-9 * np.max(np.abs(dw))
+
+
+def _partial_sum_T(op, t, seed, mk):
+    V = op.V
+    z0 = np.stack([mask.mask_values(seed, V, op.ncomp, c, mk) for c in range(op.ncomp)])
+    Ainv = np.linalg.inv(op.dense())
+    return exact.partial_sum_estimate(Ainv, hier_perm(op.dims), total_levels(op.dims), t, op.ncomp, z0).real
+
+
+@pytest.mark.parametrize("kind,mk", [(0, mask.MASK_Z2), (1, mask.MASK_Z4)])
+def test_probe_grad_finite_differences_below_V(kind, mk):
+    """s = 4 < V: the probe gradient is the derivative of T_4 with the probes fixed."""
+    dims = [2, 4, 4]
+    seed = 23
+    mf, w, U = _fields(dims, kind, 100)
+    op = Operator(dims, kind, mass_field=mf, coupling=w, links=U)
+    T, gm, gw, _ = trace_inv_probe_grad(op, 4, 1e-13, seed, mk)
+    assert abs(T.real - _partial_sum_T(op, 2, seed, mk)) <= 1e-10 * abs(T)
+    # Euler: sum m dT/dm + sum w dT/dw = -T_s
+    assert abs(np.dot(mf, gm) + np.sum(w * gw) + T.real) <= 1e-10 * abs(T)
+    h = 1e-4
+    for y in [1, 7, 30]:
+        d = np.zeros_like(mf)
+        d[y] = h
+        tp = _partial_sum_T(Operator(dims, kind, mass_field=mf + d, coupling=w, links=U), 2, seed, mk)
+        tm = _partial_sum_T(Operator(dims, kind, mass_field=mf - d, coupling=w, links=U), 2, seed, mk)
+        assert abs((tp - tm) / (2 * h) - gm[y]) <= 1e-6 * np.max(np.abs(gm))
+    for mu, y in [(0, 2), (1, 17), (2, 31)]:
+        d = np.zeros_like(w)
+        d[mu, y] = h
+        tp = _partial_sum_T(Operator(dims, kind, mass_field=mf, coupling=w + d, links=U), 2, seed, mk)
+        tm = _partial_sum_T(Operator(dims, kind, mass_field=mf, coupling=w - d, links=U), 2, seed, mk)
+        assert abs((tp - tm) / (2 * h) - gw[mu, y]) <= 1e-6 * np.max(np.abs(gw))
