@@ -254,6 +254,76 @@ TileMap make_tilemap(const Geom& g, int logB) {
 
 // Marching stencil map, or false when the geometry does not fit it
 // (TIP_MARCH=0 turns it off; TIP_MARCH_TC fixes the chunk length).
+bool env_on(const char* name) {
+  const char* e = std::getenv(name);
+  return e && std::atoi(e) != 0;
+}
+
+// Parameters of tile order 2 (see march_tile) for a 4-D lattice marched
+// along x4: split the (x2, x3) rows over the 8 XCDs into regions as square as
+// the sides allow, then pick the round (b2 x b3 rows of n1/TS tiles each) of at
+// most `round_tiles` tiles that leaves the fewest x2 / x3 neighbour rows
+// outside it.  TIP_MARCH_ORDER="g2,b2,b3" overrides the choice.
+bool plan_block_order(const Geom& g, int TS, MarchMap* mm) {
+  const int n1 = 1 << g.logn[0], n2 = 1 << g.logn[1], n3 = 1 << g.logn[2];
+  if (TS > n1 || n1 % TS != 0) return false;
+  const int n1t = n1 / TS;
+  int round_tiles = 128;
+  if (const char* e = std::getenv("TIP_ROUND_TILES")) round_tiles = std::max(1, std::atoi(e));
+  int best_g2 = -1;
+  double best_shape = 1e30;
+  for (int g2 = 1; g2 <= kNumXcd; g2 *= 2) {
+    const int g3 = kNumXcd / g2;
+    if (g2 > n2 || g3 > n3) continue;
+    const double shape = std::fabs(std::log2((double)(n2 / g2) / (double)(n3 / g3)));
+    if (shape <= best_shape) best_shape = shape, best_g2 = g2;   // ties: longer regions along x3
+  }
+  if (best_g2 < 0) return false;
+  int g2 = best_g2, b2 = 0, b3 = 0;
+  int r2 = n2 / g2, r3 = n3 / (kNumXcd / g2);
+  double best_cost = 1e30;
+  for (int c2 = 1; c2 <= r2; c2 *= 2)
+    for (int c3 = 1; c3 <= r3; c3 *= 2) {
+      if (n1t * c2 * c3 > round_tiles) continue;
+      const double cost = (c2 < n2 ? 2.0 / c2 : 0.0) + (c3 < n3 ? 2.0 / c3 : 0.0);
+      if (cost < best_cost || (cost == best_cost && c2 * c3 > b2 * b3)) best_cost = cost, b2 = c2, b3 = c3;
+    }
+  if (const char* e = std::getenv("TIP_MARCH_ORDER")) {
+    int a = 0, b = 0, c = 0;
+    if (std::sscanf(e, "%d,%d,%d", &a, &b, &c) == 3 && a >= 1 && a <= kNumXcd && (a & (a - 1)) == 0 && a <= n2 &&
+        kNumXcd / a <= n3) {
+      const int rr2 = n2 / a, rr3 = n3 / (kNumXcd / a);
+      if (b >= 1 && c >= 1 && rr2 % b == 0 && rr3 % c == 0) g2 = a, r2 = rr2, r3 = rr3, b2 = b, b3 = c;
+    }
+  }
+  if (b2 < 1 || b3 < 1) return false;
+  mm->ord_n1t = n1t;
+  mm->ord_n2 = n2;
+  mm->ord_g2 = g2;
+  mm->ord_r2 = r2;
+  mm->ord_r3 = r3;
+  mm->ord_b2 = b2;
+  mm->ord_b3 = b3;
+  return true;
+}
+
+// Every workgroup of the grid must get a distinct (tile, chunk) in range;
+// checked on the host before order 2 is used (grids up to 2^22 workgroups).
+bool block_order_is_permutation(const MarchMap& mm) {
+  const uint32_t nchunk = mm.grid / (uint32_t)mm.Q;
+  if (mm.grid > (1u << 22) || mm.grid % kNumXcd != 0) return false;
+  std::vector<unsigned char> seen(mm.grid, 0);
+  for (uint32_t b = 0; b < mm.grid; ++b) {
+    uint32_t q = 0, chunk = 0;
+    march_tile(mm, b, q, chunk);
+    if (q >= (uint32_t)mm.Q || chunk >= nchunk) return false;
+    unsigned char& v = seen[(size_t)chunk * mm.Q + q];
+    if (v) return false;
+    v = 1;
+  }
+  return true;
+}
+
 bool make_marchmap(const Geom& g, int logB, MarchMap* mm) {
   if (env_off("TIP_MARCH") || g.ndim < 2) return false;
   const int nt = 1 << g.logn[g.ndim - 1];
@@ -275,7 +345,15 @@ bool make_marchmap(const Geom& g, int logB, MarchMap* mm) {
   }
   mm->Tc = Tc;
   mm->xcd_order = !env_off("TIP_TILE_ORDER") && mm->Q % kNumXcd == 0;
+  if (mm->xcd_order && g.ndim == 4 && plan_block_order(g, TS, mm)) mm->xcd_order = 2;
+  if (const char* e = std::getenv("TIP_TILE_ORDER")) {
+    if (std::atoi(e) == 1 && mm->xcd_order == 2) mm->xcd_order = 1;
+  }
   mm->lds_links = !env_off("TIP_LDS_LINKS") && TS <= 64;
+  mm->wgs_per_cu64 = 0;
+  mm->wgs_per_cu32 = 0;
+  if (const char* e = std::getenv("TIP_WGS_PER_CU64")) mm->wgs_per_cu64 = std::atoi(e);
+  if (const char* e = std::getenv("TIP_WGS_PER_CU32")) mm->wgs_per_cu32 = std::atoi(e);
   // the 4-D specialised kernel addresses every array with 32-bit byte
   // offsets: 3 components x V x B x 16 bytes and the links must fit in 4 GiB
   const double vec_bytes = 3.0 * g.V * (double)(1 << logB) * 16.0;
@@ -283,6 +361,7 @@ bool make_marchmap(const Geom& g, int logB, MarchMap* mm) {
   mm->spec4 = !env_off("TIP_SPEC4") && g.ndim == 4 && logB >= 2 && logB <= 5 && vec_bytes < 4294967296.0 &&
               link_bytes < 4294967296.0;
   mm->grid = (uint32_t)mm->Q * (uint32_t)(nt / Tc);
+  if (mm->xcd_order == 2 && !block_order_is_permutation(*mm)) mm->xcd_order = 1;
   return true;
 }
 

@@ -27,6 +27,7 @@ struct Geom {
   int32_t shift[kMaxDim];    // log2 of the site-index stride of dimension j
 };
 
+constexpr int kLdsPerCu = 160 * 1024;   // gfx950 LDS per CU
 constexpr int kNumXcd = 8;   // MI355X: 8 XCDs, each with its own L2
 
 __device__ __forceinline__ uint32_t coord(uint32_t s, const Geom& g, int mu) {

@@ -263,18 +263,7 @@ __global__ __launch_bounds__(kBlock) void k_stencil_march(Geom g, MarchMap mm, O
   const int j = threadIdx.x & (B - 1);
   const int si = threadIdx.x >> logB;
   uint32_t q, chunk;
-  {
-    const uint32_t b = blockIdx.x;
-    if (mm.xcd_order) {
-      const uint32_t per = (uint32_t)mm.Q / kNumXcd;      // spatial tiles per XCD
-      const uint32_t xcd = b % kNumXcd, slot = b / kNumXcd;
-      q = xcd * per + slot % per;
-      chunk = slot / per;
-    } else {
-      q = b % (uint32_t)mm.Q;
-      chunk = b / (uint32_t)mm.Q;
-    }
-  }
+  march_tile(mm, blockIdx.x, q, chunk);
   const uint32_t s3_first = q * (uint32_t)TS;
   const uint32_t s3 = s3_first + (uint32_t)si;
   const size_t V = g.V;
@@ -397,16 +386,29 @@ template <class C>
 __device__ __forceinline__ C ld_off(const C* __restrict__ base, uint32_t byte_off) {
   return *reinterpret_cast<const C*>(reinterpret_cast<const char*>(base) + byte_off);
 }
+#ifndef TIP_STENCIL_NT_STORE
+#define TIP_STENCIL_NT_STORE 1
+#endif
 template <class C>
 __device__ __forceinline__ void st_off(C* __restrict__ base, uint32_t byte_off, C v) {
-  *reinterpret_cast<C*>(reinterpret_cast<char*>(base) + byte_off) = v;
+  if constexpr (TIP_STENCIL_NT_STORE) {
+    // streaming store: the written line is not kept in L2 for reuse
+    auto* d = reinterpret_cast<decltype(v.x)*>(reinterpret_cast<char*>(base) + byte_off);
+    __builtin_nontemporal_store(v.x, d);
+    __builtin_nontemporal_store(v.y, d + 1);
+  } else {
+    *reinterpret_cast<C*>(reinterpret_cast<char*>(base) + byte_off) = v;
+  }
 }
 __device__ __forceinline__ double ld_offd(const double* __restrict__ base, uint32_t byte_off) {
   return *reinterpret_cast<const double*>(reinterpret_cast<const char*>(base) + byte_off);
 }
 
+#ifndef TIP_MARCH4_WAVES
+#define TIP_MARCH4_WAVES 1
+#endif
 template <class C, int LOGB, bool HASW>
-__global__ __launch_bounds__(kBlock) void k_stencil_march4(Geom g, MarchMap mm, const C* __restrict__ U,
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(TIP_MARCH4_WAVES))) void k_stencil_march4(Geom g, MarchMap mm, const C* __restrict__ U,
                                                            const double* __restrict__ mass_field, double mass,
                                                            const double* __restrict__ w,
                                                            const int* __restrict__ state,
@@ -424,18 +426,7 @@ __global__ __launch_bounds__(kBlock) void k_stencil_march4(Geom g, MarchMap mm, 
   const int j = threadIdx.x & (B - 1);
   const int si = threadIdx.x >> LOGB;
   uint32_t q, chunk;
-  {
-    const uint32_t b = blockIdx.x;
-    if (mm.xcd_order) {
-      const uint32_t per = (uint32_t)mm.Q / kNumXcd;
-      const uint32_t xcd = b % kNumXcd, slot = b / kNumXcd;
-      q = xcd * per + slot % per;
-      chunk = slot / per;
-    } else {
-      q = b % (uint32_t)mm.Q;
-      chunk = b / (uint32_t)mm.Q;
-    }
-  }
+  march_tile(mm, blockIdx.x, q, chunk);
   const uint32_t V = g.V;
   const uint32_t V3 = mm.V3;
   const uint32_t s3_first = q * (uint32_t)TS;
@@ -1066,7 +1057,13 @@ __global__ __launch_bounds__(kBlock) void k_comp_major_to_site_major(Geom g, con
 static inline unsigned cdiv(size_t a, size_t b) { return (unsigned)((a + b - 1) / b); }
 
 size_t march_lds_bytes(const Geom& g, const MarchMap& mm, Prec prec) {
-  return (size_t)(2 * g.ndim - 1) * 9 * mm.TS * (prec == Prec::kF64 ? sizeof(double2) : sizeof(float2));
+  const size_t need = (size_t)(2 * g.ndim - 1) * 9 * mm.TS * (prec == Prec::kF64 ? sizeof(double2) : sizeof(float2));
+  const int cap = prec == Prec::kF64 ? mm.wgs_per_cu64 : mm.wgs_per_cu32;
+  if (cap < 2) return need;
+  // reserve enough LDS that at most `cap` workgroups fit on one CU (160 KiB),
+  // counting the 2 KiB of static LDS of the reduction
+  const size_t pad = (size_t)kLdsPerCu / (size_t)(cap + 1) + 512 - 2048;
+  return need > pad ? need : pad;
 }
 
 // Calls f(op_policy) for the operator / element / precision combination.

@@ -58,11 +58,55 @@ struct MarchMap {
   uint32_t V3;                 // sites per plane of the marching dimension
   int32_t Q;                   // spatial tiles, V3 / TS
   int32_t nt, Tc;
-  int32_t xcd_order;
+  int32_t xcd_order;           // workgroup -> tile order, see march_tile
+  int32_t ord_n1t, ord_n2;     // order 2: x1 tiles per row, n2
+  int32_t ord_g2;              // order 2: XCD regions along x2 (8 / ord_g2 along x3)
+  int32_t ord_r2, ord_r3;      // order 2: rows per XCD region
+  int32_t ord_b2, ord_b3;      // order 2: rows per round
   int32_t lds_links;           // stage links in LDS (covariant, TS <= 64)
+  int32_t wgs_per_cu64;        // >= 2: cap resident workgroups per CU through LDS (FP64 / FP32 kernels)
+  int32_t wgs_per_cu32;
   int32_t spec4;               // 4-D specialised kernel (32-bit offsets fit, 4 <= B <= 32)
   uint32_t grid;               // Q * nt / Tc
 };
+
+// Workgroup -> (spatial tile q, t-chunk) of the marching stencils.  Workgroups
+// are dealt to the 8 XCDs round robin (workgroup b runs on XCD b mod 8), and
+// each XCD has its own L2, so the order decides which tiles share an L2 while
+// they run.
+//   0: tile-major;
+//   1: each XCD takes a contiguous range of tiles;
+//   2: 3-D blocks (4-D lattices with whole x1 rows per tile group): XCD k owns
+//      a region of r2 x r3 rows (x2, x3) and runs it in rounds of b2 x b3 rows
+//      (all x1 tiles), so the workgroups resident on one XCD at a time cover a
+//      compact block whose x2 +- 1 and x3 +- 1 neighbour rows they load
+//      themselves (one t-chunk after another).
+__host__ __device__ inline void march_tile(const MarchMap& mm, uint32_t b, uint32_t& q, uint32_t& chunk) {
+  if (mm.xcd_order == 2) {
+    const uint32_t xcd = b % kNumXcd, slot = b / kNumXcd;
+    const uint32_t n1t = (uint32_t)mm.ord_n1t, b2 = (uint32_t)mm.ord_b2, b3 = (uint32_t)mm.ord_b3;
+    const uint32_t r2 = (uint32_t)mm.ord_r2, r3 = (uint32_t)mm.ord_r3;
+    const uint32_t per = n1t * r2 * r3;                    // tiles per XCD
+    chunk = slot / per;
+    const uint32_t k = slot % per;
+    const uint32_t bs = n1t * b2 * b3;                     // tiles per round
+    const uint32_t blk = k / bs, w = k % bs;
+    const uint32_t x1t = w % n1t, y = (w / n1t) % b2, z = w / (n1t * b2);
+    const uint32_t nb2 = r2 / b2;
+    const uint32_t g2 = (uint32_t)mm.ord_g2;
+    const uint32_t x2 = (xcd % g2) * r2 + (blk % nb2) * b2 + y;
+    const uint32_t x3 = (xcd / g2) * r3 + (blk / nb2) * b3 + z;
+    q = x1t + n1t * (x2 + (uint32_t)mm.ord_n2 * x3);
+  } else if (mm.xcd_order == 1) {
+    const uint32_t per = (uint32_t)mm.Q / kNumXcd;        // spatial tiles per XCD
+    const uint32_t xcd = b % kNumXcd, slot = b / kNumXcd;
+    q = xcd * per + slot % per;
+    chunk = slot / per;
+  } else {
+    q = b % (uint32_t)mm.Q;
+    chunk = b / (uint32_t)mm.Q;
+  }
+}
 
 // Dynamic LDS of the marching stencil when it stages links.
 size_t march_lds_bytes(const Geom& g, const MarchMap& mm, Prec prec);
