@@ -14,6 +14,13 @@
  *   3. accumulates z^H x into the estimator (1/s) sum_m z_m^H A^-1 z_m
  *      (Sec. 1, Hutchinson) reported at every s = 2^k (Sec. 1.1.4, and the
  *      nesting Z(k-1) = Z(k)(:, 1:2^{k-1}) after eq. Hperm-recursive).
+ *   The solves run CG on the even-odd reduced system whenever every side is
+ *   at least 2 and the diagonal is positive (precision FP64): the red-black
+ *   colouring of Sec. 2 makes the torus bipartite, A = D - H with H joining
+ *   opposite parities only, and CG iterates on the Schur complement
+ *   S = D_e - H_eo D_o^-1 H_oe over the even sites (half the vector length,
+ *   about half the iterations), then forms x_o = D_o^-1 (b_o + H_oe x_e).  The
+ *   acceptance test is the same FP64 true residual of the full system.
  *
  * Conventions shared by every entry point
  * ---------------------------------------
@@ -124,6 +131,10 @@ typedef struct {
   double max_quad_err_bound;   /* max over solves of ||b - A x||^2 / lambda_lb, with
                                   lambda_lb = min m(x) (valid when every coupling is
                                   >= 0, NaN otherwise): bounds each quadrature's error */
+  int64_t matvecs;             /* operator applications inside CG (one per iteration of a block) */
+  double matvec_seconds;       /* their summed device time (hipEvents), 0 if profiling off */
+  double matvec_bytes;         /* their algorithmic HBM bytes                              */
+  int32_t even_odd;            /* 1 when CG ran on the even-odd reduced system (see below) */
 } tip_stats;
 
 /* Number of estimates written by trace_inv_probe: floor(log2 n) + 1, plus one
@@ -171,7 +182,9 @@ tip_status trace_inv_probe_grad(tip_op_handle h, const tip_params* p, double* es
 
 /* One solve A x = b_{m,comp} on a prepared handle, for checks of the solver
  * and for callers that need the solution itself.  Uses tol, max_iter, seed,
- * mask, precision and stream of p; its probe-count fields are ignored.
+ * mask, precision and stream of p; its probe-count fields and rhs_block are
+ * ignored: the solve runs in a block of the library's default size, so it
+ * repeats the arithmetic of trace_inv_probe for this right-hand side.
  * x_out: DEVICE, [V][ncomp] complex128 when the solve is complex (covariant
  * operator, or Z4 mask), else [V] float64.  q_out: HOST [2] = b^H x, or NULL.
  * stats may be NULL.  Status as trace_inv_probe for a single solve. */

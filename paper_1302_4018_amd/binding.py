@@ -41,7 +41,9 @@ class tip_stats(ctypes.Structure):
                 ("n_checkpoints_done", ctypes.c_int32), ("max_true_relres", ctypes.c_double),
                 ("seconds", ctypes.c_double), ("stencil_launches", ctypes.c_int64),
                 ("stencil_seconds", ctypes.c_double), ("stencil_bytes", ctypes.c_double),
-                ("reliable_updates", ctypes.c_int64), ("max_quad_err_bound", ctypes.c_double)]
+                ("reliable_updates", ctypes.c_int64), ("max_quad_err_bound", ctypes.c_double),
+                ("matvecs", ctypes.c_int64), ("matvec_seconds", ctypes.c_double), ("matvec_bytes", ctypes.c_double),
+                ("even_odd", ctypes.c_int32)]
 
 
 def _load():
@@ -244,7 +246,7 @@ class OpHandle:
         shape = (op.V, op.ncomp, 2) if complex_solve else (op.V,)
         x = torch.empty(shape, dtype=torch.float64, device="cuda")
         q = np.zeros(2)
-        p = _params(1, tol, seed, mask, max_iter, 1, 0, np.zeros((1, 2)), stream, precision, reliable_delta)
+        p = _params(1, tol, seed, mask, max_iter, 0, 0, np.zeros((1, 2)), stream, precision, reliable_delta)
         st = tip_stats()
         _check(lib.tip_solve_probe(self._h, ctypes.byref(p), int(m), int(comp), _ptr(x),
                                    q.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), ctypes.byref(st)),

@@ -107,6 +107,7 @@ struct tip_op_s {
   double mass = 0.0;
   DevBuf links, mass_field, coupling;
   DevBuf links32;              // single-precision copy, made on first mixed-precision use
+  DevBuf diag;                 // D(x) = m(x) + sum_mu [w_mu(x) + w_mu(x - mu)], FP64
   bool has_mass_field = false, has_coupling = false, has_links32 = false;
   // lower bound of the spectrum: A = sum_e w_e L_e + diag(m) with L_e PSD, so
   // lambda_min >= min m(x) whenever every w_e >= 0 (NaN when not known)
@@ -173,6 +174,10 @@ tip_status create_handle(const tip_operator* op, hipStream_t st, tip_op_s** out)
     if (launch_repack_links(g, (const double2*)op->links, (double2*)h->links.p, st) != hipSuccess)
       return bail(fail(TIP_EDEVICE, "link repack launch failed"));
   }
+  if (h->diag.ensure(V * sizeof(double)) != hipSuccess) return bail(fail(TIP_ENOMEM, "hipMalloc diagonal"));
+  if (launch_diag(g, h->has_mass_field ? (const double*)h->mass_field.p : nullptr, op->mass,
+                  h->has_coupling ? (const double*)h->coupling.p : nullptr, (double*)h->diag.p, st) != hipSuccess)
+    return bail(fail(TIP_EDEVICE, "diagonal launch failed"));
   if (hipStreamSynchronize(st) != hipSuccess) return bail(fail(TIP_EDEVICE, "operator setup failed on the device"));
   {
     double lb = op->mass;
@@ -226,6 +231,8 @@ struct Plan {
   TileMap tm;  // generic site kernels
   MarchMap mm; // marching stencil (valid when use_march)
   bool use_march;
+  bool eo = false;  // CG on the even-odd reduced system
+  MarchMap me;      // half-lattice march (valid when eo)
 };
 
 bool env_off(const char* name) {
@@ -324,12 +331,13 @@ bool block_order_is_permutation(const MarchMap& mm) {
   return true;
 }
 
-bool make_marchmap(const Geom& g, int logB, MarchMap* mm) {
-  if (env_off("TIP_MARCH") || g.ndim < 2) return false;
-  const int nt = 1 << g.logn[g.ndim - 1];
-  if (nt < 2) return false;
+// halve_t: march the half-lattice of the even-odd system (t slices of two).
+bool make_marchmap(const Geom& g, int logB, MarchMap* mm, bool halve_t = false) {
+  if (!halve_t && (env_off("TIP_MARCH") || g.ndim < 2)) return false;
+  const int nt = (1 << g.logn[g.ndim - 1]) >> (halve_t ? 1 : 0);
+  if (nt < (halve_t ? 1 : 2)) return false;
   const int TS = kBlock >> logB;
-  const uint32_t V3 = g.V / (uint32_t)nt;
+  const uint32_t V3 = g.V >> g.logn[g.ndim - 1];
   if (V3 % (uint32_t)TS != 0) return false;
   mm->logB = logB;
   mm->TS = TS;
@@ -401,22 +409,26 @@ struct Solver {
   Prec prec = Prec::kF64;
   int max_iter, max_restarts = 8;
   double tol2, delta2 = 0.0;
-  size_t vbytes, vbytes64, pstride, nscal, nelem;
+  size_t vbytes, vbytes64, pstride, nscal, nelem, nvec;
   int gx_m, gx_u, gx_t;       // partials per rhs written by matvec, update, true residual
   void *X, *Rv, *Pv, *W, *XH; // FP64 path: X, Rv, Pv, W; mixed: X (FP64) + XH, Rv, Pv, W (FP32)
+  void *Xe = nullptr, *Tv = nullptr;   // even-odd: x_e and t_o (half lattice)
   double* part;
   CgScalars sc;
   int* ran_dev;
   double *h_q, *h_relres2;
   int *h_state, *h_iters, *h_active, *h_ran;
   OpDev od, od64;
-  double mv_bytes;
+  double mv_bytes;              // dominant stencil kernel, per launch
+  double hop_bytes = 0.0;       // even-odd: the other half-lattice kernel, per launch
+  int64_t matvecs = 0;
+  double matvec_seconds = 0.0, matvec_bytes = 0.0;
   int predicted = 8;
   int64_t reliable_updates = 0;
   // stencil accounting
   int64_t stencil_launches = 0;
   double stencil_seconds = 0.0, stencil_bytes = 0.0;
-  struct Timed { hipEvent_t a, b; };
+  struct Timed { hipEvent_t a, b, c; };
   size_t ev_used = 0;
   static constexpr int kMaxChunk = 4096;
 
@@ -463,6 +475,16 @@ struct Solver {
     while ((1 << pl.logB) < B) ++pl.logB;
     pl.tm = make_tilemap(g, pl.logB);
     pl.use_march = make_marchmap(g, pl.logB, &pl.mm);
+    // even-odd reduction: bipartite torus (every side >= 2, all powers of two
+    // are then even) and a positive diagonal (lambda_lb > 0 implies D > 0)
+    {
+      bool bip = true;
+      for (int mu = 0; mu < g.ndim; ++mu) bip = bip && g.logn[mu] >= 1;
+      pl.eo = !mixed && bip && h->lambda_lb > 0.0 && !env_off("TIP_EO") &&
+              make_marchmap(g, pl.logB, &pl.me, true);
+      // the covariant half-lattice kernel stages its tile's links in LDS
+      if (pl.eo && h->kind == TIP_KIND_COVARIANT && eo_lds_bytes(g, pl.me, prec) > 65536) pl.eo = false;
+    }
     max_iter = p->max_iter > 0 ? p->max_iter : (int)std::min<int64_t>(10 * V * ncomp, 1 << 20);
     tol2 = p->tol * p->tol;
     if (mixed) {
@@ -473,12 +495,15 @@ struct Solver {
     nelem = (size_t)B * ncomp * V;
     vbytes = nelem * pl.esz;                      // one CG vector of the block
     vbytes64 = nelem * esz64;
-    gx_m = (int)(pl.use_march ? pl.mm.grid : pl.tm.grid);
-    gx_u = (int)update_grid(nelem);
+    nvec = pl.eo ? nelem / 2 : nelem;             // elements the CG vector passes touch
+    gx_m = (int)(pl.eo ? pl.me.grid : (pl.use_march ? pl.mm.grid : pl.tm.grid));
+    gx_u = (int)update_grid(nvec);
     gx_t = (int)pl.tm.grid;
     pstride = (size_t)B * std::max(gx_m, std::max(gx_u, gx_t));
     nscal = (size_t)B;
-    const size_t vec_total = mixed ? vbytes64 + 4 * vbytes : 4 * vbytes;
+    // FP64: x, r, p, w; mixed: x (FP64) + xh, r, p, w (FP32); even-odd: x on the
+    // full lattice + x_e, r, p, w, t on the half lattice
+    const size_t vec_total = pl.eo ? vbytes + 5 * (vbytes / 2) : (mixed ? vbytes64 + 4 * vbytes : 4 * vbytes);
     if (h->vec.ensure(vec_total) != hipSuccess)
       return fail(TIP_ENOMEM, "hipMalloc of %zu bytes of CG vectors failed", vec_total);
     if (h->partial.ensure(5 * pstride * sizeof(double)) != hipSuccess) return fail(TIP_ENOMEM, "hipMalloc partials");
@@ -500,6 +525,14 @@ struct Solver {
       Rv = vb + vbytes64 + vbytes;
       Pv = vb + vbytes64 + 2 * vbytes;
       W = vb + vbytes64 + 3 * vbytes;
+    } else if (pl.eo) {
+      const size_t hb = vbytes / 2;
+      XH = nullptr;
+      Xe = vb + vbytes;
+      Rv = vb + vbytes + hb;
+      Pv = vb + vbytes + 2 * hb;
+      W = vb + vbytes + 3 * hb;
+      Tv = vb + vbytes + 4 * hb;
     } else {
       XH = nullptr;
       Rv = vb + vbytes;
@@ -543,6 +576,17 @@ struct Solver {
     if (h->has_coupling) per_site += (double)g.ndim * 8;
     if (h->has_mass_field) per_site += 8.0;
     mv_bytes = per_site * V + 2.0 * (double)vbytes;
+    if (pl.eo) {
+      // the two half-lattice kernels of S p: each reads every link and
+      // coupling once and D at its output sites; t_o = D_o^-1 H_oe p_e reads
+      // p_e and writes t_o, S p reads t_o and p_e and writes w_e
+      double link_site = 0.0;
+      if (h->kind == TIP_KIND_COVARIANT) link_site += (double)g.ndim * 9 * 2 * (mixed ? 4 : 8);
+      if (h->has_coupling) link_site += (double)g.ndim * 8;
+      const double half = (double)vbytes / 2.0;
+      hop_bytes = link_site * V + 4.0 * V + 2.0 * half;
+      mv_bytes = link_site * V + 4.0 * V + 3.0 * half;
+    }
     return TIP_OK;
   }
 
@@ -564,9 +608,19 @@ struct Solver {
     const Geom& g = h->geom;
     const MarchMap* mm = pl.use_march ? &pl.mm : nullptr;
     TIP_HIP(launch_scalars_init(sc, nb, pl.B, (double)g.V, p->tol >= 1.0 ? 1 : 0, st));
-    if (mixed) TIP_HIP(launch_init_mixed(g, pl.elem, pl.logB, rhs0, nb, p->seed, pl.mask, X, XH, Rv, Pv, st));
-    else TIP_HIP(launch_init(g, pl.elem, pl.logB, rhs0, nb, p->seed, pl.mask, X, Rv, Pv, st));
-    void* xdir = mixed ? XH : X;     // vector the direction pass updates
+    const double* diag = (const double*)h->diag.p;
+    if (pl.eo) {
+      // reduced right-hand side b_e + H_eo D_o^-1 b_o; x_e = 0, r = p = it
+      TIP_HIP(launch_eo_init_odd(g, pl.elem, prec, pl.logB, rhs0, nb, p->seed, pl.mask, diag, Tv, st));
+      TIP_HIP(launch_eo_hop(2, od, g, pl.me, 0, pl.elem, prec, diag, nullptr, nullptr, Tv, nullptr, Rv, Pv, Xe, rhs0,
+                            nb, p->seed, pl.mask, part, nullptr, st));
+      TIP_HIP(launch_reduce_rho0(sc, pl.B, part, gx_m, st));
+    } else if (mixed) {
+      TIP_HIP(launch_init_mixed(g, pl.elem, pl.logB, rhs0, nb, p->seed, pl.mask, X, XH, Rv, Pv, st));
+    } else {
+      TIP_HIP(launch_init(g, pl.elem, pl.logB, rhs0, nb, p->seed, pl.mask, X, Rv, Pv, st));
+    }
+    void* xdir = mixed ? XH : (pl.eo ? Xe : X);     // vector the direction pass updates
     bool first_chunk = true;
     std::vector<Timed> window;
     for (;;) {
@@ -583,17 +637,29 @@ struct Solver {
           if (g_profiling) {
             TIP_HIP(next_event(&tv.a));
             TIP_HIP(next_event(&tv.b));
+            TIP_HIP(next_event(&tv.c));
             TIP_HIP(hipEventRecord(tv.a, st));
           }
-          TIP_HIP(launch_stencil(od, g, pl.tm, mm, pl.elem, prec, sc.state, sc.active, Pv, W, part, ran_dev + it, st));
+          if (pl.eo) {
+            // w_e = S p_e: t_o = D_o^-1 H_oe p_e, then w_e = D_e p_e - H_eo t_o
+            TIP_HIP(launch_eo_hop(0, od, g, pl.me, 1, pl.elem, prec, diag, sc.state, sc.active, Pv, nullptr, Tv,
+                                  nullptr, nullptr, 0, 0, 0, 0, nullptr, nullptr, st));
+            if (g_profiling) TIP_HIP(hipEventRecord(tv.b, st));
+            TIP_HIP(launch_eo_hop(1, od, g, pl.me, 0, pl.elem, prec, diag, sc.state, sc.active, Tv, Pv, W, nullptr,
+                                  nullptr, 0, 0, 0, 0, part, ran_dev + it, st));
+          } else {
+            if (g_profiling) TIP_HIP(hipEventRecord(tv.b, st));
+            TIP_HIP(launch_stencil(od, g, pl.tm, mm, pl.elem, prec, sc.state, sc.active, Pv, W, part, ran_dev + it,
+                                   st));
+          }
           if (g_profiling) {
-            TIP_HIP(hipEventRecord(tv.b, st));
+            TIP_HIP(hipEventRecord(tv.c, st));
             window.push_back(tv);
           }
           TIP_HIP(launch_reduce_alpha(sc, pl.B, part, gx_m, st));
-          TIP_HIP(launch_update_r(nelem, pl.logB, pl.elem, prec, sc, Rv, W, part + pstride, st));
+          TIP_HIP(launch_update_r(nvec, pl.logB, pl.elem, prec, sc, Rv, W, part + pstride, st));
           TIP_HIP(launch_reduce_beta(sc, pl.B, part + pstride, gx_u, tol2, max_iter, delta2, st));
-          TIP_HIP(launch_direction(nelem, pl.logB, pl.elem, prec, sc, xdir, Rv, Pv, st));
+          TIP_HIP(launch_direction(nvec, pl.logB, pl.elem, prec, sc, xdir, Rv, Pv, st));
           if (mixed) {
             tip_status s = reliable(rhs0, nb, 0);
             if (s != TIP_OK) return s;
@@ -605,11 +671,15 @@ struct Solver {
         for (int i = 0; i < chunk; ++i) {
           if (!h_ran[i]) continue;
           ++stencil_launches;
+          ++matvecs;
           stencil_bytes += mv_bytes;
+          matvec_bytes += mv_bytes + hop_bytes;
           if (g_profiling) {
-            float ms = 0.f;
-            TIP_HIP(hipEventElapsedTime(&ms, window[i].a, window[i].b));
+            float ms = 0.f, ms_all = 0.f;
+            TIP_HIP(hipEventElapsedTime(&ms, window[i].b, window[i].c));
+            TIP_HIP(hipEventElapsedTime(&ms_all, window[i].a, window[i].c));
             stencil_seconds += ms * 1e-3;
+            matvec_seconds += ms_all * 1e-3;
           }
         }
         if (h_active[0] == 0) break;
@@ -619,8 +689,14 @@ struct Solver {
         tip_status s = reliable(rhs0, nb, 1);
         if (s != TIP_OK) return s;
       } else {
+        if (pl.eo) {
+          // x on the full lattice: x_e as iterated, x_o = D_o^-1 (b_o + H_oe x_e)
+          TIP_HIP(launch_eo_scatter_even(g, pl.elem, prec, pl.logB, Xe, X, st));
+          TIP_HIP(launch_eo_hop(3, od, g, pl.me, 1, pl.elem, prec, diag, nullptr, nullptr, Xe, nullptr, X, nullptr,
+                                nullptr, rhs0, nb, p->seed, pl.mask, nullptr, nullptr, st));
+        }
         TIP_HIP(launch_true_residual(od, g, pl.tm, pl.elem, sc.state, rhs0, nb, p->seed, pl.mask, X, Rv, Pv, part,
-                                     pstride, st));
+                                     pstride, pl.eo ? 1 : 0, st));
         TIP_HIP(launch_reduce_true(sc, pl.B, part, gx_t, pstride, tol2, max_iter, max_restarts, st));
       }
       TIP_HIP(hipMemcpyAsync(h_active, sc.active, sizeof(int), hipMemcpyDeviceToHost, st));
@@ -644,6 +720,10 @@ struct Solver {
     stats->stencil_launches = stencil_launches;
     stats->stencil_seconds = g_profiling ? stencil_seconds : 0.0;
     stats->stencil_bytes = stencil_bytes;
+    stats->matvecs = matvecs;
+    stats->matvec_seconds = g_profiling ? matvec_seconds : 0.0;
+    stats->matvec_bytes = matvec_bytes;
+    stats->even_odd = pl.eo ? 1 : 0;
     stats->reliable_updates = reliable_updates;
   }
 };
@@ -824,7 +904,7 @@ tip_status tip_solve_probe(tip_op_handle h, const tip_params* p, int64_t m, int3
   tip_params one = *p;           // one right-hand side; probe-count fields do not apply
   one.n_vectors = 1;
   one.m_begin = 0;
-  one.rhs_block = 1;
+  one.rhs_block = 0;             // the block size trace_inv_probe uses: same arithmetic
   int mask = 0;
   tip_status s = check_params(h, &one, &mask);
   if (s != TIP_OK) return s;
@@ -837,7 +917,7 @@ tip_status tip_solve_probe(tip_op_handle h, const tip_params* p, int64_t m, int3
   if (s != TIP_OK) return s;
   s = sv.solve_block(m * g.ncomp + comp, 1);
   if (s != TIP_OK) return s;
-  TIP_HIP(launch_layout(g, sv.pl.elem, sv.X, x_out, false, sv.st));
+  TIP_HIP(launch_layout(g, sv.pl.elem, sv.pl.logB, 0, sv.X, x_out, false, sv.st));
   TIP_HIP(hipStreamSynchronize(sv.st));
   if (q_out) {
     q_out[0] = sv.h_q[0];
@@ -898,9 +978,9 @@ tip_status tip_apply_operator(const tip_operator* op, int32_t nrhs, const double
     char* out = in + bytes;
     const char* xk = (const char*)x + k * bytes;
     char* yk = (char*)y + k * bytes;
-    if (launch_layout(g, elem, xk, in, true, st) != hipSuccess ||
+    if (launch_layout(g, elem, 0, 0, xk, in, true, st) != hipSuccess ||
         launch_stencil(h->dev(), g, tm, nullptr, elem, Prec::kF64, nullptr, nullptr, in, out, nullptr, nullptr, st) != hipSuccess ||
-        launch_layout(g, elem, out, yk, false, st) != hipSuccess)
+        launch_layout(g, elem, 0, 0, out, yk, false, st) != hipSuccess)
       ret = fail(TIP_EDEVICE, "apply launch failed");
   }
   if (ret == TIP_OK && hipStreamSynchronize(st) != hipSuccess) ret = fail(TIP_EDEVICE, "apply failed on the device");

@@ -605,6 +605,15 @@ __global__ __launch_bounds__(kBlock) void k_direction(size_t n, int logB, const 
 // component c = (rhs0 + j) % ncomp.
 // ---------------------------------------------------------------------------
 
+// Parity of the first ndim-1 coordinates of a site (or of a spatial index).
+__device__ __forceinline__ uint32_t spatial_parity(uint32_t s3, const Geom& g) {
+  uint32_t sum = 0;
+#pragma unroll
+  for (int mu = 0; mu < kMaxDim - 1; ++mu)
+    if (mu < g.ndim - 1) sum += coord(s3, g, mu);
+  return sum & 1u;
+}
+
 template <class T, int NC>
 __device__ __forceinline__ void rhs_at(const Geom& g, uint32_t s, uint32_t P, int64_t rhs0, int j, int nb,
                                        uint64_t seed, int mask, T (&b)[NC]) {
@@ -646,7 +655,7 @@ __global__ __launch_bounds__(kBlock) void k_true_residual(Geom g, TileMap tm, Op
                                                           int64_t rhs0, int nb, uint64_t seed, int mask,
                                                           const typename Op::T* __restrict__ x,
                                                           typename Op::T* __restrict__ r, typename Op::T* __restrict__ p,
-                                                          double* __restrict__ partial, size_t pstride) {
+                                                          double* __restrict__ partial, size_t pstride, int eo) {
   using T = typename Op::T;
   constexpr int NC = Op::NC;
   __shared__ double lds[3 * 4 * 64];
@@ -665,8 +674,18 @@ __global__ __launch_bounds__(kBlock) void k_true_residual(Geom g, TileMap tm, Op
       acc[1] += redot(b[c], xs[c]);
       acc[2] += imdot(b[c], xs[c]);
     }
-    store_vec<T, NC>(r, g.V, tm.logB, s, j, rt);
-    store_vec<T, NC>(p, g.V, tm.logB, s, j, rt);
+    if (!eo) {
+      store_vec<T, NC>(r, g.V, tm.logB, s, j, rt);
+      store_vec<T, NC>(p, g.V, tm.logB, s, j, rt);
+    } else if (((spatial_parity(s, g) + coord(s, g, g.ndim - 1)) & 1u) == 0u) {
+      // even-odd solve: restart the reduced system from the even part (the
+      // odd part vanishes up to rounding when x_o was formed from x_e)
+      const int tdim = g.ndim - 1;
+      const uint32_t V3 = 1u << g.shift[tdim];
+      const uint32_t h = (s & (V3 - 1u)) + V3 * (coord(s, g, tdim) >> 1);
+      store_vec<T, NC>(r, g.V >> 1, tm.logB, h, j, rt);
+      store_vec<T, NC>(p, g.V >> 1, tm.logB, h, j, rt);
+    }
   }
   seg_sum<3>(acc, B, lds);
   if ((int)threadIdx.x < B) {
@@ -1032,22 +1051,22 @@ __global__ __launch_bounds__(kBlock) void k_repack_links(Geom g, const double2* 
   for (int e = 0; e < 9; ++e) dst[((size_t)mu * 9 + e) * V + s] = src[((size_t)mu * V + s) * 9 + e];
 }
 
-// one vector: [V][nc] <-> [nc][V]
+// one vector: [V][nc] <-> lane `lane` of the block layout [nc][V][2^logB]
 template <class T>
-__global__ __launch_bounds__(kBlock) void k_site_major_to_comp_major(Geom g, const T* __restrict__ src,
-                                                                     T* __restrict__ dst) {
+__global__ __launch_bounds__(kBlock) void k_site_major_to_comp_major(Geom g, int logB, int lane,
+                                                                     const T* __restrict__ src, T* __restrict__ dst) {
   const uint32_t s = blockIdx.x * kBlock + threadIdx.x;
   if (s >= g.V) return;
   const size_t V = g.V, nc = g.ncomp;
-  for (size_t c = 0; c < nc; ++c) dst[c * V + s] = src[s * nc + c];
+  for (size_t c = 0; c < nc; ++c) dst[((c * V + s) << logB) + lane] = src[s * nc + c];
 }
 template <class T>
-__global__ __launch_bounds__(kBlock) void k_comp_major_to_site_major(Geom g, const T* __restrict__ src,
-                                                                     T* __restrict__ dst) {
+__global__ __launch_bounds__(kBlock) void k_comp_major_to_site_major(Geom g, int logB, int lane,
+                                                                     const T* __restrict__ src, T* __restrict__ dst) {
   const uint32_t s = blockIdx.x * kBlock + threadIdx.x;
   if (s >= g.V) return;
   const size_t V = g.V, nc = g.ncomp;
-  for (size_t c = 0; c < nc; ++c) dst[s * nc + c] = src[c * V + s];
+  for (size_t c = 0; c < nc; ++c) dst[s * nc + c] = src[((c * V + s) << logB) + lane];
 }
 
 // ---------------------------------------------------------------------------
@@ -1055,6 +1074,270 @@ __global__ __launch_bounds__(kBlock) void k_comp_major_to_site_major(Geom g, con
 // ---------------------------------------------------------------------------
 
 static inline unsigned cdiv(size_t a, size_t b) { return (unsigned)((a + b - 1) / b); }
+
+// ---------------------------------------------------------------------------
+// Even-odd (red-black) reduction of A x = b.  With every side even the torus
+// is bipartite: A = D - H, D = diag(m(x) + sum_mu [w_mu(x) + w_mu(x - mu)])
+// (x) I and the hopping H couples sites of opposite parity only -- the
+// red-black colouring of Sec. 2.  Eliminating the odd sites leaves the Schur
+// complement
+//     S x_e = b_e + H_eo D_o^-1 b_o,   S = D_e - H_eo D_o^-1 H_oe,
+// which is Hermitian positive definite and better conditioned than A (for a
+// diagonal-dominated A with D^-1 H of spectral radius rho, the condition
+// number drops from (1 + rho)/(1 - rho) to 1/(1 - rho^2)), after which
+// x_o = D_o^-1 (b_o + H_oe x_e).  With x_o formed this way the full residual
+// b - A x is zero on odd sites and equals the reduced residual on even ones,
+// so CG on S stopped at ||r_e|| <= tol ||b|| meets the same criterion.
+//
+// Half-lattice layout: the sites of one parity, numbered h = x + V3 (t >> 1)
+// with x the index of the first ndim-1 coordinates (V3 of them) and t the last
+// coordinate; vectors are [ncomp][V/2][B].  At fixed x the sites of parity P
+// have t = 2 tau + delta(x), delta(x) = (P + |x|) mod 2, |x| the coordinate sum.
+// For an output site of parity P at slice tau, its spatial neighbours (parity
+// 1 - P) sit in the same slice tau of the input vector and its neighbours
+// along t in slices tau + delta (forward) and tau - 1 + delta (backward), so
+// the kernel marches tau like the full stencil and carries the backward input
+// from the previous step.
+//
+// One kernel, four uses (MODE):
+//   0  out = D^-1 H in                  (t_o = D_o^-1 H_oe p_e)
+//   1  out = D cin - H in, partial Re cin^H out   (w_e = S p_e)
+//   2  out = out2 = b + H in, out3 = 0, partial ||out||^2   (reduced rhs, CG start)
+//   3  out = D^-1 (b + H in), written at full-lattice sites   (x_o)
+// b is the probing right-hand side, regenerated from site indices.
+// ---------------------------------------------------------------------------
+
+template <class Op, int MODE, int kLogB>
+__global__ __launch_bounds__(kBlock) void k_eo_hop(Geom g, MarchMap mm, int P, Op op,
+                                                   const double* __restrict__ diag, const double* __restrict__ w,
+                                                   const int* __restrict__ state, const int* __restrict__ active,
+                                                   const typename Op::T* __restrict__ in,
+                                                   const typename Op::T* __restrict__ cin,
+                                                   typename Op::T* __restrict__ out, typename Op::T* __restrict__ out2,
+                                                   typename Op::T* __restrict__ out3, int64_t rhs0, int nb,
+                                                   uint64_t seed, int mask, double* __restrict__ partial,
+                                                   int* __restrict__ ran) {
+  using T = typename Op::T;
+  constexpr int NC = Op::NC;
+  constexpr bool kCov = NC == 3;
+  const int logB = kLogB >= 0 ? kLogB : mm.logB;
+  const int B = 1 << logB;
+  const int TS = kBlock >> logB;
+  if (active && *active == 0) return;
+  if (ran && blockIdx.x == 0 && threadIdx.x == 0) *ran = 1;
+  __shared__ double lds[4 * 64];
+  T* lds_links = reinterpret_cast<T*>(tip_dyn_lds);   // covariant: [2 ndim][9][TS]
+  const int j = threadIdx.x & (B - 1);
+  const int si = threadIdx.x >> logB;
+  uint32_t q, chunk;
+  march_tile(mm, blockIdx.x, q, chunk);
+  const uint32_t V = g.V;
+  const uint32_t V3 = mm.V3;
+  const uint32_t Vh = V >> 1;
+  const int ndim = g.ndim;
+  const int tdim = ndim - 1;
+  const uint32_t nt = 1u << g.logn[tdim];
+  const uint32_t ntau = nt >> 1;
+  const uint32_t s3_first = q * (uint32_t)TS;
+  const uint32_t s3 = s3_first + (uint32_t)si;
+  const uint32_t delta = ((uint32_t)P + spatial_parity(s3, g)) & 1u;
+  const bool live = !state || state[j] == kActive;
+  double acc[1] = {0.0};
+  const uint32_t tau0 = chunk * (uint32_t)mm.Tc;
+  T xprev[NC];
+  if (live) load_vec<T, NC>(in, Vh, logB, s3 + V3 * ((tau0 + ntau - 1u + delta) % ntau), j, xprev);
+  for (uint32_t tau = tau0; tau < tau0 + (uint32_t)mm.Tc; ++tau) {
+    const uint32_t t = 2u * tau + delta;
+    const uint32_t s = s3 + V3 * t;                     // full-lattice output site
+    const uint32_t h = s3 + V3 * tau;                   // its half-lattice index
+    if constexpr (kCov) {
+      // stage the tile's links: slots 0..ndim-1 forward U_mu(s), ndim..2ndim-1 backward U_mu(s - mu)
+      __syncthreads();
+      const int nslot = 2 * ndim;
+      for (int it = threadIdx.x; it < nslot * 9 * TS; it += kBlock) {
+        const int site = it % TS;
+        const int es = it / TS;
+        const int e = es % 9;
+        const int slot = es / 9;
+        const uint32_t x3 = s3_first + (uint32_t)site;
+        const uint32_t dl = ((uint32_t)P + spatial_parity(x3, g)) & 1u;
+        const uint32_t ss = x3 + V3 * (2u * tau + dl);
+        const int mu = slot < ndim ? slot : slot - ndim;
+        const uint32_t sl = slot < ndim ? ss : nbr_bwd(ss, g, mu);
+        lds_links[it] = op.U[((size_t)mu * 9 + e) * V + sl];
+      }
+      __syncthreads();
+    }
+    if (!live) continue;
+    T hop[NC];
+#pragma unroll
+    for (int c = 0; c < NC; ++c) hop[c] = zero<T>();
+    // spatial directions: neighbours in the same slice
+#pragma unroll
+    for (int mu = 0; mu < kMaxDim - 1; ++mu) {
+      if (mu >= tdim) break;
+      const uint32_t nf = nbr_fwd(s3, g, mu), nbk = nbr_bwd(s3, g, mu);
+      const double wf = w ? w[(size_t)mu * V + s] : 1.0;
+      const double wb = w ? w[(size_t)mu * V + nbr_bwd(s, g, mu)] : 1.0;
+      T xn[NC], hh[NC];
+      load_vec<T, NC>(in, Vh, logB, nf + V3 * tau, j, xn);
+      if constexpr (kCov) {
+        T u[9];
+#pragma unroll
+        for (int e = 0; e < 9; ++e) u[e] = lds_links[(mu * 9 + e) * TS + si];
+        mul_u(u, xn, hh);
+      } else {
+        hh[0] = xn[0];
+      }
+      add_weighted<T, NC>(wf, hh, hop);
+      load_vec<T, NC>(in, Vh, logB, nbk + V3 * tau, j, xn);
+      if constexpr (kCov) {
+        T u[9];
+#pragma unroll
+        for (int e = 0; e < 9; ++e) u[e] = lds_links[((ndim + mu) * 9 + e) * TS + si];
+        mul_uh(u, xn, hh);
+      } else {
+        hh[0] = xn[0];
+      }
+      add_weighted<T, NC>(wb, hh, hop);
+    }
+    // the marching direction: forward input in slice tau + delta, backward one carried
+    {
+      const double wf = w ? w[(size_t)tdim * V + s] : 1.0;
+      const double wb = w ? w[(size_t)tdim * V + nbr_bwd(s, g, tdim)] : 1.0;
+      T xn[NC], hh[NC];
+      load_vec<T, NC>(in, Vh, logB, s3 + V3 * ((tau + delta) % ntau), j, xn);
+      if constexpr (kCov) {
+        T u[9];
+#pragma unroll
+        for (int e = 0; e < 9; ++e) u[e] = lds_links[(tdim * 9 + e) * TS + si];
+        mul_u(u, xn, hh);
+      } else {
+        hh[0] = xn[0];
+      }
+      add_weighted<T, NC>(wf, hh, hop);
+      if constexpr (kCov) {
+        T u[9];
+#pragma unroll
+        for (int e = 0; e < 9; ++e) u[e] = lds_links[((ndim + tdim) * 9 + e) * TS + si];
+        mul_uh(u, xprev, hh);
+      } else {
+        hh[0] = xprev[0];
+      }
+      add_weighted<T, NC>(wb, hh, hop);
+#pragma unroll
+      for (int c = 0; c < NC; ++c) xprev[c] = xn[c];
+    }
+    const double d = diag[s];
+    T y[NC];
+    if constexpr (MODE == 0) {
+      const double f = 1.0 / d;
+#pragma unroll
+      for (int c = 0; c < NC; ++c) y[c] = axpy(f, hop[c], zero<T>());
+      store_vec<T, NC>(out, Vh, logB, h, j, y);
+    } else if constexpr (MODE == 1) {
+      T cv[NC];
+      load_vec<T, NC>(cin, Vh, logB, h, j, cv);
+#pragma unroll
+      for (int c = 0; c < NC; ++c) {
+        y[c] = axpy(d, cv[c], axpy(-1.0, hop[c], zero<T>()));
+        acc[0] += redot(cv[c], y[c]);
+      }
+      store_vec<T, NC>(out, Vh, logB, h, j, y);
+    } else {
+      T b[NC];
+      rhs_at<T, NC>(g, s, hier_perm(s, g), rhs0, j, nb, seed, mask, b);
+      if constexpr (MODE == 2) {
+#pragma unroll
+        for (int c = 0; c < NC; ++c) {
+          y[c] = j < nb ? axpy(1.0, hop[c], b[c]) : zero<T>();
+          acc[0] += norm2(y[c]);
+        }
+        T z[NC];
+#pragma unroll
+        for (int c = 0; c < NC; ++c) z[c] = zero<T>();
+        store_vec<T, NC>(out, Vh, logB, h, j, y);
+        store_vec<T, NC>(out2, Vh, logB, h, j, y);
+        store_vec<T, NC>(out3, Vh, logB, h, j, z);
+      } else {
+        const double f = 1.0 / d;
+#pragma unroll
+        for (int c = 0; c < NC; ++c) y[c] = axpy(f, axpy(1.0, hop[c], b[c]), zero<T>());
+        store_vec<T, NC>(out, V, logB, s, j, y);
+      }
+    }
+  }
+  if (partial) {
+    seg_sum<1>(acc, B, lds);
+    if ((int)threadIdx.x < B) partial[(size_t)threadIdx.x * gridDim.x + blockIdx.x] = acc[0];
+  }
+}
+
+// Half-lattice index <-> full-lattice site of parity P (see above).
+__device__ __forceinline__ uint32_t eo_site(uint32_t h, int P, const Geom& g) {
+  const int tdim = g.ndim - 1;
+  const uint32_t V3 = 1u << g.shift[tdim];
+  const uint32_t s3 = h & (V3 - 1u), tau = h >> g.shift[tdim];
+  const uint32_t delta = ((uint32_t)P + spatial_parity(s3, g)) & 1u;
+  return s3 + V3 * (2u * tau + delta);
+}
+
+// t_o = D_o^-1 b_o on the odd half-lattice (zero for padding lanes).
+template <class T, int NC>
+__global__ __launch_bounds__(kBlock) void k_eo_init_odd(Geom g, int logB, int64_t rhs0, int nb, uint64_t seed,
+                                                        int mask, const double* __restrict__ diag,
+                                                        T* __restrict__ to) {
+  const int B = 1 << logB;
+  const int j = threadIdx.x & (B - 1);
+  const uint32_t h = blockIdx.x * (kBlock >> logB) + (threadIdx.x >> logB);
+  const uint32_t Vh = g.V >> 1;
+  if (h >= Vh) return;
+  const uint32_t s = eo_site(h, 1, g);
+  T b[NC];
+  rhs_at<T, NC>(g, s, hier_perm(s, g), rhs0, j, nb, seed, mask, b);
+  const double f = 1.0 / diag[s];
+#pragma unroll
+  for (int c = 0; c < NC; ++c) b[c] = axpy(f, b[c], zero<T>());
+  store_vec<T, NC>(to, Vh, logB, h, j, b);
+}
+
+// x (full lattice) at even sites = x_e (half lattice).
+template <class T, int NC>
+__global__ __launch_bounds__(kBlock) void k_eo_scatter_even(Geom g, int logB, const T* __restrict__ xe,
+                                                            T* __restrict__ x) {
+  const int B = 1 << logB;
+  const int j = threadIdx.x & (B - 1);
+  const uint32_t h = blockIdx.x * (kBlock >> logB) + (threadIdx.x >> logB);
+  const uint32_t Vh = g.V >> 1;
+  if (h >= Vh) return;
+  T v[NC];
+  load_vec<T, NC>(xe, Vh, logB, h, j, v);
+  store_vec<T, NC>(x, g.V, logB, eo_site(h, 0, g), j, v);
+}
+
+// D(x) = m(x) + sum_mu [w_mu(x) + w_mu(x - mu)].
+__global__ __launch_bounds__(kBlock) void k_diag(Geom g, const double* __restrict__ mass_field, double mass,
+                                                 const double* __restrict__ w, double* __restrict__ out) {
+  const uint32_t s = blockIdx.x * kBlock + threadIdx.x;
+  if (s >= g.V) return;
+  double d = mass_field ? mass_field[s] : mass;
+  for (int mu = 0; mu < g.ndim; ++mu) {
+    const double wf = w ? w[(size_t)mu * g.V + s] : 1.0;
+    const double wb = w ? w[(size_t)mu * g.V + nbr_bwd(s, g, mu)] : 1.0;
+    d += wf + wb;
+  }
+  out[s] = d;
+}
+
+// rho = rho_ref = ||r||^2 of the reduced start residual.
+__global__ __launch_bounds__(kBlock) void k_reduce_rho0(CgScalars sc, const double* __restrict__ partial, int gx) {
+  const int j = blockIdx.x;
+  if (sc.state[j] != kActive) return;            // uniform per workgroup
+  const double v = sum_partials(partial + (size_t)j * gx, gx);
+  if (threadIdx.x != 0) return;
+  sc.rho[j] = v;
+  sc.rho_ref[j] = v;
+}
 
 size_t march_lds_bytes(const Geom& g, const MarchMap& mm, Prec prec) {
   const size_t need = (size_t)(2 * g.ndim - 1) * 9 * mm.TS * (prec == Prec::kF64 ? sizeof(double2) : sizeof(float2));
@@ -1159,12 +1442,12 @@ hipError_t launch_stencil(const OpDev& od, const Geom& g, const TileMap& tm, con
 
 hipError_t launch_true_residual(const OpDev& od, const Geom& g, const TileMap& tm, Elem elem, const int* state,
                                 int64_t rhs0, int nb, uint64_t seed, int mask, const void* x, void* r, void* p,
-                                double* partial, size_t pstride, hipStream_t st) {
+                                double* partial, size_t pstride, int eo, hipStream_t st) {
   return dispatch64(od, elem, [&](auto op) {
     using Op = decltype(op);
     using T = typename Op::T;
     k_true_residual<Op><<<tm.grid, kBlock, 0, st>>>(g, tm, op, od.mass_field, od.mass, od.coupling, state, rhs0, nb,
-                                                    seed, mask, (const T*)x, (T*)r, (T*)p, partial, pstride);
+                                                    seed, mask, (const T*)x, (T*)r, (T*)p, partial, pstride, eo);
   });
 }
 
@@ -1245,6 +1528,64 @@ hipError_t launch_reduce_ru(const CgScalars& sc, int B, const double* partial, i
   return hipGetLastError();
 }
 
+size_t eo_lds_bytes(const Geom& g, const MarchMap& mm, Prec prec) {
+  return (size_t)(2 * g.ndim) * 9 * mm.TS * (prec == Prec::kF64 ? sizeof(double2) : sizeof(float2));
+}
+
+hipError_t launch_eo_hop(int mode, const OpDev& od, const Geom& g, const MarchMap& mm, int P, Elem elem, Prec prec,
+                         const double* diag, const int* state, const int* active, const void* in, const void* cin,
+                         void* out, void* out2, void* out3, int64_t rhs0, int nb, uint64_t seed, int mask,
+                         double* partial, int* ran, hipStream_t st) {
+  return dispatch(od, elem, prec, [&](auto op) {
+    using Op = decltype(op);
+    using T = typename Op::T;
+    const size_t lds = Op::NC == 3 ? eo_lds_bytes(g, mm, prec) : 0;
+    auto go = [&](auto kern) {
+      kern<<<mm.grid, kBlock, lds, st>>>(g, mm, P, op, diag, od.coupling, state, active, (const T*)in,
+                                          (const T*)cin, (T*)out, (T*)out2, (T*)out3, rhs0, nb, seed, mask, partial,
+                                          ran);
+    };
+    const bool b32 = mm.logB == 5;
+    switch (mode) {
+      case 0: b32 ? go(k_eo_hop<Op, 0, 5>) : go(k_eo_hop<Op, 0, -1>); break;
+      case 1: b32 ? go(k_eo_hop<Op, 1, 5>) : go(k_eo_hop<Op, 1, -1>); break;
+      case 2: go(k_eo_hop<Op, 2, -1>); break;
+      default: go(k_eo_hop<Op, 3, -1>); break;
+    }
+  });
+}
+
+hipError_t launch_eo_init_odd(const Geom& g, Elem elem, Prec prec, int logB, int64_t rhs0, int nb, uint64_t seed,
+                              int mask, const double* diag, void* to, hipStream_t st) {
+  const unsigned grid = cdiv(g.V >> 1, (size_t)(kBlock >> logB));
+  return by_elem(elem, prec, [&](auto tv) {
+    using T = decltype(tv);
+    if (g.ncomp == 3) k_eo_init_odd<T, 3><<<grid, kBlock, 0, st>>>(g, logB, rhs0, nb, seed, mask, diag, (T*)to);
+    else k_eo_init_odd<T, 1><<<grid, kBlock, 0, st>>>(g, logB, rhs0, nb, seed, mask, diag, (T*)to);
+  });
+}
+
+hipError_t launch_eo_scatter_even(const Geom& g, Elem elem, Prec prec, int logB, const void* xe, void* x,
+                                  hipStream_t st) {
+  const unsigned grid = cdiv(g.V >> 1, (size_t)(kBlock >> logB));
+  return by_elem(elem, prec, [&](auto tv) {
+    using T = decltype(tv);
+    if (g.ncomp == 3) k_eo_scatter_even<T, 3><<<grid, kBlock, 0, st>>>(g, logB, (const T*)xe, (T*)x);
+    else k_eo_scatter_even<T, 1><<<grid, kBlock, 0, st>>>(g, logB, (const T*)xe, (T*)x);
+  });
+}
+
+hipError_t launch_diag(const Geom& g, const double* mass_field, double mass, const double* w, double* out,
+                       hipStream_t st) {
+  k_diag<<<cdiv(g.V, kBlock), kBlock, 0, st>>>(g, mass_field, mass, w, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_reduce_rho0(const CgScalars& sc, int B, const double* partial, int gx, hipStream_t st) {
+  k_reduce_rho0<<<B, kBlock, 0, st>>>(sc, partial, gx);
+  return hipGetLastError();
+}
+
 hipError_t launch_grad_accum(const OpDev& od64, const Geom& g, Elem elem, int logB, int nb, const void* x, double* gm,
                              double* gw, hipStream_t st) {
   const unsigned grid = cdiv(g.V, (size_t)(kBlock >> logB));
@@ -1308,14 +1649,21 @@ hipError_t launch_repack_links(const Geom& g, const double2* src, double2* dst, 
   return hipGetLastError();
 }
 
-hipError_t launch_layout(const Geom& g, Elem elem, const void* src, void* dst, bool to_comp_major, hipStream_t st) {
+hipError_t launch_layout(const Geom& g, Elem elem, int logB, int lane, const void* src, void* dst,
+                         bool to_comp_major, hipStream_t st) {
   const unsigned grid = cdiv(g.V, kBlock);
   if (elem == Elem::kReal) {
-    if (to_comp_major) k_site_major_to_comp_major<double><<<grid, kBlock, 0, st>>>(g, (const double*)src, (double*)dst);
-    else k_comp_major_to_site_major<double><<<grid, kBlock, 0, st>>>(g, (const double*)src, (double*)dst);
+    if (to_comp_major)
+      k_site_major_to_comp_major<double><<<grid, kBlock, 0, st>>>(g, logB, lane, (const double*)src, (double*)dst);
+    else
+      k_comp_major_to_site_major<double><<<grid, kBlock, 0, st>>>(g, logB, lane, (const double*)src, (double*)dst);
   } else {
-    if (to_comp_major) k_site_major_to_comp_major<double2><<<grid, kBlock, 0, st>>>(g, (const double2*)src, (double2*)dst);
-    else k_comp_major_to_site_major<double2><<<grid, kBlock, 0, st>>>(g, (const double2*)src, (double2*)dst);
+    if (to_comp_major)
+      k_site_major_to_comp_major<double2><<<grid, kBlock, 0, st>>>(g, logB, lane, (const double2*)src,
+                                                                    (double2*)dst);
+    else
+      k_comp_major_to_site_major<double2><<<grid, kBlock, 0, st>>>(g, logB, lane, (const double2*)src,
+                                                                    (double2*)dst);
   }
   return hipGetLastError();
 }

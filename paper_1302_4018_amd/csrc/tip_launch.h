@@ -116,7 +116,7 @@ hipError_t launch_stencil(const OpDev& op, const Geom& g, const TileMap& tm, con
                           hipStream_t st);
 hipError_t launch_true_residual(const OpDev& op, const Geom& g, const TileMap& tm, Elem elem, const int* state,
                                 int64_t rhs0, int nb, uint64_t seed, int mask, const void* x, void* r, void* p,
-                                double* partial, size_t pstride, hipStream_t st);
+                                double* partial, size_t pstride, int eo, hipStream_t st);
 hipError_t launch_init(const Geom& g, Elem elem, int logB, int64_t rhs0, int nb, uint64_t seed, int mask, void* x,
                        void* r, void* p, hipStream_t st);
 // Workgroups of the update pass (= partials per right-hand side).
@@ -142,6 +142,19 @@ hipError_t launch_cast_links(size_t n, const double2* src, float2* dst, hipStrea
 hipError_t launch_grad_accum(const OpDev& od64, const Geom& g, Elem elem, int logB, int nb, const void* x, double* gm,
                              double* gw, hipStream_t st);
 hipError_t launch_scale(size_t n, double* a, double f, hipStream_t st);
+// even-odd reduced system (half-lattice vectors [ncomp][V/2][B], see k_eo_hop)
+size_t eo_lds_bytes(const Geom& g, const MarchMap& mm, Prec prec);
+hipError_t launch_eo_hop(int mode, const OpDev& od, const Geom& g, const MarchMap& mm, int P, Elem elem, Prec prec,
+                         const double* diag, const int* state, const int* active, const void* in, const void* cin,
+                         void* out, void* out2, void* out3, int64_t rhs0, int nb, uint64_t seed, int mask,
+                         double* partial, int* ran, hipStream_t st);
+hipError_t launch_eo_init_odd(const Geom& g, Elem elem, Prec prec, int logB, int64_t rhs0, int nb, uint64_t seed,
+                              int mask, const double* diag, void* to, hipStream_t st);
+hipError_t launch_eo_scatter_even(const Geom& g, Elem elem, Prec prec, int logB, const void* xe, void* x,
+                                  hipStream_t st);
+hipError_t launch_diag(const Geom& g, const double* mass_field, double mass, const double* w, double* out,
+                       hipStream_t st);
+hipError_t launch_reduce_rho0(const CgScalars& sc, int B, const double* partial, int gx, hipStream_t st);
 hipError_t launch_fill(size_t n, double* a, double v, hipStream_t st);
 hipError_t launch_scalars_init(const CgScalars& sc, int nb, int B, double bnorm2, int start_frozen, hipStream_t st);
 hipError_t launch_reduce_alpha(const CgScalars& sc, int B, const double* partial, int gx, hipStream_t st);
@@ -153,6 +166,8 @@ hipError_t launch_hier_perm(const Geom& g, uint32_t* out, hipStream_t st);
 hipError_t launch_probe_vectors(const Geom& g, uint64_t seed, int mask, int64_t m0, int count, int comp, double2* out,
                                 hipStream_t st);
 hipError_t launch_repack_links(const Geom& g, const double2* src, double2* dst, hipStream_t st);
-hipError_t launch_layout(const Geom& g, Elem elem, const void* src, void* dst, bool to_comp_major, hipStream_t st);
+// [V][ncomp] <-> lane `lane` of the block layout [ncomp][V][2^logB] (FP64)
+hipError_t launch_layout(const Geom& g, Elem elem, int logB, int lane, const void* src, void* dst,
+                         bool to_comp_major, hipStream_t st);
 
 }  // namespace tip
