@@ -32,9 +32,14 @@ HBM_PEAK_GBS = 8000.0
 METRIC = "probing-vector solves/sec (4D 32^4, rel.res 1e-10) + stencil HBM GB/s vs peak"
 KERNEL_SOURCES = ["paper_1302_4018_amd/csrc/tip_kernels.hip", "paper_1302_4018_amd/csrc/tip_device.h"]
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "stencil_traffic.json")
-# the dominant kernel: the 4-D marching stencil on FP64 complex 3-vectors
-STENCIL_FP64 = "k_stencil_march4<HIP_vector_type<double, 2u>"
-STENCIL_FP32 = "k_stencil_march4<HIP_vector_type<float, 2u>"
+# the dominant kernel: with the even-odd reduction (FP64), the half-lattice
+# stencil that forms S p; without it (mixed precision), the 4-D marching stencil
+STENCIL = {
+    (True, "fp64"): "k_eo_hop<tip::CovOp<HIP_vector_type<double, 2u> >, 1, 5>",
+    (True, "fp32"): "k_eo_hop<tip::CovOp<HIP_vector_type<float, 2u> >, 1, 5>",
+    (False, "fp64"): "k_stencil_march4<HIP_vector_type<double, 2u>, 5, false>",
+    (False, "fp32"): "k_stencil_march4<HIP_vector_type<float, 2u>, 5, false>",
+}
 
 
 def log(*a):
@@ -158,7 +163,7 @@ def main():
     ap.add_argument("--traffic-command", default="", help="command recorded with --traffic-from")
     args = ap.parse_args()
     if args.traffic_from:
-        write_traffic(args.traffic_from[0], args.traffic_from[1], STENCIL_FP64, args.traffic_command)
+        write_traffic(args.traffic_from[0], args.traffic_from[1], STENCIL[(True, "fp64")], args.traffic_command)
         return
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -192,7 +197,6 @@ def main():
     log(f"operator handle (link repack) {repack_s * 1e3:.1f} ms")
 
     n_rhs = args.n_vectors * 3
-    kernel_names = {tip.PREC_FP64: STENCIL_FP64, tip.PREC_MIXED: STENCIL_FP32}
 
     def timed(precision):
         """W warmup calls, then K timed calls of the whole path at one precision."""
@@ -202,7 +206,7 @@ def main():
             est, q, st = handle.trace_inv_probe(args.n_vectors, args.tol, args.seed, **kw)
             log(f"[{precision}] warmup {w}: {st['seconds']:.3f} s, {st['total_iters'] / st['solves']:.2f} it/solve")
         tot = {"launches": 0, "seconds": 0.0, "bytes": 0.0, "iters": 0, "solves": 0, "relres": 0.0, "ru": 0,
-               "bound": 0.0}
+               "bound": 0.0, "mv": 0, "mv_seconds": 0.0, "mv_bytes": 0.0, "eo": False}
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         for k in range(args.steps):
@@ -215,6 +219,10 @@ def main():
             tot["ru"] += st["reliable_updates"]
             tot["relres"] = max(tot["relres"], st["max_true_relres"])
             tot["bound"] = max(tot["bound"], st["max_quad_err_bound"])
+            tot["mv"] += st["matvecs"]
+            tot["mv_seconds"] += st["matvec_seconds"]
+            tot["mv_bytes"] += st["matvec_bytes"]
+            tot["eo"] = bool(st["even_odd"])
             log(f"[{precision}] step {k}: {st['seconds']:.3f} s, {st['solves']} solves, "
                 f"max rel.res {st['max_true_relres']:.2e}")
         torch.cuda.synchronize()
@@ -223,12 +231,17 @@ def main():
         avg_launch_s = tot["seconds"] / max(tot["launches"], 1)
         bytes_per_launch = tot["bytes"] / max(tot["launches"], 1)
         achieved = bytes_per_launch / avg_launch_s / 1e9 if avg_launch_s > 0 else 0.0
-        name = kernel_names[precision]
+        name = STENCIL[(tot["eo"], "fp64" if precision == tip.PREC_FP64 else "fp32")]
         roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": measured_traffic(name),
                 "kernel": name, "alg_bytes_per_launch": bytes_per_launch,
                 "avg_launch_us": round(avg_launch_s * 1e6, 2), "launches": tot["launches"]}
-        return {"value": n_rhs * args.steps / elapsed, "elapsed": elapsed, "roofline": roof, "est": est,
+        if tot["mv"] and tot["mv_seconds"] > 0:
+            # the whole operator application (both half-lattice kernels with the reduction)
+            roof["operator"] = {"applications": tot["mv"], "avg_us": round(tot["mv_seconds"] / tot["mv"] * 1e6, 2),
+                                "alg_bytes": tot["mv_bytes"] / tot["mv"],
+                                "achieved": round(tot["mv_bytes"] / tot["mv_seconds"] / 1e9, 1)}
+        return {"value": n_rhs * args.steps / elapsed, "elapsed": elapsed, "roofline": roof, "est": est, "eo": tot["eo"],
                 "iters_per_solve": tot["iters"] / max(tot["solves"], 1), "max_true_relres": tot["relres"],
                 "reliable_updates_per_step": tot["ru"] / args.steps, "max_quad_err_bound": tot["bound"]}
 
@@ -267,6 +280,7 @@ def main():
                                   f"{args.n_vectors} hierarchical probes x 3 = {n_rhs} CG solves, tol {args.tol:g}",
                       "lattice": DIMS, "n_vectors": args.n_vectors, "rhs_per_step": n_rhs, "tol": args.tol,
                       "mask": "Z4", "iters_per_solve": round(iters_per_solve, 2),
+                      "solver": "CG on the even-odd reduced system" if main["eo"] else "CG",
                       "max_true_relres": main["max_true_relres"], "repack_ms": round(repack_s * 1e3, 2)},
            "roofline": roofline, "cpu_baseline": cpu, "mixed_precision": mixed}
     print(json.dumps(out), flush=True)

@@ -108,6 +108,8 @@ struct tip_op_s {
   DevBuf links, mass_field, coupling;
   DevBuf links32;              // single-precision copy, made on first mixed-precision use
   DevBuf diag;                 // D(x) = m(x) + sum_mu [w_mu(x) + w_mu(x - mu)], FP64
+  DevBuf links_eo;             // covariant, every side even: links by parity (see k_repack_links_eo)
+  bool has_links_eo = false;
   bool has_mass_field = false, has_coupling = false, has_links32 = false;
   // lower bound of the spectrum: A = sum_e w_e L_e + diag(m) with L_e PSD, so
   // lambda_min >= min m(x) whenever every w_e >= 0 (NaN when not known)
@@ -124,6 +126,7 @@ struct tip_op_s {
     o.mass_field = has_mass_field ? (const double*)mass_field.p : nullptr;
     o.coupling = has_coupling ? (const double*)coupling.p : nullptr;
     o.links = kind == 1 ? (const double*)(single ? links32.p : links.p) : nullptr;
+    o.links_eo = kind == 1 && !single && has_links_eo ? (const double*)links_eo.p : nullptr;
     return o;
   }
   ~tip_op_s() {
@@ -173,6 +176,14 @@ tip_status create_handle(const tip_operator* op, hipStream_t st, tip_op_s** out)
     if (h->links.ensure(n) != hipSuccess) return bail(fail(TIP_ENOMEM, "hipMalloc links (%zu bytes)", n));
     if (launch_repack_links(g, (const double2*)op->links, (double2*)h->links.p, st) != hipSuccess)
       return bail(fail(TIP_EDEVICE, "link repack launch failed"));
+    bool bip = true;
+    for (int mu = 0; mu < g.ndim; ++mu) bip = bip && g.logn[mu] >= 1;
+    if (bip) {
+      if (h->links_eo.ensure(n) != hipSuccess) return bail(fail(TIP_ENOMEM, "hipMalloc even-odd links (%zu bytes)", n));
+      if (launch_repack_links_eo(g, (const double2*)h->links.p, (double2*)h->links_eo.p, st) != hipSuccess)
+        return bail(fail(TIP_EDEVICE, "even-odd link repack launch failed"));
+      h->has_links_eo = true;
+    }
   }
   if (h->diag.ensure(V * sizeof(double)) != hipSuccess) return bail(fail(TIP_ENOMEM, "hipMalloc diagonal"));
   if (launch_diag(g, h->has_mass_field ? (const double*)h->mass_field.p : nullptr, op->mass,
@@ -271,11 +282,10 @@ bool env_on(const char* name) {
 // the sides allow, then pick the round (b2 x b3 rows of n1/TS tiles each) of at
 // most `round_tiles` tiles that leaves the fewest x2 / x3 neighbour rows
 // outside it.  TIP_MARCH_ORDER="g2,b2,b3" overrides the choice.
-bool plan_block_order(const Geom& g, int TS, MarchMap* mm) {
+bool plan_block_order(const Geom& g, int TS, MarchMap* mm, int round_tiles) {
   const int n1 = 1 << g.logn[0], n2 = 1 << g.logn[1], n3 = 1 << g.logn[2];
   if (TS > n1 || n1 % TS != 0) return false;
   const int n1t = n1 / TS;
-  int round_tiles = 128;
   if (const char* e = std::getenv("TIP_ROUND_TILES")) round_tiles = std::max(1, std::atoi(e));
   int best_g2 = -1;
   double best_shape = 1e30;
@@ -353,7 +363,9 @@ bool make_marchmap(const Geom& g, int logB, MarchMap* mm, bool halve_t = false) 
   }
   mm->Tc = Tc;
   mm->xcd_order = !env_off("TIP_TILE_ORDER") && mm->Q % kNumXcd == 0;
-  if (mm->xcd_order && g.ndim == 4 && plan_block_order(g, TS, mm)) mm->xcd_order = 2;
+  // rounds of 128 tiles for the full stencil, 256 for the half-lattice one
+  // (measured on the 32^4 covariant workload)
+  if (mm->xcd_order && g.ndim == 4 && plan_block_order(g, TS, mm, halve_t ? 256 : 128)) mm->xcd_order = 2;
   if (const char* e = std::getenv("TIP_TILE_ORDER")) {
     if (std::atoi(e) == 1 && mm->xcd_order == 2) mm->xcd_order = 1;
   }
@@ -483,7 +495,8 @@ struct Solver {
       pl.eo = !mixed && bip && h->lambda_lb > 0.0 && !env_off("TIP_EO") &&
               make_marchmap(g, pl.logB, &pl.me, true);
       // the covariant half-lattice kernel stages its tile's links in LDS
-      if (pl.eo && h->kind == TIP_KIND_COVARIANT && eo_lds_bytes(g, pl.me, prec) > 65536) pl.eo = false;
+      if (pl.eo && h->kind == TIP_KIND_COVARIANT && (eo_lds_bytes(g, pl.me, prec) > 65536 || !h->has_links_eo))
+        pl.eo = false;
     }
     max_iter = p->max_iter > 0 ? p->max_iter : (int)std::min<int64_t>(10 * V * ncomp, 1 << 20);
     tol2 = p->tol * p->tol;

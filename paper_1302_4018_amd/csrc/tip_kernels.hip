@@ -1154,17 +1154,33 @@ __global__ __launch_bounds__(kBlock) void k_eo_hop(Geom g, MarchMap mm, int P, O
       // stage the tile's links: slots 0..ndim-1 forward U_mu(s), ndim..2ndim-1 backward U_mu(s - mu)
       __syncthreads();
       const int nslot = 2 * ndim;
+      // op.U holds the even-odd link layout [parity][mu][9][V/2]: forward
+      // links of the tile's own sites (parity P, index x + V3 tau), backward
+      // ones at the neighbours of parity 1 - P (same slice for spatial mu,
+      // slice tau - 1 + delta along t)
       for (int it = threadIdx.x; it < nslot * 9 * TS; it += kBlock) {
         const int site = it % TS;
         const int es = it / TS;
         const int e = es % 9;
         const int slot = es / 9;
         const uint32_t x3 = s3_first + (uint32_t)site;
-        const uint32_t dl = ((uint32_t)P + spatial_parity(x3, g)) & 1u;
-        const uint32_t ss = x3 + V3 * (2u * tau + dl);
-        const int mu = slot < ndim ? slot : slot - ndim;
-        const uint32_t sl = slot < ndim ? ss : nbr_bwd(ss, g, mu);
-        lds_links[it] = op.U[((size_t)mu * 9 + e) * V + sl];
+        uint32_t hl, par;
+        int mu;
+        if (slot < ndim) {
+          mu = slot;
+          par = (uint32_t)P;
+          hl = x3 + V3 * tau;
+        } else {
+          mu = slot - ndim;
+          par = 1u - (uint32_t)P;
+          if (mu < tdim) {
+            hl = nbr_bwd(x3, g, mu) + V3 * tau;
+          } else {
+            const uint32_t dl = ((uint32_t)P + spatial_parity(x3, g)) & 1u;
+            hl = x3 + V3 * ((tau + ntau - 1u + dl) % ntau);
+          }
+        }
+        lds_links[it] = op.U[(((size_t)par * ndim + mu) * 9 + e) * Vh + hl];
       }
       __syncthreads();
     }
@@ -1536,7 +1552,9 @@ hipError_t launch_eo_hop(int mode, const OpDev& od, const Geom& g, const MarchMa
                          const double* diag, const int* state, const int* active, const void* in, const void* cin,
                          void* out, void* out2, void* out3, int64_t rhs0, int nb, uint64_t seed, int mask,
                          double* partial, int* ran, hipStream_t st) {
-  return dispatch(od, elem, prec, [&](auto op) {
+  OpDev oe = od;
+  oe.links = od.links_eo;
+  return dispatch(oe, elem, prec, [&](auto op) {
     using Op = decltype(op);
     using T = typename Op::T;
     const size_t lds = Op::NC == 3 ? eo_lds_bytes(g, mm, prec) : 0;
@@ -1641,6 +1659,30 @@ hipError_t launch_hier_perm(const Geom& g, uint32_t* out, hipStream_t st) {
 hipError_t launch_probe_vectors(const Geom& g, uint64_t seed, int mask, int64_t m0, int count, int comp, double2* out,
                                 hipStream_t st) {
   k_probe_vectors<<<dim3(cdiv(g.V, kBlock), count), kBlock, 0, st>>>(g, seed, mask, m0, comp, out);
+  return hipGetLastError();
+}
+
+// Links of the even-odd kernels: [parity][mu][9][V/2], the site of parity P at
+// half-lattice index h holding U_mu(site) at [P][mu][e][h].  A tile of
+// consecutive h then reads whole cache lines of links (in the full-lattice
+// layout its sites alternate between two t planes).
+__global__ __launch_bounds__(kBlock) void k_repack_links_eo(Geom g, const double2* __restrict__ links,
+                                                            double2* __restrict__ dst) {
+  const uint32_t s = blockIdx.x * kBlock + threadIdx.x;
+  if (s >= g.V) return;
+  const int mu = blockIdx.y;
+  const int tdim = g.ndim - 1;
+  const uint32_t t = coord(s, g, tdim);
+  const uint32_t P = (spatial_parity(s, g) + t) & 1u;
+  const uint32_t V3 = 1u << g.shift[tdim];
+  const uint32_t h = (s & (V3 - 1u)) + V3 * (t >> 1);
+  const size_t V = g.V, Vh = V >> 1;
+#pragma unroll
+  for (int e = 0; e < 9; ++e) dst[(((size_t)P * g.ndim + mu) * 9 + e) * Vh + h] = links[((size_t)mu * 9 + e) * V + s];
+}
+
+hipError_t launch_repack_links_eo(const Geom& g, const double2* links, double2* dst, hipStream_t st) {
+  k_repack_links_eo<<<dim3(cdiv(g.V, kBlock), g.ndim), kBlock, 0, st>>>(g, links, dst);
   return hipGetLastError();
 }
 

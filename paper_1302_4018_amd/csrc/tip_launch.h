@@ -22,6 +22,7 @@ struct OpDev {
   const double* mass_field;    // [V] or null
   const double* coupling;      // [ndim][V] or null
   const double* links;         // [ndim][9][V] double2 (covariant)
+  const double* links_eo;      // [2][ndim][9][V/2] double2, even-odd kernels (covariant, or null)
 };
 
 // Per right-hand-side CG scalars, device arrays of length B (q: 2B).
@@ -165,6 +166,7 @@ hipError_t launch_reduce_true(const CgScalars& sc, int B, const double* partial,
 hipError_t launch_hier_perm(const Geom& g, uint32_t* out, hipStream_t st);
 hipError_t launch_probe_vectors(const Geom& g, uint64_t seed, int mask, int64_t m0, int count, int comp, double2* out,
                                 hipStream_t st);
+hipError_t launch_repack_links_eo(const Geom& g, const double2* links, double2* dst, hipStream_t st);
 hipError_t launch_repack_links(const Geom& g, const double2* src, double2* dst, hipStream_t st);
 // [V][ncomp] <-> lane `lane` of the block layout [ncomp][V][2^logB] (FP64)
 hipError_t launch_layout(const Geom& g, Elem elem, int logB, int lane, const void* src, void* dst,
