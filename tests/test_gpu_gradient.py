@@ -187,3 +187,16 @@ def test_autograd_function():
     # no gradient asked: the plain run
     with torch.no_grad():
         assert float(trace_inv(mf, w, U, **kw)) == float(T)
+
+
+def test_c1_uniform_mass_gradient_closed_form():
+    """16^2 free torus, m = 0.1, all 256 probes: the GPU gradient summed over
+    sites is d Tr(A^-1)/dm = -sum_k lambda(k)^-2 = -231.195071582666."""
+    tip = gpu_binding()
+    import torch
+    gop = tip.Operator([16, 16], tip.KIND_SCALAR, mass_field=torch.full((256,), 0.1, dtype=torch.float64,
+                                                                        device="cuda"))
+    with tip.OpHandle(gop) as h:
+        est, q, gm, gw, st = h.trace_inv_probe_grad(256, 1e-13, 4018)
+    assert abs(float(gm.sum()) - (-231.195071582666)) <= 1e-9 * 231.195071582666
+    assert abs(est[-1].real - 116.949743403339) <= 1e-10 * 116.949743403339

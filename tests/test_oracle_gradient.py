@@ -128,3 +128,12 @@ def test_probe_grad_finite_differences_below_V(kind, mk):
         tp = _partial_sum_T(Operator(dims, kind, mass_field=mf, coupling=w + d, links=U), 2, seed, mk)
         tm = _partial_sum_T(Operator(dims, kind, mass_field=mf, coupling=w - d, links=U), 2, seed, mk)
         assert abs((tp - tm) / (2 * h) - gw[mu, y]) <= 1e-6 * np.max(np.abs(gw))
+
+
+def test_c1_uniform_mass_gradient_closed_form():
+    """16^2 free torus, m = 0.1: d Tr(A^-1)/dm = -sum_k lambda(k)^-2 = -231.195071582666,
+    recovered by the probe gradient at s = V (Z2 mask) summed over sites."""
+    op = Operator([16, 16], 0, mass=0.1)
+    T, gm, gw, _ = trace_inv_probe_grad(op, 256, 1e-13, 4018, mask.MASK_Z2)
+    assert abs(gm.sum() - (-231.195071582666)) <= 1e-9 * 231.195071582666
+    assert abs(T.real - 116.949743403339) <= 1e-10 * 116.949743403339
