@@ -30,7 +30,8 @@ sys.path.insert(0, ROOT)
 DIMS = [32, 32, 32, 32]
 HBM_PEAK_GBS = 8000.0
 METRIC = "probing-vector solves/sec (4D 32^4, rel.res 1e-10) + stencil HBM GB/s vs peak"
-KERNEL_SOURCES = ["paper_1302_4018_amd/csrc/tip_kernels.hip", "paper_1302_4018_amd/csrc/tip_device.h"]
+KERNEL_SOURCES = ["paper_1302_4018_amd/csrc/tip_kernels.hip", "paper_1302_4018_amd/csrc/tip_device.h",
+                  "paper_1302_4018_amd/csrc/tip_launch.h"]
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "stencil_traffic.json")
 # the dominant kernel: with the even-odd reduction (FP64), the half-lattice
 # stencil that forms S p; without it (mixed precision), the 4-D marching stencil
