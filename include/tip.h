@@ -24,9 +24,13 @@
  *
  * Conventions shared by every entry point
  * ---------------------------------------
- * Lattice: ndim in 1..4, sides dims[0..ndim-1] = n_1..n_ndim, each a power of
- *   two >= 1 (Sec. 3); V = prod n_j <= 2^31.  Sites are numbered
- *   s = x_1 + n_1 (x_2 + n_2 (x_3 + n_3 x_4)).
+ * Lattice: ndim in 1..4, sides dims[0..ndim-1] = n_1..n_ndim >= 1; V = prod n_j
+ *   <= 2^31.  Sites are numbered s = x_1 + n_1 (x_2 + n_2 (x_3 + n_3 x_4)).
+ *   Sides that are powers of two give the hierarchical probing of Sec. 3 and
+ *   the fastest kernels.  Other sides n_j = 2^{k_j} p_j (p_j odd) follow
+ *   Sec. 3.4: binary red-black levels while every side with a remaining size
+ *   above 1 is even, then one level coloured by the three-colouring theorem of
+ *   Sec. 3.4 (see "Right-hand sides").
  * Operator: A = sum_e w_e L_e + diag(m(x)) (x) I_ncomp over the edges e = (x, x+mu)
  *   of the torus (the shifted periodic Laplacian of Sec. 5), with
  *     TIP_KIND_SCALAR    (ncomp = 1): L_e = [[1, -1], [-1, 1]];
@@ -43,6 +47,13 @@
  *   z0(y, c) uses counter n = y * ncomp + c of SplitMix64(seed) (state
  *   seed + (n+1) * 0x9E3779B97F4A7C15, then the published 64-bit mix):
  *   Z2: +1 / -1 from the top output bit; Z4: i^t, t = the top two bits.
+ *   Sides with odd factors: P(y) is the binary colour over the B binary
+ *   levels (LB bits) and gamma = 2^LB (x 3 with a three-colouring level)
+ *   colours make one sweep.  Probe m = r gamma + j takes column j of the
+ *   general recursion eq. Hperm-general-recursive: H(P(y), bitrev_LB(j mod
+ *   2^LB)) times w^{(j >> LB) C(y)}, w = -1/2 + i sqrt(3)/2 and C the
+ *   three-colouring of the sub-torus y >> B; sweep r uses mask outputs
+ *   n = (r V + y) ncomp + c.  Probes past 2^LB are complex (complex solves).
  * Memory: every pointer documented as "device" is caller-owned device memory
  *   and is never freed by the library; "host" pointers likewise.  Complex
  *   numbers are interleaved (re, im) float64 pairs.
@@ -196,7 +207,8 @@ tip_status tip_solve_probe(tip_op_handle h, const tip_params* p, int64_t m, int3
 tip_status tip_apply_operator(const tip_operator* op, int32_t nrhs,
                               const double* x, double* y, void* stream);
 
-/* P(x) of every site (Alg. 5): DEVICE uint32 [V]. */
+/* P(x) of every site (Alg. 5): DEVICE uint32 [V].  With odd factors in the
+ * sides: the binary colour over the B binary levels, in [0, 2^LB). */
 tip_status tip_hier_perm(int32_t ndim, const int64_t* dims, uint32_t* P_out, void* stream);
 
 /* Probing vectors b_{m,comp}(y, comp) = z0(y, comp) H(P(y), bitrev_L(m)) for

@@ -15,14 +15,14 @@ edge matrix L_e of e = (y, y+mu), whose quadratic form is
 ||x(y) - U_mu(y) x(y+mu)||^2 (U = 1 for the scalar operator).
 
 The solves are the oracle's CG solves (textbook CG with a true-residual
-acceptance test); nothing here is blocked or fused.
+acceptance test) of the probes of oracle/general.py, which are Alg. 5's on
+power-of-two sides; nothing here is blocked or fused.
 """
 
 import numpy as np
 
 from .cg import cg_solve
-from .hierperm import hier_perm
-from .probing import rhs
+from .general import Levels, binary_colour, last_level_colour, rhs
 
 
 def edge_forms(op, x):
@@ -54,14 +54,15 @@ def trace_inv_probe_grad(op, n_vectors, tol, seed, mask_kind, max_iter=None):
     """
     if max_iter is None:
         max_iter = 10 * op.V * op.ncomp
-    P = hier_perm(op.dims)
+    lv = Levels(op.dims)
+    PB, C = binary_colour(op.dims, lv), last_level_colour(op.dims, lv)
     gm = np.zeros(op.V)
     gw = np.zeros((op.ndim, op.V))
     total = 0.0 + 0.0j
     iters = []
     for m in range(n_vectors):
         for c in range(op.ncomp):
-            b = rhs(op.dims, op.ncomp, m, c, seed, mask_kind, P)
+            b = rhs(op.dims, op.ncomp, m, c, seed, mask_kind, lv, PB, C)
             if op.kind == 0 and np.all(b.imag == 0):
                 b = b.real
             x, it, _ = cg_solve(op.apply, b, tol, max_iter)

@@ -57,19 +57,49 @@ tip_status make_geom(int32_t ndim, const int64_t* dims, int ncomp, Geom* g) {
   g->ndim = ndim;
   g->ncomp = ncomp;
   int64_t V = 1;
-  int shift = 0;
+  bool pow2 = true;
   for (int j = 0; j < ndim; ++j) {
-    if (!is_pow2(dims[j])) return fail(TIP_EINVAL, "dims[%d] = %lld is not a power of two >= 1", j, (long long)dims[j]);
-    const int k = ilog2(dims[j]);
-    g->logn[j] = k;
-    g->shift[j] = shift;
-    shift += k;
-    g->nlevels = std::max(g->nlevels, k);
+    if (dims[j] < 1) return fail(TIP_EINVAL, "dims[%d] = %lld must be >= 1", j, (long long)dims[j]);
+    if (V * dims[j] > (int64_t(1) << 31)) return fail(TIP_EINVAL, "lattice volume exceeds 2^31 sites");
+    g->n[j] = (uint32_t)dims[j];
+    g->stride[j] = (uint32_t)V;
     V *= dims[j];
-    if (V > (int64_t(1) << 31)) return fail(TIP_EINVAL, "lattice volume exceeds 2^31 sites");
+    pow2 = pow2 && is_pow2(dims[j]);
   }
   g->V = (uint32_t)V;
-  g->L = shift;
+  g->pow2 = pow2 ? 1 : 0;
+  if (pow2) {
+    int shift = 0;
+    for (int j = 0; j < ndim; ++j) {
+      const int k = ilog2(dims[j]);
+      g->logn[j] = k;
+      g->shift[j] = shift;
+      shift += k;
+      g->nlevels = std::max(g->nlevels, k);
+    }
+    g->L = shift;
+  }
+  // levels of the probing colouring: binary levels while every side with a
+  // remaining size above 1 is even, then one three-colouring level when a
+  // side has an odd factor (Sec. 3.4)
+  int kmin_odd = 1 << 30, kmax = 0;
+  bool odd = false;
+  for (int j = 0; j < ndim; ++j) {
+    int64_t n = dims[j];
+    int k = 0;
+    while (n % 2 == 0) n /= 2, ++k;
+    g->k2[j] = k;
+    kmax = std::max(kmax, k);
+    if (n > 1) odd = true, kmin_odd = std::min(kmin_odd, k);
+  }
+  g->B = odd ? kmin_odd : kmax;
+  g->LB = 0;
+  for (int m = 0; m < g->B; ++m)
+    for (int j = 0; j < ndim; ++j) g->LB += g->k2[j] > m ? 1 : 0;
+  g->has3 = odd ? 1 : 0;
+  for (int j = 0; j < ndim; ++j) g->sub[j] = (uint32_t)(dims[j] >> g->B);
+  const uint64_t gamma = (uint64_t(1) << g->LB) * (odd ? 3u : 1u);
+  g->gamma = (uint32_t)std::min<uint64_t>(gamma, uint64_t(1) << 31);
   return TIP_OK;
 }
 
@@ -176,7 +206,7 @@ tip_status create_handle(const tip_operator* op, hipStream_t st, tip_op_s** out)
     if (h->links.ensure(n) != hipSuccess) return bail(fail(TIP_ENOMEM, "hipMalloc links (%zu bytes)", n));
     if (launch_repack_links(g, (const double2*)op->links, (double2*)h->links.p, st) != hipSuccess)
       return bail(fail(TIP_EDEVICE, "link repack launch failed"));
-    bool bip = true;
+    bool bip = g.pow2 != 0;
     for (int mu = 0; mu < g.ndim; ++mu) bip = bip && g.logn[mu] >= 1;
     if (bip) {
       if (h->links_eo.ensure(n) != hipSuccess) return bail(fail(TIP_ENOMEM, "hipMalloc even-odd links (%zu bytes)", n));
@@ -259,8 +289,8 @@ TileMap make_tilemap(const Geom& g, int logB) {
   tm.grid = (uint32_t)ntiles;
   // XCD-aware order: whole tiles, a tile count divisible by the XCD count and
   // whole planes of the last dimension per XCD chunk (TIP_TILE_ORDER=0: off).
-  const int64_t n_last = int64_t(1) << g.logn[g.ndim - 1];
-  if (!env_off("TIP_TILE_ORDER") && V % tm.TS == 0 && ntiles % kNumXcd == 0 && ntiles % n_last == 0) {
+  const int64_t n_last = g.n[g.ndim - 1];
+  if (g.pow2 && !env_off("TIP_TILE_ORDER") && V % tm.TS == 0 && ntiles % kNumXcd == 0 && ntiles % n_last == 0) {
     const int64_t P = ntiles / n_last, C = ntiles / kNumXcd;
     if (C % P == 0) {
       tm.pc = (int32_t)(C / P);
@@ -343,6 +373,7 @@ bool block_order_is_permutation(const MarchMap& mm) {
 
 // halve_t: march the half-lattice of the even-odd system (t slices of two).
 bool make_marchmap(const Geom& g, int logB, MarchMap* mm, bool halve_t = false) {
+  if (!g.pow2) return false;                         // the marching kernels index with shifts
   if (!halve_t && (env_off("TIP_MARCH") || g.ndim < 2)) return false;
   const int nt = (1 << g.logn[g.ndim - 1]) >> (halve_t ? 1 : 0);
   if (nt < (halve_t ? 1 : 2)) return false;
@@ -465,7 +496,10 @@ struct Solver {
     const int64_t V = g.V;
     const int ncomp = g.ncomp;
     pl.mask = mask;
-    pl.elem = (h->kind == TIP_KIND_COVARIANT || mask == TIP_MASK_Z4) ? Elem::kComplex : Elem::kReal;
+    // complex solves: covariant operator, Z4 mask, or a probe past the binary
+    // columns (F_3 columns of the three-colouring level are complex)
+    const bool f3 = g.has3 && p->n_vectors > (int64_t(1) << g.LB);
+    pl.elem = (h->kind == TIP_KIND_COVARIANT || mask == TIP_MASK_Z4 || f3) ? Elem::kComplex : Elem::kReal;
     const size_t esz64 = pl.elem == Elem::kReal ? sizeof(double) : sizeof(double2);
     pl.esz = mixed ? esz64 / 2 : esz64;
     // block size: a power of two <= 64; 32 shares each link among 32 solves;
@@ -490,7 +524,7 @@ struct Solver {
     // even-odd reduction: bipartite torus (every side >= 2, all powers of two
     // are then even) and a positive diagonal (lambda_lb > 0 implies D > 0)
     {
-      bool bip = true;
+      bool bip = g.pow2 != 0;
       for (int mu = 0; mu < g.ndim; ++mu) bip = bip && g.logn[mu] >= 1;
       pl.eo = !mixed && bip && h->lambda_lb > 0.0 && !env_off("TIP_EO") &&
               make_marchmap(g, pl.logB, &pl.me, true);

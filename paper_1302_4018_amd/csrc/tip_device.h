@@ -21,29 +21,51 @@ struct Geom {
   int32_t ndim;
   int32_t ncomp;
   uint32_t V;
-  int32_t L;                 // sum_j k_j = log2 V
-  int32_t nlevels;           // max_j k_j
-  int32_t logn[kMaxDim];     // k_j
-  int32_t shift[kMaxDim];    // log2 of the site-index stride of dimension j
+  int32_t L;                 // sum_j k_j = log2 V (power-of-two sides)
+  int32_t nlevels;           // max_j k_j (power-of-two sides)
+  int32_t logn[kMaxDim];     // k_j (power-of-two sides)
+  int32_t shift[kMaxDim];    // log2 of the site-index stride of dimension j (power-of-two sides)
+  // any sides
+  int32_t pow2;              // every side a power of two: logn / shift above are valid
+  uint32_t n[kMaxDim];       // sides
+  uint32_t stride[kMaxDim];  // site-index stride of dimension j
+  // levels of the probing colouring (Sec. 3; Sec. 3.4 for odd factors)
+  int32_t k2[kMaxDim];       // 2-adic valuation of n_j
+  int32_t B;                 // binary levels (= nlevels for power-of-two sides)
+  int32_t LB;                // bits of the binary colour (= L for power-of-two sides)
+  int32_t has3;              // a three-colouring level follows the binary ones
+  uint32_t sub[kMaxDim];     // sides n_j >> B of the sub-torus it colours
+  uint32_t gamma;            // colours of one sweep: 2^LB, times 3 with that level
 };
 
 constexpr int kLdsPerCu = 160 * 1024;   // gfx950 LDS per CU
 constexpr int kNumXcd = 8;   // MI355X: 8 XCDs, each with its own L2
 
-__device__ __forceinline__ uint32_t coord(uint32_t s, const Geom& g, int mu) {
+// Coordinate and periodic neighbours of a site.  The _p2 forms use shifts
+// and serve the kernels that only run on power-of-two sides; the plain forms
+// take any sides.
+__device__ __forceinline__ uint32_t coord_p2(uint32_t s, const Geom& g, int mu) {
   return (s >> g.shift[mu]) & ((1u << g.logn[mu]) - 1u);
 }
-
-// s + mu_hat and s - mu_hat with periodic wrap.
-__device__ __forceinline__ uint32_t nbr_fwd(uint32_t s, const Geom& g, int mu) {
+__device__ __forceinline__ uint32_t nbr_fwd_p2(uint32_t s, const Geom& g, int mu) {
   const uint32_t n = 1u << g.logn[mu];
   const uint32_t stride = 1u << g.shift[mu];
-  return coord(s, g, mu) == n - 1u ? s - (n - 1u) * stride : s + stride;
+  return coord_p2(s, g, mu) == n - 1u ? s - (n - 1u) * stride : s + stride;
+}
+__device__ __forceinline__ uint32_t nbr_bwd_p2(uint32_t s, const Geom& g, int mu) {
+  const uint32_t n = 1u << g.logn[mu];
+  const uint32_t stride = 1u << g.shift[mu];
+  return coord_p2(s, g, mu) == 0u ? s + (n - 1u) * stride : s - stride;
+}
+__device__ __forceinline__ uint32_t coord(uint32_t s, const Geom& g, int mu) {
+  if (g.pow2) return coord_p2(s, g, mu);
+  return (s / g.stride[mu]) % g.n[mu];
+}
+__device__ __forceinline__ uint32_t nbr_fwd(uint32_t s, const Geom& g, int mu) {
+  return coord(s, g, mu) == g.n[mu] - 1u ? s - (g.n[mu] - 1u) * g.stride[mu] : s + g.stride[mu];
 }
 __device__ __forceinline__ uint32_t nbr_bwd(uint32_t s, const Geom& g, int mu) {
-  const uint32_t n = 1u << g.logn[mu];
-  const uint32_t stride = 1u << g.shift[mu];
-  return coord(s, g, mu) == 0u ? s + (n - 1u) * stride : s - stride;
+  return coord(s, g, mu) == 0u ? s + (g.n[mu] - 1u) * g.stride[mu] : s - g.stride[mu];
 }
 
 // Location of site s in the hierarchical permutation (Sec. 3.3, Alg. 5).
@@ -53,17 +75,20 @@ __device__ __forceinline__ uint32_t nbr_bwd(uint32_t s, const Geom& g, int mu) {
 // the one-bits of i, which is what c_j = [c_{j-1}, not c_{j-1}] unrolls to).
 // The Theorem of Sec. 3.3 makes the a-dimensional table the one to use when
 // only a dimensions are active, so no d-dimensional table is needed.
+// With odd factors in the sides only the B binary levels are taken (dimension
+// j active at level m while m < k_j, its 2-adic valuation); the result is
+// then the binary colour of the site, in [0, 2^LB).
 __device__ __forceinline__ uint32_t hier_perm(uint32_t s, const Geom& g) {
   uint32_t x[kMaxDim];
 #pragma unroll
   for (int mu = 0; mu < kMaxDim; ++mu) x[mu] = mu < g.ndim ? coord(s, g, mu) : 0u;
   uint32_t loc = 0;
-  for (int m = 0; m < g.nlevels; ++m) {
+  for (int m = 0; m < g.B; ++m) {
     uint32_t idx = 0;
     int a = 0;
 #pragma unroll
     for (int mu = 0; mu < kMaxDim; ++mu) {
-      if (mu < g.ndim && m < g.logn[mu]) {
+      if (mu < g.ndim && m < g.k2[mu]) {
         idx = (idx << 1) | ((x[mu] >> m) & 1u);
         ++a;
       }
@@ -96,20 +121,68 @@ __device__ __forceinline__ uint64_t splitmix64_at(uint64_t seed, uint64_t n) {
 
 enum MaskKind { kMaskNone = 0, kMaskZ2 = 1, kMaskZ4 = 2 };
 
-// Entry (s, comp) of the probing right-hand side b_{m,comp} = z0 .* z_m:
-// (re, im), each exactly 0 or +-1.
-__device__ __forceinline__ double2 probe_value(uint32_t s, uint32_t P, uint32_t col, int comp,
-                                               const Geom& g, uint64_t seed, int mask) {
-  const double h = hadamard_sign(P, col);
-  if (mask == kMaskNone) return make_double2(h, 0.0);
-  const uint64_t u = splitmix64_at(seed, (uint64_t)s * (uint64_t)g.ncomp + (uint64_t)comp);
-  if (mask == kMaskZ2) return make_double2((u >> 63) ? -h : h, 0.0);
-  switch ((int)(u >> 62)) {            // i^t
-    case 0: return make_double2(h, 0.0);
-    case 1: return make_double2(0.0, h);
-    case 2: return make_double2(-h, 0.0);
-    default: return make_double2(0.0, -h);
+// Three-colouring of Sec. 3.4 on the sub-torus y_j = x_j >> B (sides sub_j):
+// C = (sum_j y_j + sum_j delta_j) mod 3, delta_j = 1 iff y_j = sub_j - 1 and
+// (sub_j - 1) mod 3 = 0; sides of 1 take no part.
+__device__ __forceinline__ uint32_t three_colour(uint32_t s, const Geom& g) {
+  uint32_t total = 0;
+#pragma unroll
+  for (int mu = 0; mu < kMaxDim; ++mu) {
+    if (mu >= g.ndim || g.sub[mu] <= 1u) continue;
+    const uint32_t y = coord(s, g, mu) >> g.B;
+    total += y + ((y == g.sub[mu] - 1u && (g.sub[mu] - 1u) % 3u == 0u) ? 1u : 0u);
   }
+  return total % 3u;
+}
+
+// Column of probe m: sweep r = m / gamma, within it column j = m mod gamma
+// with binary part j mod 2^LB (Hadamard column through eq. HpermSequence)
+// and F_3 part j3 = j >> LB (eq. Hperm-general-recursive, newest level's
+// column most significant).
+struct ProbeCol {
+  uint32_t col;   // Hadamard column
+  uint32_t j3;    // F_3 column, 0 without the three-colouring level
+  uint32_t r;     // mask sweep
+};
+__device__ __forceinline__ ProbeCol probe_column(uint64_t m, const Geom& g) {
+  ProbeCol pc;
+  pc.r = (uint32_t)(m / g.gamma);
+  const uint64_t j = m % g.gamma;
+  pc.j3 = (uint32_t)(j >> g.LB);
+  pc.col = hadamard_column((uint32_t)(j & ((1ull << g.LB) - 1ull)), g.LB);
+  return pc;
+}
+
+// Entry (s, comp) of the probing right-hand side b_{m,comp} = z0_r .* z_m:
+// (re, im), each exactly 0 or +-1 except the F_3 factor w^k, whose parts are
+// -1/2 and +-(the double nearest sqrt(3)/2).  z0_r takes outputs
+// (r V + s) ncomp + comp of SplitMix64(seed).
+__device__ __forceinline__ double2 probe_value(uint32_t s, uint32_t P, ProbeCol pc, int comp, const Geom& g,
+                                               uint64_t seed, int mask) {
+  const double h = hadamard_sign(P, pc.col);
+  double2 v = make_double2(h, 0.0);
+  if (mask != kMaskNone) {
+    const uint64_t n = ((uint64_t)pc.r * (uint64_t)g.V + (uint64_t)s) * (uint64_t)g.ncomp + (uint64_t)comp;
+    const uint64_t u = splitmix64_at(seed, n);
+    if (mask == kMaskZ2) {
+      v = make_double2((u >> 63) ? -h : h, 0.0);
+    } else {
+      switch ((int)(u >> 62)) {            // i^t
+        case 0: v = make_double2(h, 0.0); break;
+        case 1: v = make_double2(0.0, h); break;
+        case 2: v = make_double2(-h, 0.0); break;
+        default: v = make_double2(0.0, -h); break;
+      }
+    }
+  }
+  if (pc.j3 != 0u) {
+    const uint32_t k = (three_colour(s, g) * pc.j3) % 3u;
+    if (k != 0u) {
+      const double wr = -0.5, wi = k == 1u ? 0.8660254037844386 : -0.8660254037844386;
+      v = make_double2(v.x * wr - v.y * wi, v.x * wi + v.y * wr);
+    }
+  }
+  return v;
 }
 
 // ---- complex helpers (double2 = re, im) ----------------------------------

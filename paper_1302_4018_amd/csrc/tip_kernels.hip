@@ -298,7 +298,7 @@ __global__ __launch_bounds__(kBlock) void k_stencil_march(Geom g, MarchMap mm, O
         const int slot = es / 9;
         const uint32_t ss = s3_first + (uint32_t)site + V3 * (uint32_t)t;
         const int mu = slot < g.ndim ? slot : slot - g.ndim;
-        const uint32_t sl = slot < g.ndim ? ss : nbr_bwd(ss, g, mu);
+        const uint32_t sl = slot < g.ndim ? ss : nbr_bwd_p2(ss, g, mu);
         lds_links[it] = op.U[((size_t)mu * 9 + e) * V + sl];
       }
       __syncthreads();
@@ -310,8 +310,8 @@ __global__ __launch_bounds__(kBlock) void k_stencil_march(Geom g, MarchMap mm, O
     for (int c = 0; c < NC; ++c) hop[c] = zero<T>();
     double diag = mass_field ? mass_field[s] : mass;
     for (int mu = 0; mu < mt; ++mu) {
-      const uint32_t sf = nbr_fwd(s, g, mu);
-      const uint32_t sb = nbr_bwd(s, g, mu);
+      const uint32_t sf = nbr_fwd_p2(s, g, mu);
+      const uint32_t sb = nbr_bwd_p2(s, g, mu);
       const double wf = w ? w[(size_t)mu * V + s] : 1.0;
       const double wb = w ? w[(size_t)mu * V + sb] : 1.0;
       diag += wf + wb;
@@ -605,12 +605,13 @@ __global__ __launch_bounds__(kBlock) void k_direction(size_t n, int logB, const 
 // component c = (rhs0 + j) % ncomp.
 // ---------------------------------------------------------------------------
 
-// Parity of the first ndim-1 coordinates of a site (or of a spatial index).
+// Parity of the first ndim-1 coordinates of a site (or of a spatial index);
+// power-of-two sides (the even-odd kernels run only there).
 __device__ __forceinline__ uint32_t spatial_parity(uint32_t s3, const Geom& g) {
   uint32_t sum = 0;
 #pragma unroll
   for (int mu = 0; mu < kMaxDim - 1; ++mu)
-    if (mu < g.ndim - 1) sum += coord(s3, g, mu);
+    if (mu < g.ndim - 1) sum += coord_p2(s3, g, mu);
   return sum & 1u;
 }
 
@@ -622,8 +623,7 @@ __device__ __forceinline__ void rhs_at(const Geom& g, uint32_t s, uint32_t P, in
   if (j >= nb) return;
   const int64_t rg = rhs0 + j;
   const int cj = (int)(rg % NC);
-  const uint32_t col = hadamard_column((uint32_t)(rg / NC), g.L);
-  const T v = from_c<T>(probe_value(s, P, col, cj, g, seed, mask));
+  const T v = from_c<T>(probe_value(s, P, probe_column((uint64_t)(rg / NC), g), cj, g, seed, mask));
 #pragma unroll
   for (int c = 0; c < NC; ++c)
     if (c == cj) b[c] = v;
@@ -677,12 +677,12 @@ __global__ __launch_bounds__(kBlock) void k_true_residual(Geom g, TileMap tm, Op
     if (!eo) {
       store_vec<T, NC>(r, g.V, tm.logB, s, j, rt);
       store_vec<T, NC>(p, g.V, tm.logB, s, j, rt);
-    } else if (((spatial_parity(s, g) + coord(s, g, g.ndim - 1)) & 1u) == 0u) {
+    } else if (((spatial_parity(s, g) + coord_p2(s, g, g.ndim - 1)) & 1u) == 0u) {
       // even-odd solve: restart the reduced system from the even part (the
       // odd part vanishes up to rounding when x_o was formed from x_e)
       const int tdim = g.ndim - 1;
       const uint32_t V3 = 1u << g.shift[tdim];
-      const uint32_t h = (s & (V3 - 1u)) + V3 * (coord(s, g, tdim) >> 1);
+      const uint32_t h = (s & (V3 - 1u)) + V3 * (coord_p2(s, g, tdim) >> 1);
       store_vec<T, NC>(r, g.V >> 1, tm.logB, h, j, rt);
       store_vec<T, NC>(p, g.V >> 1, tm.logB, h, j, rt);
     }
@@ -1037,7 +1037,7 @@ __global__ __launch_bounds__(kBlock) void k_probe_vectors(Geom g, uint64_t seed,
   if (s >= g.V) return;
   const int64_t m = m0 + blockIdx.y;
   const uint32_t P = hier_perm(s, g);
-  out[(size_t)blockIdx.y * g.V + s] = probe_value(s, P, hadamard_column((uint32_t)m, g.L), comp, g, seed, mask);
+  out[(size_t)blockIdx.y * g.V + s] = probe_value(s, P, probe_column((uint64_t)m, g), comp, g, seed, mask);
 }
 
 // [ndim][V][3][3] complex (caller) -> [ndim][9][V] complex (kernels)
@@ -1174,7 +1174,7 @@ __global__ __launch_bounds__(kBlock) void k_eo_hop(Geom g, MarchMap mm, int P, O
           mu = slot - ndim;
           par = 1u - (uint32_t)P;
           if (mu < tdim) {
-            hl = nbr_bwd(x3, g, mu) + V3 * tau;
+            hl = nbr_bwd_p2(x3, g, mu) + V3 * tau;
           } else {
             const uint32_t dl = ((uint32_t)P + spatial_parity(x3, g)) & 1u;
             hl = x3 + V3 * ((tau + ntau - 1u + dl) % ntau);
@@ -1192,9 +1192,9 @@ __global__ __launch_bounds__(kBlock) void k_eo_hop(Geom g, MarchMap mm, int P, O
 #pragma unroll
     for (int mu = 0; mu < kMaxDim - 1; ++mu) {
       if (mu >= tdim) break;
-      const uint32_t nf = nbr_fwd(s3, g, mu), nbk = nbr_bwd(s3, g, mu);
+      const uint32_t nf = nbr_fwd_p2(s3, g, mu), nbk = nbr_bwd_p2(s3, g, mu);
       const double wf = w ? w[(size_t)mu * V + s] : 1.0;
-      const double wb = w ? w[(size_t)mu * V + nbr_bwd(s, g, mu)] : 1.0;
+      const double wb = w ? w[(size_t)mu * V + nbr_bwd_p2(s, g, mu)] : 1.0;
       T xn[NC], hh[NC];
       load_vec<T, NC>(in, Vh, logB, nf + V3 * tau, j, xn);
       if constexpr (kCov) {
@@ -1220,7 +1220,7 @@ __global__ __launch_bounds__(kBlock) void k_eo_hop(Geom g, MarchMap mm, int P, O
     // the marching direction: forward input in slice tau + delta, backward one carried
     {
       const double wf = w ? w[(size_t)tdim * V + s] : 1.0;
-      const double wb = w ? w[(size_t)tdim * V + nbr_bwd(s, g, tdim)] : 1.0;
+      const double wb = w ? w[(size_t)tdim * V + nbr_bwd_p2(s, g, tdim)] : 1.0;
       T xn[NC], hh[NC];
       load_vec<T, NC>(in, Vh, logB, s3 + V3 * ((tau + delta) % ntau), j, xn);
       if constexpr (kCov) {
@@ -1672,7 +1672,7 @@ __global__ __launch_bounds__(kBlock) void k_repack_links_eo(Geom g, const double
   if (s >= g.V) return;
   const int mu = blockIdx.y;
   const int tdim = g.ndim - 1;
-  const uint32_t t = coord(s, g, tdim);
+  const uint32_t t = coord_p2(s, g, tdim);
   const uint32_t P = (spatial_parity(s, g) + t) & 1u;
   const uint32_t V3 = 1u << g.shift[tdim];
   const uint32_t h = (s & (V3 - 1u)) + V3 * (t >> 1);
