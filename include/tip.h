@@ -161,6 +161,20 @@ int32_t tip_num_checkpoints(int64_t n_vectors);
 tip_status trace_inv_probe(const tip_operator* op, const tip_params* p,
                            double* estimates, tip_stats* stats);
 
+/* Many independent problems in one call, e.g. a batch of uneven 3-D tori.
+ * Problem i is ops[i] with params[i] (its stream field is ignored) and writes
+ * estimates[i] (HOST [tip_num_checkpoints(params[i].n_vectors)][2]) and, when
+ * stats is not NULL, stats[i].  The library runs n_streams host threads (0 =
+ * 4), each with a HIP stream of its own on the caller's current device, that
+ * take the problems largest first (V n_vectors ncomp); every problem gets
+ * exactly the arithmetic of a trace_inv_probe call.  statuses: HOST [count]
+ * per-problem status, or NULL.  All arguments are validated before any work
+ * starts (TIP_EINVAL names the problem); otherwise the return value is TIP_OK
+ * or the status of the lowest-numbered failing problem. */
+tip_status trace_inv_probe_batch(const tip_operator* ops, const tip_params* params, int32_t count,
+                                 int32_t n_streams, double* const* estimates, tip_stats* stats,
+                                 int32_t* statuses);
+
 /* Operator handle: validates op and repacks links/couplings into the kernels'
  * layout in library-owned device memory (one time, on `stream`).  The caller's
  * arrays are not referenced after tip_op_create returns. */

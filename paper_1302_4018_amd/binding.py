@@ -55,6 +55,8 @@ def _load():
     sig = {
         "tip_num_checkpoints": (ctypes.c_int32, [ctypes.c_int64]),
         "trace_inv_probe": (ctypes.c_int, [P(tip_operator), P(tip_params), P(ctypes.c_double), P(tip_stats)]),
+        "trace_inv_probe_batch": (ctypes.c_int, [P(tip_operator), P(tip_params), ctypes.c_int32, ctypes.c_int32,
+                                                 P(P(ctypes.c_double)), P(tip_stats), P(ctypes.c_int32)]),
         "tip_op_create": (ctypes.c_int, [P(tip_operator), ctypes.c_void_p, P(ctypes.c_void_p)]),
         "tip_op_destroy": (ctypes.c_int, [ctypes.c_void_p]),
         "trace_inv_probe_op": (ctypes.c_int, [ctypes.c_void_p, P(tip_params), P(ctypes.c_double), P(tip_stats)]),
@@ -202,6 +204,36 @@ def trace_inv_probe(op, n_vectors, tol, seed, mask=MASK_DEFAULT, max_iter=0, rhs
     s = op.c_struct()
     return _run(lib.trace_inv_probe, ctypes.byref(s), n_vectors, tol, seed, mask, max_iter, rhs_block, m_begin,
                 quadratures, stream, raise_on_error, precision, reliable_delta)
+
+
+def trace_inv_probe_batch(ops, n_vectors, tol, seed, mask=MASK_DEFAULT, max_iter=0, rhs_block=0,
+                          precision=PREC_FP64, reliable_delta=0.0, n_streams=0, raise_on_error=True):
+    """Independent problems in one call: ops and n_vectors are sequences of
+    equal length.  Returns a list of (estimates complex numpy, stats dict)."""
+    count = len(ops)
+    if len(n_vectors) != count:
+        raise ValueError("ops and n_vectors differ in length")
+    structs = (tip_operator * count)(*[op.c_struct() for op in ops])
+    params = (tip_params * count)()
+    ests, qs = [], []
+    for i, n in enumerate(n_vectors):
+        q = np.zeros((int(n), 2))
+        qs.append(q)
+        params[i] = _params(n, tol, seed, mask, max_iter, rhs_block, 0, q, None, precision, reliable_delta)
+        ests.append(np.zeros((tip_num_checkpoints(n), 2)))
+    est_ptrs = (ctypes.POINTER(ctypes.c_double) * count)(*[e.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+                                                          for e in ests])
+    stats = (tip_stats * count)()
+    statuses = (ctypes.c_int32 * count)()
+    status = lib.trace_inv_probe_batch(structs, params, count, int(n_streams), est_ptrs, stats, statuses)
+    if raise_on_error:
+        _check(status, "trace_inv_probe_batch")
+    out = []
+    for i in range(count):
+        st = _stats_dict(stats[i])
+        st["status"] = statuses[i]
+        out.append((ests[i][:, 0] + 1j * ests[i][:, 1], st))
+    return out
 
 
 class OpHandle:

@@ -20,6 +20,9 @@
 #include <new>
 #include <string>
 #include <vector>
+#include <atomic>
+#include <mutex>
+#include <thread>
 
 #include "../../include/tip.h"
 #include "tip_launch.h"
@@ -1002,6 +1005,67 @@ tip_status trace_inv_probe(const tip_operator* op, const tip_params* p, double* 
   delete h;
   g_err = msg;
   return s;
+}
+
+tip_status trace_inv_probe_batch(const tip_operator* ops, const tip_params* params, int32_t count, int32_t n_streams,
+                                 double* const* estimates, tip_stats* stats, int32_t* statuses) {
+  if (count < 0) return fail(TIP_EINVAL, "count = %d must be >= 0", count);
+  if (count > 0 && (!ops || !params || !estimates)) return fail(TIP_EINVAL, "ops, params or estimates is NULL");
+  if (n_streams < 0) return fail(TIP_EINVAL, "n_streams = %d must be >= 0", n_streams);
+  for (int32_t i = 0; i < count; ++i) {
+    Geom g;
+    tip_status s = validate_op(&ops[i], &g);
+    if (s != TIP_OK) return fail(s, "torus %d: %s", i, g_err.c_str());
+    if (!estimates[i]) return fail(TIP_EINVAL, "torus %d: estimates is NULL", i);
+    if (params[i].n_vectors < 1 || params[i].n_vectors > (int64_t)g.V)
+      return fail(TIP_EINVAL, "torus %d: n_vectors = %lld must be in [1, V = %u]", i,
+                  (long long)params[i].n_vectors, g.V);
+  }
+  if (count == 0) return TIP_OK;
+  int device = 0;
+  if (hipGetDevice(&device) != hipSuccess) return fail(TIP_EDEVICE, "hipGetDevice failed");
+  // longest first: work ~ V * n_vectors * ncomp
+  std::vector<int32_t> order((size_t)count);
+  std::vector<double> work((size_t)count);
+  for (int32_t i = 0; i < count; ++i) {
+    double v = (double)params[i].n_vectors * (ops[i].kind == TIP_KIND_COVARIANT ? 3.0 : 1.0);
+    for (int j = 0; j < ops[i].ndim; ++j) v *= (double)ops[i].dims[j];
+    work[(size_t)i] = v;
+    order[(size_t)i] = i;
+  }
+  std::stable_sort(order.begin(), order.end(), [&](int32_t a, int32_t b) { return work[(size_t)a] > work[(size_t)b]; });
+  const int workers = std::max(1, std::min<int>(n_streams > 0 ? n_streams : 4, count));
+  std::vector<tip_status> st((size_t)count, TIP_OK);
+  std::vector<std::string> msg((size_t)count);
+  std::atomic<int32_t> next{0};
+  auto run = [&]() {
+    (void)hipSetDevice(device);
+    hipStream_t stream = nullptr;
+    // non-blocking: no implicit ordering with the null stream or the other workers
+    if (hipStreamCreateWithFlags(&stream, hipStreamNonBlocking) != hipSuccess) stream = nullptr;
+    for (;;) {
+      const int32_t k = next.fetch_add(1);
+      if (k >= count) break;
+      const int32_t i = order[(size_t)k];
+      tip_params p = params[i];
+      p.stream = stream;
+      st[(size_t)i] = trace_inv_probe(&ops[i], &p, estimates[i], stats ? &stats[i] : nullptr);
+      if (st[(size_t)i] != TIP_OK) msg[(size_t)i] = g_err;
+    }
+    if (stream) (void)hipStreamDestroy(stream);
+  };
+  std::vector<std::thread> pool;
+  for (int w = 1; w < workers; ++w) pool.emplace_back(run);
+  run();
+  for (auto& t : pool) t.join();
+  tip_status first = TIP_OK;
+  int32_t first_i = -1;
+  for (int32_t i = 0; i < count; ++i) {
+    if (statuses) statuses[i] = st[(size_t)i];
+    if (st[(size_t)i] != TIP_OK && first_i < 0) first = st[(size_t)i], first_i = i;
+  }
+  if (first_i >= 0) return fail(first, "torus %d: %s", first_i, msg[(size_t)first_i].c_str());
+  return TIP_OK;
 }
 
 tip_status tip_apply_operator(const tip_operator* op, int32_t nrhs, const double* x, double* y, void* stream) {

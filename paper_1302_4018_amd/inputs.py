@@ -74,3 +74,8 @@ def uneven_tori(count=64, lo=8, hi=48, seed=OPERATOR_SEED + 3):
     nvec = 2 ** rng.integers(4, 9, size=count)            # 16 .. 256
     return [dict(dims=[int(v) for v in s], mass=float(m), n_vectors=int(k))
             for s, m, k in zip(sides, masses, nvec)]
+
+
+def uneven_torus_couplings(dims, index, lo=0.5, hi=1.5):
+    """w_mu(x) ~ U[lo, hi] iid per forward edge of torus `index` of the batch."""
+    return couplings(dims, lo, hi, seed=OPERATOR_SEED + 100 + int(index))
