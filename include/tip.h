@@ -14,8 +14,8 @@
  *   3. accumulates z^H x into the estimator (1/s) sum_m z_m^H A^-1 z_m
  *      (Sec. 1, Hutchinson) reported at every s = 2^k (Sec. 1.1.4, and the
  *      nesting Z(k-1) = Z(k)(:, 1:2^{k-1}) after eq. Hperm-recursive).
- *   The solves run CG on the even-odd reduced system whenever every side is
- *   at least 2 and the diagonal is positive (precision FP64): the red-black
+ *   The solves run CG on the even-odd reduced system whenever every side is a
+ *   power of two >= 2 and the diagonal is positive (both precisions): the red-black
  *   colouring of Sec. 2 makes the torus bipartite, A = D - H with H joining
  *   opposite parities only, and CG iterates on the Schur complement
  *   S = D_e - H_eo D_o^-1 H_oe over the even sites (half the vector length,
@@ -125,7 +125,7 @@ typedef struct {
                            (same operator, seed, mask) and are read: this resumes a
                            run, reusing earlier levels' quadratures.                */
   double reliable_delta; /* MIXED: reliable update when the FP32 residual norm has
-                            fallen by this factor since the last one; 0 = 0.01     */
+                            fallen by this factor since the last one; 0 = 1e-3     */
 } tip_params;
 
 typedef struct {

@@ -53,6 +53,13 @@ struct ScalarOp {                      // 1 component, real or complex vectors
   static constexpr int NC = 1;
 };
 
+// Single-precision type of an FP64 vector element.
+template <class T> struct SingleOf;
+template <> struct SingleOf<double> { using type = float; };
+template <> struct SingleOf<double2> { using type = float2; };
+template <> struct SingleOf<float> { using type = float; };      // already single
+template <> struct SingleOf<float2> { using type = float2; };
+
 // y = U x and y = U^H x for a 3x3 complex matrix u[3a+b].
 template <class C>
 __device__ __forceinline__ void mul_u(const C (&u)[9], const C (&x)[3], C (&y)[3]) {
@@ -92,6 +99,39 @@ template <class T, int NC>
 __device__ __forceinline__ void store_vec(T* __restrict__ out, size_t V, int logB, uint32_t s, int j, const T (&x)[NC]) {
 #pragma unroll
   for (int c = 0; c < NC; ++c) out[((((size_t)c * V + s)) << logB) + j] = x[c];
+}
+
+// Streaming forms for data a kernel touches once: the lines are not kept in
+// L2, which leaves room for the neighbour data that other workgroups reuse.
+__device__ __forceinline__ void st_nt(double* p, double v) { __builtin_nontemporal_store(v, p); }
+__device__ __forceinline__ void st_nt(float* p, float v) { __builtin_nontemporal_store(v, p); }
+__device__ __forceinline__ void st_nt(double2* p, double2 v) {
+  __builtin_nontemporal_store(v.x, &p->x);
+  __builtin_nontemporal_store(v.y, &p->y);
+}
+__device__ __forceinline__ void st_nt(float2* p, float2 v) {
+  __builtin_nontemporal_store(v.x, &p->x);
+  __builtin_nontemporal_store(v.y, &p->y);
+}
+__device__ __forceinline__ double ld_nt(const double* p) { return __builtin_nontemporal_load(p); }
+__device__ __forceinline__ float ld_nt(const float* p) { return __builtin_nontemporal_load(p); }
+__device__ __forceinline__ double2 ld_nt(const double2* p) {
+  return make_double2(__builtin_nontemporal_load(&p->x), __builtin_nontemporal_load(&p->y));
+}
+__device__ __forceinline__ float2 ld_nt(const float2* p) {
+  return make_float2(__builtin_nontemporal_load(&p->x), __builtin_nontemporal_load(&p->y));
+}
+template <class T, int NC>
+__device__ __forceinline__ void store_vec_nt(T* __restrict__ out, size_t V, int logB, uint32_t s, int j,
+                                             const T (&x)[NC]) {
+#pragma unroll
+  for (int c = 0; c < NC; ++c) st_nt(&out[((((size_t)c * V + s)) << logB) + j], x[c]);
+}
+template <class T, int NC>
+__device__ __forceinline__ void load_vec_nt(const T* __restrict__ in, size_t V, int logB, uint32_t s, int j,
+                                            T (&x)[NC]) {
+#pragma unroll
+  for (int c = 0; c < NC; ++c) x[c] = ld_nt(&in[((((size_t)c * V + s)) << logB) + j]);
 }
 
 // One hop term h = U x (fwd) or U^H x (bwd) for the operator policy.
@@ -813,10 +853,6 @@ __global__ __launch_bounds__(kBlock) void k_reduce_true(CgScalars sc, const doub
 // iterating, 1 = frozen (final check).
 // ---------------------------------------------------------------------------
 
-template <class T> struct SingleOf;
-template <> struct SingleOf<double> { using type = float; };
-template <> struct SingleOf<double2> { using type = float2; };
-
 __device__ __forceinline__ bool ru_selected(const CgScalars& sc, int mode, int j) {
   return mode == 0 ? (sc.ru[j] != 0 && sc.state[j] == kActive) : sc.state[j] == kFrozen;
 }
@@ -871,7 +907,7 @@ __global__ __launch_bounds__(kBlock) void k_ru_residual(Geom g, TileMap tm, Op64
                                                         int64_t rhs0, int nb, uint64_t seed, int mask,
                                                         const typename Op64::T* __restrict__ x, T32* __restrict__ rh,
                                                         T32* __restrict__ ph, double* __restrict__ partial,
-                                                        size_t pstride) {
+                                                        size_t pstride, int eo) {
   using T = typename Op64::T;
   constexpr int NC = Op64::NC;
   if (mode == 0 && *sc.n_ru == 0) return;
@@ -898,8 +934,17 @@ __global__ __launch_bounds__(kBlock) void k_ru_residual(Geom g, TileMap tm, Op64
         acc[4] += imdot(xs[c], rt);
         r32[c] = to_single(rt);
       }
-      store_vec<T32, NC>(rh, g.V, tm.logB, s, j, r32);
-      if (mode == 1) store_vec<T32, NC>(ph, g.V, tm.logB, s, j, r32);
+      if (!eo) {
+        store_vec<T32, NC>(rh, g.V, tm.logB, s, j, r32);
+        if (mode == 1) store_vec<T32, NC>(ph, g.V, tm.logB, s, j, r32);
+      } else if (((spatial_parity(s, g) + coord_p2(s, g, g.ndim - 1)) & 1u) == 0u) {
+        // even-odd solve: the reduced system restarts from the even part
+        const int tdim = g.ndim - 1;
+        const uint32_t V3 = 1u << g.shift[tdim];
+        const uint32_t hh = (s & (V3 - 1u)) + V3 * (coord_p2(s, g, tdim) >> 1);
+        store_vec<T32, NC>(rh, g.V >> 1, tm.logB, hh, j, r32);
+        if (mode == 1) store_vec<T32, NC>(ph, g.V >> 1, tm.logB, hh, j, r32);
+      }
     }
   }
   seg_sum<5>(acc, B, lds);
@@ -947,6 +992,18 @@ __global__ __launch_bounds__(kBlock) void k_reduce_ru(CgScalars sc, const double
   } else {
     sc.state[j] = kNoConv;
   }
+}
+
+// Mixed even-odd start: r = p = single(b_hat), x_h = 0 (flat half vectors).
+template <class T64, class T32>
+__global__ __launch_bounds__(kBlock) void k_eo_cast_init(size_t n, const T64* __restrict__ bh, T32* __restrict__ r,
+                                                         T32* __restrict__ p, T32* __restrict__ xh) {
+  const size_t i = (size_t)blockIdx.x * kBlock + threadIdx.x;
+  if (i >= n) return;
+  const T32 v = to_single(bh[i]);
+  r[i] = v;
+  p[i] = v;
+  xh[i] = zero<T32>();
 }
 
 // FP64 links [ndim][9][V] -> single-precision copy, same layout.
@@ -1104,9 +1161,14 @@ static inline unsigned cdiv(size_t a, size_t b) { return (unsigned)((a + b - 1) 
 //   1  out = D cin - H in, partial Re cin^H out   (w_e = S p_e)
 //   2  out = out2 = b + H in, out3 = 0, partial ||out||^2   (reduced rhs, CG start)
 //   3  out = D^-1 (b + H in), written at full-lattice sites   (x_o)
+//   4  (FP64) out32 = single(cin2 - (D cin - H in)), partial ||.||^2, lanes
+//      flagged in ru only   (reliable update of the reduced residual)
 // b is the probing right-hand side, regenerated from site indices.
 // ---------------------------------------------------------------------------
 
+#ifndef TIP_EO_STREAMING
+#define TIP_EO_STREAMING 1
+#endif
 template <class Op, int MODE, int kLogB>
 __global__ __launch_bounds__(kBlock) void k_eo_hop(Geom g, MarchMap mm, int P, Op op,
                                                    const double* __restrict__ diag, const double* __restrict__ w,
@@ -1116,7 +1178,8 @@ __global__ __launch_bounds__(kBlock) void k_eo_hop(Geom g, MarchMap mm, int P, O
                                                    typename Op::T* __restrict__ out, typename Op::T* __restrict__ out2,
                                                    typename Op::T* __restrict__ out3, int64_t rhs0, int nb,
                                                    uint64_t seed, int mask, double* __restrict__ partial,
-                                                   int* __restrict__ ran) {
+                                                   int* __restrict__ ran, const int* __restrict__ ru,
+                                                   const typename Op::T* __restrict__ cin2, void* __restrict__ out32) {
   using T = typename Op::T;
   constexpr int NC = Op::NC;
   constexpr bool kCov = NC == 3;
@@ -1141,7 +1204,7 @@ __global__ __launch_bounds__(kBlock) void k_eo_hop(Geom g, MarchMap mm, int P, O
   const uint32_t s3_first = q * (uint32_t)TS;
   const uint32_t s3 = s3_first + (uint32_t)si;
   const uint32_t delta = ((uint32_t)P + spatial_parity(s3, g)) & 1u;
-  const bool live = !state || state[j] == kActive;
+  const bool live = (!state || state[j] == kActive) && (!ru || ru[j] != 0);
   double acc[1] = {0.0};
   const uint32_t tau0 = chunk * (uint32_t)mm.Tc;
   T xprev[NC];
@@ -1250,16 +1313,37 @@ __global__ __launch_bounds__(kBlock) void k_eo_hop(Geom g, MarchMap mm, int P, O
       const double f = 1.0 / d;
 #pragma unroll
       for (int c = 0; c < NC; ++c) y[c] = axpy(f, hop[c], zero<T>());
-      store_vec<T, NC>(out, Vh, logB, h, j, y);
+      if constexpr (TIP_EO_STREAMING) store_vec_nt<T, NC>(out, Vh, logB, h, j, y);
+      else store_vec<T, NC>(out, Vh, logB, h, j, y);
     } else if constexpr (MODE == 1) {
       T cv[NC];
-      load_vec<T, NC>(cin, Vh, logB, h, j, cv);
+      if constexpr (TIP_EO_STREAMING) load_vec_nt<T, NC>(cin, Vh, logB, h, j, cv);
+      else load_vec<T, NC>(cin, Vh, logB, h, j, cv);
 #pragma unroll
       for (int c = 0; c < NC; ++c) {
         y[c] = axpy(d, cv[c], axpy(-1.0, hop[c], zero<T>()));
         acc[0] += redot(cv[c], y[c]);
       }
-      store_vec<T, NC>(out, Vh, logB, h, j, y);
+      if constexpr (TIP_EO_STREAMING) store_vec_nt<T, NC>(out, Vh, logB, h, j, y);
+      else store_vec<T, NC>(out, Vh, logB, h, j, y);
+    } else if constexpr (MODE == 4) {
+      if constexpr (sizeof(typename SingleOf<T>::type) * 2 == sizeof(T)) {
+        // reliable update of the reduced system: r = b_hat - (D x_e - H t_o),
+        // b_hat = cin2, x_e = cin, t_o = in; rounded to single into out32
+        using T32 = typename SingleOf<T>::type;
+        T xv[NC], bv[NC];
+        T32 r32[NC];
+        load_vec<T, NC>(cin, Vh, logB, h, j, xv);
+        load_vec<T, NC>(cin2, Vh, logB, h, j, bv);
+#pragma unroll
+        for (int c = 0; c < NC; ++c) {
+          const T sx = axpy(d, xv[c], axpy(-1.0, hop[c], zero<T>()));
+          y[c] = axpy(-1.0, sx, bv[c]);
+          acc[0] += norm2(y[c]);
+          r32[c] = to_single(y[c]);
+        }
+        store_vec<T32, NC>(reinterpret_cast<T32*>(out32), Vh, logB, h, j, r32);
+      }
     } else {
       T b[NC];
       rhs_at<T, NC>(g, s, hier_perm(s, g), rhs0, j, nb, seed, mask, b);
@@ -1273,8 +1357,8 @@ __global__ __launch_bounds__(kBlock) void k_eo_hop(Geom g, MarchMap mm, int P, O
 #pragma unroll
         for (int c = 0; c < NC; ++c) z[c] = zero<T>();
         store_vec<T, NC>(out, Vh, logB, h, j, y);
-        store_vec<T, NC>(out2, Vh, logB, h, j, y);
-        store_vec<T, NC>(out3, Vh, logB, h, j, z);
+        if (out2) store_vec<T, NC>(out2, Vh, logB, h, j, y);
+        if (out3) store_vec<T, NC>(out3, Vh, logB, h, j, z);
       } else {
         const double f = 1.0 / d;
 #pragma unroll
@@ -1527,14 +1611,14 @@ hipError_t launch_ru_accumulate(size_t n, int logB, Elem elem, const CgScalars& 
 
 hipError_t launch_ru_residual(const OpDev& od64, const Geom& g, const TileMap& tm, Elem elem, const CgScalars& sc,
                               int mode, int64_t rhs0, int nb, uint64_t seed, int mask, const void* x64, void* rh,
-                              void* ph, double* partial, size_t pstride, hipStream_t st) {
+                              void* ph, double* partial, size_t pstride, int eo, hipStream_t st) {
   return dispatch64(od64, elem, [&](auto op) {
     using Op = decltype(op);
     using T = typename Op::T;
     using T32 = typename SingleOf<T>::type;
     k_ru_residual<Op, T32><<<ru_grid(tm), kBlock, 0, st>>>(g, tm, op, od64.mass_field, od64.mass, od64.coupling, sc, mode,
                                                        rhs0, nb, seed, mask, (const T*)x64, (T32*)rh, (T32*)ph,
-                                                       partial, pstride);
+                                                       partial, pstride, eo);
   });
 }
 
@@ -1551,7 +1635,7 @@ size_t eo_lds_bytes(const Geom& g, const MarchMap& mm, Prec prec) {
 hipError_t launch_eo_hop(int mode, const OpDev& od, const Geom& g, const MarchMap& mm, int P, Elem elem, Prec prec,
                          const double* diag, const int* state, const int* active, const void* in, const void* cin,
                          void* out, void* out2, void* out3, int64_t rhs0, int nb, uint64_t seed, int mask,
-                         double* partial, int* ran, hipStream_t st) {
+                         double* partial, int* ran, hipStream_t st, const int* ru, const void* cin2, void* out32) {
   OpDev oe = od;
   oe.links = od.links_eo;
   return dispatch(oe, elem, prec, [&](auto op) {
@@ -1561,14 +1645,17 @@ hipError_t launch_eo_hop(int mode, const OpDev& od, const Geom& g, const MarchMa
     auto go = [&](auto kern) {
       kern<<<mm.grid, kBlock, lds, st>>>(g, mm, P, op, diag, od.coupling, state, active, (const T*)in,
                                           (const T*)cin, (T*)out, (T*)out2, (T*)out3, rhs0, nb, seed, mask, partial,
-                                          ran);
+                                          ran, ru, (const T*)cin2, out32);
     };
     const bool b32 = mm.logB == 5;
     switch (mode) {
       case 0: b32 ? go(k_eo_hop<Op, 0, 5>) : go(k_eo_hop<Op, 0, -1>); break;
       case 1: b32 ? go(k_eo_hop<Op, 1, 5>) : go(k_eo_hop<Op, 1, -1>); break;
       case 2: go(k_eo_hop<Op, 2, -1>); break;
-      default: go(k_eo_hop<Op, 3, -1>); break;
+      case 3: go(k_eo_hop<Op, 3, -1>); break;
+      default:
+        if constexpr (sizeof(typename SingleOf<T>::type) * 2 == sizeof(T)) go(k_eo_hop<Op, 4, -1>);
+        break;
     }
   });
 }
@@ -1621,6 +1708,16 @@ hipError_t launch_scale(size_t n, double* a, double f, hipStream_t st) {
 
 hipError_t launch_fill(size_t n, double* a, double v, hipStream_t st) {
   k_fill<<<cdiv(n, kBlock), kBlock, 0, st>>>(n, a, v);
+  return hipGetLastError();
+}
+
+hipError_t launch_eo_cast_init(size_t n, Elem elem, const void* bh, void* r, void* p, void* xh, hipStream_t st) {
+  const unsigned grid = cdiv(n, kBlock);
+  if (elem == Elem::kReal)
+    k_eo_cast_init<double, float><<<grid, kBlock, 0, st>>>(n, (const double*)bh, (float*)r, (float*)p, (float*)xh);
+  else
+    k_eo_cast_init<double2, float2><<<grid, kBlock, 0, st>>>(n, (const double2*)bh, (float2*)r, (float2*)p,
+                                                             (float2*)xh);
   return hipGetLastError();
 }
 

@@ -135,7 +135,7 @@ hipError_t launch_ru_accumulate(size_t n, int logB, Elem elem, const CgScalars& 
                                 hipStream_t st);
 hipError_t launch_ru_residual(const OpDev& od64, const Geom& g, const TileMap& tm, Elem elem, const CgScalars& sc,
                               int mode, int64_t rhs0, int nb, uint64_t seed, int mask, const void* x64, void* rh,
-                              void* ph, double* partial, size_t pstride, hipStream_t st);
+                              void* ph, double* partial, size_t pstride, int eo, hipStream_t st);
 hipError_t launch_reduce_ru(const CgScalars& sc, int B, const double* partial, int gx, size_t pstride, int mode,
                             double tol2, int max_iter, int max_restarts, hipStream_t st);
 hipError_t launch_cast_links(size_t n, const double2* src, float2* dst, hipStream_t st);
@@ -148,7 +148,9 @@ size_t eo_lds_bytes(const Geom& g, const MarchMap& mm, Prec prec);
 hipError_t launch_eo_hop(int mode, const OpDev& od, const Geom& g, const MarchMap& mm, int P, Elem elem, Prec prec,
                          const double* diag, const int* state, const int* active, const void* in, const void* cin,
                          void* out, void* out2, void* out3, int64_t rhs0, int nb, uint64_t seed, int mask,
-                         double* partial, int* ran, hipStream_t st);
+                         double* partial, int* ran, hipStream_t st, const int* ru = nullptr,
+                         const void* cin2 = nullptr, void* out32 = nullptr);
+hipError_t launch_eo_cast_init(size_t n, Elem elem, const void* bh, void* r, void* p, void* xh, hipStream_t st);
 hipError_t launch_eo_init_odd(const Geom& g, Elem elem, Prec prec, int logB, int64_t rhs0, int nb, uint64_t seed,
                               int mask, const double* diag, void* to, hipStream_t st);
 hipError_t launch_eo_scatter_even(const Geom& g, Elem elem, Prec prec, int logB, const void* xe, void* x,

@@ -109,3 +109,22 @@ def test_even_odd_full_size_solution():
     rel = float(torch.linalg.vector_norm(bfull - ax) / torch.linalg.vector_norm(bfull))
     assert rel <= 1e-10
     assert abs(q - complex(torch.vdot(bfull.flatten(), x.flatten()))) <= 1e-12 * abs(q)
+
+
+@pytest.mark.parametrize("dims,kind,n,mask", [
+    ([8, 8, 8, 8], 1, 8, MASK_Z4),
+    ([16, 16], 0, 32, MASK_Z2),
+    ([4, 4, 4, 8], 1, 16, MASK_Z4),
+])
+def test_mixed_even_odd_matches_oracle(dims, kind, n, mask):
+    """FP32 CG on the reduced system with FP64 reliable updates of r_e = b_hat - S x_e
+    and the same FP64 acceptance: estimates at the 1e-10 bar, within the bound."""
+    tip = gpu_binding()
+    orc, gop = _ops(tip, dims, kind, seed=430 + kind)
+    tol = 1e-12
+    est, q, st = tip.trace_inv_probe(gop, n, tol, 4018, mask=mask, precision=tip.PREC_MIXED)
+    est_o, q_o, _ = oracle_trace(orc, n, tol, 4018, mask)
+    assert st["even_odd"] == 1 and st["reliable_updates"] > 0
+    assert st["max_true_relres"] <= tol
+    assert _rel(est, est_o) <= REL and _rel(q, q_o) <= REL
+    assert np.all(np.abs(q - q_o) <= 2 * st["max_quad_err_bound"] + 1e-13 * np.abs(q_o))
