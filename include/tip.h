@@ -94,6 +94,14 @@ enum { TIP_MASK_DEFAULT = -1, TIP_MASK_NONE = 0, TIP_MASK_Z2 = 1, TIP_MASK_Z4 = 
  * whose error r^H A^-1 r <= ||r||^2 / lambda_min is second order in the
  * residual. */
 enum { TIP_PREC_FP64 = 0, TIP_PREC_MIXED = 1 };
+/* Probe kinds.  HIERARCHICAL: the probes described above (default).  The
+ * comparison probes of Sec. 5 run through the same solver and estimator:
+ * NATURAL, Hadamard columns in natural order on the natural site numbering,
+ * b_{m,c}(y, c) = z0(y, c) H(y, m) (power-of-two sides); RANDOM, plain Monte
+ * Carlo (Sec. 1, Hutchinson): b_{m,c}(y, c) = z0_m(y, c), the mask of sweep m
+ * (SplitMix64 outputs (m V + y) ncomp + c), so every probe is an independent
+ * Z2 / Z4 noise vector (a Z2 or Z4 mask is required). */
+enum { TIP_PROBE_HIERARCHICAL = 0, TIP_PROBE_NATURAL = 1, TIP_PROBE_RANDOM = 2 };
 
 /* Operator description.  Arrays are DEVICE pointers, read only. */
 typedef struct {
@@ -126,6 +134,7 @@ typedef struct {
                            run, reusing earlier levels' quadratures.                */
   double reliable_delta; /* MIXED: reliable update when the FP32 residual norm has
                             fallen by this factor since the last one; 0 = 1e-3     */
+  int32_t probe;         /* TIP_PROBE_*; 0 = hierarchical                           */
 } tip_params;
 
 typedef struct {
@@ -226,11 +235,11 @@ tip_status tip_apply_operator(const tip_operator* op, int32_t nrhs,
 tip_status tip_hier_perm(int32_t ndim, const int64_t* dims, uint32_t* P_out, void* stream);
 
 /* Probing vectors b_{m,comp}(y, comp) = z0(y, comp) H(P(y), bitrev_L(m)) for
- * m = m0 .. m0+count-1: DEVICE complex128 [count][V].  mask as in tip_params
- * (DEFAULT resolves with ncomp: 1 -> Z2, 3 -> Z4). */
+ * m = m0 .. m0+count-1 (or the probe kind given): DEVICE complex128 [count][V].
+ * mask as in tip_params (DEFAULT resolves with ncomp: 1 -> Z2, 3 -> Z4). */
 tip_status tip_probe_vectors(int32_t ndim, const int64_t* dims, int32_t ncomp, int32_t mask,
                              uint64_t seed, int64_t m0, int64_t count, int32_t comp,
-                             double* out, void* stream);
+                             int32_t probe, double* out, void* stream);
 
 /* Turn per-launch hipEvent timing of the stencil kernel on (1) or off (0). */
 void tip_set_profiling(int32_t on);

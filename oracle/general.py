@@ -164,9 +164,10 @@ def rhs(dims, ncomp, m, c, seed, mask_kind, lv=None, PB=None, C=None):
     return b
 
 
-def trace_inv_probe(op, n_vectors, tol, seed, mask_kind, max_iter=None):
-    """Estimates (1/s) sum_{m<s} q_m at the checkpoints, with these probes;
-    q_m = sum_c b_{m,c}^H x_{m,c} by the oracle's CG.  Returns (est, q, stats)."""
+def trace_inv_probe(op, n_vectors, tol, seed, mask_kind, max_iter=None, probe=0):
+    """Estimates (1/s) sum_{m<s} q_m at the checkpoints, with these probes (or the
+    comparison probe kind given); q_m = sum_c b_{m,c}^H x_{m,c} by the oracle's
+    CG.  Returns (est, q, stats)."""
     from .cg import cg_solve
     from .estimator import estimates_from_quadratures
     if max_iter is None:
@@ -178,7 +179,7 @@ def trace_inv_probe(op, n_vectors, tol, seed, mask_kind, max_iter=None):
     for m in range(n_vectors):
         qm = 0.0 + 0.0j
         for c in range(op.ncomp):
-            b = rhs(op.dims, op.ncomp, m, c, seed, mask_kind, lv, PB, C)
+            b = rhs_kind(op.dims, op.ncomp, m, c, seed, mask_kind, probe, lv, PB, C)
             if op.kind == 0 and np.all(b.imag == 0):
                 b = b.real
             x, it, _ = cg_solve(op.apply, b, tol, max_iter)
@@ -186,3 +187,51 @@ def trace_inv_probe(op, n_vectors, tol, seed, mask_kind, max_iter=None):
             iters.append(it)
         q.append(qm)
     return estimates_from_quadratures(q), np.array(q), {"iters": iters}
+
+
+# ---------------------------------------------------------------------------
+# The comparison probes of Sec. 5 (test infrastructure only).  Sec. 5 sets
+# hierarchical probing against random Z2 vectors (plain Monte Carlo) and
+# against Hadamard vectors taken in natural order; both run through the same
+# estimator and solver here.
+#   PROBE_HIERARCHICAL: the probes above.
+#   PROBE_NATURAL: z_m(x) = H(s(x), m), the Hadamard columns in natural order
+#     on the natural site numbering (power-of-two sides), times the mask.
+#   PROBE_RANDOM: z_m = the mask of sweep m alone, i.e. independent Z2 / Z4
+#     noise vectors (Hutchinson's estimator of Sec. 1).
+# ---------------------------------------------------------------------------
+
+PROBE_HIERARCHICAL, PROBE_NATURAL, PROBE_RANDOM = 0, 1, 2
+
+
+def rhs_kind(dims, ncomp, m, c, seed, mask_kind, probe, lv=None, PB=None, C=None):
+    """b_{m,c} for the given probe kind: complex128 [V, ncomp]."""
+    V = volume(dims)
+    if probe == PROBE_HIERARCHICAL:
+        return rhs(dims, ncomp, m, c, seed, mask_kind, lv, PB, C)
+    b = np.zeros((V, ncomp), dtype=np.complex128)
+    if probe == PROBE_NATURAL:
+        if V & (V - 1):
+            raise ValueError("natural-order Hadamard probes need a power-of-two volume")
+        z = (1 - 2 * _parity(np.arange(V, dtype=np.uint64) & np.uint64(m))).astype(np.complex128)
+        b[:, c] = mask_sweep(seed, V, ncomp, c, mask_kind, 0) * z
+    elif probe == PROBE_RANDOM:
+        if mask_kind == MASK_NONE:
+            raise ValueError("random probes need a Z2 or Z4 mask")
+        b[:, c] = mask_sweep(seed, V, ncomp, c, mask_kind, m)
+    else:
+        raise ValueError(f"unknown probe kind {probe}")
+    return b
+
+
+def estimates_dense(Ainv, dims, ncomp, n, seed, mask_kind, probe):
+    """T_s at the checkpoints from exact quadratures b^H A^-1 b (dense A^-1, tiny lattices)."""
+    from .estimator import estimates_from_quadratures
+    lv = Levels(dims)
+    PB, C = binary_colour(dims, lv), last_level_colour(dims, lv)
+    q = np.zeros(n, dtype=np.complex128)
+    for c in range(ncomp):
+        Z = np.stack([rhs_kind(dims, ncomp, m, c, seed, mask_kind, probe, lv, PB, C).reshape(-1)
+                      for m in range(n)], axis=1)
+        q += np.sum(np.conj(Z) * (Ainv @ Z), axis=0)       # b_m^H A^-1 b_m for every m at once
+    return estimates_from_quadratures(q)

@@ -440,6 +440,12 @@ tip_status check_params(const tip_op_s* h, const tip_params* p, int* mask_out) {
   int mask = p->mask;
   if (mask == TIP_MASK_DEFAULT) mask = h->kind == TIP_KIND_COVARIANT ? TIP_MASK_Z4 : TIP_MASK_Z2;
   if (mask < TIP_MASK_NONE || mask > TIP_MASK_Z4) return fail(TIP_EINVAL, "unknown mask %d", p->mask);
+  if (p->probe < TIP_PROBE_HIERARCHICAL || p->probe > TIP_PROBE_RANDOM)
+    return fail(TIP_EINVAL, "unknown probe kind %d", p->probe);
+  if (p->probe == TIP_PROBE_NATURAL && !h->geom.pow2)
+    return fail(TIP_EINVAL, "natural-order Hadamard probes need power-of-two sides");
+  if (p->probe == TIP_PROBE_RANDOM && mask == TIP_MASK_NONE)
+    return fail(TIP_EINVAL, "random probes need a Z2 or Z4 mask");
   *mask_out = mask;
   return TIP_OK;
 }
@@ -452,6 +458,7 @@ tip_status check_params(const tip_op_s* h, const tip_params* p, int* mask_out) {
 struct Solver {
   tip_op_s* h;
   const tip_params* p;
+  Geom geom;                 // the operator's lattice with this call's probe kind
   hipStream_t st;
   Plan pl;
   bool mixed = false;
@@ -496,10 +503,12 @@ struct Solver {
   tip_status setup(tip_op_s* handle, const tip_params* params, int mask) {
     h = handle;
     p = params;
+    geom = h->geom;
+    geom.probe = p->probe;
     st = (hipStream_t)p->stream;
     mixed = p->precision == TIP_PREC_MIXED;
     prec = mixed ? Prec::kF32 : Prec::kF64;
-    const Geom& g = h->geom;
+    const Geom& g = geom;
     const int64_t V = g.V;
     const int ncomp = g.ncomp;
     pl.mask = mask;
@@ -672,7 +681,7 @@ struct Solver {
   // every iteration; the kernels return at once when none is pending) or the
   // final check of frozen ones (mode 1) in the mixed solver.
   tip_status reliable(int64_t rhs0, int nb, int mode) {
-    const Geom& g = h->geom;
+    const Geom& g = geom;
     if (pl.eo) {
       const double* diag = (const double*)h->diag.p;
       TIP_HIP(launch_ru_accumulate(nvec, pl.logB, pl.elem, sc, mode, Xe, XH, st));
@@ -706,7 +715,7 @@ struct Solver {
   // Solve right-hand sides rhs0 .. rhs0+nb-1; x (FP64) stays in X.  Fills the
   // host mirrors h_q, h_relres2, h_state, h_iters for those nb right-hand sides.
   tip_status solve_block(int64_t rhs0, int nb) {
-    const Geom& g = h->geom;
+    const Geom& g = geom;
     const MarchMap* mm = pl.use_march ? &pl.mm : nullptr;
     TIP_HIP(launch_scalars_init(sc, nb, pl.B, (double)g.V, p->tol >= 1.0 ? 1 : 0, st));
     const double* diag = (const double*)h->diag.p;
@@ -1169,13 +1178,18 @@ tip_status tip_hier_perm(int32_t ndim, const int64_t* dims, uint32_t* P_out, voi
 }
 
 tip_status tip_probe_vectors(int32_t ndim, const int64_t* dims, int32_t ncomp, int32_t mask, uint64_t seed,
-                             int64_t m0, int64_t count, int32_t comp, double* out, void* stream) {
+                             int64_t m0, int64_t count, int32_t comp, int32_t probe, double* out, void* stream) {
   if (ncomp != 1 && ncomp != 3) return fail(TIP_EINVAL, "ncomp = %d, expected 1 or 3", ncomp);
   Geom g;
   tip_status s = make_geom(ndim, dims, ncomp, &g);
   if (s != TIP_OK) return s;
   if (mask == TIP_MASK_DEFAULT) mask = ncomp == 1 ? TIP_MASK_Z2 : TIP_MASK_Z4;
   if (mask < TIP_MASK_NONE || mask > TIP_MASK_Z4) return fail(TIP_EINVAL, "unknown mask %d", mask);
+  if (probe < TIP_PROBE_HIERARCHICAL || probe > TIP_PROBE_RANDOM) return fail(TIP_EINVAL, "unknown probe kind %d", probe);
+  if (probe == TIP_PROBE_NATURAL && !g.pow2)
+    return fail(TIP_EINVAL, "natural-order Hadamard probes need power-of-two sides");
+  if (probe == TIP_PROBE_RANDOM && mask == TIP_MASK_NONE) return fail(TIP_EINVAL, "random probes need a Z2 or Z4 mask");
+  g.probe = probe;
   if (comp < 0 || comp >= ncomp) return fail(TIP_EINVAL, "comp = %d out of range", comp);
   if (m0 < 0 || count < 0 || m0 + count > (int64_t)g.V) return fail(TIP_EINVAL, "probe range outside [0, V)");
   if (!out && count > 0) return fail(TIP_EINVAL, "out is NULL");

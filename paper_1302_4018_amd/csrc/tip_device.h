@@ -36,6 +36,7 @@ struct Geom {
   int32_t has3;              // a three-colouring level follows the binary ones
   uint32_t sub[kMaxDim];     // sides n_j >> B of the sub-torus it colours
   uint32_t gamma;            // colours of one sweep: 2^LB, times 3 with that level
+  int32_t probe;             // probe kind of the call: 0 hierarchical, 1 natural-order Hadamard, 2 random
 };
 
 constexpr int kLdsPerCu = 160 * 1024;   // gfx950 LDS per CU
@@ -153,6 +154,11 @@ __device__ __forceinline__ ProbeCol probe_column(uint64_t m, const Geom& g) {
   return pc;
 }
 
+// Probe kinds (the comparison probes of Sec. 5 run through the same path):
+// hierarchical (above); natural-order Hadamard, z_m(x) = H(s(x), m) on the
+// natural site numbering; random, z_m = the mask of sweep m alone.
+enum ProbeKind { kProbeHierarchical = 0, kProbeNatural = 1, kProbeRandom = 2 };
+
 // Entry (s, comp) of the probing right-hand side b_{m,comp} = z0_r .* z_m:
 // (re, im), each exactly 0 or +-1 except the F_3 factor w^k, whose parts are
 // -1/2 and +-(the double nearest sqrt(3)/2).  z0_r takes outputs
@@ -184,6 +190,26 @@ __device__ __forceinline__ double2 probe_value(uint32_t s, uint32_t P, ProbeCol 
   }
   return v;
 }
+
+// Entry (s, comp) of right-hand side m for the call's probe kind.
+__device__ __forceinline__ double2 probe_entry(uint32_t s, uint64_t m, int comp, const Geom& g, uint64_t seed,
+                                               int mask) {
+  ProbeCol pc;
+  if (g.probe == kProbeNatural) {
+    pc.col = (uint32_t)m;
+    pc.j3 = 0u;
+    pc.r = 0u;
+    return probe_value(s, s, pc, comp, g, seed, mask);
+  }
+  if (g.probe == kProbeRandom) {
+    pc.col = 0u;
+    pc.j3 = 0u;
+    pc.r = (uint32_t)m;
+    return probe_value(s, 0u, pc, comp, g, seed, mask);
+  }
+  return probe_value(s, hier_perm(s, g), probe_column(m, g), comp, g, seed, mask);
+}
+
 
 // ---- complex helpers (double2 = re, im) ----------------------------------
 __device__ __forceinline__ double2 cadd(double2 a, double2 b) { return make_double2(a.x + b.x, a.y + b.y); }

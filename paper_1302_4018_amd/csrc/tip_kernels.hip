@@ -656,14 +656,14 @@ __device__ __forceinline__ uint32_t spatial_parity(uint32_t s3, const Geom& g) {
 }
 
 template <class T, int NC>
-__device__ __forceinline__ void rhs_at(const Geom& g, uint32_t s, uint32_t P, int64_t rhs0, int j, int nb,
+__device__ __forceinline__ void rhs_at(const Geom& g, uint32_t s, int64_t rhs0, int j, int nb,
                                        uint64_t seed, int mask, T (&b)[NC]) {
 #pragma unroll
   for (int c = 0; c < NC; ++c) b[c] = zero<T>();
   if (j >= nb) return;
   const int64_t rg = rhs0 + j;
   const int cj = (int)(rg % NC);
-  const T v = from_c<T>(probe_value(s, P, probe_column((uint64_t)(rg / NC), g), cj, g, seed, mask));
+  const T v = from_c<T>(probe_entry(s, (uint64_t)(rg / NC), cj, g, seed, mask));
 #pragma unroll
   for (int c = 0; c < NC; ++c)
     if (c == cj) b[c] = v;
@@ -678,7 +678,7 @@ __global__ __launch_bounds__(kBlock) void k_init(Geom g, int logB, int64_t rhs0,
   const uint32_t s = blockIdx.x * (kBlock >> logB) + (threadIdx.x >> logB);
   if (s >= g.V) return;
   T b[NC], z[NC];
-  rhs_at<T, NC>(g, s, hier_perm(s, g), rhs0, j, nb, seed, mask, b);
+  rhs_at<T, NC>(g, s, rhs0, j, nb, seed, mask, b);
 #pragma unroll
   for (int c = 0; c < NC; ++c) z[c] = zero<T>();
   store_vec<T, NC>(x, g.V, logB, s, j, z);
@@ -706,7 +706,7 @@ __global__ __launch_bounds__(kBlock) void k_true_residual(Geom g, TileMap tm, Op
   if (s < g.V && state[j] == kFrozen) {
     T xs[NC], ax[NC], b[NC], rt[NC];
     stencil_site(op, g, tm.logB, s, j, mass_field, mass, w, x, xs, ax);
-    rhs_at<T, NC>(g, s, hier_perm(s, g), rhs0, j, nb, seed, mask, b);
+    rhs_at<T, NC>(g, s, rhs0, j, nb, seed, mask, b);
 #pragma unroll
     for (int c = 0; c < NC; ++c) {
       rt[c] = axpy(-1.0, ax[c], b[c]);
@@ -868,7 +868,7 @@ __global__ __launch_bounds__(kBlock) void k_init_mixed(Geom g, int logB, int64_t
   if (s >= g.V) return;
   T32 b[NC], z[NC];
   T64 z64[NC];
-  rhs_at<T32, NC>(g, s, hier_perm(s, g), rhs0, j, nb, seed, mask, b);
+  rhs_at<T32, NC>(g, s, rhs0, j, nb, seed, mask, b);
 #pragma unroll
   for (int c = 0; c < NC; ++c) {
     z[c] = zero<T32>();
@@ -923,7 +923,7 @@ __global__ __launch_bounds__(kBlock) void k_ru_residual(Geom g, TileMap tm, Op64
       T xs[NC], ax[NC], b[NC];
       T32 r32[NC];
       stencil_site(op, g, tm.logB, s, j, mass_field, mass, w, x, xs, ax);
-      rhs_at<T, NC>(g, s, hier_perm(s, g), rhs0, j, nb, seed, mask, b);
+      rhs_at<T, NC>(g, s, rhs0, j, nb, seed, mask, b);
 #pragma unroll
       for (int c = 0; c < NC; ++c) {
         const T rt = axpy(-1.0, ax[c], b[c]);
@@ -1093,8 +1093,7 @@ __global__ __launch_bounds__(kBlock) void k_probe_vectors(Geom g, uint64_t seed,
   const uint32_t s = blockIdx.x * kBlock + threadIdx.x;
   if (s >= g.V) return;
   const int64_t m = m0 + blockIdx.y;
-  const uint32_t P = hier_perm(s, g);
-  out[(size_t)blockIdx.y * g.V + s] = probe_value(s, P, probe_column((uint64_t)m, g), comp, g, seed, mask);
+  out[(size_t)blockIdx.y * g.V + s] = probe_entry(s, (uint64_t)m, comp, g, seed, mask);
 }
 
 // [ndim][V][3][3] complex (caller) -> [ndim][9][V] complex (kernels)
@@ -1346,7 +1345,7 @@ __global__ __launch_bounds__(kBlock) void k_eo_hop(Geom g, MarchMap mm, int P, O
       }
     } else {
       T b[NC];
-      rhs_at<T, NC>(g, s, hier_perm(s, g), rhs0, j, nb, seed, mask, b);
+      rhs_at<T, NC>(g, s, rhs0, j, nb, seed, mask, b);
       if constexpr (MODE == 2) {
 #pragma unroll
         for (int c = 0; c < NC; ++c) {
@@ -1394,7 +1393,7 @@ __global__ __launch_bounds__(kBlock) void k_eo_init_odd(Geom g, int logB, int64_
   if (h >= Vh) return;
   const uint32_t s = eo_site(h, 1, g);
   T b[NC];
-  rhs_at<T, NC>(g, s, hier_perm(s, g), rhs0, j, nb, seed, mask, b);
+  rhs_at<T, NC>(g, s, rhs0, j, nb, seed, mask, b);
   const double f = 1.0 / diag[s];
 #pragma unroll
   for (int c = 0; c < NC; ++c) b[c] = axpy(f, b[c], zero<T>());
