@@ -200,6 +200,49 @@ def bench_c4(args):
     print(json.dumps(out), flush=True)
 
 
+def bench_compare(args):
+    """The comparison study of Sec. 5 on the GPU path: a 32^3 free torus with
+    m = 0.05 (condition number about 240), whose Tr(A^-1) is known in closed
+    form; the RMS over masks of the relative error of T_s at s = 2^k for the
+    three probe kinds, up to s = 1024 (the 3-D completion points are 2, 16,
+    128, 1024).  One JSON line; every solve is a FP64 CG to 1e-10 on the GPU."""
+    import numpy as np
+    import torch
+
+    from paper_1302_4018_amd import binding as tip
+
+    dims, m, n = [32, 32, 32], 0.05, 1024
+    V = dims[0] * dims[1] * dims[2]
+    k = np.arange(V)
+    lam = m + sum(4.0 * np.sin(np.pi * ((k // st) % nn) / nn) ** 2
+                  for nn, st in zip(dims, (1, dims[0], dims[0] * dims[1])))
+    exact = float(np.sum(1.0 / lam))            # Fourier modes diagonalise the free torus (Sec. 5)
+    gop = tip.Operator(dims, tip.KIND_SCALAR, mass=m)
+    kinds = {"hierarchical": tip.PROBE_HIERARCHICAL, "natural": tip.PROBE_NATURAL, "random": tip.PROBE_RANDOM}
+    table, solves = {}, 0
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for name, probe in kinds.items():
+        errs = []
+        for seed in range(args.masks):
+            est, _, st = tip.trace_inv_probe(gop, n, 1e-10, 1000 + seed, mask=tip.MASK_Z2, probe=probe)
+            errs.append(np.abs(est.real - exact) / exact)
+            solves += st["solves"]
+        table[name] = [float(f"{v:.3e}") for v in np.sqrt(np.mean(np.array(errs) ** 2, axis=0))]
+        log(f"[compare] {name}: {table[name]}")
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    out = {"metric": "relative error of T_s against the exact Tr(A^-1), RMS over masks (32^3 free torus, m=0.05)",
+           "value": table["hierarchical"][-1], "unit": "relative error at s=1024", "n_gpus": 1,
+           "steps": 1, "warmup": 0, "ms_per_step": round(el * 1e3, 1), "higher_is_better": False,
+           "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+           "config": {"workload": "32^3 scalar Laplacian, m=0.05, Z2 masks, s = 1..1024", "masks": args.masks,
+                      "exact_trace": exact, "s": [2 ** i for i in range(11)], "solves": solves,
+                      "solves_per_s": round(solves / el, 1)},
+           "errors": table}
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -219,8 +262,11 @@ def main():
                     help="write the stencil's measured HBM bytes per launch from two rocprofv3 --pmc "
                          "counter_collection.csv files, then exit (no GPU work)")
     ap.add_argument("--traffic-command", default="", help="command recorded with --traffic-from")
-    ap.add_argument("--workload", choices=["c5", "c4"], default="c5",
-                    help="c5: the 32^4 covariant probing run (default); c4: the batch of 64 uneven 3-D tori")
+    ap.add_argument("--workload", choices=["c5", "c4", "compare"], default="c5",
+                    help="c5: the 32^4 covariant probing run (default); c4: the batch of 64 uneven 3-D tori; "
+                         "compare: hierarchical vs natural-order Hadamard vs Monte-Carlo probes on a 32^3 torus "
+                         "with a closed-form trace")
+    ap.add_argument("--masks", type=int, default=4, help="compare: masks averaged per probe kind")
     args = ap.parse_args()
     if args.traffic_from:
         write_traffic(args.traffic_from[0], args.traffic_from[1], STENCIL[(True, "fp64")], args.traffic_command)
@@ -241,6 +287,9 @@ def main():
 
     if args.workload == "c4":
         bench_c4(args)
+        return
+    if args.workload == "compare":
+        bench_compare(args)
         return
 
     if args.copy_calibration:

@@ -57,8 +57,11 @@
  * Memory: every pointer documented as "device" is caller-owned device memory
  *   and is never freed by the library; "host" pointers likewise.  Complex
  *   numbers are interleaved (re, im) float64 pairs.
- * Streams: `stream` is a hipStream_t (NULL = the default stream).  All work of
- *   a call is enqueued on that stream; calls that return synchronise it.
+ * Streams: `stream` is a hipStream_t.  All work of a call is enqueued on that
+ *   stream; calls that return synchronise it.  With NULL the library first
+ *   synchronises the null stream, then works on a non-blocking stream of the
+ *   operator handle, so that chunks of CG iterations can be replayed as HIP
+ *   graphs (set TIP_GRAPH=0 to keep the null stream and eager launches).
  * Errors: no exception crosses the ABI.  Argument validation fails with
  *   TIP_EINVAL before any output is written or any device work is enqueued;
  *   tip_last_error() then returns a thread-local message.

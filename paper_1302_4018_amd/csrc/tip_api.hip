@@ -106,12 +106,23 @@ tip_status make_geom(int32_t ndim, const int64_t* dims, int ncomp, Geom* g) {
   return TIP_OK;
 }
 
+// Device allocation, frees, stream creation and device-wide synchronisation
+// may synchronise the device, which must not happen while another thread
+// captures a HIP graph (trace_inv_probe_batch runs calls on several threads).
+// They and the captures take this lock.
+std::mutex g_device_mu;
+
 struct DevBuf {
   void* p = nullptr;
   size_t n = 0;
-  ~DevBuf() { if (p) (void)hipFree(p); }
+  ~DevBuf() {
+    if (!p) return;
+    std::lock_guard<std::mutex> lk(g_device_mu);
+    (void)hipFree(p);
+  }
   hipError_t ensure(size_t bytes) {
     if (bytes <= n) return hipSuccess;
+    std::lock_guard<std::mutex> lk(g_device_mu);
     if (p) { (void)hipFree(p); p = nullptr; n = 0; }
     hipError_t e = hipMalloc(&p, bytes);
     if (e == hipSuccess) n = bytes;
@@ -122,9 +133,14 @@ struct DevBuf {
 struct HostPinned {
   void* p = nullptr;
   size_t n = 0;
-  ~HostPinned() { if (p) (void)hipHostFree(p); }
+  ~HostPinned() {
+    if (!p) return;
+    std::lock_guard<std::mutex> lk(g_device_mu);
+    (void)hipHostFree(p);
+  }
   hipError_t ensure(size_t bytes) {
     if (bytes <= n) return hipSuccess;
+    std::lock_guard<std::mutex> lk(g_device_mu);
     if (p) { (void)hipHostFree(p); p = nullptr; n = 0; }
     hipError_t e = hipHostMalloc(&p, bytes, hipHostMallocDefault);
     if (e == hipSuccess) n = bytes;
@@ -152,6 +168,10 @@ struct tip_op_s {
   DevBuf vec, partial, scal;
   HostPinned host;
   std::vector<hipEvent_t> events;
+  // a non-blocking stream of the handle's own, used when the caller passes the
+  // null stream (which cannot be captured into a graph); calls synchronise it
+  // before they return
+  hipStream_t own_stream = nullptr;
 
   OpDev dev(bool single = false) const {
     OpDev o;
@@ -167,6 +187,10 @@ struct tip_op_s {
   }
   ~tip_op_s() {
     for (hipEvent_t e : events) (void)hipEventDestroy(e);
+    if (own_stream) {
+      std::lock_guard<std::mutex> lk(g_device_mu);
+      (void)hipStreamDestroy(own_stream);
+    }
   }
 };
 
@@ -230,14 +254,22 @@ tip_status create_handle(const tip_operator* op, hipStream_t st, tip_op_s** out)
     double lb = op->mass;
     if (op->mass_field) {
       std::vector<double> m(V);
-      if (hipMemcpy(m.data(), op->mass_field, V * sizeof(double), hipMemcpyDeviceToHost) != hipSuccess)
-        return bail(fail(TIP_EDEVICE, "reading mass_field failed"));
+      hipError_t e;
+      {
+        std::lock_guard<std::mutex> lk(g_device_mu);   // a null-stream copy
+        e = hipMemcpy(m.data(), op->mass_field, V * sizeof(double), hipMemcpyDeviceToHost);
+      }
+      if (e != hipSuccess) return bail(fail(TIP_EDEVICE, "reading mass_field failed"));
       lb = *std::min_element(m.begin(), m.end());
     }
     if (op->coupling) {
       std::vector<double> w((size_t)g.ndim * V);
-      if (hipMemcpy(w.data(), op->coupling, w.size() * sizeof(double), hipMemcpyDeviceToHost) != hipSuccess)
-        return bail(fail(TIP_EDEVICE, "reading coupling failed"));
+      hipError_t e;
+      {
+        std::lock_guard<std::mutex> lk(g_device_mu);   // a null-stream copy
+        e = hipMemcpy(w.data(), op->coupling, w.size() * sizeof(double), hipMemcpyDeviceToHost);
+      }
+      if (e != hipSuccess) return bail(fail(TIP_EDEVICE, "reading coupling failed"));
       if (*std::min_element(w.begin(), w.end()) < 0.0) lb = std::nan("");
     }
     h->lambda_lb = lb;
@@ -506,6 +538,17 @@ struct Solver {
     geom = h->geom;
     geom.probe = p->probe;
     st = (hipStream_t)p->stream;
+    if (!st && !env_off("TIP_GRAPH")) {
+      if (!h->own_stream) {
+        std::lock_guard<std::mutex> lk(g_device_mu);
+        if (hipStreamCreateWithFlags(&h->own_stream, hipStreamNonBlocking) != hipSuccess) h->own_stream = nullptr;
+      }
+      if (h->own_stream) {
+        // work the caller queued on the null stream comes first
+        TIP_HIP(hipStreamSynchronize(nullptr));
+        st = h->own_stream;
+      }
+    }
     mixed = p->precision == TIP_PREC_MIXED;
     prec = mixed ? Prec::kF32 : Prec::kF64;
     const Geom& g = geom;
@@ -714,9 +757,91 @@ struct Solver {
 
   // Solve right-hand sides rhs0 .. rhs0+nb-1; x (FP64) stays in X.  Fills the
   // host mirrors h_q, h_relres2, h_state, h_iters for those nb right-hand sides.
-  tip_status solve_block(int64_t rhs0, int nb) {
+  // One CG iteration of the block: w = A p (with p^H w), alpha, r -= alpha w
+  // (with ||r||^2), beta, x += alpha p and p = r + beta p, then in mixed
+  // precision any pending reliable update.  tv: events around the operator
+  // application, or NULL.
+  tip_status enqueue_iteration(int it, const Timed* tv, int64_t rhs0, int nb, void* xdir) {
     const Geom& g = geom;
     const MarchMap* mm = pl.use_march ? &pl.mm : nullptr;
+    const double* diag = (const double*)h->diag.p;
+    if (tv) TIP_HIP(hipEventRecord(tv->a, st));
+    if (pl.eo) {
+      // w_e = S p_e: t_o = D_o^-1 H_oe p_e, then w_e = D_e p_e - H_eo t_o
+      TIP_HIP(launch_eo_hop(0, od, g, pl.me, 1, pl.elem, prec, diag, sc.state, sc.active, Pv, nullptr, Tv,
+                            nullptr, nullptr, 0, 0, 0, 0, nullptr, nullptr, st));
+      if (tv) TIP_HIP(hipEventRecord(tv->b, st));
+      TIP_HIP(launch_eo_hop(1, od, g, pl.me, 0, pl.elem, prec, diag, sc.state, sc.active, Tv, Pv, W, nullptr,
+                            nullptr, 0, 0, 0, 0, part, ran_dev + it, st));
+    } else {
+      if (tv) TIP_HIP(hipEventRecord(tv->b, st));
+      TIP_HIP(launch_stencil(od, g, pl.tm, mm, pl.elem, prec, sc.state, sc.active, Pv, W, part, ran_dev + it,
+                             st));
+    }
+    if (tv) TIP_HIP(hipEventRecord(tv->c, st));
+    TIP_HIP(launch_reduce_alpha(sc, pl.B, part, gx_m, st));
+    TIP_HIP(launch_update_r(nvec, pl.logB, pl.elem, prec, sc, Rv, W, part + pstride, st));
+    TIP_HIP(launch_reduce_beta(sc, pl.B, part + pstride, gx_u, tol2, max_iter, delta2, st));
+    TIP_HIP(launch_direction(nvec, pl.logB, pl.elem, prec, sc, xdir, Rv, Pv, st));
+    if (mixed) {
+      tip_status s = reliable(rhs0, nb, 0);
+      if (s != TIP_OK) return s;
+    }
+    return TIP_OK;
+  }
+
+  // Chunks of CG iterations replayed as HIP graphs (kernel nodes only): one
+  // graph per chunk length, captured on first use and replayed for every
+  // later chunk of that length in this call.  The reset of the per-launch
+  // flags stays outside the graph.  Eager launches instead: with profiling on
+  // (per-kernel hipEvent timing needs events on the stream), in plain-CG
+  // mixed precision (its reliable updates regenerate b, which ties a chunk to
+  // its block), with TIP_GRAPH=0, and for the rest of the call after a failed
+  // capture.
+  struct GraphEntry {
+    int chunk;
+    hipGraphExec_t exec;
+  };
+  std::vector<GraphEntry> graphs;
+  bool graphs_ok = true;
+
+  int graph_for(int chunk, int64_t rhs0, int nb, void* xdir) {
+    if (!graphs_ok || g_profiling || (mixed && !pl.eo) || env_off("TIP_GRAPH")) return -1;
+    for (size_t i = 0; i < graphs.size(); ++i)
+      if (graphs[i].chunk == chunk) return (int)i;
+    GraphEntry ge{chunk, nullptr};
+    std::lock_guard<std::mutex> lk(g_device_mu);
+    if (hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal) != hipSuccess) {
+      graphs_ok = false;
+      (void)hipGetLastError();
+      return -1;
+    }
+    tip_status s = TIP_OK;
+    for (int it = 0; it < chunk && s == TIP_OK; ++it)
+      s = enqueue_iteration(it, nullptr, rhs0, nb, xdir);
+    hipGraph_t graph = nullptr;
+    const hipError_t e = hipStreamEndCapture(st, &graph);
+    hipError_t ei = hipErrorUnknown;
+    if (s == TIP_OK && e == hipSuccess && graph) ei = hipGraphInstantiate(&ge.exec, graph, nullptr, nullptr, 0);
+    if (graph) (void)hipGraphDestroy(graph);
+    if (ei != hipSuccess) {
+      graphs_ok = false;
+      (void)hipGetLastError();
+      return -1;
+    }
+    graphs.push_back(ge);
+    return (int)graphs.size() - 1;
+  }
+
+  ~Solver() {
+    if (graphs.empty()) return;
+    std::lock_guard<std::mutex> lk(g_device_mu);
+    for (GraphEntry& ge : graphs)
+      if (ge.exec) (void)hipGraphExecDestroy(ge.exec);
+  }
+
+  tip_status solve_block(int64_t rhs0, int nb) {
+    const Geom& g = geom;
     TIP_HIP(launch_scalars_init(sc, nb, pl.B, (double)g.V, p->tol >= 1.0 ? 1 : 0, st));
     const double* diag = (const double*)h->diag.p;
     if (pl.eo && mixed) {
@@ -749,36 +874,19 @@ struct Solver {
         window.clear();
         ev_used = 0;
         TIP_HIP(hipMemsetAsync(ran_dev, 0, chunk * sizeof(int), st));
-        for (int it = 0; it < chunk; ++it) {
-          Timed tv{};
-          if (g_profiling) {
-            TIP_HIP(next_event(&tv.a));
-            TIP_HIP(next_event(&tv.b));
-            TIP_HIP(next_event(&tv.c));
-            TIP_HIP(hipEventRecord(tv.a, st));
-          }
-          if (pl.eo) {
-            // w_e = S p_e: t_o = D_o^-1 H_oe p_e, then w_e = D_e p_e - H_eo t_o
-            TIP_HIP(launch_eo_hop(0, od, g, pl.me, 1, pl.elem, prec, diag, sc.state, sc.active, Pv, nullptr, Tv,
-                                  nullptr, nullptr, 0, 0, 0, 0, nullptr, nullptr, st));
-            if (g_profiling) TIP_HIP(hipEventRecord(tv.b, st));
-            TIP_HIP(launch_eo_hop(1, od, g, pl.me, 0, pl.elem, prec, diag, sc.state, sc.active, Tv, Pv, W, nullptr,
-                                  nullptr, 0, 0, 0, 0, part, ran_dev + it, st));
-          } else {
-            if (g_profiling) TIP_HIP(hipEventRecord(tv.b, st));
-            TIP_HIP(launch_stencil(od, g, pl.tm, mm, pl.elem, prec, sc.state, sc.active, Pv, W, part, ran_dev + it,
-                                   st));
-          }
-          if (g_profiling) {
-            TIP_HIP(hipEventRecord(tv.c, st));
-            window.push_back(tv);
-          }
-          TIP_HIP(launch_reduce_alpha(sc, pl.B, part, gx_m, st));
-          TIP_HIP(launch_update_r(nvec, pl.logB, pl.elem, prec, sc, Rv, W, part + pstride, st));
-          TIP_HIP(launch_reduce_beta(sc, pl.B, part + pstride, gx_u, tol2, max_iter, delta2, st));
-          TIP_HIP(launch_direction(nvec, pl.logB, pl.elem, prec, sc, xdir, Rv, Pv, st));
-          if (mixed) {
-            tip_status s = reliable(rhs0, nb, 0);
+        const int gi = graph_for(chunk, rhs0, nb, xdir);
+        if (gi >= 0) {
+          TIP_HIP(hipGraphLaunch(graphs[(size_t)gi].exec, st));
+        } else {
+          for (int it = 0; it < chunk; ++it) {
+            Timed tv{};
+            if (g_profiling) {
+              TIP_HIP(next_event(&tv.a));
+              TIP_HIP(next_event(&tv.b));
+              TIP_HIP(next_event(&tv.c));
+              window.push_back(tv);
+            }
+            tip_status s = enqueue_iteration(it, g_profiling ? &tv : nullptr, rhs0, nb, xdir);
             if (s != TIP_OK) return s;
           }
         }
@@ -865,7 +973,10 @@ tip_status tip_op_create(const tip_operator* op, void* stream, tip_op_handle* ou
 
 tip_status tip_op_destroy(tip_op_handle h) {
   if (!h) return fail(TIP_EINVAL, "handle is NULL");
-  (void)hipDeviceSynchronize();
+  {
+    std::lock_guard<std::mutex> lk(g_device_mu);
+    (void)hipDeviceSynchronize();
+  }
   delete h;
   return TIP_OK;
 }
@@ -1109,7 +1220,10 @@ tip_status trace_inv_probe_batch(const tip_operator* ops, const tip_params* para
     (void)hipSetDevice(device);
     hipStream_t stream = nullptr;
     // non-blocking: no implicit ordering with the null stream or the other workers
-    if (hipStreamCreateWithFlags(&stream, hipStreamNonBlocking) != hipSuccess) stream = nullptr;
+    {
+      std::lock_guard<std::mutex> lk(g_device_mu);
+      if (hipStreamCreateWithFlags(&stream, hipStreamNonBlocking) != hipSuccess) stream = nullptr;
+    }
     for (;;) {
       const int32_t k = next.fetch_add(1);
       if (k >= count) break;
@@ -1119,7 +1233,10 @@ tip_status trace_inv_probe_batch(const tip_operator* ops, const tip_params* para
       st[(size_t)i] = trace_inv_probe(&ops[i], &p, estimates[i], stats ? &stats[i] : nullptr);
       if (st[(size_t)i] != TIP_OK) msg[(size_t)i] = g_err;
     }
-    if (stream) (void)hipStreamDestroy(stream);
+    if (stream) {
+      std::lock_guard<std::mutex> lk(g_device_mu);
+      (void)hipStreamDestroy(stream);
+    }
   };
   std::vector<std::thread> pool;
   for (int w = 1; w < workers; ++w) pool.emplace_back(run);
