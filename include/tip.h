@@ -138,6 +138,10 @@ typedef struct {
   double reliable_delta; /* MIXED: reliable update when the FP32 residual norm has
                             fallen by this factor since the last one; 0 = 1e-3     */
   int32_t probe;         /* TIP_PROBE_*; 0 = hierarchical                           */
+  int32_t round_tiles;   /* 4-D power-of-two lattices: stencil tiles per XCD round of the
+                            workgroup order (0 = library choice; see tip_autotune) */
+  int32_t march_tc;      /* lattice slices one stencil workgroup marches (power of two;
+                            0 = library choice)                                    */
 } tip_params;
 
 typedef struct {
@@ -197,6 +201,27 @@ tip_status tip_op_destroy(tip_op_handle h);
 /* trace_inv_probe on a prepared handle (no repack inside the call). */
 tip_status trace_inv_probe_op(tip_op_handle h, const tip_params* p,
                               double* estimates, tip_stats* stats);
+
+/* Launch configuration found by tip_autotune. */
+typedef struct {
+  int32_t rhs_block;          /* right-hand sides per block                         */
+  int32_t round_tiles;        /* tiles per XCD round (0 = library choice)           */
+  int32_t march_tc;           /* marched slices (0 = library choice)                */
+  double seconds_per_solve;   /* measured on the sample                             */
+} tip_tuning;
+
+/* Times trace_inv_probe_op on the first sample_vectors probes (0 = 64) for each
+ * candidate launch configuration and returns the fastest in best: rhs_block in
+ * {16, 32, 64} unless p->rhs_block fixes it, and on 4-D power-of-two lattices
+ * round_tiles in {library choice, 64, 128, 256, 512} unless p->round_tiles
+ * fixes it.  Every candidate runs twice (the first run warms up) and keeps
+ * the other fields of p (precision, mask, probe, tol, stream).  tried: HOST
+ * [max_tried] candidates in the order timed, or NULL with max_tried = 0;
+ * n_tried: how many were timed (may exceed max_tried), or NULL.  Copy the
+ * result into tip_params.rhs_block / round_tiles / march_tc.  Results differ
+ * between block sizes in rounding only. */
+tip_status tip_autotune(tip_op_handle h, const tip_params* p, int64_t sample_vectors, tip_tuning* best,
+                        tip_tuning* tried, int32_t max_tried, int32_t* n_tried);
 
 /* trace_inv_probe_op plus the gradient of the last estimate, T = (1/s) sum_{m<s} q_m
  * at s = n_vectors, with respect to the operator's parameters, the probes held

@@ -1,0 +1,51 @@
+"""Launch configurations chosen by measurement, with a small on-disk cache.
+
+tip_autotune (in the HIP library) times the candidate right-hand-side block
+sizes and stencil tile rounds on a sample of probes; this module keys its
+answer by what the choice depends on (lattice sides, operator kind,
+precision, mask, probe kind, whether couplings are present) and keeps it in a
+JSON file, so a later run on the same shape reuses it without timing again.
+The file is TIP_TUNE_CACHE, or ~/.cache/paper_1302_4018_amd/tuning.json.
+"""
+
+import json
+import os
+
+from . import binding as tip
+
+
+def cache_path():
+    return os.environ.get("TIP_TUNE_CACHE",
+                          os.path.join(os.path.expanduser("~"), ".cache", "paper_1302_4018_amd", "tuning.json"))
+
+
+def _key(op, precision, mask, probe):
+    return json.dumps({"dims": op.dims, "kind": op.kind, "precision": int(precision), "mask": int(mask),
+                       "probe": int(probe), "coupling": op.coupling is not None}, sort_keys=True)
+
+
+def _load(path):
+    try:
+        with open(path) as f:
+            return json.load(f)
+    except (OSError, ValueError):
+        return {}
+
+
+def tuned(handle, tol=1e-10, seed=0, mask=tip.MASK_DEFAULT, precision=tip.PREC_FP64, probe=tip.PROBE_HIERARCHICAL,
+          sample_vectors=64, path=None, retune=False):
+    """kwargs (rhs_block, round_tiles, march_tc) for trace_inv_probe on this handle."""
+    path = path or cache_path()
+    key = _key(handle.op, precision, mask, probe)
+    table = _load(path)
+    if key not in table or retune:
+        best, tried = handle.autotune(tol, seed, sample_vectors=sample_vectors, mask=mask, precision=precision,
+                                      probe=probe)
+        table[key] = {"best": best, "tried": tried}
+        os.makedirs(os.path.dirname(path) or ".", exist_ok=True)
+        tmp = path + ".tmp"
+        with open(tmp, "w") as f:
+            json.dump(table, f, indent=1, sort_keys=True)
+        os.replace(tmp, path)
+    b = table[key]["best"]
+    return {"rhs_block": b["rhs_block"], "round_tiles": b["round_tiles"], "march_tc": b["march_tc"]}

@@ -35,7 +35,12 @@ class tip_params(ctypes.Structure):
                 ("max_iter", ctypes.c_int32), ("seed", ctypes.c_uint64), ("mask", ctypes.c_int32),
                 ("rhs_block", ctypes.c_int32), ("precision", ctypes.c_int32), ("stream", ctypes.c_void_p),
                 ("quadratures", ctypes.POINTER(ctypes.c_double)), ("reliable_delta", ctypes.c_double),
-                ("probe", ctypes.c_int32)]
+                ("probe", ctypes.c_int32), ("round_tiles", ctypes.c_int32), ("march_tc", ctypes.c_int32)]
+
+
+class tip_tuning(ctypes.Structure):
+    _fields_ = [("rhs_block", ctypes.c_int32), ("round_tiles", ctypes.c_int32), ("march_tc", ctypes.c_int32),
+                ("seconds_per_solve", ctypes.c_double)]
 
 
 class tip_stats(ctypes.Structure):
@@ -59,6 +64,8 @@ def _load():
         "trace_inv_probe": (ctypes.c_int, [P(tip_operator), P(tip_params), P(ctypes.c_double), P(tip_stats)]),
         "trace_inv_probe_batch": (ctypes.c_int, [P(tip_operator), P(tip_params), ctypes.c_int32, ctypes.c_int32,
                                                  P(P(ctypes.c_double)), P(tip_stats), P(ctypes.c_int32)]),
+        "tip_autotune": (ctypes.c_int, [ctypes.c_void_p, P(tip_params), ctypes.c_int64, P(tip_tuning), P(tip_tuning),
+                                        ctypes.c_int32, P(ctypes.c_int32)]),
         "tip_op_create": (ctypes.c_int, [P(tip_operator), ctypes.c_void_p, P(ctypes.c_void_p)]),
         "tip_op_destroy": (ctypes.c_int, [ctypes.c_void_p]),
         "trace_inv_probe_op": (ctypes.c_int, [ctypes.c_void_p, P(tip_params), P(ctypes.c_double), P(tip_stats)]),
@@ -157,7 +164,7 @@ class Operator:
 
 
 def _params(n_vectors, tol, seed, mask, max_iter, rhs_block, m_begin, quadratures, stream, precision=PREC_FP64,
-            reliable_delta=0.0, probe=PROBE_HIERARCHICAL):
+            reliable_delta=0.0, probe=PROBE_HIERARCHICAL, round_tiles=0, march_tc=0):
     p = tip_params()
     p.n_vectors = int(n_vectors)
     p.m_begin = int(m_begin)
@@ -168,9 +175,12 @@ def _params(n_vectors, tol, seed, mask, max_iter, rhs_block, m_begin, quadrature
     p.rhs_block = int(rhs_block)
     p.precision = int(precision)
     p.stream = _stream(stream)
-    p.quadratures = quadratures.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+    p.quadratures = (None if quadratures is None
+                     else quadratures.ctypes.data_as(ctypes.POINTER(ctypes.c_double)))
     p.reliable_delta = float(reliable_delta)
     p.probe = int(probe)
+    p.round_tiles = int(round_tiles)
+    p.march_tc = int(march_tc)
     return p
 
 
@@ -183,13 +193,14 @@ def tip_num_checkpoints(n_vectors):
 
 
 def _run(fn, first, n_vectors, tol, seed, mask, max_iter, rhs_block, m_begin, quadratures, stream, raise_on_error,
-         precision=PREC_FP64, reliable_delta=0.0, probe=PROBE_HIERARCHICAL):
+         precision=PREC_FP64, reliable_delta=0.0, probe=PROBE_HIERARCHICAL, round_tiles=0, march_tc=0):
     nck = tip_num_checkpoints(n_vectors)
     est = np.zeros((nck, 2), dtype=np.float64)
     q = np.zeros((int(n_vectors), 2), dtype=np.float64)
     if quadratures is not None:
         q[:m_begin] = np.asarray(quadratures, dtype=np.complex128)[:m_begin].view(np.float64).reshape(-1, 2)
-    p = _params(n_vectors, tol, seed, mask, max_iter, rhs_block, m_begin, q, stream, precision, reliable_delta, probe)
+    p = _params(n_vectors, tol, seed, mask, max_iter, rhs_block, m_begin, q, stream, precision, reliable_delta, probe,
+                round_tiles, march_tc)
     st = tip_stats()
     status = fn(first, ctypes.byref(p), est.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), ctypes.byref(st))
     stats = _stats_dict(st)
@@ -252,9 +263,21 @@ class OpHandle:
 
     def trace_inv_probe(self, n_vectors, tol, seed, mask=MASK_DEFAULT, max_iter=0, rhs_block=0, m_begin=0,
                         quadratures=None, stream=None, raise_on_error=True, precision=PREC_FP64, reliable_delta=0.0,
-                        probe=PROBE_HIERARCHICAL):
+                        probe=PROBE_HIERARCHICAL, round_tiles=0, march_tc=0):
         return _run(lib.trace_inv_probe_op, self._h, n_vectors, tol, seed, mask, max_iter, rhs_block, m_begin,
-                    quadratures, stream, raise_on_error, precision, reliable_delta, probe)
+                    quadratures, stream, raise_on_error, precision, reliable_delta, probe, round_tiles, march_tc)
+
+    def autotune(self, tol, seed, sample_vectors=64, mask=MASK_DEFAULT, precision=PREC_FP64, probe=PROBE_HIERARCHICAL,
+                 rhs_block=0, round_tiles=0, stream=None):
+        """tip_autotune: (best tuning dict, list of tried dicts)."""
+        p = _params(1, tol, seed, mask, 0, rhs_block, 0, None, stream, precision, 0.0, probe, round_tiles, 0)
+        best = tip_tuning()
+        tried = (tip_tuning * 32)()
+        n = ctypes.c_int32(0)
+        _check(lib.tip_autotune(self._h, ctypes.byref(p), int(sample_vectors), ctypes.byref(best), tried, 32,
+                                ctypes.byref(n)), "tip_autotune")
+        as_dict = lambda t: {f: getattr(t, f) for f, _ in tip_tuning._fields_}
+        return as_dict(best), [as_dict(tried[i]) for i in range(min(n.value, 32))]
 
     def trace_inv_probe_grad(self, n_vectors, tol, seed, mask=MASK_DEFAULT, max_iter=0, rhs_block=0, stream=None,
                              precision=PREC_FP64, reliable_delta=0.0, mass=True, coupling=True,
@@ -369,3 +392,7 @@ def tip_set_profiling(on):
 
 def tip_last_error():
     return lib.tip_last_error().decode(errors="replace")
+
+
+def tip_autotune(handle, *args, **kwargs):
+    return handle.autotune(*args, **kwargs)

@@ -354,7 +354,7 @@ bool plan_block_order(const Geom& g, int TS, MarchMap* mm, int round_tiles) {
   const int n1 = 1 << g.logn[0], n2 = 1 << g.logn[1], n3 = 1 << g.logn[2];
   if (TS > n1 || n1 % TS != 0) return false;
   const int n1t = n1 / TS;
-  if (const char* e = std::getenv("TIP_ROUND_TILES")) round_tiles = std::max(1, std::atoi(e));
+  if (const char* e = std::getenv("TIP_ROUND_TILES")) round_tiles = std::max(1, std::atoi(e));   // experiments
   int best_g2 = -1;
   double best_shape = 1e30;
   for (int g2 = 1; g2 <= kNumXcd; g2 *= 2) {
@@ -410,7 +410,8 @@ bool block_order_is_permutation(const MarchMap& mm) {
 }
 
 // halve_t: march the half-lattice of the even-odd system (t slices of two).
-bool make_marchmap(const Geom& g, int logB, MarchMap* mm, bool halve_t = false) {
+// round_tiles / tc: per-call tuning (0 = the defaults below).
+bool make_marchmap(const Geom& g, int logB, MarchMap* mm, bool halve_t = false, int round_tiles = 0, int tc = 0) {
   if (!g.pow2) return false;                         // the marching kernels index with shifts
   if (!halve_t && (env_off("TIP_MARCH") || g.ndim < 2)) return false;
   const int nt = (1 << g.logn[g.ndim - 1]) >> (halve_t ? 1 : 0);
@@ -424,9 +425,10 @@ bool make_marchmap(const Geom& g, int logB, MarchMap* mm, bool halve_t = false) 
   mm->Q = (int32_t)(V3 / TS);
   mm->nt = nt;
   int Tc = nt;
-  if (const char* e = std::getenv("TIP_MARCH_TC")) {
-    const int v = std::atoi(e);
-    if (v >= 1 && v <= nt && (v & (v - 1)) == 0) Tc = v;
+  const char* env_tc = std::getenv("TIP_MARCH_TC");
+  const int want_tc = tc > 0 ? tc : (env_tc ? std::atoi(env_tc) : 0);
+  if (want_tc >= 1 && want_tc <= nt && (want_tc & (want_tc - 1)) == 0) {
+    Tc = want_tc;
   } else {
     while (Tc > 1 && (int64_t)mm->Q * (nt / Tc) < 2048) Tc /= 2;
   }
@@ -434,7 +436,8 @@ bool make_marchmap(const Geom& g, int logB, MarchMap* mm, bool halve_t = false) 
   mm->xcd_order = !env_off("TIP_TILE_ORDER") && mm->Q % kNumXcd == 0;
   // rounds of 128 tiles for the full stencil, 256 for the half-lattice one
   // (measured on the 32^4 covariant workload)
-  if (mm->xcd_order && g.ndim == 4 && plan_block_order(g, TS, mm, halve_t ? 256 : 128)) mm->xcd_order = 2;
+  if (mm->xcd_order && g.ndim == 4 && plan_block_order(g, TS, mm, round_tiles > 0 ? round_tiles : (halve_t ? 256 : 128)))
+    mm->xcd_order = 2;
   if (const char* e = std::getenv("TIP_TILE_ORDER")) {
     if (std::atoi(e) == 1 && mm->xcd_order == 2) mm->xcd_order = 1;
   }
@@ -474,6 +477,7 @@ tip_status check_params(const tip_op_s* h, const tip_params* p, int* mask_out) {
   if (mask < TIP_MASK_NONE || mask > TIP_MASK_Z4) return fail(TIP_EINVAL, "unknown mask %d", p->mask);
   if (p->probe < TIP_PROBE_HIERARCHICAL || p->probe > TIP_PROBE_RANDOM)
     return fail(TIP_EINVAL, "unknown probe kind %d", p->probe);
+  if (p->round_tiles < 0 || p->march_tc < 0) return fail(TIP_EINVAL, "round_tiles and march_tc must be >= 0");
   if (p->probe == TIP_PROBE_NATURAL && !h->geom.pow2)
     return fail(TIP_EINVAL, "natural-order Hadamard probes need power-of-two sides");
   if (p->probe == TIP_PROBE_RANDOM && mask == TIP_MASK_NONE)
@@ -579,14 +583,14 @@ struct Solver {
     pl.logB = 0;
     while ((1 << pl.logB) < B) ++pl.logB;
     pl.tm = make_tilemap(g, pl.logB);
-    pl.use_march = make_marchmap(g, pl.logB, &pl.mm);
+    pl.use_march = make_marchmap(g, pl.logB, &pl.mm, false, p->round_tiles, p->march_tc);
     // even-odd reduction: bipartite torus (every side >= 2, all powers of two
     // are then even) and a positive diagonal (lambda_lb > 0 implies D > 0)
     {
       bool bip = g.pow2 != 0;
       for (int mu = 0; mu < g.ndim; ++mu) bip = bip && g.logn[mu] >= 1;
       pl.eo = bip && h->lambda_lb > 0.0 && !env_off("TIP_EO") &&
-              make_marchmap(g, pl.logB, &pl.me, true);
+              make_marchmap(g, pl.logB, &pl.me, true, p->round_tiles, p->march_tc);
       // the covariant half-lattice kernel stages its tile's links in LDS
       if (pl.eo && h->kind == TIP_KIND_COVARIANT && (eo_lds_bytes(g, pl.me, prec) > 65536 || !h->has_links_eo))
         pl.eo = false;
@@ -1163,6 +1167,51 @@ tip_status tip_solve_probe(tip_op_handle h, const tip_params* p, int64_t m, int3
   }
   if (sv.h_state[0] == kBreakdown) return fail(TIP_EBREAKDOWN, "solve broke down (p^H A p <= 0)");
   if (sv.h_state[0] != kAccepted) return fail(TIP_ENOCONV, "solve did not converge within max_iter");
+  return TIP_OK;
+}
+
+tip_status tip_autotune(tip_op_handle h, const tip_params* p, int64_t sample_vectors, tip_tuning* best,
+                        tip_tuning* tried, int32_t max_tried, int32_t* n_tried) {
+  if (!h) return fail(TIP_EINVAL, "handle is NULL");
+  if (!p) return fail(TIP_EINVAL, "params is NULL");
+  if (!best) return fail(TIP_EINVAL, "best is NULL");
+  if (max_tried < 0 || (max_tried > 0 && !tried)) return fail(TIP_EINVAL, "tried is NULL");
+  const Geom& g = h->geom;
+  tip_params q = *p;
+  q.n_vectors = std::max<int64_t>(1, std::min<int64_t>(sample_vectors > 0 ? sample_vectors : 64, g.V));
+  q.m_begin = 0;
+  q.quadratures = nullptr;
+  int mask = 0;
+  tip_status s = check_params(h, &q, &mask);
+  if (s != TIP_OK) return s;
+  // candidates: right-hand sides per block, and (4-D power-of-two lattices,
+  // where the XCD block order applies) the tiles per round
+  std::vector<int> blocks = p->rhs_block > 0 ? std::vector<int>{p->rhs_block} : std::vector<int>{16, 32, 64};
+  std::vector<int> rounds{0};
+  if (g.pow2 && g.ndim == 4 && p->round_tiles == 0) rounds = {0, 64, 128, 256, 512};
+  else if (p->round_tiles > 0) rounds = {p->round_tiles};
+  std::vector<double> est((size_t)num_checkpoints(q.n_vectors) * 2);
+  int count = 0;
+  double best_t = 1e300;
+  for (int b : blocks)
+    for (int r : rounds) {
+      q.rhs_block = b;
+      q.round_tiles = r;
+      tip_stats st{};
+      s = trace_inv_probe_op(h, &q, est.data(), &st);            // warm-up (allocation, first launches)
+      if (s != TIP_OK) return s;
+      s = trace_inv_probe_op(h, &q, est.data(), &st);
+      if (s != TIP_OK) return s;
+      tip_tuning t{};
+      t.rhs_block = b;
+      t.round_tiles = r;
+      t.march_tc = q.march_tc;
+      t.seconds_per_solve = st.seconds / (double)std::max<int64_t>(1, st.solves);
+      if (count < max_tried) tried[count] = t;
+      ++count;
+      if (t.seconds_per_solve < best_t) best_t = t.seconds_per_solve, *best = t;
+    }
+  if (n_tried) *n_tried = count;
   return TIP_OK;
 }
 

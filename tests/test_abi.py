@@ -45,7 +45,7 @@ int main(void) {
   printf("tip_stats %zu\\n", sizeof(tip_stats));
   P(tip_operator, dims) P(tip_operator, kind) P(tip_operator, mass) P(tip_operator, links)
   P(tip_params, tol) P(tip_params, seed) P(tip_params, mask) P(tip_params, stream) P(tip_params, quadratures)
-  P(tip_params, reliable_delta) P(tip_params, probe)
+  P(tip_params, reliable_delta) P(tip_params, probe) P(tip_params, round_tiles) P(tip_params, march_tc)
   P(tip_stats, max_true_relres) P(tip_stats, stencil_launches) P(tip_stats, stencil_bytes)
   P(tip_stats, reliable_updates) P(tip_stats, max_quad_err_bound) P(tip_stats, matvecs)
   P(tip_stats, matvec_seconds) P(tip_stats, matvec_bytes) P(tip_stats, even_odd)
