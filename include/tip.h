@@ -181,7 +181,7 @@ tip_status trace_inv_probe(const tip_operator* op, const tip_params* p,
  * Problem i is ops[i] with params[i] (its stream field is ignored) and writes
  * estimates[i] (HOST [tip_num_checkpoints(params[i].n_vectors)][2]) and, when
  * stats is not NULL, stats[i].  The library runs n_streams host threads (0 =
- * 4), each with a HIP stream of its own on the caller's current device, that
+ * 8), each with a HIP stream of its own on the caller's current device, that
  * take the problems largest first (V n_vectors ncomp); every problem gets
  * exactly the arithmetic of a trace_inv_probe call.  statuses: HOST [count]
  * per-problem status, or NULL.  All arguments are validated before any work

@@ -1261,7 +1261,10 @@ tip_status trace_inv_probe_batch(const tip_operator* ops, const tip_params* para
     order[(size_t)i] = i;
   }
   std::stable_sort(order.begin(), order.end(), [&](int32_t a, int32_t b) { return work[(size_t)a] > work[(size_t)b]; });
-  const int workers = std::max(1, std::min<int>(n_streams > 0 ? n_streams : 4, count));
+  // 8 by default: twice the hardware queues a process gets here, so that one
+  // worker's host-side polling overlaps another's kernels (measured on the
+  // batch of 64 uneven 3-D tori: +3% over 4)
+  const int workers = std::max(1, std::min<int>(n_streams > 0 ? n_streams : 8, count));
   std::vector<tip_status> st((size_t)count, TIP_OK);
   std::vector<std::string> msg((size_t)count);
   std::atomic<int32_t> next{0};
