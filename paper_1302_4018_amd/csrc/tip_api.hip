@@ -610,7 +610,7 @@ struct Solver {
     nvec = pl.eo ? nelem / 2 : nelem;             // elements the CG vector passes touch
     gx_m = (int)(pl.eo ? pl.me.grid : (pl.use_march ? pl.mm.grid : pl.tm.grid));
     gx_u = (int)update_grid(nvec);
-    gx_t = (int)pl.tm.grid;
+    gx_t = (int)ru_grid(pl.tm);
     pstride = (size_t)B * std::max(gx_m, std::max(gx_u, gx_t));
     nscal = (size_t)B;
     // FP64: x, r, p, w; mixed: x (FP64) + xh, r, p, w (FP32); even-odd: x on the

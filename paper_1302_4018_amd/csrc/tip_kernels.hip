@@ -701,9 +701,12 @@ __global__ __launch_bounds__(kBlock) void k_true_residual(Geom g, TileMap tm, Op
   __shared__ double lds[3 * 4 * 64];
   const int B = 1 << tm.logB;
   const int j = threadIdx.x & (B - 1);
-  const uint32_t s = tile_first_site(blockIdx.x, tm) + (threadIdx.x >> tm.logB);
   double acc[3] = {0.0, 0.0, 0.0};
-  if (s < g.V && state[j] == kFrozen) {
+  // grid-stride over the tiles: one partial per workgroup, so the reduction
+  // that follows reads gridDim.x values per rhs, not one per tile
+  for (uint32_t tile = blockIdx.x; tile < tm.grid && state[j] == kFrozen; tile += gridDim.x) {
+    const uint32_t s = tile_first_site(tile, tm) + (threadIdx.x >> tm.logB);
+    if (s >= g.V) continue;
     T xs[NC], ax[NC], b[NC], rt[NC];
     stencil_site(op, g, tm.logB, s, j, mass_field, mass, w, x, xs, ax);
     rhs_at<T, NC>(g, s, rhs0, j, nb, seed, mask, b);
@@ -1545,7 +1548,7 @@ hipError_t launch_true_residual(const OpDev& od, const Geom& g, const TileMap& t
   return dispatch64(od, elem, [&](auto op) {
     using Op = decltype(op);
     using T = typename Op::T;
-    k_true_residual<Op><<<tm.grid, kBlock, 0, st>>>(g, tm, op, od.mass_field, od.mass, od.coupling, state, rhs0, nb,
+    k_true_residual<Op><<<ru_grid(tm), kBlock, 0, st>>>(g, tm, op, od.mass_field, od.mass, od.coupling, state, rhs0, nb,
                                                     seed, mask, (const T*)x, (T*)r, (T*)p, partial, pstride, eo);
   });
 }
