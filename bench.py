@@ -247,6 +247,127 @@ def bench_compare(args):
     print(json.dumps(out), flush=True)
 
 
+def free_spectrum(dims, m):
+    """Eigenvalues m + sum_mu 4 sin^2(pi k_mu / n_mu) of the free shifted
+    Laplacian (its Fourier modes diagonalise it), one per site."""
+    import numpy as np
+    grids = np.meshgrid(*[np.arange(n) for n in dims], indexing="ij")
+    return (m + sum(4.0 * np.sin(np.pi * k / n) ** 2 for k, n in zip(grids, dims))).ravel()
+
+
+def bench_study(args):
+    """The experiments of Sec. 5 on the GPU path, every solve a FP64 CG to 1e-10.
+
+    A (Sec. 5.1): 64^3 free torus at condition number 100, no mask; the
+      hierarchy stopped after 1..5 bit-levels against the full one (6 levels).
+    B (Sec. 5.2): the three lattices 64^3, 32^4 and 64 x 128^2 at condition
+      numbers 1e2, 1e4 and 1e6; hierarchical, Fourier-grouped, natural-order
+      Hadamard and random Z2 probes, RMS over Z2 masks of the relative error.
+    C (Sec. 5.2, variance over 100 masks): 16^4 at condition number 100; the
+      sample variance over masks of the hierarchical T_s against the exact
+      variance of plain Z2 Monte Carlo with s vectors, 2 (sum 1/lam^2 -
+      (sum 1/lam)^2 / V) / s, and their ratio (the variance reduction at equal
+      work).
+    The free tori have Tr(A^-1) = sum_k 1/lam(k) in closed form."""
+    import numpy as np
+    import torch
+
+    from paper_1302_4018_amd import binding as tip
+
+    def exact(dims, m):
+        lam = free_spectrum(dims, m)
+        return float(np.sum(1.0 / lam)), float(np.sum(lam ** -2.0))
+
+    def mass_for(dims, kappa):                 # lam_max = m + 4 d, lam_min = m
+        return 4.0 * len(dims) / (kappa - 1.0)
+
+    out = {"metric": "relative error of T_s against the exact Tr(A^-1) (Sec. 5 study)", "n_gpus": 1,
+           "higher_is_better": False, "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+           "unit": "relative error", "steps": 1, "warmup": 0}
+    solves = 0
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    parts = set(args.study.split(","))
+
+    if "A" in parts:
+        dims, kappa, n = [64, 64, 64], 100.0, 4096
+        m = mass_for(dims, kappa)
+        tr, _ = exact(dims, m)
+        table = {}
+        with tip.OpHandle(tip.Operator(dims, tip.KIND_SCALAR, mass=m)) as h:
+            for lev in (1, 2, 3, 4, 5, 6):
+                est, _, st = h.trace_inv_probe(n, args.tol, 1, mask=tip.MASK_NONE, probe=tip.PROBE_STOPPED,
+                                               stop_levels=lev)
+                solves += st["solves"]
+                table[f"levels={lev}"] = [float(f"{v:.3e}") for v in np.abs(est.real - tr) / tr]
+                log(f"[study A] stopped at {lev} levels: {table[f'levels={lev}']}")
+        out["A_stopped_levels"] = {"lattice": dims, "kappa": kappa, "mass": m, "mask": "none", "exact_trace": tr,
+                                   "s": [2 ** i for i in range(13)], "rel_error": table}
+
+    if "B" in parts:
+        kinds = {"hierarchical": tip.PROBE_HIERARCHICAL, "fourier_grouped": tip.PROBE_FOURIER,
+                 "natural": tip.PROBE_NATURAL, "random_z2": tip.PROBE_RANDOM}
+        res = {}
+        for dims, kappa, n in (([64, 64, 64], 1e2, 4096), ([32, 32, 32, 32], 1e4, 1024),
+                               ([64, 128, 128], 1e6, 256)):
+            m = mass_for(dims, kappa)
+            tr, _ = exact(dims, m)
+            name = "x".join(map(str, dims))
+            # FP64 CG reaches a true relative residual of about eps * kappa, so at
+            # kappa = 1e6 the solves stop at 1e-8; the quadrature error is then
+            # <= kappa tol^2 = 1e-10, far below the estimator errors compared here
+            tol_b = max(args.tol, 1e-8) if kappa > 1e5 else args.tol
+            rows = {}
+            with tip.OpHandle(tip.Operator(dims, tip.KIND_SCALAR, mass=m)) as h:
+                for kname, probe in kinds.items():
+                    errs = []
+                    for seed in range(args.masks):
+                        est, _, st = h.trace_inv_probe(n, tol_b, 1000 + seed, mask=tip.MASK_Z2, probe=probe,
+                                                       max_iter=200000)
+                        solves += st["solves"]
+                        errs.append(np.abs(est.real - tr) / tr)
+                    rows[kname] = [float(f"{v:.3e}") for v in np.sqrt(np.mean(np.array(errs) ** 2, axis=0))]
+                    log(f"[study B] {name} kappa {kappa:g} {kname}: {rows[kname]}")
+            res[name] = {"kappa": kappa, "mass": m, "tol": tol_b, "exact_trace": tr,
+                         "s": [2 ** i for i in range(len(rows["natural"]))], "rms_rel_error": rows}
+        out["B_vs_monte_carlo"] = {"masks": args.masks, "lattices": res}
+
+    if "C" in parts:
+        dims, kappa, n, masks = [16, 16, 16, 16], 100.0, 1024, args.variance_masks
+        m = mass_for(dims, kappa)
+        tr, tr2 = exact(dims, m)
+        V = int(np.prod(dims))
+        var_q = 2.0 * (tr2 - tr * tr / V)                  # one Z2 quadrature: 2 sum_{x != y} G(x - y)^2
+        ests = []
+        with tip.OpHandle(tip.Operator(dims, tip.KIND_SCALAR, mass=m)) as h:
+            for seed in range(masks):
+                est, _, st = h.trace_inv_probe(n, args.tol, 5000 + seed, mask=tip.MASK_Z2)
+                solves += st["solves"]
+                ests.append(est.real)
+        ests = np.array(ests)
+        s = np.array([2 ** i for i in range(ests.shape[1])], dtype=float)
+        var_hp = np.var(ests, axis=0, ddof=1)
+        var_mc = var_q / s
+        out["C_variance"] = {"lattice": dims, "kappa": kappa, "mass": m, "masks": masks, "exact_trace": tr,
+                             "s": s.astype(int).tolist(),
+                             "mean_rel_error": [float(f"{v:.3e}") for v in np.abs(ests.mean(axis=0) - tr) / tr],
+                             "var_hierarchical": [float(f"{v:.4e}") for v in var_hp],
+                             "var_monte_carlo_exact": [float(f"{v:.4e}") for v in var_mc],
+                             "reduction": [float(f"{v:.4g}") for v in var_mc / np.maximum(var_hp, 1e-300)]}
+        log(f"[study C] variance reduction at s = 2^k: {out['C_variance']['reduction']}")
+
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    out["ms_per_step"] = round(el * 1e3, 1)
+    out["config"] = {"workload": "Sec. 5 study on free shifted Laplacians (parts " + ",".join(sorted(parts)) + ")",
+                     "solves": solves, "solves_per_s": round(solves / el, 1), "tol": args.tol}
+    first = out.get("C_variance", {}).get("reduction") or [None]
+    out["value"] = first[-1]
+    out["unit"] = "variance reduction over Z2 Monte Carlo at s=1024 (16^4, 100 masks)" if first[-1] else "see parts"
+    out["higher_is_better"] = True
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -266,11 +387,15 @@ def main():
                     help="write the stencil's measured HBM bytes per launch from two rocprofv3 --pmc "
                          "counter_collection.csv files, then exit (no GPU work)")
     ap.add_argument("--traffic-command", default="", help="command recorded with --traffic-from")
-    ap.add_argument("--workload", choices=["c5", "c4", "compare"], default="c5",
+    ap.add_argument("--workload", choices=["c5", "c4", "compare", "study"], default="c5",
                     help="c5: the 32^4 covariant probing run (default); c4: the batch of 64 uneven 3-D tori; "
                          "compare: hierarchical vs natural-order Hadamard vs Monte-Carlo probes on a 32^3 torus "
-                         "with a closed-form trace")
-    ap.add_argument("--masks", type=int, default=4, help="compare: masks averaged per probe kind")
+                         "with a closed-form trace; study: the experiments of Sec. 5 (stopped levels, three "
+                         "lattices and condition numbers, variance over 100 masks)")
+    ap.add_argument("--masks", type=int, default=4, help="compare / study B: masks averaged per probe kind")
+    ap.add_argument("--study", default="A,B,C", help="study: parts to run (A stopped levels, B lattices x "
+                    "condition numbers, C variance over masks)")
+    ap.add_argument("--variance-masks", type=int, default=100, help="study C: masks")
     args = ap.parse_args()
     if args.traffic_from:
         write_traffic(args.traffic_from[0], args.traffic_from[1], STENCIL[(True, "fp64")], args.traffic_command)
@@ -294,6 +419,9 @@ def main():
         return
     if args.workload == "compare":
         bench_compare(args)
+        return
+    if args.workload == "study":
+        bench_study(args)
         return
 
     if args.copy_calibration:

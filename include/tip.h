@@ -103,8 +103,20 @@ enum { TIP_PREC_FP64 = 0, TIP_PREC_MIXED = 1 };
  * b_{m,c}(y, c) = z0(y, c) H(y, m) (power-of-two sides); RANDOM, plain Monte
  * Carlo (Sec. 1, Hutchinson): b_{m,c}(y, c) = z0_m(y, c), the mask of sweep m
  * (SplitMix64 outputs (m V + y) ncomp + c), so every probe is an independent
- * Z2 / Z4 noise vector (a Z2 or Z4 mask is required). */
-enum { TIP_PROBE_HIERARCHICAL = 0, TIP_PROBE_NATURAL = 1, TIP_PROBE_RANDOM = 2 };
+ * Z2 / Z4 noise vector (a Z2 or Z4 mask is required).
+ * STOPPED (Sec. 5.1, power-of-two sides): the colouring recursion stopped
+ * after stop_levels bit-levels; each colour class keeps its natural order, so
+ * P_k(y) = [Alg. 5 string of levels 1..k | natural index of the coarse
+ * coordinates y_j >> min(k, k_j)] and b = z0 H(P_k(y), bitrev_L(m)).  k = 0 is
+ * the natural site order, k >= max k_j the full hierarchy.
+ * FOURIER (power-of-two sides, complex solves): eq. Hperm-general-recursive
+ * with the a active bits of one Alg. 5 level taken as one level of 2^a colours,
+ * z_m(y) = prod_l exp(2 pi i s_l(y) j_l / 2^{a_l}), m = sum_l j_l 2^{a_1 + .. + a_{l-1}},
+ * s_l the level's Red-Black index (Lemma 3.3); entries are 16th roots of unity
+ * made of the doubles nearest cos(pi/8), sin(pi/8) and sqrt(2)/2.  Equal to the
+ * hierarchical estimate at every level boundary s = 2^{a_1 + .. + a_k}. */
+enum { TIP_PROBE_HIERARCHICAL = 0, TIP_PROBE_NATURAL = 1, TIP_PROBE_RANDOM = 2, TIP_PROBE_STOPPED = 3,
+       TIP_PROBE_FOURIER = 4 };
 
 /* Operator description.  Arrays are DEVICE pointers, read only. */
 typedef struct {
@@ -142,6 +154,7 @@ typedef struct {
                             workgroup order (0 = library choice; see tip_autotune) */
   int32_t march_tc;      /* lattice slices one stencil workgroup marches (power of two;
                             0 = library choice)                                    */
+  int32_t stop_levels;   /* TIP_PROBE_STOPPED: bit-levels of the colouring kept (>= 0) */
 } tip_params;
 
 typedef struct {
@@ -263,11 +276,12 @@ tip_status tip_apply_operator(const tip_operator* op, int32_t nrhs,
 tip_status tip_hier_perm(int32_t ndim, const int64_t* dims, uint32_t* P_out, void* stream);
 
 /* Probing vectors b_{m,comp}(y, comp) = z0(y, comp) H(P(y), bitrev_L(m)) for
- * m = m0 .. m0+count-1 (or the probe kind given): DEVICE complex128 [count][V].
- * mask as in tip_params (DEFAULT resolves with ncomp: 1 -> Z2, 3 -> Z4). */
+ * m = m0 .. m0+count-1 (or the probe kind given, with stop_levels for
+ * TIP_PROBE_STOPPED): DEVICE complex128 [count][V].  mask as in tip_params
+ * (DEFAULT resolves with ncomp: 1 -> Z2, 3 -> Z4). */
 tip_status tip_probe_vectors(int32_t ndim, const int64_t* dims, int32_t ncomp, int32_t mask,
                              uint64_t seed, int64_t m0, int64_t count, int32_t comp,
-                             int32_t probe, double* out, void* stream);
+                             int32_t probe, int32_t stop_levels, double* out, void* stream);
 
 /* Turn per-launch hipEvent timing of the stencil kernel on (1) or off (0). */
 void tip_set_profiling(int32_t on);

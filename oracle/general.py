@@ -164,7 +164,7 @@ def rhs(dims, ncomp, m, c, seed, mask_kind, lv=None, PB=None, C=None):
     return b
 
 
-def trace_inv_probe(op, n_vectors, tol, seed, mask_kind, max_iter=None, probe=0):
+def trace_inv_probe(op, n_vectors, tol, seed, mask_kind, max_iter=None, probe=0, levels=0):
     """Estimates (1/s) sum_{m<s} q_m at the checkpoints, with these probes (or the
     comparison probe kind given); q_m = sum_c b_{m,c}^H x_{m,c} by the oracle's
     CG.  Returns (est, q, stats)."""
@@ -179,7 +179,7 @@ def trace_inv_probe(op, n_vectors, tol, seed, mask_kind, max_iter=None, probe=0)
     for m in range(n_vectors):
         qm = 0.0 + 0.0j
         for c in range(op.ncomp):
-            b = rhs_kind(op.dims, op.ncomp, m, c, seed, mask_kind, probe, lv, PB, C)
+            b = rhs_kind(op.dims, op.ncomp, m, c, seed, mask_kind, probe, lv, PB, C, levels)
             if op.kind == 0 and np.all(b.imag == 0):
                 b = b.real
             x, it, _ = cg_solve(op.apply, b, tol, max_iter)
@@ -202,15 +202,25 @@ def trace_inv_probe(op, n_vectors, tol, seed, mask_kind, max_iter=None, probe=0)
 # ---------------------------------------------------------------------------
 
 PROBE_HIERARCHICAL, PROBE_NATURAL, PROBE_RANDOM = 0, 1, 2
+# the variants of oracle/variants.py: the hierarchy stopped after `levels`
+# bit-levels (Sec. 5.1) and the Fourier-grouped columns; power-of-two sides,
+# one mask for all probes
+PROBE_STOPPED, PROBE_FOURIER = 3, 4
 
 
-def rhs_kind(dims, ncomp, m, c, seed, mask_kind, probe, lv=None, PB=None, C=None):
+def rhs_kind(dims, ncomp, m, c, seed, mask_kind, probe, lv=None, PB=None, C=None, levels=0):
     """b_{m,c} for the given probe kind: complex128 [V, ncomp]."""
     V = volume(dims)
     if probe == PROBE_HIERARCHICAL:
         return rhs(dims, ncomp, m, c, seed, mask_kind, lv, PB, C)
     b = np.zeros((V, ncomp), dtype=np.complex128)
-    if probe == PROBE_NATURAL:
+    if probe in (PROBE_STOPPED, PROBE_FOURIER):
+        from . import variants
+        if not 0 <= int(m) < V:
+            raise ValueError(f"probe {m} outside [0, V)")
+        z = variants.stopped_probe(dims, m, levels) if probe == PROBE_STOPPED else variants.fourier_probe(dims, m)
+        b[:, c] = mask_sweep(seed, V, ncomp, c, mask_kind, 0) * z
+    elif probe == PROBE_NATURAL:
         if V & (V - 1):
             raise ValueError("natural-order Hadamard probes need a power-of-two volume")
         z = (1 - 2 * _parity(np.arange(V, dtype=np.uint64) & np.uint64(m))).astype(np.complex128)
@@ -224,14 +234,14 @@ def rhs_kind(dims, ncomp, m, c, seed, mask_kind, probe, lv=None, PB=None, C=None
     return b
 
 
-def estimates_dense(Ainv, dims, ncomp, n, seed, mask_kind, probe):
+def estimates_dense(Ainv, dims, ncomp, n, seed, mask_kind, probe, levels=0):
     """T_s at the checkpoints from exact quadratures b^H A^-1 b (dense A^-1, tiny lattices)."""
     from .estimator import estimates_from_quadratures
     lv = Levels(dims)
     PB, C = binary_colour(dims, lv), last_level_colour(dims, lv)
     q = np.zeros(n, dtype=np.complex128)
     for c in range(ncomp):
-        Z = np.stack([rhs_kind(dims, ncomp, m, c, seed, mask_kind, probe, lv, PB, C).reshape(-1)
+        Z = np.stack([rhs_kind(dims, ncomp, m, c, seed, mask_kind, probe, lv, PB, C, levels).reshape(-1)
                       for m in range(n)], axis=1)
         q += np.sum(np.conj(Z) * (Ainv @ Z), axis=0)       # b_m^H A^-1 b_m for every m at once
     return estimates_from_quadratures(q)

@@ -21,7 +21,7 @@ STATUS_NAMES = {0: "TIP_OK", -1: "TIP_EINVAL", -2: "TIP_ENOMEM", -3: "TIP_ENOCON
 KIND_SCALAR, KIND_COVARIANT = 0, 1
 MASK_DEFAULT, MASK_NONE, MASK_Z2, MASK_Z4 = -1, 0, 1, 2
 PREC_FP64, PREC_MIXED = 0, 1
-PROBE_HIERARCHICAL, PROBE_NATURAL, PROBE_RANDOM = 0, 1, 2
+PROBE_HIERARCHICAL, PROBE_NATURAL, PROBE_RANDOM, PROBE_STOPPED, PROBE_FOURIER = 0, 1, 2, 3, 4
 
 
 class tip_operator(ctypes.Structure):
@@ -35,7 +35,8 @@ class tip_params(ctypes.Structure):
                 ("max_iter", ctypes.c_int32), ("seed", ctypes.c_uint64), ("mask", ctypes.c_int32),
                 ("rhs_block", ctypes.c_int32), ("precision", ctypes.c_int32), ("stream", ctypes.c_void_p),
                 ("quadratures", ctypes.POINTER(ctypes.c_double)), ("reliable_delta", ctypes.c_double),
-                ("probe", ctypes.c_int32), ("round_tiles", ctypes.c_int32), ("march_tc", ctypes.c_int32)]
+                ("probe", ctypes.c_int32), ("round_tiles", ctypes.c_int32), ("march_tc", ctypes.c_int32),
+                ("stop_levels", ctypes.c_int32)]
 
 
 class tip_tuning(ctypes.Structure):
@@ -78,7 +79,7 @@ def _load():
         "tip_hier_perm": (ctypes.c_int, [ctypes.c_int32, P(ctypes.c_int64), ctypes.c_void_p, ctypes.c_void_p]),
         "tip_probe_vectors": (ctypes.c_int, [ctypes.c_int32, P(ctypes.c_int64), ctypes.c_int32, ctypes.c_int32,
                                              ctypes.c_uint64, ctypes.c_int64, ctypes.c_int64, ctypes.c_int32,
-                                             ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p]),
+                                             ctypes.c_int32, ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p]),
         "tip_set_profiling": (None, [ctypes.c_int32]),
         "tip_last_error": (ctypes.c_char_p, []),
     }
@@ -164,7 +165,7 @@ class Operator:
 
 
 def _params(n_vectors, tol, seed, mask, max_iter, rhs_block, m_begin, quadratures, stream, precision=PREC_FP64,
-            reliable_delta=0.0, probe=PROBE_HIERARCHICAL, round_tiles=0, march_tc=0):
+            reliable_delta=0.0, probe=PROBE_HIERARCHICAL, round_tiles=0, march_tc=0, stop_levels=0):
     p = tip_params()
     p.n_vectors = int(n_vectors)
     p.m_begin = int(m_begin)
@@ -181,6 +182,7 @@ def _params(n_vectors, tol, seed, mask, max_iter, rhs_block, m_begin, quadrature
     p.probe = int(probe)
     p.round_tiles = int(round_tiles)
     p.march_tc = int(march_tc)
+    p.stop_levels = int(stop_levels)
     return p
 
 
@@ -193,14 +195,15 @@ def tip_num_checkpoints(n_vectors):
 
 
 def _run(fn, first, n_vectors, tol, seed, mask, max_iter, rhs_block, m_begin, quadratures, stream, raise_on_error,
-         precision=PREC_FP64, reliable_delta=0.0, probe=PROBE_HIERARCHICAL, round_tiles=0, march_tc=0):
+         precision=PREC_FP64, reliable_delta=0.0, probe=PROBE_HIERARCHICAL, round_tiles=0, march_tc=0,
+         stop_levels=0):
     nck = tip_num_checkpoints(n_vectors)
     est = np.zeros((nck, 2), dtype=np.float64)
     q = np.zeros((int(n_vectors), 2), dtype=np.float64)
     if quadratures is not None:
         q[:m_begin] = np.asarray(quadratures, dtype=np.complex128)[:m_begin].view(np.float64).reshape(-1, 2)
     p = _params(n_vectors, tol, seed, mask, max_iter, rhs_block, m_begin, q, stream, precision, reliable_delta, probe,
-                round_tiles, march_tc)
+                round_tiles, march_tc, stop_levels)
     st = tip_stats()
     status = fn(first, ctypes.byref(p), est.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), ctypes.byref(st))
     stats = _stats_dict(st)
@@ -214,16 +217,16 @@ def _run(fn, first, n_vectors, tol, seed, mask, max_iter, rhs_block, m_begin, qu
 
 def trace_inv_probe(op, n_vectors, tol, seed, mask=MASK_DEFAULT, max_iter=0, rhs_block=0, m_begin=0,
                     quadratures=None, stream=None, raise_on_error=True, precision=PREC_FP64, reliable_delta=0.0,
-                    probe=PROBE_HIERARCHICAL):
+                    probe=PROBE_HIERARCHICAL, stop_levels=0):
     """Estimates at s = 2^k (complex numpy), quadratures q_m (complex numpy), stats dict."""
     s = op.c_struct()
     return _run(lib.trace_inv_probe, ctypes.byref(s), n_vectors, tol, seed, mask, max_iter, rhs_block, m_begin,
-                quadratures, stream, raise_on_error, precision, reliable_delta, probe)
+                quadratures, stream, raise_on_error, precision, reliable_delta, probe, stop_levels=stop_levels)
 
 
 def trace_inv_probe_batch(ops, n_vectors, tol, seed, mask=MASK_DEFAULT, max_iter=0, rhs_block=0,
                           precision=PREC_FP64, reliable_delta=0.0, n_streams=0, raise_on_error=True,
-                          probe=PROBE_HIERARCHICAL):
+                          probe=PROBE_HIERARCHICAL, stop_levels=0):
     """Independent problems in one call: ops and n_vectors are sequences of
     equal length.  Returns a list of (estimates complex numpy, stats dict)."""
     count = len(ops)
@@ -235,7 +238,8 @@ def trace_inv_probe_batch(ops, n_vectors, tol, seed, mask=MASK_DEFAULT, max_iter
     for i, n in enumerate(n_vectors):
         q = np.zeros((int(n), 2))
         qs.append(q)
-        params[i] = _params(n, tol, seed, mask, max_iter, rhs_block, 0, q, None, precision, reliable_delta, probe)
+        params[i] = _params(n, tol, seed, mask, max_iter, rhs_block, 0, q, None, precision, reliable_delta, probe,
+                            stop_levels=stop_levels)
         ests.append(np.zeros((tip_num_checkpoints(n), 2)))
     est_ptrs = (ctypes.POINTER(ctypes.c_double) * count)(*[e.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
                                                           for e in ests])
@@ -263,9 +267,10 @@ class OpHandle:
 
     def trace_inv_probe(self, n_vectors, tol, seed, mask=MASK_DEFAULT, max_iter=0, rhs_block=0, m_begin=0,
                         quadratures=None, stream=None, raise_on_error=True, precision=PREC_FP64, reliable_delta=0.0,
-                        probe=PROBE_HIERARCHICAL, round_tiles=0, march_tc=0):
+                        probe=PROBE_HIERARCHICAL, round_tiles=0, march_tc=0, stop_levels=0):
         return _run(lib.trace_inv_probe_op, self._h, n_vectors, tol, seed, mask, max_iter, rhs_block, m_begin,
-                    quadratures, stream, raise_on_error, precision, reliable_delta, probe, round_tiles, march_tc)
+                    quadratures, stream, raise_on_error, precision, reliable_delta, probe, round_tiles, march_tc,
+                    stop_levels)
 
     def autotune(self, tol, seed, sample_vectors=64, mask=MASK_DEFAULT, precision=PREC_FP64, probe=PROBE_HIERARCHICAL,
                  rhs_block=0, round_tiles=0, stream=None):
@@ -281,7 +286,7 @@ class OpHandle:
 
     def trace_inv_probe_grad(self, n_vectors, tol, seed, mask=MASK_DEFAULT, max_iter=0, rhs_block=0, stream=None,
                              precision=PREC_FP64, reliable_delta=0.0, mass=True, coupling=True,
-                             probe=PROBE_HIERARCHICAL):
+                             probe=PROBE_HIERARCHICAL, stop_levels=0):
         """Estimates, quadratures, dT/dm [V] and dT/dw [ndim, V] of the last estimate
         (float64 tensors on the GPU, or None where not asked for), stats."""
         import torch
@@ -291,7 +296,8 @@ class OpHandle:
         nck = tip_num_checkpoints(n_vectors)
         est = np.zeros((nck, 2), dtype=np.float64)
         q = np.zeros((int(n_vectors), 2), dtype=np.float64)
-        p = _params(n_vectors, tol, seed, mask, max_iter, rhs_block, 0, q, stream, precision, reliable_delta, probe)
+        p = _params(n_vectors, tol, seed, mask, max_iter, rhs_block, 0, q, stream, precision, reliable_delta, probe,
+                    stop_levels=stop_levels)
         st = tip_stats()
         _check(lib.trace_inv_probe_grad(self._h, ctypes.byref(p), est.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
                                         _ptr(gm) if gm is not None else None,
@@ -300,15 +306,16 @@ class OpHandle:
         return est[:, 0] + 1j * est[:, 1], q[:, 0] + 1j * q[:, 1], gm, gw, _stats_dict(st)
 
     def solve_probe(self, m, comp, tol, seed, mask=MASK_DEFAULT, max_iter=0, stream=None, precision=PREC_FP64,
-                    reliable_delta=0.0, probe=PROBE_HIERARCHICAL):
+                    reliable_delta=0.0, probe=PROBE_HIERARCHICAL, stop_levels=0):
         """x = A^-1 b_{m,comp} (torch tensor on the GPU), q = b^H x, stats."""
         import torch
         op = self.op
-        complex_solve = op.kind == KIND_COVARIANT or mask == MASK_Z4
+        complex_solve = op.kind == KIND_COVARIANT or mask == MASK_Z4 or probe == PROBE_FOURIER
         shape = (op.V, op.ncomp, 2) if complex_solve else (op.V,)
         x = torch.empty(shape, dtype=torch.float64, device="cuda")
         q = np.zeros(2)
-        p = _params(1, tol, seed, mask, max_iter, 0, 0, np.zeros((1, 2)), stream, precision, reliable_delta, probe)
+        p = _params(1, tol, seed, mask, max_iter, 0, 0, np.zeros((1, 2)), stream, precision, reliable_delta, probe,
+                    stop_levels=stop_levels)
         st = tip_stats()
         _check(lib.tip_solve_probe(self._h, ctypes.byref(p), int(m), int(comp), _ptr(x),
                                    q.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), ctypes.byref(st)),
@@ -375,14 +382,15 @@ def tip_hier_perm(dims, stream=None):
     return out
 
 
-def tip_probe_vectors(dims, ncomp, mask, seed, m0, count, comp, stream=None, probe=PROBE_HIERARCHICAL):
+def tip_probe_vectors(dims, ncomp, mask, seed, m0, count, comp, stream=None, probe=PROBE_HIERARCHICAL, stop_levels=0):
     """b_{m,comp} restricted to component comp, m = m0..m0+count-1: complex128 [count, V]."""
     import torch
     V = int(np.prod(dims))
     out = torch.empty((int(count), V, 2), dtype=torch.float64, device="cuda")
     d = (ctypes.c_int64 * 4)(*[int(n) for n in dims])
     _check(lib.tip_probe_vectors(len(dims), d, int(ncomp), int(mask), int(seed) & ((1 << 64) - 1), int(m0),
-                                 int(count), int(comp), int(probe), _ptr(out), _stream(stream)), "tip_probe_vectors")
+                                 int(count), int(comp), int(probe), int(stop_levels), _ptr(out), _stream(stream)),
+           "tip_probe_vectors")
     return torch.view_as_complex(out)
 
 

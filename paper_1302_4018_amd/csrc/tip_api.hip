@@ -475,11 +475,13 @@ tip_status check_params(const tip_op_s* h, const tip_params* p, int* mask_out) {
   int mask = p->mask;
   if (mask == TIP_MASK_DEFAULT) mask = h->kind == TIP_KIND_COVARIANT ? TIP_MASK_Z4 : TIP_MASK_Z2;
   if (mask < TIP_MASK_NONE || mask > TIP_MASK_Z4) return fail(TIP_EINVAL, "unknown mask %d", p->mask);
-  if (p->probe < TIP_PROBE_HIERARCHICAL || p->probe > TIP_PROBE_RANDOM)
+  if (p->probe < TIP_PROBE_HIERARCHICAL || p->probe > TIP_PROBE_FOURIER)
     return fail(TIP_EINVAL, "unknown probe kind %d", p->probe);
   if (p->round_tiles < 0 || p->march_tc < 0) return fail(TIP_EINVAL, "round_tiles and march_tc must be >= 0");
-  if (p->probe == TIP_PROBE_NATURAL && !h->geom.pow2)
-    return fail(TIP_EINVAL, "natural-order Hadamard probes need power-of-two sides");
+  if ((p->probe == TIP_PROBE_NATURAL || p->probe == TIP_PROBE_STOPPED || p->probe == TIP_PROBE_FOURIER) &&
+      !h->geom.pow2)
+    return fail(TIP_EINVAL, "probe kind %d needs power-of-two sides", p->probe);
+  if (p->stop_levels < 0) return fail(TIP_EINVAL, "stop_levels must be >= 0");
   if (p->probe == TIP_PROBE_RANDOM && mask == TIP_MASK_NONE)
     return fail(TIP_EINVAL, "random probes need a Z2 or Z4 mask");
   *mask_out = mask;
@@ -541,6 +543,7 @@ struct Solver {
     p = params;
     geom = h->geom;
     geom.probe = p->probe;
+    geom.stop = p->stop_levels;
     st = (hipStream_t)p->stream;
     if (!st && !env_off("TIP_GRAPH")) {
       if (!h->own_stream) {
@@ -562,7 +565,8 @@ struct Solver {
     // complex solves: covariant operator, Z4 mask, or a probe past the binary
     // columns (F_3 columns of the three-colouring level are complex)
     const bool f3 = g.has3 && p->n_vectors > (int64_t(1) << g.LB);
-    pl.elem = (h->kind == TIP_KIND_COVARIANT || mask == TIP_MASK_Z4 || f3) ? Elem::kComplex : Elem::kReal;
+    const bool fourier = p->probe == TIP_PROBE_FOURIER;          // roots of unity w16^e
+    pl.elem = (h->kind == TIP_KIND_COVARIANT || mask == TIP_MASK_Z4 || f3 || fourier) ? Elem::kComplex : Elem::kReal;
     const size_t esz64 = pl.elem == Elem::kReal ? sizeof(double) : sizeof(double2);
     pl.esz = mixed ? esz64 / 2 : esz64;
     // block size: a power of two <= 64; 32 shares each link among 32 solves;
@@ -1347,18 +1351,21 @@ tip_status tip_hier_perm(int32_t ndim, const int64_t* dims, uint32_t* P_out, voi
 }
 
 tip_status tip_probe_vectors(int32_t ndim, const int64_t* dims, int32_t ncomp, int32_t mask, uint64_t seed,
-                             int64_t m0, int64_t count, int32_t comp, int32_t probe, double* out, void* stream) {
+                             int64_t m0, int64_t count, int32_t comp, int32_t probe, int32_t stop_levels,
+                             double* out, void* stream) {
   if (ncomp != 1 && ncomp != 3) return fail(TIP_EINVAL, "ncomp = %d, expected 1 or 3", ncomp);
   Geom g;
   tip_status s = make_geom(ndim, dims, ncomp, &g);
   if (s != TIP_OK) return s;
   if (mask == TIP_MASK_DEFAULT) mask = ncomp == 1 ? TIP_MASK_Z2 : TIP_MASK_Z4;
   if (mask < TIP_MASK_NONE || mask > TIP_MASK_Z4) return fail(TIP_EINVAL, "unknown mask %d", mask);
-  if (probe < TIP_PROBE_HIERARCHICAL || probe > TIP_PROBE_RANDOM) return fail(TIP_EINVAL, "unknown probe kind %d", probe);
-  if (probe == TIP_PROBE_NATURAL && !g.pow2)
-    return fail(TIP_EINVAL, "natural-order Hadamard probes need power-of-two sides");
+  if (probe < TIP_PROBE_HIERARCHICAL || probe > TIP_PROBE_FOURIER) return fail(TIP_EINVAL, "unknown probe kind %d", probe);
+  if ((probe == TIP_PROBE_NATURAL || probe == TIP_PROBE_STOPPED || probe == TIP_PROBE_FOURIER) && !g.pow2)
+    return fail(TIP_EINVAL, "probe kind %d needs power-of-two sides", probe);
   if (probe == TIP_PROBE_RANDOM && mask == TIP_MASK_NONE) return fail(TIP_EINVAL, "random probes need a Z2 or Z4 mask");
+  if (stop_levels < 0) return fail(TIP_EINVAL, "stop_levels must be >= 0");
   g.probe = probe;
+  g.stop = stop_levels;
   if (comp < 0 || comp >= ncomp) return fail(TIP_EINVAL, "comp = %d out of range", comp);
   if (m0 < 0 || count < 0 || m0 + count > (int64_t)g.V) return fail(TIP_EINVAL, "probe range outside [0, V)");
   if (!out && count > 0) return fail(TIP_EINVAL, "out is NULL");

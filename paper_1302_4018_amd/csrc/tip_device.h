@@ -36,7 +36,8 @@ struct Geom {
   int32_t has3;              // a three-colouring level follows the binary ones
   uint32_t sub[kMaxDim];     // sides n_j >> B of the sub-torus it colours
   uint32_t gamma;            // colours of one sweep: 2^LB, times 3 with that level
-  int32_t probe;             // probe kind of the call: 0 hierarchical, 1 natural-order Hadamard, 2 random
+  int32_t probe;             // probe kind of the call (ProbeKind)
+  int32_t stop;              // stopped hierarchy: bit-levels of the colouring kept
 };
 
 constexpr int kLdsPerCu = 160 * 1024;   // gfx950 LDS per CU
@@ -156,8 +157,94 @@ __device__ __forceinline__ ProbeCol probe_column(uint64_t m, const Geom& g) {
 
 // Probe kinds (the comparison probes of Sec. 5 run through the same path):
 // hierarchical (above); natural-order Hadamard, z_m(x) = H(s(x), m) on the
-// natural site numbering; random, z_m = the mask of sweep m alone.
-enum ProbeKind { kProbeHierarchical = 0, kProbeNatural = 1, kProbeRandom = 2 };
+// natural site numbering; random, z_m = the mask of sweep m alone; the
+// hierarchy stopped after g.stop levels; Fourier-grouped columns.  The last
+// two take power-of-two sides.
+enum ProbeKind { kProbeHierarchical = 0, kProbeNatural = 1, kProbeRandom = 2, kProbeStopped = 3, kProbeFourier = 4 };
+
+// Red-Black index of Alg. 5 level m (0-based) of a site with coordinates x
+// on power-of-two sides, and the number a of dimensions active at it.
+__device__ __forceinline__ uint32_t level_rb(const uint32_t (&x)[kMaxDim], const Geom& g, int m, int& a) {
+  uint32_t idx = 0;
+  a = 0;
+#pragma unroll
+  for (int mu = 0; mu < kMaxDim; ++mu) {
+    if (mu < g.ndim && m < g.logn[mu]) {
+      idx = (idx << 1) | ((x[mu] >> m) & 1u);
+      ++a;
+    }
+  }
+  return (idx >> 1) | ((uint32_t)(__popc(idx) & 1) << (a - 1));
+}
+
+// Stopped hierarchy (Sec. 5.1): the recursion of Sec. 3 run for g.stop
+// levels leaves the members of each colour class in natural order.  On
+// power-of-two sides a class after k levels fixes the low k bits of every
+// coordinate and its members differ in y_j = x_j >> min(k, k_j), so the
+// location is the Alg. 5 string of levels 0..k-1 (t bits) followed by the
+// natural index of y on the sub-torus of sides n_j >> min(k, k_j).
+__device__ __forceinline__ uint32_t stopped_perm(uint32_t s, const Geom& g) {
+  uint32_t x[kMaxDim];
+#pragma unroll
+  for (int mu = 0; mu < kMaxDim; ++mu) x[mu] = mu < g.ndim ? coord_p2(s, g, mu) : 0u;
+  const int kmax = g.stop < g.nlevels ? g.stop : g.nlevels;
+  uint32_t loc = 0;
+  int t = 0;
+  for (int m = 0; m < kmax; ++m) {
+    int a;
+    const uint32_t rb = level_rb(x, g, m, a);
+    loc = (loc << a) | rb;
+    t += a;
+  }
+  uint32_t nat = 0;
+  int sh = 0;
+#pragma unroll
+  for (int mu = 0; mu < kMaxDim; ++mu) {
+    if (mu >= g.ndim) break;
+    const int cut = kmax < g.logn[mu] ? kmax : g.logn[mu];
+    nat |= (x[mu] >> cut) << sh;
+    sh += g.logn[mu] - cut;
+  }
+  return t == 0 ? nat : ((loc << (g.L - t)) | nat);
+}
+
+// w16^e = exp(2 pi i e / 16) from the doubles nearest cos(pi/8), sin(pi/8)
+// and sqrt(2)/2, rotated by i^(e >> 2).
+__device__ __forceinline__ double2 omega16(uint32_t e) {
+  const double c = 0.9238795325112867, sn = 0.3826834323650898, h = 0.7071067811865476;
+  double2 v;
+  switch (e & 3u) {
+    case 0: v = make_double2(1.0, 0.0); break;
+    case 1: v = make_double2(c, sn); break;
+    case 2: v = make_double2(h, h); break;
+    default: v = make_double2(sn, c); break;
+  }
+  for (uint32_t q = (e >> 2) & 3u; q > 0; --q) v = make_double2(-v.y, v.x);
+  return v;
+}
+
+// Fourier-grouped columns: eq. Hperm-general-recursive with the a bits of one
+// Alg. 5 level taken as one level of c = 2^a colours, so probe
+// m = sum_l j_l prod_{l' < l} c_{l'} is prod_l F_c(s_l(x), j_l) with s_l the
+// level's Red-Black index and F_n(i, j) = exp(2 pi i i j / n) (eq.
+// FourierElements).  With c <= 16 the entry is w16^e,
+// e = sum_l (s_l j_l mod c_l) 16 / c_l.
+__device__ __forceinline__ uint32_t fourier_exponent(uint32_t s, uint64_t m, const Geom& g) {
+  uint32_t x[kMaxDim];
+#pragma unroll
+  for (int mu = 0; mu < kMaxDim; ++mu) x[mu] = mu < g.ndim ? coord_p2(s, g, mu) : 0u;
+  uint32_t e = 0;
+  uint64_t rest = m;
+  for (int l = 0; l < g.nlevels; ++l) {
+    int a;
+    const uint32_t sl = level_rb(x, g, l, a);
+    const uint32_t c = 1u << a;
+    const uint32_t j = (uint32_t)(rest & (c - 1u));
+    rest >>= a;
+    e += ((sl * j) & (c - 1u)) << (4 - a);
+  }
+  return e & 15u;
+}
 
 // Entry (s, comp) of the probing right-hand side b_{m,comp} = z0_r .* z_m:
 // (re, im), each exactly 0 or +-1 except the F_3 factor w^k, whose parts are
@@ -206,6 +293,20 @@ __device__ __forceinline__ double2 probe_entry(uint32_t s, uint64_t m, int comp,
     pc.j3 = 0u;
     pc.r = (uint32_t)m;
     return probe_value(s, 0u, pc, comp, g, seed, mask);
+  }
+  if (g.probe == kProbeStopped) {
+    pc.col = hadamard_column((uint32_t)m, g.L);
+    pc.j3 = 0u;
+    pc.r = 0u;
+    return probe_value(s, stopped_perm(s, g), pc, comp, g, seed, mask);
+  }
+  if (g.probe == kProbeFourier) {
+    pc.col = 0u;
+    pc.j3 = 0u;
+    pc.r = 0u;
+    const double2 z0 = probe_value(s, 0u, pc, comp, g, seed, mask);   // the mask entry
+    const double2 w = omega16(fourier_exponent(s, m, g));
+    return make_double2(z0.x * w.x - z0.y * w.y, z0.x * w.y + z0.y * w.x);
   }
   return probe_value(s, hier_perm(s, g), probe_column(m, g), comp, g, seed, mask);
 }

@@ -46,6 +46,7 @@ int main(void) {
   P(tip_operator, dims) P(tip_operator, kind) P(tip_operator, mass) P(tip_operator, links)
   P(tip_params, tol) P(tip_params, seed) P(tip_params, mask) P(tip_params, stream) P(tip_params, quadratures)
   P(tip_params, reliable_delta) P(tip_params, probe) P(tip_params, round_tiles) P(tip_params, march_tc)
+  P(tip_params, stop_levels)
   P(tip_stats, max_true_relres) P(tip_stats, stencil_launches) P(tip_stats, stencil_bytes)
   P(tip_stats, reliable_updates) P(tip_stats, max_quad_err_bound) P(tip_stats, matvecs)
   P(tip_stats, matvec_seconds) P(tip_stats, matvec_bytes) P(tip_stats, even_odd)
@@ -99,8 +100,15 @@ def test_validation_rejects_bad_arguments_without_device_work():
     assert call(op, n=17) == b.TIP_EINVAL
     d = (ctypes.c_int64 * 4)(1 << 16, 1 << 16, 1, 1)
     assert lib.tip_hier_perm(2, d, None, None) == b.TIP_EINVAL       # V > 2^31 is fine at 2^32? no: rejected
-    assert lib.tip_probe_vectors(2, (ctypes.c_int64 * 4)(4, 4, 0, 0), 2, -1, 1, 0, 1, 0, 0, None, None) == b.TIP_EINVAL
-    assert lib.tip_probe_vectors(2, (ctypes.c_int64 * 4)(4, 4, 0, 0), 1, 0, 1, 0, 1, 0, 2, None, None) == b.TIP_EINVAL
+    d44 = (ctypes.c_int64 * 4)(4, 4, 0, 0)
+    assert lib.tip_probe_vectors(2, d44, 2, -1, 1, 0, 1, 0, 0, 0, None, None) == b.TIP_EINVAL
+    assert lib.tip_probe_vectors(2, d44, 1, 0, 1, 0, 1, 0, 2, 0, None, None) == b.TIP_EINVAL
     assert "Z2 or Z4" in b.tip_last_error()
-    assert lib.tip_probe_vectors(2, (ctypes.c_int64 * 4)(6, 4, 0, 0), 1, 1, 1, 0, 1, 0, 1, None, None) == b.TIP_EINVAL
-    assert "power-of-two" in b.tip_last_error()
+    for kind in (b.PROBE_NATURAL, b.PROBE_STOPPED, b.PROBE_FOURIER):
+        assert lib.tip_probe_vectors(2, (ctypes.c_int64 * 4)(6, 4, 0, 0), 1, 1, 1, 0, 1, 0, kind, 0, None,
+                                     None) == b.TIP_EINVAL
+        assert "power-of-two" in b.tip_last_error()
+    assert lib.tip_probe_vectors(2, d44, 1, 1, 1, 0, 1, 0, b.PROBE_STOPPED, -1, None, None) == b.TIP_EINVAL
+    assert "stop_levels" in b.tip_last_error()
+    assert lib.tip_probe_vectors(2, d44, 1, 1, 1, 0, 1, 0, 5, 0, None, None) == b.TIP_EINVAL
+    assert "probe kind" in b.tip_last_error()
