@@ -175,6 +175,8 @@ typedef struct {
   double matvec_seconds;       /* their summed device time (hipEvents), 0 if profiling off */
   double matvec_bytes;         /* their algorithmic HBM bytes                              */
   int32_t even_odd;            /* 1 when CG ran on the even-odd reduced system (see below) */
+  int64_t restarts;            /* restarts of CG from x after a failed FP64 true-residual
+                                  check (the recursive residual had drifted)               */
 } tip_stats;
 
 /* Number of estimates written by trace_inv_probe: floor(log2 n) + 1, plus one

@@ -500,9 +500,11 @@ struct Solver {
   hipStream_t st;
   Plan pl;
   bool mixed = false;
+  bool need_x = false;          // even-odd: assemble x on the full lattice (gradient, solve_probe)
   Prec prec = Prec::kF64;
   int max_iter, max_restarts = 8;
   double tol2, delta2 = 0.0;
+  double freeze2;               // recursive-residual freeze threshold (tol2 unless TIP_FREEZE_SLACK)
   size_t vbytes, vbytes64, pstride, nscal, nelem, nvec;
   int gx_m, gx_u, gx_t;       // partials per rhs written by matvec, update, true residual
   void *X, *Rv, *Pv, *W, *XH; // FP64 path: X, Rv, Pv, W; mixed: X (FP64) + XH, Rv, Pv, W (FP32)
@@ -512,7 +514,7 @@ struct Solver {
   CgScalars sc;
   int* ran_dev;
   double *h_q, *h_relres2;
-  int *h_state, *h_iters, *h_active, *h_ran;
+  int *h_state, *h_iters, *h_restarts, *h_active, *h_ran;
   OpDev od, od64;
   double mv_bytes;              // dominant stencil kernel, per launch
   double hop_bytes = 0.0;       // even-odd: the other half-lattice kernel, per launch
@@ -520,6 +522,7 @@ struct Solver {
   double matvec_seconds = 0.0, matvec_bytes = 0.0;
   int predicted = 8;
   int64_t reliable_updates = 0;
+  int64_t restarts = 0;          // solves restarted after a failed true-residual check
   // stencil accounting
   int64_t stencil_launches = 0;
   double stencil_seconds = 0.0, stencil_bytes = 0.0;
@@ -601,6 +604,15 @@ struct Solver {
     }
     max_iter = p->max_iter > 0 ? p->max_iter : (int)std::min<int64_t>(10 * V * ncomp, 1 << 20);
     tol2 = p->tol * p->tol;
+    // TIP_FREEZE_SLACK = f > 1 (tests): freeze a solve that has not restarted
+    // once its recursive residual is below f tol, so the first FP64
+    // true-residual check fails and the solve restarts from x -- the path a
+    // drifting recursive residual takes; after that the threshold is tol
+    freeze2 = tol2;
+    if (const char* e = std::getenv("TIP_FREEZE_SLACK")) {
+      const double f = std::atof(e);
+      if (f > 1.0 && std::isfinite(f)) freeze2 = tol2 * f * f;
+    }
     if (mixed) {
       // 1e-3: measured on the 32^4 workload to need no more iterations than
       // 1e-2 with a third fewer FP64 updates (the acceptance test is FP64 either way)
@@ -626,10 +638,12 @@ struct Solver {
                                    : (mixed ? vbytes64 + 4 * vbytes : 4 * vbytes);
     if (h->vec.ensure(vec_total) != hipSuccess)
       return fail(TIP_ENOMEM, "hipMalloc of %zu bytes of CG vectors failed", vec_total);
-    if (h->partial.ensure(5 * pstride * sizeof(double)) != hipSuccess) return fail(TIP_ENOMEM, "hipMalloc partials");
+    // 5 rows of per-workgroup partials, and 5 more for the second pass of the
+    // even-odd true residual
+    if (h->partial.ensure(10 * pstride * sizeof(double)) != hipSuccess) return fail(TIP_ENOMEM, "hipMalloc partials");
     const size_t scal_bytes = nscal * (9 * sizeof(double) + 4 * sizeof(int)) + 128 + kMaxChunk * sizeof(int);
     if (h->scal.ensure(scal_bytes) != hipSuccess) return fail(TIP_ENOMEM, "hipMalloc scalars");
-    const size_t host_bytes = nscal * (3 * sizeof(double) + 2 * sizeof(int)) + 128 + kMaxChunk * sizeof(int);
+    const size_t host_bytes = nscal * (3 * sizeof(double) + 3 * sizeof(int)) + 128 + kMaxChunk * sizeof(int);
     if (h->host.ensure(host_bytes) != hipSuccess) return fail(TIP_ENOMEM, "hipHostMalloc");
     if (mixed && h->kind == TIP_KIND_COVARIANT && !h->has_links32) {
       const size_t n = (size_t)g.ndim * 9 * V;
@@ -701,7 +715,8 @@ struct Solver {
     h_relres2 = h_q + 2 * nscal;
     h_state = (int*)(h_relres2 + nscal);
     h_iters = h_state + nscal;
-    h_active = h_iters + nscal;      // [0] active, [2] reliable updates of the block
+    h_restarts = h_iters + nscal;
+    h_active = h_restarts + nscal;   // [0] active, [2] reliable updates of the block
     h_ran = h_active + 32;
 
     od = h->dev(mixed);
@@ -747,13 +762,18 @@ struct Solver {
         TIP_HIP(launch_reduce_ru(sc, pl.B, part, gx_m, pstride, 0, tol2, max_iter, max_restarts, st));
         return TIP_OK;
       }
-      // final check: x on the full lattice, then the full FP64 residual
-      TIP_HIP(launch_eo_scatter_even(g, pl.elem, Prec::kF64, pl.logB, Xe, X, st));
-      TIP_HIP(launch_eo_hop(3, od64, g, pl.me, 1, pl.elem, Prec::kF64, diag, nullptr, nullptr, Xe, nullptr, X, nullptr,
-                            nullptr, rhs0, nb, p->seed, pl.mask, nullptr, nullptr, st));
-      TIP_HIP(launch_ru_residual(od64, g, pl.tm, pl.elem, sc, 1, rhs0, nb, p->seed, pl.mask, X, Rv, Pv, part, pstride,
-                                 1, st));
-      TIP_HIP(launch_reduce_ru(sc, pl.B, part, (int)ru_grid(pl.tm), pstride, 1, tol2, max_iter, max_restarts, st));
+      // final check: the FP64 true residual b - A x in two half-lattice passes,
+      // x_o = D_o^-1 (b_o + H_oe x_e) with the odd sites' part, then the even
+      // sites' part (restart_residual stores r_e for lanes that fail)
+      TIP_HIP(launch_eo_hop(3, od64, g, pl.me, 1, pl.elem, Prec::kF64, diag, nullptr, nullptr, Xe, nullptr, T64,
+                            need_x ? X : nullptr, nullptr, rhs0, nb, p->seed, pl.mask, part, nullptr, st, nullptr,
+                            nullptr, nullptr, pstride));
+      if (need_x) TIP_HIP(launch_eo_scatter_even(g, pl.elem, Prec::kF64, pl.logB, Xe, X, st));
+      TIP_HIP(launch_eo_hop(5, od64, g, pl.me, 0, pl.elem, Prec::kF64, diag, nullptr, nullptr, T64, Xe, nullptr,
+                            nullptr, nullptr, rhs0, nb, p->seed, pl.mask, part + 5 * pstride, nullptr, st, nullptr,
+                            nullptr, nullptr, pstride));
+      TIP_HIP(launch_reduce_ru(sc, pl.B, part, gx_m, pstride, 1, tol2, max_iter, max_restarts, st,
+                               part + 5 * pstride));
       return TIP_OK;
     }
     TIP_HIP(launch_ru_accumulate(nelem, pl.logB, pl.elem, sc, mode, X, XH, st));
@@ -789,7 +809,7 @@ struct Solver {
     if (tv) TIP_HIP(hipEventRecord(tv->c, st));
     TIP_HIP(launch_reduce_alpha(sc, pl.B, part, gx_m, st));
     TIP_HIP(launch_update_r(nvec, pl.logB, pl.elem, prec, sc, Rv, W, part + pstride, st));
-    TIP_HIP(launch_reduce_beta(sc, pl.B, part + pstride, gx_u, tol2, max_iter, delta2, st));
+    TIP_HIP(launch_reduce_beta(sc, pl.B, part + pstride, gx_u, tol2, max_iter, delta2, st, freeze2));
     TIP_HIP(launch_direction(nvec, pl.logB, pl.elem, prec, sc, xdir, Rv, Pv, st));
     if (mixed) {
       tip_status s = reliable(rhs0, nb, 0);
@@ -923,26 +943,51 @@ struct Solver {
         if (s != TIP_OK) return s;
       } else {
         if (pl.eo) {
-          // x on the full lattice: x_e as iterated, x_o = D_o^-1 (b_o + H_oe x_e)
-          TIP_HIP(launch_eo_scatter_even(g, pl.elem, prec, pl.logB, Xe, X, st));
-          TIP_HIP(launch_eo_hop(3, od, g, pl.me, 1, pl.elem, prec, diag, nullptr, nullptr, Xe, nullptr, X, nullptr,
-                                nullptr, rhs0, nb, p->seed, pl.mask, nullptr, nullptr, st));
+          // the true residual b - A x in two half-lattice passes: x_o = D_o^-1
+          // (b_o + H_oe x_e) with the odd sites' part, then the even sites'
+          // part r_e = b_e - D_e x_e + H_eo x_o (the restart r = p for lanes
+          // that fail); x on the full lattice only when the caller reads it
+          TIP_HIP(launch_eo_hop(3, od, g, pl.me, 1, pl.elem, prec, diag, nullptr, nullptr, Xe, nullptr, Tv,
+                                need_x ? X : nullptr, nullptr, rhs0, nb, p->seed, pl.mask, part, nullptr, st, nullptr,
+                                nullptr, nullptr, pstride));
+          if (need_x) TIP_HIP(launch_eo_scatter_even(g, pl.elem, prec, pl.logB, Xe, X, st));
+          TIP_HIP(launch_eo_hop(5, od, g, pl.me, 0, pl.elem, prec, diag, nullptr, nullptr, Tv, Xe, nullptr, nullptr,
+                                nullptr, rhs0, nb, p->seed, pl.mask, part + 5 * pstride, nullptr, st, nullptr, nullptr,
+                                nullptr, pstride));
+          TIP_HIP(launch_reduce_true(sc, pl.B, part, gx_m, pstride, tol2, max_iter, max_restarts, st,
+                                     part + 5 * pstride));
+        } else {
+          TIP_HIP(launch_true_residual(od, g, pl.tm, pl.elem, sc.state, rhs0, nb, p->seed, pl.mask, X, Rv, Pv, part,
+                                       pstride, 0, st));
+          TIP_HIP(launch_reduce_true(sc, pl.B, part, gx_t, pstride, tol2, max_iter, max_restarts, st));
         }
-        TIP_HIP(launch_true_residual(od, g, pl.tm, pl.elem, sc.state, rhs0, nb, p->seed, pl.mask, X, Rv, Pv, part,
-                                     pstride, pl.eo ? 1 : 0, st));
-        TIP_HIP(launch_reduce_true(sc, pl.B, part, gx_t, pstride, tol2, max_iter, max_restarts, st));
       }
       TIP_HIP(hipMemcpyAsync(h_active, sc.active, sizeof(int), hipMemcpyDeviceToHost, st));
       TIP_HIP(hipStreamSynchronize(st));
       if (h_active[0] == 0) break;
+      if (pl.eo) {
+        // some lanes failed the check and are active again: their CG restarts
+        // from r = p = the reduced residual (the even sites' part of b - A x;
+        // the x_o of the check is still in the t buffer)
+        const double* diag = (const double*)h->diag.p;
+        if (mixed)
+          TIP_HIP(launch_eo_hop(5, od64, g, pl.me, 0, pl.elem, Prec::kF64, diag, sc.state, nullptr, T64, Xe, nullptr,
+                                nullptr, Pv, rhs0, nb, p->seed, pl.mask, nullptr, nullptr, st, nullptr, nullptr, Rv,
+                                pstride));
+        else
+          TIP_HIP(launch_eo_hop(5, od, g, pl.me, 0, pl.elem, prec, diag, sc.state, nullptr, Tv, Xe, Rv, Pv, nullptr,
+                                rhs0, nb, p->seed, pl.mask, nullptr, nullptr, st, nullptr, nullptr, nullptr, pstride));
+      }
     }
     TIP_HIP(hipMemcpyAsync(h_q, sc.q, 2 * nb * sizeof(double), hipMemcpyDeviceToHost, st));
     TIP_HIP(hipMemcpyAsync(h_relres2, sc.relres2, nb * sizeof(double), hipMemcpyDeviceToHost, st));
     TIP_HIP(hipMemcpyAsync(h_state, sc.state, nb * sizeof(int), hipMemcpyDeviceToHost, st));
     TIP_HIP(hipMemcpyAsync(h_iters, sc.iters, nb * sizeof(int), hipMemcpyDeviceToHost, st));
+    TIP_HIP(hipMemcpyAsync(h_restarts, sc.restarts, nb * sizeof(int), hipMemcpyDeviceToHost, st));
     TIP_HIP(hipMemcpyAsync(h_active + 2, sc.ru_count, sizeof(int), hipMemcpyDeviceToHost, st));
     TIP_HIP(hipStreamSynchronize(st));
     reliable_updates += h_active[2];
+    for (int j = 0; j < nb; ++j) restarts += h_restarts[j];
     int blk_max = 0;
     for (int j = 0; j < nb; ++j) blk_max = std::max(blk_max, h_iters[j]);
     predicted = std::max(1, blk_max);
@@ -958,6 +1003,7 @@ struct Solver {
     stats->matvec_bytes = matvec_bytes;
     stats->even_odd = pl.eo ? 1 : 0;
     stats->reliable_updates = reliable_updates;
+    stats->restarts = restarts;
   }
 };
 
@@ -1011,6 +1057,7 @@ tip_status run_probe(tip_op_handle h, const tip_params* p, double* estimates, do
   const int64_t probes = p->n_vectors - p->m_begin;
   const int64_t n_rhs = probes * ncomp;
   Solver sv;
+  sv.need_x = want_grad;
   s = sv.setup(h, p, mask);
   if (s != TIP_OK) return s;
   const size_t V = h->geom.V;
@@ -1149,6 +1196,7 @@ tip_status tip_solve_probe(tip_op_handle h, const tip_params* p, int64_t m, int3
   if (comp < 0 || comp >= g.ncomp) return fail(TIP_EINVAL, "comp = %d out of range", comp);
   if (!x_out) return fail(TIP_EINVAL, "x_out is NULL");
   Solver sv;
+  sv.need_x = true;
   s = sv.setup(h, &one, mask);
   if (s != TIP_OK) return s;
   s = sv.solve_block(m * g.ncomp + comp, 1);

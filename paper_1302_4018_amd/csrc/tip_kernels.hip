@@ -749,6 +749,14 @@ __device__ __forceinline__ double sum_partials(const double* __restrict__ part, 
   return v[0];
 }
 
+// The same sum over two partial arrays (two passes that each cover part of
+// the lattice); partial2 may be NULL.
+__device__ __forceinline__ double sum_partials2(const double* __restrict__ p1, const double* __restrict__ p2,
+                                                size_t off, int n) {
+  const double a = sum_partials(p1 + off, n);
+  return p2 ? a + sum_partials(p2 + off, n) : a;
+}
+
 __global__ void k_scalars_init(CgScalars sc, int nb, int B, double bnorm2, int start_frozen) {
   const int j = blockIdx.x * blockDim.x + threadIdx.x;
   if (j == 0) {
@@ -791,7 +799,7 @@ __global__ __launch_bounds__(kBlock) void k_reduce_alpha(CgScalars sc, const dou
 // at max_iter.  xalpha = the x update the direction pass applies this
 // iteration (alpha for a rhs that iterated, 0 otherwise).
 __global__ __launch_bounds__(kBlock) void k_reduce_beta(CgScalars sc, const double* __restrict__ partial, int gx,
-                                                        double tol2, int max_iter, double delta2) {
+                                                        double tol2, int max_iter, double delta2, double first2) {
   const int j = blockIdx.x;
   if (sc.state[j] != kActive) {                // uniform per workgroup
     if (threadIdx.x == 0) sc.xalpha[j] = 0.0;
@@ -807,7 +815,7 @@ __global__ __launch_bounds__(kBlock) void k_reduce_beta(CgScalars sc, const doub
   if (!isfinite(rho_new)) {
     sc.state[j] = kBreakdown;
     atomicSub(sc.active, 1);
-  } else if (rho_new <= tol2 * sc.bnorm2[j]) {
+  } else if (rho_new <= (sc.restarts[j] == 0 ? first2 : tol2) * sc.bnorm2[j]) {
     sc.state[j] = kFrozen;
     atomicSub(sc.active, 1);
   } else if (it >= max_iter) {
@@ -821,14 +829,15 @@ __global__ __launch_bounds__(kBlock) void k_reduce_beta(CgScalars sc, const doub
 
 // Accept a frozen solve when its true residual passes, else restart CG from x
 // (r and p already hold the true residual).
-__global__ __launch_bounds__(kBlock) void k_reduce_true(CgScalars sc, const double* __restrict__ partial, int gx,
-                                                        size_t pstride, double tol2, int max_iter, int max_restarts) {
+__global__ __launch_bounds__(kBlock) void k_reduce_true(CgScalars sc, const double* __restrict__ partial,
+                                                        const double* __restrict__ partial2, int gx, size_t pstride,
+                                                        double tol2, int max_iter, int max_restarts) {
   const int j = blockIdx.x;
   if (threadIdx.x == 0) sc.xalpha[j] = 0.0;
   if (sc.state[j] != kFrozen) return;
-  const double rt2 = sum_partials(partial + (size_t)j * gx, gx);
-  const double qre = sum_partials(partial + pstride + (size_t)j * gx, gx);
-  const double qim = sum_partials(partial + 2 * pstride + (size_t)j * gx, gx);
+  const double rt2 = sum_partials2(partial, partial2, (size_t)j * gx, gx);
+  const double qre = sum_partials2(partial, partial2, pstride + (size_t)j * gx, gx);
+  const double qim = sum_partials2(partial, partial2, 2 * pstride + (size_t)j * gx, gx);
   if (threadIdx.x != 0) return;
   sc.relres2[j] = rt2 / sc.bnorm2[j];
   if (rt2 <= tol2 * sc.bnorm2[j]) {
@@ -960,15 +969,15 @@ __global__ __launch_bounds__(kBlock) void k_ru_residual(Geom g, TileMap tm, Op64
 // Mode 0: the recursive residual restarts from the true one.  Mode 1: accept
 // with the variational quadrature b^H x + x^H r = 2 Re(b^H x) - x^H A x, whose
 // error r^H A^-1 r is second order in the residual, or restart CG from x.
-__global__ __launch_bounds__(kBlock) void k_reduce_ru(CgScalars sc, const double* __restrict__ partial, int gx,
-                                                      size_t pstride, int mode, double tol2, int max_iter,
-                                                      int max_restarts) {
+__global__ __launch_bounds__(kBlock) void k_reduce_ru(CgScalars sc, const double* __restrict__ partial,
+                                                      const double* __restrict__ partial2, int gx, size_t pstride,
+                                                      int mode, double tol2, int max_iter, int max_restarts) {
   const int j = blockIdx.x;
   if (mode == 0 && *sc.n_ru == 0) return;
   if (!ru_selected(sc, mode, j)) return;      // uniform per workgroup
   double v[5];
 #pragma unroll
-  for (int k = 0; k < 5; ++k) v[k] = sum_partials(partial + k * pstride + (size_t)j * gx, gx);
+  for (int k = 0; k < 5; ++k) v[k] = sum_partials2(partial, partial2, k * pstride + (size_t)j * gx, gx);
   if (threadIdx.x != 0) return;
   const double rt2 = v[0];
   if (sc.ru[j]) {
@@ -1162,9 +1171,22 @@ static inline unsigned cdiv(size_t a, size_t b) { return (unsigned)((a + b - 1) 
 //   0  out = D^-1 H in                  (t_o = D_o^-1 H_oe p_e)
 //   1  out = D cin - H in, partial Re cin^H out   (w_e = S p_e)
 //   2  out = out2 = b + H in, out3 = 0, partial ||out||^2   (reduced rhs, CG start)
-//   3  out = D^-1 (b + H in), written at full-lattice sites   (x_o)
+//   3  out = D^-1 (b + H in)   (x_o from x_e; also at full-lattice sites
+//      into out2 when given); partials (5 rows, pstride apart) of the odd
+//      sites' part of the true residual: ||y - D out||^2 with y = b + H in
+//      (zero up to rounding), Re/Im b^H x_o, Re/Im x_o^H r_o
 //   4  (FP64) out32 = single(cin2 - (D cin - H in)), partial ||.||^2, lanes
 //      flagged in ru only   (reliable update of the reduced residual)
+//   5  r_e = b - (D cin - H in), the even sites' part of the true residual
+//      b - A x with x_e = cin, x_o = in; partials ||r_e||^2, Re/Im b^H x_e,
+//      Re/Im x_e^H r_e.  With state given, lanes in state kActive (those the
+//      check just restarted) store r_e to out and out2 (FP64 restart) or,
+//      rounded to single, to out32 and to out3 read as single precision
+//      (mixed restart: r and p)
+// With x_o formed by mode 3, b - A x vanishes on the odd sites up to
+// rounding and equals the reduced residual b_hat - S x_e on the even ones, so
+// modes 3 and 5 together give the full FP64 true residual and the quadrature
+// in two half-lattice passes.
 // b is the probing right-hand side, regenerated from site indices.
 // ---------------------------------------------------------------------------
 
@@ -1181,16 +1203,19 @@ __global__ __launch_bounds__(kBlock) void k_eo_hop(Geom g, MarchMap mm, int P, O
                                                    typename Op::T* __restrict__ out3, int64_t rhs0, int nb,
                                                    uint64_t seed, int mask, double* __restrict__ partial,
                                                    int* __restrict__ ran, const int* __restrict__ ru,
-                                                   const typename Op::T* __restrict__ cin2, void* __restrict__ out32) {
+                                                   const typename Op::T* __restrict__ cin2, void* __restrict__ out32,
+                                                   size_t pstride) {
   using T = typename Op::T;
   constexpr int NC = Op::NC;
   constexpr bool kCov = NC == 3;
+  constexpr bool kResidual = MODE == 3 || MODE == 5;      // true-residual passes: 5 partial rows
+  constexpr int NP = kResidual ? 5 : 1;
   const int logB = kLogB >= 0 ? kLogB : mm.logB;
   const int B = 1 << logB;
   const int TS = kBlock >> logB;
   if (active && *active == 0) return;
   if (ran && blockIdx.x == 0 && threadIdx.x == 0) *ran = 1;
-  __shared__ double lds[4 * 64];
+  __shared__ double lds[NP * 4 * 64];
   T* lds_links = reinterpret_cast<T*>(tip_dyn_lds);   // covariant: [2 ndim][9][TS]
   const int j = threadIdx.x & (B - 1);
   const int si = threadIdx.x >> logB;
@@ -1206,8 +1231,10 @@ __global__ __launch_bounds__(kBlock) void k_eo_hop(Geom g, MarchMap mm, int P, O
   const uint32_t s3_first = q * (uint32_t)TS;
   const uint32_t s3 = s3_first + (uint32_t)si;
   const uint32_t delta = ((uint32_t)P + spatial_parity(s3, g)) & 1u;
-  const bool live = (!state || state[j] == kActive) && (!ru || ru[j] != 0);
-  double acc[1] = {0.0};
+  const bool live = kResidual || ((!state || state[j] == kActive) && (!ru || ru[j] != 0));
+  double acc[NP];
+#pragma unroll
+  for (int k = 0; k < NP; ++k) acc[k] = 0.0;
   const uint32_t tau0 = chunk * (uint32_t)mm.Tc;
   T xprev[NC];
   if (live) load_vec<T, NC>(in, Vh, logB, s3 + V3 * ((tau0 + ntau - 1u + delta) % ntau), j, xprev);
@@ -1361,17 +1388,57 @@ __global__ __launch_bounds__(kBlock) void k_eo_hop(Geom g, MarchMap mm, int P, O
         store_vec<T, NC>(out, Vh, logB, h, j, y);
         if (out2) store_vec<T, NC>(out2, Vh, logB, h, j, y);
         if (out3) store_vec<T, NC>(out3, Vh, logB, h, j, z);
-      } else {
+      } else if constexpr (MODE == 3) {
         const double f = 1.0 / d;
 #pragma unroll
-        for (int c = 0; c < NC; ++c) y[c] = axpy(f, axpy(1.0, hop[c], b[c]), zero<T>());
-        store_vec<T, NC>(out, V, logB, s, j, y);
+        for (int c = 0; c < NC; ++c) {
+          const T yv = axpy(1.0, hop[c], b[c]);              // b_o + H_oe x_e
+          y[c] = axpy(f, yv, zero<T>());                       // x_o
+          const T ro = axpy(-d, y[c], yv);                     // b_o + H_oe x_e - D_o x_o
+          acc[0] += norm2(ro);
+          acc[1] += redot(b[c], y[c]);
+          acc[2] += imdot(b[c], y[c]);
+          acc[3] += redot(y[c], ro);
+          acc[4] += imdot(y[c], ro);
+        }
+        store_vec<T, NC>(out, Vh, logB, h, j, y);
+        if (out2) store_vec<T, NC>(out2, V, logB, s, j, y);
+      } else if constexpr (MODE == 5) {
+        T xv[NC];
+        load_vec<T, NC>(cin, Vh, logB, h, j, xv);
+#pragma unroll
+        for (int c = 0; c < NC; ++c) {
+          const T ax = axpy(d, xv[c], axpy(-1.0, hop[c], zero<T>()));   // D_e x_e - H_eo x_o
+          y[c] = axpy(-1.0, ax, b[c]);
+          acc[0] += norm2(y[c]);
+          acc[1] += redot(b[c], xv[c]);
+          acc[2] += imdot(b[c], xv[c]);
+          acc[3] += redot(xv[c], y[c]);
+          acc[4] += imdot(xv[c], y[c]);
+        }
+        if (state && state[j] == kActive) {
+          if (out) store_vec<T, NC>(out, Vh, logB, h, j, y);
+          if (out2) store_vec<T, NC>(out2, Vh, logB, h, j, y);
+          if constexpr (sizeof(typename SingleOf<T>::type) * 2 == sizeof(T)) {
+            using T32 = typename SingleOf<T>::type;
+            if (out32) {
+              T32 r32[NC];
+#pragma unroll
+              for (int c = 0; c < NC; ++c) r32[c] = to_single(y[c]);
+              store_vec<T32, NC>(reinterpret_cast<T32*>(out32), Vh, logB, h, j, r32);
+              if (out3) store_vec<T32, NC>(reinterpret_cast<T32*>(out3), Vh, logB, h, j, r32);
+            }
+          }
+        }
       }
     }
   }
   if (partial) {
-    seg_sum<1>(acc, B, lds);
-    if ((int)threadIdx.x < B) partial[(size_t)threadIdx.x * gridDim.x + blockIdx.x] = acc[0];
+    seg_sum<NP>(acc, B, lds);
+    if ((int)threadIdx.x < B) {
+#pragma unroll
+      for (int k = 0; k < NP; ++k) partial[k * pstride + (size_t)threadIdx.x * gridDim.x + blockIdx.x] = acc[k];
+    }
   }
 }
 
@@ -1625,8 +1692,8 @@ hipError_t launch_ru_residual(const OpDev& od64, const Geom& g, const TileMap& t
 }
 
 hipError_t launch_reduce_ru(const CgScalars& sc, int B, const double* partial, int gx, size_t pstride, int mode,
-                            double tol2, int max_iter, int max_restarts, hipStream_t st) {
-  k_reduce_ru<<<B, kBlock, 0, st>>>(sc, partial, gx, pstride, mode, tol2, max_iter, max_restarts);
+                            double tol2, int max_iter, int max_restarts, hipStream_t st, const double* partial2) {
+  k_reduce_ru<<<B, kBlock, 0, st>>>(sc, partial, partial2, gx, pstride, mode, tol2, max_iter, max_restarts);
   return hipGetLastError();
 }
 
@@ -1637,7 +1704,8 @@ size_t eo_lds_bytes(const Geom& g, const MarchMap& mm, Prec prec) {
 hipError_t launch_eo_hop(int mode, const OpDev& od, const Geom& g, const MarchMap& mm, int P, Elem elem, Prec prec,
                          const double* diag, const int* state, const int* active, const void* in, const void* cin,
                          void* out, void* out2, void* out3, int64_t rhs0, int nb, uint64_t seed, int mask,
-                         double* partial, int* ran, hipStream_t st, const int* ru, const void* cin2, void* out32) {
+                         double* partial, int* ran, hipStream_t st, const int* ru, const void* cin2, void* out32,
+                         size_t pstride) {
   OpDev oe = od;
   oe.links = od.links_eo;
   return dispatch(oe, elem, prec, [&](auto op) {
@@ -1647,7 +1715,7 @@ hipError_t launch_eo_hop(int mode, const OpDev& od, const Geom& g, const MarchMa
     auto go = [&](auto kern) {
       kern<<<mm.grid, kBlock, lds, st>>>(g, mm, P, op, diag, od.coupling, state, active, (const T*)in,
                                           (const T*)cin, (T*)out, (T*)out2, (T*)out3, rhs0, nb, seed, mask, partial,
-                                          ran, ru, (const T*)cin2, out32);
+                                          ran, ru, (const T*)cin2, out32, pstride);
     };
     const bool b32 = mm.logB == 5;
     switch (mode) {
@@ -1655,6 +1723,7 @@ hipError_t launch_eo_hop(int mode, const OpDev& od, const Geom& g, const MarchMa
       case 1: b32 ? go(k_eo_hop<Op, 1, 5>) : go(k_eo_hop<Op, 1, -1>); break;
       case 2: go(k_eo_hop<Op, 2, -1>); break;
       case 3: go(k_eo_hop<Op, 3, -1>); break;
+      case 5: go(k_eo_hop<Op, 5, -1>); break;
       default:
         if constexpr (sizeof(typename SingleOf<T>::type) * 2 == sizeof(T)) go(k_eo_hop<Op, 4, -1>);
         break;
@@ -1739,14 +1808,14 @@ hipError_t launch_reduce_alpha(const CgScalars& sc, int B, const double* partial
 }
 
 hipError_t launch_reduce_beta(const CgScalars& sc, int B, const double* partial, int gx, double tol2, int max_iter,
-                              double delta2, hipStream_t st) {
-  k_reduce_beta<<<B, kBlock, 0, st>>>(sc, partial, gx, tol2, max_iter, delta2);
+                              double delta2, hipStream_t st, double first2) {
+  k_reduce_beta<<<B, kBlock, 0, st>>>(sc, partial, gx, tol2, max_iter, delta2, first2 > 0.0 ? first2 : tol2);
   return hipGetLastError();
 }
 
 hipError_t launch_reduce_true(const CgScalars& sc, int B, const double* partial, int gx, size_t pstride, double tol2,
-                              int max_iter, int max_restarts, hipStream_t st) {
-  k_reduce_true<<<B, kBlock, 0, st>>>(sc, partial, gx, pstride, tol2, max_iter, max_restarts);
+                              int max_iter, int max_restarts, hipStream_t st, const double* partial2) {
+  k_reduce_true<<<B, kBlock, 0, st>>>(sc, partial, partial2, gx, pstride, tol2, max_iter, max_restarts);
   return hipGetLastError();
 }
 

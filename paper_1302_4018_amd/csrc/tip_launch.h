@@ -137,7 +137,8 @@ hipError_t launch_ru_residual(const OpDev& od64, const Geom& g, const TileMap& t
                               int mode, int64_t rhs0, int nb, uint64_t seed, int mask, const void* x64, void* rh,
                               void* ph, double* partial, size_t pstride, int eo, hipStream_t st);
 hipError_t launch_reduce_ru(const CgScalars& sc, int B, const double* partial, int gx, size_t pstride, int mode,
-                            double tol2, int max_iter, int max_restarts, hipStream_t st);
+                            double tol2, int max_iter, int max_restarts, hipStream_t st,
+                            const double* partial2 = nullptr);
 hipError_t launch_cast_links(size_t n, const double2* src, float2* dst, hipStream_t st);
 // gradient: gm[s] += sum_j ||x_j(s)||^2, gw[mu][s] += sum_j ||x_j(s) - U_mu(s) x_j(s+mu)||^2 over lanes j < nb
 hipError_t launch_grad_accum(const OpDev& od64, const Geom& g, Elem elem, int logB, int nb, const void* x, double* gm,
@@ -149,7 +150,7 @@ hipError_t launch_eo_hop(int mode, const OpDev& od, const Geom& g, const MarchMa
                          const double* diag, const int* state, const int* active, const void* in, const void* cin,
                          void* out, void* out2, void* out3, int64_t rhs0, int nb, uint64_t seed, int mask,
                          double* partial, int* ran, hipStream_t st, const int* ru = nullptr,
-                         const void* cin2 = nullptr, void* out32 = nullptr);
+                         const void* cin2 = nullptr, void* out32 = nullptr, size_t pstride = 0);
 hipError_t launch_eo_cast_init(size_t n, Elem elem, const void* bh, void* r, void* p, void* xh, hipStream_t st);
 hipError_t launch_eo_init_odd(const Geom& g, Elem elem, Prec prec, int logB, int64_t rhs0, int nb, uint64_t seed,
                               int mask, const double* diag, void* to, hipStream_t st);
@@ -161,10 +162,11 @@ hipError_t launch_reduce_rho0(const CgScalars& sc, int B, const double* partial,
 hipError_t launch_fill(size_t n, double* a, double v, hipStream_t st);
 hipError_t launch_scalars_init(const CgScalars& sc, int nb, int B, double bnorm2, int start_frozen, hipStream_t st);
 hipError_t launch_reduce_alpha(const CgScalars& sc, int B, const double* partial, int gx, hipStream_t st);
+// first2 > 0: freeze threshold for solves not yet restarted (tol2 otherwise)
 hipError_t launch_reduce_beta(const CgScalars& sc, int B, const double* partial, int gx, double tol2, int max_iter,
-                              double delta2, hipStream_t st);
+                              double delta2, hipStream_t st, double first2 = 0.0);
 hipError_t launch_reduce_true(const CgScalars& sc, int B, const double* partial, int gx, size_t pstride, double tol2,
-                              int max_iter, int max_restarts, hipStream_t st);
+                              int max_iter, int max_restarts, hipStream_t st, const double* partial2 = nullptr);
 hipError_t launch_hier_perm(const Geom& g, uint32_t* out, hipStream_t st);
 hipError_t launch_probe_vectors(const Geom& g, uint64_t seed, int mask, int64_t m0, int count, int comp, double2* out,
                                 hipStream_t st);

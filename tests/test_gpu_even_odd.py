@@ -128,3 +128,57 @@ def test_mixed_even_odd_matches_oracle(dims, kind, n, mask):
     assert st["max_true_relres"] <= tol
     assert _rel(est, est_o) <= REL and _rel(q, q_o) <= REL
     assert np.all(np.abs(q - q_o) <= 2 * st["max_quad_err_bound"] + 1e-13 * np.abs(q_o))
+
+
+def _with_env(name, value, fn):
+    os.environ[name] = value
+    try:
+        return fn()
+    finally:
+        del os.environ[name]
+
+
+@pytest.mark.parametrize("dims,kind,n,mask,prec", [
+    ([8, 8, 8, 8], 1, 8, MASK_Z4, "fp64"),
+    ([8, 8, 8, 8], 1, 8, MASK_Z4, "mixed"),
+    ([16, 16], 0, 32, MASK_Z2, "fp64"),
+    ([8, 4, 8], 0, 24, MASK_Z4, "mixed"),
+])
+def test_even_odd_restart_after_failed_true_residual(dims, kind, n, mask, prec):
+    """TIP_FREEZE_SLACK = 10 freezes a solve once its recursive residual is below
+    10 tol, so the FP64 true-residual check (two half-lattice passes) fails and
+    CG restarts from x with r = p = the reduced residual: the estimates still
+    match the oracle and the plain run, every solve meets tol, and the restarts
+    are counted."""
+    tip = gpu_binding()
+    orc, gop = _ops(tip, dims, kind, seed=450 + kind)
+    tol = 1e-11
+    precision = tip.PREC_MIXED if prec == "mixed" else tip.PREC_FP64
+    print(f"even-odd restart: dims {dims} kind {kind} n {n} {prec}", flush=True)
+    est, q, st = tip.trace_inv_probe(gop, n, tol, 4018, mask=mask, precision=precision)
+    est_r, q_r, st_r = _with_env("TIP_FREEZE_SLACK", "10",
+                                 lambda: tip.trace_inv_probe(gop, n, tol, 4018, mask=mask, precision=precision))
+    est_o, q_o, _ = oracle_trace(orc, n, tol, 4018, mask)
+    assert st["even_odd"] == 1 and st_r["even_odd"] == 1
+    assert st["restarts"] == 0 and st_r["restarts"] >= 1
+    assert st_r["max_true_relres"] <= tol
+    assert _rel(est_r, est_o) <= REL and _rel(q_r, q_o) <= REL
+    assert _rel(est_r, est) <= REL
+
+
+def test_even_odd_gradient_and_solution_assemble_x():
+    """Only the gradient and solve_probe read x on the full lattice: with the
+    half-lattice true residual both still see x_e and x_o in place."""
+    tip = gpu_binding()
+    import torch
+    orc, gop = _ops(tip, [4, 4, 4, 8], 1, seed=460)
+    with tip.OpHandle(gop) as h:
+        x, qx, st = h.solve_probe(3, 2, 1e-12, 4018)
+        assert st["even_odd"] == 1
+        est, q, gm, gw, stg = h.trace_inv_probe_grad(4, 1e-12, 4018)
+        assert stg["even_odd"] == 1
+    from oracle.probing import rhs as oracle_rhs
+    b = oracle_rhs(orc.dims, 3, 3, 2, 4018, MASK_Z4)
+    ax = orc.apply(x.cpu().numpy().reshape(orc.V, 3))
+    assert np.linalg.norm(ax - b) <= 1e-12 * np.linalg.norm(b) * 1.01
+    assert np.all(gm.cpu().numpy() < 0)
