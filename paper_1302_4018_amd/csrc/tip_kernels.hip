@@ -1217,6 +1217,9 @@ __global__ __launch_bounds__(kBlock) void k_eo_hop(Geom g, MarchMap mm, int P, O
   if (ran && blockIdx.x == 0 && threadIdx.x == 0) *ran = 1;
   __shared__ double lds[NP * 4 * 64];
   T* lds_links = reinterpret_cast<T*>(tip_dyn_lds);   // covariant: [2 ndim][9][TS]
+  // scalar operator with couplings: the tile's weights [2 ndim][TS] (forward
+  // w_mu(s), backward w_mu(s - mu)), read once per site instead of per lane
+  __shared__ double lds_w[kCov ? 1 : 2 * kMaxDim * kBlock];
   const int j = threadIdx.x & (B - 1);
   const int si = threadIdx.x >> logB;
   uint32_t q, chunk;
@@ -1275,6 +1278,21 @@ __global__ __launch_bounds__(kBlock) void k_eo_hop(Geom g, MarchMap mm, int P, O
         lds_links[it] = op.U[(((size_t)par * ndim + mu) * 9 + e) * Vh + hl];
       }
       __syncthreads();
+    } else {
+      if (w) {
+        __syncthreads();
+        const int nslot = 2 * ndim;
+        for (int it = threadIdx.x; it < nslot * TS; it += kBlock) {
+          const int site = it % TS;
+          const int slot = it / TS;
+          const uint32_t x3 = s3_first + (uint32_t)site;
+          const uint32_t dl = ((uint32_t)P + spatial_parity(x3, g)) & 1u;
+          const uint32_t sf = x3 + V3 * (2u * tau + dl);        // full-lattice site of the tile
+          const int mu = slot < ndim ? slot : slot - ndim;
+          lds_w[it] = w[(size_t)mu * V + (slot < ndim ? sf : nbr_bwd_p2(sf, g, mu))];
+        }
+        __syncthreads();
+      }
     }
     if (!live) continue;
     T hop[NC];
@@ -1285,8 +1303,16 @@ __global__ __launch_bounds__(kBlock) void k_eo_hop(Geom g, MarchMap mm, int P, O
     for (int mu = 0; mu < kMaxDim - 1; ++mu) {
       if (mu >= tdim) break;
       const uint32_t nf = nbr_fwd_p2(s3, g, mu), nbk = nbr_bwd_p2(s3, g, mu);
-      const double wf = w ? w[(size_t)mu * V + s] : 1.0;
-      const double wb = w ? w[(size_t)mu * V + nbr_bwd_p2(s, g, mu)] : 1.0;
+      double wf = 1.0, wb = 1.0;
+      if (w) {
+        if constexpr (kCov) {
+          wf = w[(size_t)mu * V + s];
+          wb = w[(size_t)mu * V + nbr_bwd_p2(s, g, mu)];
+        } else {
+          wf = lds_w[mu * TS + si];
+          wb = lds_w[(ndim + mu) * TS + si];
+        }
+      }
       T xn[NC], hh[NC];
       load_vec<T, NC>(in, Vh, logB, nf + V3 * tau, j, xn);
       if constexpr (kCov) {
@@ -1311,8 +1337,16 @@ __global__ __launch_bounds__(kBlock) void k_eo_hop(Geom g, MarchMap mm, int P, O
     }
     // the marching direction: forward input in slice tau + delta, backward one carried
     {
-      const double wf = w ? w[(size_t)tdim * V + s] : 1.0;
-      const double wb = w ? w[(size_t)tdim * V + nbr_bwd_p2(s, g, tdim)] : 1.0;
+      double wf = 1.0, wb = 1.0;
+      if (w) {
+        if constexpr (kCov) {
+          wf = w[(size_t)tdim * V + s];
+          wb = w[(size_t)tdim * V + nbr_bwd_p2(s, g, tdim)];
+        } else {
+          wf = lds_w[tdim * TS + si];
+          wb = lds_w[(ndim + tdim) * TS + si];
+        }
+      }
       T xn[NC], hh[NC];
       load_vec<T, NC>(in, Vh, logB, s3 + V3 * ((tau + delta) % ntau), j, xn);
       if constexpr (kCov) {
