@@ -93,6 +93,11 @@ enum { TIP_MASK_DEFAULT = -1, TIP_MASK_NONE = 0, TIP_MASK_Z2 = 1, TIP_MASK_Z4 = 
  * from x with the FP64 operator whenever the FP32 residual has fallen by
  * reliable_delta; Sleijpen & van der Vorst 1996) and the final true-residual
  * test, so a solve is accepted on the same FP64 criterion as in FP64 mode.
+ * In MIXED a single-precision p^H A p <= 0 (rounding on a badly conditioned
+ * operator) is not a breakdown: the solve goes to the FP64 check and restarts
+ * from the FP64 residual (counted in tip_stats.restarts; TIP_ENOCONV once the
+ * restart budget is spent).  FP32 CG suits condition numbers up to about
+ * 1e5; beyond that FP64 converges in fewer iterations.
  * MIXED reports the variational quadrature 2 Re(b^H x) - x^H A x = b^H x + x^H r,
  * whose error r^H A^-1 r <= ||r||^2 / lambda_min is second order in the
  * residual. */

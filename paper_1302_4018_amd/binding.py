@@ -58,6 +58,10 @@ def _load():
     if not os.path.exists(LIB_PATH):
         raise RuntimeError(f"{LIB_PATH} is not built: run `python -m paper_1302_4018_amd.build` "
                            "(there is no CPU fallback)")
+    # torch first: the library then binds to the HIP runtime torch has loaded,
+    # so it shares torch's device context and streams (the caller's tensors
+    # and streams are torch's)
+    import torch  # noqa: F401
     lib = ctypes.CDLL(LIB_PATH)
     P = ctypes.POINTER
     sig = {

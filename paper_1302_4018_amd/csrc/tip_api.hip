@@ -219,33 +219,38 @@ tip_status create_handle(const tip_operator* op, hipStream_t st, tip_op_s** out)
   const size_t V = g.V;
   auto bail = [&](tip_status code) { delete h; return code; };
   if (op->mass_field) {
-    if (h->mass_field.ensure(V * sizeof(double)) != hipSuccess) return bail(fail(TIP_ENOMEM, "hipMalloc mass_field"));
+    if (const hipError_t e_ = h->mass_field.ensure(V * sizeof(double)); e_ != hipSuccess)
+      return bail(fail(TIP_ENOMEM, "hipMalloc mass_field: %s", hipGetErrorString(e_)));
     if (hipMemcpyAsync(h->mass_field.p, op->mass_field, V * sizeof(double), hipMemcpyDeviceToDevice, st) != hipSuccess)
       return bail(fail(TIP_EDEVICE, "copy of mass_field failed"));
     h->has_mass_field = true;
   }
   if (op->coupling) {
     const size_t n = (size_t)g.ndim * V * sizeof(double);
-    if (h->coupling.ensure(n) != hipSuccess) return bail(fail(TIP_ENOMEM, "hipMalloc coupling"));
+    if (const hipError_t e_ = h->coupling.ensure(n); e_ != hipSuccess)
+      return bail(fail(TIP_ENOMEM, "hipMalloc coupling: %s", hipGetErrorString(e_)));
     if (hipMemcpyAsync(h->coupling.p, op->coupling, n, hipMemcpyDeviceToDevice, st) != hipSuccess)
       return bail(fail(TIP_EDEVICE, "copy of coupling failed"));
     h->has_coupling = true;
   }
   if (op->kind == TIP_KIND_COVARIANT) {
     const size_t n = (size_t)g.ndim * 9 * V * sizeof(double2);
-    if (h->links.ensure(n) != hipSuccess) return bail(fail(TIP_ENOMEM, "hipMalloc links (%zu bytes)", n));
+    if (const hipError_t e_ = h->links.ensure(n); e_ != hipSuccess)
+      return bail(fail(TIP_ENOMEM, "hipMalloc links (%zu bytes): %s", n, hipGetErrorString(e_)));
     if (launch_repack_links(g, (const double2*)op->links, (double2*)h->links.p, st) != hipSuccess)
       return bail(fail(TIP_EDEVICE, "link repack launch failed"));
     bool bip = g.pow2 != 0;
     for (int mu = 0; mu < g.ndim; ++mu) bip = bip && g.logn[mu] >= 1;
     if (bip) {
-      if (h->links_eo.ensure(n) != hipSuccess) return bail(fail(TIP_ENOMEM, "hipMalloc even-odd links (%zu bytes)", n));
+      if (const hipError_t e_ = h->links_eo.ensure(n); e_ != hipSuccess)
+      return bail(fail(TIP_ENOMEM, "hipMalloc even-odd links (%zu bytes): %s", n, hipGetErrorString(e_)));
       if (launch_repack_links_eo(g, (const double2*)h->links.p, (double2*)h->links_eo.p, st) != hipSuccess)
         return bail(fail(TIP_EDEVICE, "even-odd link repack launch failed"));
       h->has_links_eo = true;
     }
   }
-  if (h->diag.ensure(V * sizeof(double)) != hipSuccess) return bail(fail(TIP_ENOMEM, "hipMalloc diagonal"));
+  if (const hipError_t e_ = h->diag.ensure(V * sizeof(double)); e_ != hipSuccess)
+      return bail(fail(TIP_ENOMEM, "hipMalloc diagonal: %s", hipGetErrorString(e_)));
   if (launch_diag(g, h->has_mass_field ? (const double*)h->mass_field.p : nullptr, op->mass,
                   h->has_coupling ? (const double*)h->coupling.p : nullptr, (double*)h->diag.p, st) != hipSuccess)
     return bail(fail(TIP_EDEVICE, "diagonal launch failed"));
@@ -505,6 +510,7 @@ struct Solver {
   int max_iter, max_restarts = 8;
   double tol2, delta2 = 0.0;
   double freeze2;               // recursive-residual freeze threshold (tol2 unless TIP_FREEZE_SLACK)
+  int force_breakdown = 0;      // TIP_FORCE_BREAKDOWN = k (tests): iteration k of a fresh solve breaks down
   size_t vbytes, vbytes64, pstride, nscal, nelem, nvec;
   int gx_m, gx_u, gx_t;       // partials per rhs written by matvec, update, true residual
   void *X, *Rv, *Pv, *W, *XH; // FP64 path: X, Rv, Pv, W; mixed: X (FP64) + XH, Rv, Pv, W (FP32)
@@ -609,6 +615,7 @@ struct Solver {
     // true-residual check fails and the solve restarts from x -- the path a
     // drifting recursive residual takes; after that the threshold is tol
     freeze2 = tol2;
+    if (const char* e = std::getenv("TIP_FORCE_BREAKDOWN")) force_breakdown = std::max(0, std::atoi(e));
     if (const char* e = std::getenv("TIP_FREEZE_SLACK")) {
       const double f = std::atof(e);
       if (f > 1.0 && std::isfinite(f)) freeze2 = tol2 * f * f;
@@ -636,24 +643,29 @@ struct Solver {
     const size_t vec_total = pl.eo ? (mixed ? vbytes64 + 3 * (vbytes64 / 2) + 5 * (vbytes / 2)
                                             : vbytes + 5 * (vbytes / 2))
                                    : (mixed ? vbytes64 + 4 * vbytes : 4 * vbytes);
-    if (h->vec.ensure(vec_total) != hipSuccess)
-      return fail(TIP_ENOMEM, "hipMalloc of %zu bytes of CG vectors failed", vec_total);
+    if (const hipError_t e_ = h->vec.ensure(vec_total); e_ != hipSuccess)
+      return fail(TIP_ENOMEM, "hipMalloc of %zu bytes of CG vectors failed: %s", vec_total, hipGetErrorString(e_));
     // 5 rows of per-workgroup partials, and 5 more for the second pass of the
     // even-odd true residual
-    if (h->partial.ensure(10 * pstride * sizeof(double)) != hipSuccess) return fail(TIP_ENOMEM, "hipMalloc partials");
+    if (const hipError_t e_ = h->partial.ensure(10 * pstride * sizeof(double)); e_ != hipSuccess)
+      return fail(TIP_ENOMEM, "hipMalloc partials: %s", hipGetErrorString(e_));
     const size_t scal_bytes = nscal * (9 * sizeof(double) + 4 * sizeof(int)) + 128 + kMaxChunk * sizeof(int);
-    if (h->scal.ensure(scal_bytes) != hipSuccess) return fail(TIP_ENOMEM, "hipMalloc scalars");
+    if (const hipError_t e_ = h->scal.ensure(scal_bytes); e_ != hipSuccess)
+      return fail(TIP_ENOMEM, "hipMalloc scalars: %s", hipGetErrorString(e_));
     const size_t host_bytes = nscal * (3 * sizeof(double) + 3 * sizeof(int)) + 128 + kMaxChunk * sizeof(int);
-    if (h->host.ensure(host_bytes) != hipSuccess) return fail(TIP_ENOMEM, "hipHostMalloc");
+    if (const hipError_t e_ = h->host.ensure(host_bytes); e_ != hipSuccess)
+      return fail(TIP_ENOMEM, "hipHostMalloc: %s", hipGetErrorString(e_));
     if (mixed && h->kind == TIP_KIND_COVARIANT && !h->has_links32) {
       const size_t n = (size_t)g.ndim * 9 * V;
-      if (h->links32.ensure(n * sizeof(float2)) != hipSuccess) return fail(TIP_ENOMEM, "hipMalloc FP32 links");
+      if (const hipError_t e_ = h->links32.ensure(n * sizeof(float2)); e_ != hipSuccess)
+      return fail(TIP_ENOMEM, "hipMalloc FP32 links: %s", hipGetErrorString(e_));
       TIP_HIP(launch_cast_links(n, (const double2*)h->links.p, (float2*)h->links32.p, st));
       h->has_links32 = true;
     }
     if (mixed && pl.eo && h->kind == TIP_KIND_COVARIANT && !h->has_links_eo32) {
       const size_t n = (size_t)g.ndim * 9 * V;
-      if (h->links_eo32.ensure(n * sizeof(float2)) != hipSuccess) return fail(TIP_ENOMEM, "hipMalloc FP32 links");
+      if (const hipError_t e_ = h->links_eo32.ensure(n * sizeof(float2)); e_ != hipSuccess)
+      return fail(TIP_ENOMEM, "hipMalloc FP32 links: %s", hipGetErrorString(e_));
       TIP_HIP(launch_cast_links(n, (const double2*)h->links_eo.p, (float2*)h->links_eo32.p, st));
       h->has_links_eo32 = true;
     }
@@ -807,7 +819,7 @@ struct Solver {
                              st));
     }
     if (tv) TIP_HIP(hipEventRecord(tv->c, st));
-    TIP_HIP(launch_reduce_alpha(sc, pl.B, part, gx_m, st));
+    TIP_HIP(launch_reduce_alpha(sc, pl.B, part, gx_m, st, mixed ? 1 : 0, force_breakdown));
     TIP_HIP(launch_update_r(nvec, pl.logB, pl.elem, prec, sc, Rv, W, part + pstride, st));
     TIP_HIP(launch_reduce_beta(sc, pl.B, part + pstride, gx_u, tol2, max_iter, delta2, st, freeze2));
     TIP_HIP(launch_direction(nvec, pl.logB, pl.elem, prec, sc, xdir, Rv, Pv, st));

@@ -782,13 +782,20 @@ __global__ void k_scalars_init(CgScalars sc, int nb, int B, double bnorm2, int s
 }
 
 // alpha = rho / p^H A p; breakdown when p^H A p is not positive and finite.
-__global__ __launch_bounds__(kBlock) void k_reduce_alpha(CgScalars sc, const double* __restrict__ partial, int gx) {
+// soft (mixed precision): a single-precision p^H A p <= 0 says nothing about
+// the FP64 operator, so the solve is frozen instead and the FP64 true
+// residual decides: accept, or restart CG from it.  force_iter > 0 (tests)
+// treats iteration force_iter of a solve that has not restarted as such a
+// breakdown.
+__global__ __launch_bounds__(kBlock) void k_reduce_alpha(CgScalars sc, const double* __restrict__ partial, int gx,
+                                                         int soft, int force_iter) {
   const int j = blockIdx.x;
   if (*sc.active == 0 || sc.state[j] != kActive) return;     // uniform per workgroup
   const double pAp = sum_partials(partial + (size_t)j * gx, gx);
   if (threadIdx.x != 0) return;
-  if (!(pAp > 0.0) || !isfinite(pAp)) {
-    sc.state[j] = kBreakdown;
+  const bool forced = force_iter > 0 && sc.restarts[j] == 0 && sc.iters[j] + 1 == force_iter;
+  if (!(pAp > 0.0) || !isfinite(pAp) || forced) {
+    sc.state[j] = soft ? kFrozen : kBreakdown;
     atomicSub(sc.active, 1);
     return;
   }
@@ -1836,8 +1843,9 @@ hipError_t launch_scalars_init(const CgScalars& sc, int nb, int B, double bnorm2
   return hipGetLastError();
 }
 
-hipError_t launch_reduce_alpha(const CgScalars& sc, int B, const double* partial, int gx, hipStream_t st) {
-  k_reduce_alpha<<<B, kBlock, 0, st>>>(sc, partial, gx);
+hipError_t launch_reduce_alpha(const CgScalars& sc, int B, const double* partial, int gx, hipStream_t st, int soft,
+                               int force_iter) {
+  k_reduce_alpha<<<B, kBlock, 0, st>>>(sc, partial, gx, soft, force_iter);
   return hipGetLastError();
 }
 

@@ -161,7 +161,9 @@ hipError_t launch_diag(const Geom& g, const double* mass_field, double mass, con
 hipError_t launch_reduce_rho0(const CgScalars& sc, int B, const double* partial, int gx, hipStream_t st);
 hipError_t launch_fill(size_t n, double* a, double v, hipStream_t st);
 hipError_t launch_scalars_init(const CgScalars& sc, int nb, int B, double bnorm2, int start_frozen, hipStream_t st);
-hipError_t launch_reduce_alpha(const CgScalars& sc, int B, const double* partial, int gx, hipStream_t st);
+// soft: freeze instead of failing on p^H A p <= 0 (mixed precision); force_iter: test hook
+hipError_t launch_reduce_alpha(const CgScalars& sc, int B, const double* partial, int gx, hipStream_t st,
+                               int soft = 0, int force_iter = 0);
 // first2 > 0: freeze threshold for solves not yet restarted (tol2 otherwise)
 hipError_t launch_reduce_beta(const CgScalars& sc, int B, const double* partial, int gx, double tol2, int max_iter,
                               double delta2, hipStream_t st, double first2 = 0.0);

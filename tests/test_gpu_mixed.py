@@ -96,3 +96,32 @@ def test_mixed_full_size_matches_fp64():
     assert _rel(q32, q64) <= REL
     assert _rel(est32, est64) <= REL
     assert st32["max_true_relres"] <= 1e-10
+
+
+@pytest.mark.parametrize("eo", ["1", "0"])
+def test_mixed_single_precision_breakdown_restarts_from_fp64_residual(eo):
+    """TIP_FORCE_BREAKDOWN = 3 makes iteration 3 of every fresh solve report
+    p^H A p <= 0.  In mixed precision that freezes the solve, the FP64 true
+    residual fails and CG restarts from it: every solve still converges to the
+    oracle's quadratures.  In FP64 the same condition is a breakdown error."""
+    import os
+    tip = gpu_binding()
+    dims = [8, 8, 8, 8]
+    U = inputs.haar_links(dims, seed=470)
+    mf = inputs.mass_field(dims, seed=471)
+    orc = OracleOp(dims, 1, mass_field=mf, links=U)
+    gop = tip.Operator(dims, tip.KIND_COVARIANT, mass_field=to_dev(mf), links=to_dev(U))
+    print(f"forced breakdown: even-odd {eo}", flush=True)
+    os.environ["TIP_FORCE_BREAKDOWN"] = "3"
+    os.environ["TIP_EO"] = eo
+    try:
+        est, q, st = tip.trace_inv_probe(gop, 8, 1e-11, 4018, precision=tip.PREC_MIXED)
+        est64, q64, st64 = tip.trace_inv_probe(gop, 8, 1e-11, 4018, precision=tip.PREC_FP64, raise_on_error=False)
+    finally:
+        del os.environ["TIP_FORCE_BREAKDOWN"]
+        del os.environ["TIP_EO"]
+    assert st["even_odd"] == int(eo)
+    assert st["restarts"] >= st["solves"] and st["max_true_relres"] <= 1e-11
+    est_o, q_o, _ = oracle_trace(orc, 8, 1e-11, 4018, MASK_Z4)
+    assert np.max(np.abs(est - est_o) / np.abs(est_o)) <= 1e-10
+    assert st64["status"] == tip.TIP_EBREAKDOWN
