@@ -54,6 +54,10 @@
  *   2^LB)) times w^{(j >> LB) C(y)}, w = -1/2 + i sqrt(3)/2 and C the
  *   three-colouring of the sub-torus y >> B; sweep r uses mask outputs
  *   n = (r V + y) ncomp + c.  Probes past 2^LB are complex (complex solves).
+ *   For the scalar (real) operator with a Z2 or no mask, column j3 = 2 of a
+ *   sweep is the conjugate of column j3 = 1 (w^2 = conj w), so its quadrature
+ *   is the conjugate of the one of probe m - 2^LB and is not solved again
+ *   (stats->reused), and the j3 = 0 probes are solved in real arithmetic.
  * Memory: every pointer documented as "device" is caller-owned device memory
  *   and is never freed by the library; "host" pointers likewise.  Complex
  *   numbers are interleaved (re, im) float64 pairs.
@@ -182,6 +186,9 @@ typedef struct {
   int32_t even_odd;            /* 1 when CG ran on the even-odd reduced system (see below) */
   int64_t restarts;            /* restarts of CG from x after a failed FP64 true-residual
                                   check (the recursive residual had drifted)               */
+  int64_t reused;              /* right-hand sides whose quadrature is the conjugate of an
+                                  already solved one (conjugate F_3 columns of a real
+                                  operator, see TIP_PROBE_HIERARCHICAL); not in solves     */
 } tip_stats;
 
 /* Number of estimates written by trace_inv_probe: floor(log2 n) + 1, plus one

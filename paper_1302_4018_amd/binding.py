@@ -51,7 +51,7 @@ class tip_stats(ctypes.Structure):
                 ("stencil_seconds", ctypes.c_double), ("stencil_bytes", ctypes.c_double),
                 ("reliable_updates", ctypes.c_int64), ("max_quad_err_bound", ctypes.c_double),
                 ("matvecs", ctypes.c_int64), ("matvec_seconds", ctypes.c_double), ("matvec_bytes", ctypes.c_double),
-                ("even_odd", ctypes.c_int32), ("restarts", ctypes.c_int64)]
+                ("even_odd", ctypes.c_int32), ("restarts", ctypes.c_int64), ("reused", ctypes.c_int64)]
 
 
 def _load():

@@ -506,6 +506,8 @@ struct Solver {
   Plan pl;
   bool mixed = false;
   bool need_x = false;          // even-odd: assemble x on the full lattice (gradient, solve_probe)
+  int force_elem = -1;          // 0 real, 1 complex solves (the caller knows the right-hand sides); -1 automatic
+  int64_t rhs_hint = 0;         // > 0: right-hand sides of this pass (bounds the block size when rhs_block = 0)
   Prec prec = Prec::kF64;
   int max_iter, max_restarts = 8;
   double tol2, delta2 = 0.0;
@@ -576,13 +578,15 @@ struct Solver {
     const bool f3 = g.has3 && p->n_vectors > (int64_t(1) << g.LB);
     const bool fourier = p->probe == TIP_PROBE_FOURIER;          // roots of unity w16^e
     pl.elem = (h->kind == TIP_KIND_COVARIANT || mask == TIP_MASK_Z4 || f3 || fourier) ? Elem::kComplex : Elem::kReal;
+    if (force_elem >= 0) pl.elem = force_elem ? Elem::kComplex : Elem::kReal;
     const size_t esz64 = pl.elem == Elem::kReal ? sizeof(double) : sizeof(double2);
     pl.esz = mixed ? esz64 / 2 : esz64;
     // block size: a power of two <= 64; 32 shares each link among 32 solves;
     // small lattices take more right-hand sides per block to fill the GPU.
     // B depends only on the operator and rhs_block, so a right-hand side is
     // solved with the same arithmetic whichever block it falls in (resumed
-    // runs reproduce uninterrupted ones bit for bit).
+    // runs reproduce uninterrupted ones bit for bit), except in the probe
+    // classes of odd-sided real problems below.
     int B = 1;
     if (p->rhs_block > 0) {
       while (B < p->rhs_block && B < 64) B *= 2;
@@ -590,6 +594,10 @@ struct Solver {
       B = 32;
       while (B < 64 && V * B < (int64_t(1) << 18)) B *= 2;
     }
+    // a pass over fewer right-hand sides than that (a probe class of an
+    // odd-sided lattice) takes the smallest power of two that holds them
+    if (p->rhs_block <= 0 && rhs_hint > 0)
+      while (B > 1 && B / 2 >= rhs_hint) B /= 2;
     // keep the CG vectors of a block within 32 GiB
     while (B > 1 && 4.5 * B * ncomp * (double)V * esz64 > 32.0 * (1ull << 30)) B /= 2;
     pl.B = B;
@@ -790,7 +798,7 @@ struct Solver {
     }
     TIP_HIP(launch_ru_accumulate(nelem, pl.logB, pl.elem, sc, mode, X, XH, st));
     TIP_HIP(launch_ru_residual(od64, g, pl.tm, pl.elem, sc, mode, rhs0, nb, p->seed, pl.mask, X, Rv, Pv, part,
-                               pstride, 0, st));
+                               pstride, st));
     TIP_HIP(launch_reduce_ru(sc, pl.B, part, (int)ru_grid(pl.tm), pstride, mode, tol2, max_iter, max_restarts, st));
     return TIP_OK;
   }
@@ -970,7 +978,7 @@ struct Solver {
                                      part + 5 * pstride));
         } else {
           TIP_HIP(launch_true_residual(od, g, pl.tm, pl.elem, sc.state, rhs0, nb, p->seed, pl.mask, X, Rv, Pv, part,
-                                       pstride, 0, st));
+                                       pstride, st));
           TIP_HIP(launch_reduce_true(sc, pl.B, part, gx_t, pstride, tol2, max_iter, max_restarts, st));
         }
       }
@@ -1068,37 +1076,139 @@ tip_status run_probe(tip_op_handle h, const tip_params* p, double* estimates, do
   const int ncomp = h->geom.ncomp;
   const int64_t probes = p->n_vectors - p->m_begin;
   const int64_t n_rhs = probes * ncomp;
-  Solver sv;
-  sv.need_x = want_grad;
-  s = sv.setup(h, p, mask);
-  if (s != TIP_OK) return s;
-  const size_t V = h->geom.V;
-  if (grad_mass) TIP_HIP(launch_fill(V, grad_mass, 0.0, sv.st));
-  if (grad_coupling) TIP_HIP(launch_fill((size_t)h->geom.ndim * V, grad_coupling, 0.0, sv.st));
-
+  const Geom& gg = h->geom;
+  const size_t V = gg.V;
   std::vector<double> qre((size_t)n_rhs, 0.0), qim((size_t)n_rhs, 0.0), rhs_relres((size_t)n_rhs, 0.0);
   std::vector<int> rhs_state((size_t)n_rhs, kPadding), rhs_iters((size_t)n_rhs, 0);
-  int64_t first_bad_rhs = -1;
-  tip_status bad_status = TIP_OK;
-  for (int64_t blk0 = 0; blk0 < n_rhs && first_bad_rhs < 0; blk0 += sv.pl.B) {
-    const int nb = (int)std::min<int64_t>(sv.pl.B, n_rhs - blk0);
-    s = sv.solve_block(p->m_begin * ncomp + blk0, nb);
-    if (s != TIP_OK) return s;
-    if (want_grad)
-      TIP_HIP(launch_grad_accum(sv.od64, h->geom, sv.pl.elem, sv.pl.logB, nb, sv.X, grad_mass, grad_coupling, sv.st));
-    for (int j = 0; j < nb; ++j) {
-      const size_t k = (size_t)(blk0 + j);
-      qre[k] = sv.h_q[2 * j];
-      qim[k] = sv.h_q[2 * j + 1];
-      rhs_state[k] = sv.h_state[j];
-      rhs_iters[k] = sv.h_iters[j];
-      rhs_relres[k] = std::sqrt(sv.h_relres2[j]);
-      if (sv.h_state[j] != kAccepted && first_bad_rhs < 0) {
-        first_bad_rhs = (int64_t)k;
-        bad_status = sv.h_state[j] == kBreakdown ? TIP_EBREAKDOWN : TIP_ENOCONV;
+  tip_stats acc_stats;
+  std::memset(&acc_stats, 0, sizeof acc_stats);
+  bool failed = false;
+  hipStream_t st_used = nullptr;
+  // Solve right-hand sides [r0, r1) in blocks: rhs r (lane rhs of the kernels)
+  // is result slot slot(r); stops at the first block holding a failed solve.
+  auto run_range = [&](Solver& sv, int64_t r0, int64_t r1, auto slot) -> tip_status {
+    for (int64_t blk0 = r0; blk0 < r1 && !failed; blk0 += sv.pl.B) {
+      const int nb = (int)std::min<int64_t>(sv.pl.B, r1 - blk0);
+      tip_status s2 = sv.solve_block(blk0, nb);
+      if (s2 != TIP_OK) return s2;
+      if (want_grad)
+        TIP_HIP(launch_grad_accum(sv.od64, gg, sv.pl.elem, sv.pl.logB, nb, sv.X, grad_mass, grad_coupling, sv.st));
+      for (int j = 0; j < nb; ++j) {
+        const size_t k = slot(blk0 + j);
+        qre[k] = sv.h_q[2 * j];
+        qim[k] = sv.h_q[2 * j + 1];
+        rhs_state[k] = sv.h_state[j];
+        rhs_iters[k] = sv.h_iters[j];
+        rhs_relres[k] = std::sqrt(sv.h_relres2[j]);
+        if (sv.h_state[j] != kAccepted) failed = true;
       }
     }
+    return TIP_OK;
+  };
+  auto add_stats = [&](const Solver& sv) {
+    tip_stats t;
+    std::memset(&t, 0, sizeof t);
+    sv.fill_stats(&t);
+    acc_stats.stencil_launches += t.stencil_launches;
+    acc_stats.stencil_seconds += t.stencil_seconds;
+    acc_stats.stencil_bytes += t.stencil_bytes;
+    acc_stats.matvecs += t.matvecs;
+    acc_stats.matvec_seconds += t.matvec_seconds;
+    acc_stats.matvec_bytes += t.matvec_bytes;
+    acc_stats.reliable_updates += t.reliable_updates;
+    acc_stats.restarts += t.restarts;
+    acc_stats.even_odd = acc_stats.even_odd || t.even_odd;
+  };
+  // Conjugate F_3 columns (Sec. 3.4, eq. Hperm-general-recursive): for a real
+  // operator and a real mask, probe column j3 = 2 of a sweep is the complex
+  // conjugate of column j3 = 1 (w^2 = conj w), so its quadrature is the
+  // conjugate of that one, and the j3 = 0 columns are real.  Then the j3 = 0
+  // probes are solved in real arithmetic, the j3 = 1 ones in complex, and the
+  // j3 = 2 ones take conj(q) of their partner probe m - 2^LB: half the work of
+  // complex solves for all of them.  Not with the gradient (it needs every x).
+  const int64_t nb_cols = int64_t(1) << gg.LB;
+  const bool split = gg.has3 && h->kind == TIP_KIND_SCALAR && (mask == TIP_MASK_Z2 || mask == TIP_MASK_NONE) &&
+                     p->probe == TIP_PROBE_HIERARCHICAL && !want_grad && p->n_vectors > nb_cols &&
+                     !env_off("TIP_CONJ_SPLIT");
+  std::vector<char> copied((size_t)n_rhs, 0);
+  if (!split) {
+    Solver sv;
+    sv.need_x = want_grad;
+    s = sv.setup(h, p, mask);
+    if (s != TIP_OK) return s;
+    st_used = sv.st;
+    if (grad_mass) TIP_HIP(launch_fill(V, grad_mass, 0.0, sv.st));
+    if (grad_coupling) TIP_HIP(launch_fill((size_t)gg.ndim * V, grad_coupling, 0.0, sv.st));
+    const int64_t base = p->m_begin * ncomp;
+    s = run_range(sv, base, base + n_rhs, [&](int64_t r) { return (size_t)(r - base); });
+    if (s != TIP_OK) return s;
+    add_stats(sv);
+  } else {
+    // each class of F_3 digit j3 numbers its probes i = 0, 1, ... (class_probe);
+    // the class members in [m_begin, n_vectors) have consecutive i
+    const int64_t gam = (int64_t)gg.gamma;
+    auto class_index = [&](int64_t m, int j3) { return (m / gam) * nb_cols + (m % gam - j3 * nb_cols); };
+    auto first_member = [&](int64_t m, int j3) {      // smallest member >= m
+      const int64_t r = m / gam, j = m % gam;
+      if (j < j3 * nb_cols) return r * gam + j3 * nb_cols;
+      if (j < (j3 + 1) * nb_cols) return m;
+      return (r + 1) * gam + j3 * nb_cols;
+    };
+    // each class runs up to its own first failure; the checkpoints then stop
+    // at the first probe, in probe order, that is not accepted
+    for (int pass = 0; pass < 2; ++pass) {
+      failed = false;
+      const int64_t m0 = first_member(p->m_begin, pass);
+      if (m0 >= p->n_vectors) continue;
+      const int64_t i0 = class_index(m0, pass);
+      const int64_t i1 = class_index(first_member(p->n_vectors, pass), pass);   // one past the last member
+      Solver sv;
+      sv.force_elem = pass;          // j3 = 0: real, j3 = 1: complex
+      sv.rhs_hint = (i1 - i0) * ncomp;
+      s = sv.setup(h, p, mask);
+      if (s != TIP_OK) return s;
+      sv.geom.cls_gamma = (int32_t)gam;
+      sv.geom.cls_nbc = (int32_t)nb_cols;
+      sv.geom.cls_j3 = pass;
+      st_used = sv.st;
+      s = run_range(sv, i0 * ncomp, i1 * ncomp, [&](int64_t r) {
+        const int64_t m = (int64_t)class_probe((uint64_t)(r / ncomp), sv.geom);
+        return (size_t)((m - p->m_begin) * ncomp + r % ncomp);
+      });
+      if (s != TIP_OK) return s;
+      add_stats(sv);
+    }
+    // j3 = 2: the conjugate of the partner's quadrature (and its state)
+    for (int64_t m = p->m_begin; m < p->n_vectors; ++m) {
+      if ((m % gam) / nb_cols != 2) continue;
+        for (int c = 0; c < ncomp; ++c) {
+          const size_t k = (size_t)((m - p->m_begin) * ncomp + c);
+          const int64_t mp = m - nb_cols;                   // same sweep, column j3 = 1
+          copied[k] = 1;
+          if (mp < p->m_begin) {                              // from the earlier call's quadratures
+            if (ncomp != 1) { rhs_state[k] = kNoConv; failed = true; continue; }
+            qre[k] = p->quadratures[2 * mp];
+            qim[k] = -p->quadratures[2 * mp + 1];
+            rhs_state[k] = kAccepted;
+            continue;
+          }
+          const size_t kp = (size_t)((mp - p->m_begin) * ncomp + c);
+          qre[k] = qre[kp];
+          qim[k] = -qim[kp];
+          rhs_state[k] = rhs_state[kp] == kPadding ? kNoConv : rhs_state[kp];
+          rhs_relres[k] = rhs_relres[kp];
+          if (rhs_state[k] != kAccepted) failed = true;
+        }
+    }
   }
+  int64_t first_bad_rhs = -1;
+  tip_status bad_status = TIP_OK;
+  for (int64_t k = 0; k < n_rhs; ++k)
+    if (rhs_state[(size_t)k] != kAccepted) {
+      first_bad_rhs = k;
+      bad_status = rhs_state[(size_t)k] == kBreakdown ? TIP_EBREAKDOWN : TIP_ENOCONV;
+      break;
+    }
 
   // ---- quadratures per probe, compensated sums, checkpoints ---------------
   const int64_t n = p->n_vectors;
@@ -1147,7 +1257,7 @@ tip_status run_probe(tip_op_handle h, const tip_params* p, double* estimates, do
     int64_t tot = 0;
     int mx_it = 0, solved = 0;
     for (int64_t k = 0; k < n_rhs; ++k) {
-      if (rhs_state[k] == kPadding) continue;
+      if (rhs_state[k] == kPadding || copied[(size_t)k]) continue;
       ++solved;
       tot += rhs_iters[k];
       mx_it = std::max(mx_it, rhs_iters[k]);
@@ -1160,14 +1270,25 @@ tip_status run_probe(tip_op_handle h, const tip_params* p, double* estimates, do
     stats->max_true_relres = mx_rr;
     // error of one quadrature: r^H A^-1 r <= ||r||^2 / lambda_min, ||b||^2 = V
     stats->max_quad_err_bound = mx_rr * mx_rr * (double)h->geom.V / h->lambda_lb;
-    sv.fill_stats(stats);
+    stats->stencil_launches = acc_stats.stencil_launches;
+    stats->stencil_seconds = acc_stats.stencil_seconds;
+    stats->stencil_bytes = acc_stats.stencil_bytes;
+    stats->matvecs = acc_stats.matvecs;
+    stats->matvec_seconds = acc_stats.matvec_seconds;
+    stats->matvec_bytes = acc_stats.matvec_bytes;
+    stats->reliable_updates = acc_stats.reliable_updates;
+    stats->restarts = acc_stats.restarts;
+    stats->even_odd = acc_stats.even_odd;
+    int64_t reused = 0;
+    for (char c : copied) reused += c ? 1 : 0;
+    stats->reused = reused;
     stats->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t_start).count();
   }
   if (want_grad && first_bad_rhs < 0) {
     const double f = -1.0 / (double)n;
-    if (grad_mass) TIP_HIP(launch_scale(V, grad_mass, f, sv.st));
-    if (grad_coupling) TIP_HIP(launch_scale((size_t)h->geom.ndim * V, grad_coupling, f, sv.st));
-    TIP_HIP(hipStreamSynchronize(sv.st));
+    if (grad_mass) TIP_HIP(launch_scale(V, grad_mass, f, st_used));
+    if (grad_coupling) TIP_HIP(launch_scale((size_t)h->geom.ndim * V, grad_coupling, f, st_used));
+    TIP_HIP(hipStreamSynchronize(st_used));
   }
   if (first_bad_rhs >= 0) {
     const int64_t bad_m = p->m_begin + first_bad_rhs / ncomp;

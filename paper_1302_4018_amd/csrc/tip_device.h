@@ -38,7 +38,18 @@ struct Geom {
   uint32_t gamma;            // colours of one sweep: 2^LB, times 3 with that level
   int32_t probe;             // probe kind of the call (ProbeKind)
   int32_t stop;              // stopped hierarchy: bit-levels of the colouring kept
+  // probe classes: with cls_gamma > 0 a call solves only the probes whose
+  // F_3 digit is cls_j3, numbered i = 0, 1, ...: probe(i) = (i / cls_nbc)
+  // cls_gamma + cls_j3 cls_nbc + i mod cls_nbc, with cls_nbc = 2^LB
+  int32_t cls_gamma, cls_nbc, cls_j3;
 };
+
+// The probe index of class-local probe i (identity without classes).
+__host__ __device__ inline uint64_t class_probe(uint64_t i, const Geom& g) {
+  if (g.cls_gamma == 0) return i;
+  const uint64_t nbc = (uint64_t)g.cls_nbc;
+  return (i / nbc) * (uint64_t)g.cls_gamma + (uint64_t)g.cls_j3 * nbc + i % nbc;
+}
 
 constexpr int kLdsPerCu = 160 * 1024;   // gfx950 LDS per CU
 constexpr int kNumXcd = 8;   // MI355X: 8 XCDs, each with its own L2

@@ -641,7 +641,8 @@ __global__ __launch_bounds__(kBlock) void k_direction(size_t n, int logB, const 
 
 // ---------------------------------------------------------------------------
 // Right-hand sides, initial state and the true residual.  Lane j of the block
-// is global right-hand side rhs0 + j: spatial probe m = (rhs0 + j) / ncomp,
+// is global right-hand side rhs0 + j: spatial probe m = (rhs0 + j) / ncomp
+// (through class_probe when the call solves one class of probes),
 // component c = (rhs0 + j) % ncomp.
 // ---------------------------------------------------------------------------
 
@@ -663,7 +664,7 @@ __device__ __forceinline__ void rhs_at(const Geom& g, uint32_t s, int64_t rhs0, 
   if (j >= nb) return;
   const int64_t rg = rhs0 + j;
   const int cj = (int)(rg % NC);
-  const T v = from_c<T>(probe_entry(s, (uint64_t)(rg / NC), cj, g, seed, mask));
+  const T v = from_c<T>(probe_entry(s, class_probe((uint64_t)(rg / NC), g), cj, g, seed, mask));
 #pragma unroll
   for (int c = 0; c < NC; ++c)
     if (c == cj) b[c] = v;
@@ -695,7 +696,7 @@ __global__ __launch_bounds__(kBlock) void k_true_residual(Geom g, TileMap tm, Op
                                                           int64_t rhs0, int nb, uint64_t seed, int mask,
                                                           const typename Op::T* __restrict__ x,
                                                           typename Op::T* __restrict__ r, typename Op::T* __restrict__ p,
-                                                          double* __restrict__ partial, size_t pstride, int eo) {
+                                                          double* __restrict__ partial, size_t pstride) {
   using T = typename Op::T;
   constexpr int NC = Op::NC;
   __shared__ double lds[3 * 4 * 64];
@@ -717,18 +718,8 @@ __global__ __launch_bounds__(kBlock) void k_true_residual(Geom g, TileMap tm, Op
       acc[1] += redot(b[c], xs[c]);
       acc[2] += imdot(b[c], xs[c]);
     }
-    if (!eo) {
-      store_vec<T, NC>(r, g.V, tm.logB, s, j, rt);
-      store_vec<T, NC>(p, g.V, tm.logB, s, j, rt);
-    } else if (((spatial_parity(s, g) + coord_p2(s, g, g.ndim - 1)) & 1u) == 0u) {
-      // even-odd solve: restart the reduced system from the even part (the
-      // odd part vanishes up to rounding when x_o was formed from x_e)
-      const int tdim = g.ndim - 1;
-      const uint32_t V3 = 1u << g.shift[tdim];
-      const uint32_t h = (s & (V3 - 1u)) + V3 * (coord_p2(s, g, tdim) >> 1);
-      store_vec<T, NC>(r, g.V >> 1, tm.logB, h, j, rt);
-      store_vec<T, NC>(p, g.V >> 1, tm.logB, h, j, rt);
-    }
+    store_vec<T, NC>(r, g.V, tm.logB, s, j, rt);
+    store_vec<T, NC>(p, g.V, tm.logB, s, j, rt);
   }
   seg_sum<3>(acc, B, lds);
   if ((int)threadIdx.x < B) {
@@ -926,7 +917,7 @@ __global__ __launch_bounds__(kBlock) void k_ru_residual(Geom g, TileMap tm, Op64
                                                         int64_t rhs0, int nb, uint64_t seed, int mask,
                                                         const typename Op64::T* __restrict__ x, T32* __restrict__ rh,
                                                         T32* __restrict__ ph, double* __restrict__ partial,
-                                                        size_t pstride, int eo) {
+                                                        size_t pstride) {
   using T = typename Op64::T;
   constexpr int NC = Op64::NC;
   if (mode == 0 && *sc.n_ru == 0) return;
@@ -953,17 +944,8 @@ __global__ __launch_bounds__(kBlock) void k_ru_residual(Geom g, TileMap tm, Op64
         acc[4] += imdot(xs[c], rt);
         r32[c] = to_single(rt);
       }
-      if (!eo) {
-        store_vec<T32, NC>(rh, g.V, tm.logB, s, j, r32);
-        if (mode == 1) store_vec<T32, NC>(ph, g.V, tm.logB, s, j, r32);
-      } else if (((spatial_parity(s, g) + coord_p2(s, g, g.ndim - 1)) & 1u) == 0u) {
-        // even-odd solve: the reduced system restarts from the even part
-        const int tdim = g.ndim - 1;
-        const uint32_t V3 = 1u << g.shift[tdim];
-        const uint32_t hh = (s & (V3 - 1u)) + V3 * (coord_p2(s, g, tdim) >> 1);
-        store_vec<T32, NC>(rh, g.V >> 1, tm.logB, hh, j, r32);
-        if (mode == 1) store_vec<T32, NC>(ph, g.V >> 1, tm.logB, hh, j, r32);
-      }
+      store_vec<T32, NC>(rh, g.V, tm.logB, s, j, r32);
+      if (mode == 1) store_vec<T32, NC>(ph, g.V, tm.logB, s, j, r32);
     }
   }
   seg_sum<5>(acc, B, lds);
@@ -1652,12 +1634,12 @@ hipError_t launch_stencil(const OpDev& od, const Geom& g, const TileMap& tm, con
 
 hipError_t launch_true_residual(const OpDev& od, const Geom& g, const TileMap& tm, Elem elem, const int* state,
                                 int64_t rhs0, int nb, uint64_t seed, int mask, const void* x, void* r, void* p,
-                                double* partial, size_t pstride, int eo, hipStream_t st) {
+                                double* partial, size_t pstride, hipStream_t st) {
   return dispatch64(od, elem, [&](auto op) {
     using Op = decltype(op);
     using T = typename Op::T;
     k_true_residual<Op><<<ru_grid(tm), kBlock, 0, st>>>(g, tm, op, od.mass_field, od.mass, od.coupling, state, rhs0, nb,
-                                                    seed, mask, (const T*)x, (T*)r, (T*)p, partial, pstride, eo);
+                                                    seed, mask, (const T*)x, (T*)r, (T*)p, partial, pstride);
   });
 }
 
@@ -1721,14 +1703,14 @@ hipError_t launch_ru_accumulate(size_t n, int logB, Elem elem, const CgScalars& 
 
 hipError_t launch_ru_residual(const OpDev& od64, const Geom& g, const TileMap& tm, Elem elem, const CgScalars& sc,
                               int mode, int64_t rhs0, int nb, uint64_t seed, int mask, const void* x64, void* rh,
-                              void* ph, double* partial, size_t pstride, int eo, hipStream_t st) {
+                              void* ph, double* partial, size_t pstride, hipStream_t st) {
   return dispatch64(od64, elem, [&](auto op) {
     using Op = decltype(op);
     using T = typename Op::T;
     using T32 = typename SingleOf<T>::type;
     k_ru_residual<Op, T32><<<ru_grid(tm), kBlock, 0, st>>>(g, tm, op, od64.mass_field, od64.mass, od64.coupling, sc, mode,
                                                        rhs0, nb, seed, mask, (const T*)x64, (T32*)rh, (T32*)ph,
-                                                       partial, pstride, eo);
+                                                       partial, pstride);
   });
 }
 

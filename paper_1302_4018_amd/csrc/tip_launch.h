@@ -117,7 +117,7 @@ hipError_t launch_stencil(const OpDev& op, const Geom& g, const TileMap& tm, con
                           hipStream_t st);
 hipError_t launch_true_residual(const OpDev& op, const Geom& g, const TileMap& tm, Elem elem, const int* state,
                                 int64_t rhs0, int nb, uint64_t seed, int mask, const void* x, void* r, void* p,
-                                double* partial, size_t pstride, int eo, hipStream_t st);
+                                double* partial, size_t pstride, hipStream_t st);
 hipError_t launch_init(const Geom& g, Elem elem, int logB, int64_t rhs0, int nb, uint64_t seed, int mask, void* x,
                        void* r, void* p, hipStream_t st);
 // Workgroups of the update pass (= partials per right-hand side).
@@ -135,7 +135,7 @@ hipError_t launch_ru_accumulate(size_t n, int logB, Elem elem, const CgScalars& 
                                 hipStream_t st);
 hipError_t launch_ru_residual(const OpDev& od64, const Geom& g, const TileMap& tm, Elem elem, const CgScalars& sc,
                               int mode, int64_t rhs0, int nb, uint64_t seed, int mask, const void* x64, void* rh,
-                              void* ph, double* partial, size_t pstride, int eo, hipStream_t st);
+                              void* ph, double* partial, size_t pstride, hipStream_t st);
 hipError_t launch_reduce_ru(const CgScalars& sc, int B, const double* partial, int gx, size_t pstride, int mode,
                             double tol2, int max_iter, int max_restarts, hipStream_t st,
                             const double* partial2 = nullptr);

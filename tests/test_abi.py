@@ -49,7 +49,7 @@ int main(void) {
   P(tip_params, stop_levels)
   P(tip_stats, max_true_relres) P(tip_stats, stencil_launches) P(tip_stats, stencil_bytes)
   P(tip_stats, reliable_updates) P(tip_stats, max_quad_err_bound) P(tip_stats, matvecs)
-  P(tip_stats, matvec_seconds) P(tip_stats, matvec_bytes) P(tip_stats, even_odd) P(tip_stats, restarts)
+  P(tip_stats, matvec_seconds) P(tip_stats, matvec_bytes) P(tip_stats, even_odd) P(tip_stats, restarts) P(tip_stats, reused)
   return 0;
 }
 """)

@@ -78,3 +78,56 @@ def test_gradient_on_an_odd_torus():
     assert abs(est[-1] - T) <= REL * abs(T)
     for a, b in ((gm.cpu().numpy(), gm_o), (gw.cpu().numpy(), gw_o)):
         assert np.sum(np.abs(a - b)) <= 4 * kappa * 1e-12 * np.sum(np.abs(b))
+
+
+def _no_split(tip, fn):
+    import os
+    os.environ["TIP_CONJ_SPLIT"] = "0"
+    try:
+        return fn()
+    finally:
+        del os.environ["TIP_CONJ_SPLIT"]
+
+
+@pytest.mark.parametrize("dims,n,prec,reused", [
+    ([12, 5, 8], 9, "fp64", 3),      # gamma = 3: probes 2, 5, 8 are conjugates of 1, 4, 7
+    ([6, 10], 60, "fp64", 20),       # gamma = 12: columns 8..11 of each of 5 sweeps
+    ([6, 10], 60, "mixed", 20),
+])
+def test_conjugate_f3_columns_reuse_their_partner(dims, n, prec, reused):
+    """Real operator, Z2 mask: column j3 = 2 is the conjugate of column j3 = 1,
+    so its quadrature is conj(q) of probe m - 2^LB and is not solved; j3 = 0
+    probes run in real arithmetic.  Same estimates as solving every probe."""
+    tip = gpu_binding()
+    w = inputs.couplings(dims, seed=520)
+    mf = inputs.mass_field(dims, m0=0.2, seed=521)
+    orc = OracleOp(dims, 0, mass_field=mf, coupling=w)
+    gop = tip.Operator(dims, 0, mass_field=to_dev(mf), coupling=to_dev(w))
+    precision = tip.PREC_MIXED if prec == "mixed" else tip.PREC_FP64
+    print(f"conjugate split: dims {dims} n {n} {prec}", flush=True)
+    est, q, st = tip.trace_inv_probe(gop, n, 1e-12, 4018, mask=MASK_Z2, precision=precision)
+    est_a, q_a, st_a = _no_split(tip, lambda: tip.trace_inv_probe(gop, n, 1e-12, 4018, mask=MASK_Z2,
+                                                                   precision=precision))
+    assert st["reused"] == reused and st["solves"] == n - reused
+    assert st_a["reused"] == 0 and st_a["solves"] == n
+    assert np.max(np.abs(q - q_a) / np.abs(q_a)) <= 1e-10
+    assert np.max(np.abs(est - est_a) / np.abs(est_a)) <= 1e-12
+    est_o, q_o, _ = general.trace_inv_probe(orc, n, 1e-12, 4018, MASK_Z2)
+    assert np.max(np.abs(est - est_o) / np.abs(est_o)) <= REL
+    assert np.max(np.abs(q - q_o) / np.abs(q_o)) <= REL
+
+
+def test_conjugate_reuse_across_a_resumed_run():
+    """m_begin = 30 on [6, 10] (gamma = 12): probes 32..35 take the conjugates of
+    28..31, two of which come from the earlier call's quadratures."""
+    tip = gpu_binding()
+    dims = [6, 10]
+    w = inputs.couplings(dims, seed=530)
+    gop = tip.Operator(dims, 0, mass=0.3, coupling=to_dev(w))
+    est, q, st = tip.trace_inv_probe(gop, 60, 1e-12, 7, mask=MASK_Z2)
+    est1, q1, _ = tip.trace_inv_probe(gop, 30, 1e-12, 7, mask=MASK_Z2)
+    est2, q2, st2 = tip.trace_inv_probe(gop, 60, 1e-12, 7, mask=MASK_Z2, m_begin=30, quadratures=q1)
+    assert np.array_equal(q2[:30], q1)
+    assert np.max(np.abs(q2 - q) / np.abs(q)) <= 1e-10
+    assert np.max(np.abs(est2 - est) / np.abs(est)) <= 1e-12
+    assert st2["reused"] == 12
