@@ -160,6 +160,9 @@ def bench_c4(args):
         ops.append(tip.Operator(t["dims"], tip.KIND_SCALAR, mass=t["mass"], coupling=w))
     ns = [t["n_vectors"] for t in tori]
     total = sum(ns)
+    if args.sequential:
+        bench_c4_sequential(args, tip, ops, ns)
+        return
     res = {}
     for name, prec in (("mixed", tip.PREC_MIXED), ("fp64", tip.PREC_FP64)):
         # timed steps without per-kernel events, so that iteration chunks replay
@@ -202,6 +205,36 @@ def bench_c4(args):
            "cpu_baseline": None,
            "fp64": {"value": round(res["fp64"][0], 2), "ms_per_step": round(res["fp64"][1] / args.steps * 1e3, 2)}}
     print(json.dumps(out), flush=True)
+
+
+def bench_c4_sequential(args, tip, ops, ns):
+    """The same tori one after another on the calling thread (one
+    trace_inv_probe per torus, mixed precision): the form a kernel trace can
+    follow.  Prints one JSON line."""
+    import torch
+    handles = [tip.OpHandle(op) for op in ops]
+    for _ in range(args.warmup):
+        for h, n in zip(handles, ns):
+            h.trace_inv_probe(n, args.tol, args.seed, mask=tip.MASK_Z2, precision=tip.PREC_MIXED)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    quads = solves = 0
+    for _ in range(args.steps):
+        for h, n in zip(handles, ns):
+            _, _, st = h.trace_inv_probe(n, args.tol, args.seed, mask=tip.MASK_Z2, precision=tip.PREC_MIXED)
+            quads += n
+            solves += st["solves"]
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    for h in handles:
+        h.close()
+    print(json.dumps({"metric": "probe quadratures/sec, 64 uneven 3-D tori one after another (one thread)",
+                      "value": round(quads / el, 1), "unit": "quadratures/s", "n_gpus": 1, "steps": args.steps,
+                      "warmup": args.warmup, "ms_per_step": round(el / args.steps * 1e3, 2),
+                      "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+                      "dtype": "f32 CG + f64 reliable updates", "data": "synthetic",
+                      "config": {"workload": "64 independent 3-D tori, sides iid U{8..48}, sequential",
+                                 "solves_per_s": round(solves / el, 1)}}), flush=True)
 
 
 def bench_compare(args):
@@ -447,6 +480,8 @@ def main():
                          "with a closed-form trace; study: the experiments of Sec. 5 (stopped levels, three "
                          "lattices and condition numbers, variance over 100 masks)")
     ap.add_argument("--masks", type=int, default=4, help="compare / study B: masks averaged per probe kind")
+    ap.add_argument("--sequential", action="store_true",
+                    help="c4: solve the tori one after another on one thread instead of the batch call")
     ap.add_argument("--study", default="A,B,C", help="study: parts to run (A stopped levels, B lattices x "
                     "condition numbers, C variance over masks)")
     ap.add_argument("--variance-masks", type=int, default=100, help="study C: masks")
