@@ -734,8 +734,18 @@ __global__ __launch_bounds__(kBlock) void k_true_residual(Geom g, TileMap tm, Op
 
 __device__ __forceinline__ double sum_partials(const double* __restrict__ part, int n) {
   __shared__ double lds[4];
-  double v[1] = {0.0};
-  for (int i = threadIdx.x; i < n; i += kBlock) v[0] += part[i];
+  // four independent running sums keep four loads in flight per thread; the
+  // order of the additions is fixed, so the result is reproducible
+  double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+  int i = threadIdx.x;
+  for (; i + 3 * kBlock < n; i += 4 * kBlock) {
+    a0 += part[i];
+    a1 += part[i + kBlock];
+    a2 += part[i + 2 * kBlock];
+    a3 += part[i + 3 * kBlock];
+  }
+  for (; i < n; i += kBlock) a0 += part[i];
+  double v[1] = {(a0 + a1) + (a2 + a3)};
   block_sum<1>(v, lds);
   return v[0];
 }
