@@ -587,6 +587,9 @@ __global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(TIP_MARC
 // r -= alpha w for active right-hand sides; partial = ||r||^2.  Grid-stride:
 // the stride is a multiple of 256, so a thread always meets the same rhs and
 // the number of partials per rhs is the (moderate) grid size.
+#ifndef TIP_UPD_UNROLL
+#define TIP_UPD_UNROLL 4
+#endif
 template <class T>
 __global__ __launch_bounds__(kBlock) void k_update_r(size_t n, int logB, const CgScalars sc, T* __restrict__ r,
                                                      const T* __restrict__ Ap, double* __restrict__ partial) {
@@ -598,15 +601,16 @@ __global__ __launch_bounds__(kBlock) void k_update_r(size_t n, int logB, const C
     const double a = sc.alpha[j];
     const size_t stride = (size_t)gridDim.x * kBlock;
     size_t i = (size_t)blockIdx.x * kBlock + threadIdx.x;
-    for (; i + 3 * stride < n; i += 4 * stride) {      // four independent loads in flight
-      T rr[4], ww[4];
+    constexpr int U = TIP_UPD_UNROLL;
+    for (; i + (U - 1) * stride < n; i += U * stride) {      // U independent loads in flight
+      T rr[U], ww[U];
 #pragma unroll
-      for (int k = 0; k < 4; ++k) {
+      for (int k = 0; k < U; ++k) {
         rr[k] = r[i + k * stride];
         ww[k] = Ap[i + k * stride];
       }
 #pragma unroll
-      for (int k = 0; k < 4; ++k) {
+      for (int k = 0; k < U; ++k) {
         rr[k] = axpy(-a, ww[k], rr[k]);
         r[i + k * stride] = rr[k];
         acc[0] += norm2(rr[k]);
@@ -1665,7 +1669,14 @@ hipError_t launch_init(const Geom& g, Elem elem, int logB, int64_t rhs0, int nb,
   return hipGetLastError();
 }
 
-unsigned update_grid(size_t n) { return std::min<unsigned>(cdiv(n, kBlock), 8192u); }
+// workgroups of the grid-stride update pass: more spread the 3-vector stream
+// better, but the reduction after it reads one partial per workgroup and rhs
+// (32^4 covariant, k_update_r + k_reduce_beta: 487 us at 8192, 466 at 32768,
+// 479 at 65536)
+#ifndef TIP_UPD_GRID
+#define TIP_UPD_GRID 32768u
+#endif
+unsigned update_grid(size_t n) { return std::min<unsigned>(cdiv(n, kBlock), TIP_UPD_GRID); }
 unsigned ru_grid(const TileMap& tm) { return std::min<unsigned>(tm.grid, 4096u); }
 
 hipError_t launch_update_r(size_t n, int logB, Elem elem, Prec prec, const CgScalars& sc, void* r, const void* Ap,
@@ -1703,7 +1714,9 @@ hipError_t launch_init_mixed(const Geom& g, Elem elem, int logB, int64_t rhs0, i
 
 hipError_t launch_ru_accumulate(size_t n, int logB, Elem elem, const CgScalars& sc, int mode, void* x64, void* xh,
                                 hipStream_t st) {
-  const unsigned grid = update_grid(n);
+  // launched every iteration and returning at once while no update is
+  // pending: a smaller grid than the update pass keeps that cheap
+  const unsigned grid = std::min<unsigned>(cdiv(n, kBlock), 8192u);
   if (elem == Elem::kReal)
     k_ru_accumulate<double, float><<<grid, kBlock, 0, st>>>(n, logB, sc, mode, (double*)x64, (float*)xh);
   else
