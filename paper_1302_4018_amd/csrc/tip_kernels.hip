@@ -1767,11 +1767,14 @@ hipError_t launch_eo_hop(int mode, const OpDev& od, const Geom& g, const MarchMa
     switch (mode) {
       case 0: b32 ? go(k_eo_hop<Op, 0, 5>) : go(k_eo_hop<Op, 0, -1>); break;
       case 1: b32 ? go(k_eo_hop<Op, 1, 5>) : go(k_eo_hop<Op, 1, -1>); break;
-      case 2: go(k_eo_hop<Op, 2, -1>); break;
-      case 3: go(k_eo_hop<Op, 3, -1>); break;
-      case 5: go(k_eo_hop<Op, 5, -1>); break;
+      case 2: b32 ? go(k_eo_hop<Op, 2, 5>) : go(k_eo_hop<Op, 2, -1>); break;
+      case 3: b32 ? go(k_eo_hop<Op, 3, 5>) : go(k_eo_hop<Op, 3, -1>); break;
+      case 5: b32 ? go(k_eo_hop<Op, 5, 5>) : go(k_eo_hop<Op, 5, -1>); break;
       default:
-        if constexpr (sizeof(typename SingleOf<T>::type) * 2 == sizeof(T)) go(k_eo_hop<Op, 4, -1>);
+        if constexpr (sizeof(typename SingleOf<T>::type) * 2 == sizeof(T)) {
+          if (b32) go(k_eo_hop<Op, 4, 5>);
+          else go(k_eo_hop<Op, 4, -1>);
+        }
         break;
     }
   });
