@@ -93,15 +93,23 @@ enum { TIP_KIND_SCALAR = 0, TIP_KIND_COVARIANT = 1 };
 enum { TIP_MASK_DEFAULT = -1, TIP_MASK_NONE = 0, TIP_MASK_Z2 = 1, TIP_MASK_Z4 = 2 };
 /* Precision of the CG solves.  FP64: vectors, links and arithmetic in FP64.
  * MIXED: CG vectors and links stored and combined in FP32, with FP64 kept for
- * the solution x, the CG scalars, reliable updates (the residual recomputed
- * from x with the FP64 operator whenever the FP32 residual has fallen by
- * reliable_delta; Sleijpen & van der Vorst 1996) and the final true-residual
- * test, so a solve is accepted on the same FP64 criterion as in FP64 mode.
+ * the solution x, the CG scalars, reliable updates (the FP32 correction folded
+ * into x and the residual recomputed from x with the FP64 operator; Sleijpen &
+ * van der Vorst 1996) and the final true-residual test, so a solve is
+ * accepted on the same FP64 criterion as in FP64 mode.  An update is made
+ * when a bound on the drift of the FP32 residual from b - A x, accumulated
+ * from the CG scalars (van der Vorst & Ye 2000), passes 2^-5 of the residual
+ * norm, and also, if reliable_delta > 0, when the residual has fallen by
+ * reliable_delta since the last update.  The drift bound grows with
+ * ||A|| ||x_h||, so ill-conditioned operators get the updates they need:
+ * free fields at condition numbers 1e4, 1e5 and 1e6 converge to 1e-10 with
+ * 1.3x, 1.9x and 3.1x the FP64 iteration count.  FP32 pays on the
+ * well-conditioned end (the 32^4 covariant workload: 12 iterations either
+ * way, one update per solve).
  * In MIXED a single-precision p^H A p <= 0 (rounding on a badly conditioned
  * operator) is not a breakdown: the solve goes to the FP64 check and restarts
  * from the FP64 residual (counted in tip_stats.restarts; TIP_ENOCONV once the
- * restart budget is spent).  FP32 CG suits condition numbers up to about
- * 1e5; beyond that FP64 converges in fewer iterations.
+ * restart budget is spent).
  * MIXED reports the variational quadrature 2 Re(b^H x) - x^H A x = b^H x + x^H r,
  * whose error r^H A^-1 r <= ||r||^2 / lambda_min is second order in the
  * residual. */
@@ -156,8 +164,9 @@ typedef struct {
                            entries [0, m_begin) must hold the q_m of an earlier call
                            (same operator, seed, mask) and are read: this resumes a
                            run, reusing earlier levels' quadratures.                */
-  double reliable_delta; /* MIXED: reliable update when the FP32 residual norm has
-                            fallen by this factor since the last one; 0 = 1e-3     */
+  double reliable_delta; /* MIXED: also update when the FP32 residual norm has
+                            fallen by this factor since the last update; 0 = the
+                            drift bound alone                                      */
   int32_t probe;         /* TIP_PROBE_*; 0 = hierarchical                           */
   int32_t round_tiles;   /* 4-D power-of-two lattices: stencil tiles per XCD round of the
                             workgroup order (0 = library choice; see tip_autotune) */

@@ -510,7 +510,7 @@ struct Solver {
   int64_t rhs_hint = 0;         // > 0: right-hand sides of this pass (bounds the block size when rhs_block = 0)
   Prec prec = Prec::kF64;
   int max_iter, max_restarts = 8;
-  double tol2, delta2 = 0.0;
+  double tol2, delta2 = 0.0, ru_eps = 0.0, ru_tau2 = 0.0;
   double freeze2;               // recursive-residual freeze threshold (tol2 unless TIP_FREEZE_SLACK)
   int force_breakdown = 0;      // TIP_FORCE_BREAKDOWN = k (tests): iteration k of a fresh solve breaks down
   size_t vbytes, vbytes64, pstride, nscal, nelem, nvec;
@@ -629,10 +629,14 @@ struct Solver {
       if (f > 1.0 && std::isfinite(f)) freeze2 = tol2 * f * f;
     }
     if (mixed) {
-      // 1e-3: measured on the 32^4 workload to need no more iterations than
-      // 1e-2 with a third fewer FP64 updates (the acceptance test is FP64 either way)
-      const double d = p->reliable_delta > 0.0 ? p->reliable_delta : 1e-3;
-      delta2 = d * d;
+      // residual replacement once the drift bound passes tau ||r||, tau = 2^-5.
+      // Measured against tau = 2^-12 (sqrt of the unit roundoff) and 2^-8: at
+      // 32^4 one FP64 update per solve instead of two (1308 against 1204
+      // solves/s), and on free fields at kappa 1e4..1e6 no restarts and at most
+      // 4% more iterations.
+      ru_eps = 0x1p-24;
+      ru_tau2 = 0x1p-10;
+      delta2 = p->reliable_delta * p->reliable_delta;
     }
 
     nelem = (size_t)B * ncomp * V;
@@ -657,7 +661,7 @@ struct Solver {
     // even-odd true residual
     if (const hipError_t e_ = h->partial.ensure(10 * pstride * sizeof(double)); e_ != hipSuccess)
       return fail(TIP_ENOMEM, "hipMalloc partials: %s", hipGetErrorString(e_));
-    const size_t scal_bytes = nscal * (9 * sizeof(double) + 4 * sizeof(int)) + 128 + kMaxChunk * sizeof(int);
+    const size_t scal_bytes = nscal * (13 * sizeof(double) + 4 * sizeof(int)) + 128 + kMaxChunk * sizeof(int);
     if (const hipError_t e_ = h->scal.ensure(scal_bytes); e_ != hipSuccess)
       return fail(TIP_ENOMEM, "hipMalloc scalars: %s", hipGetErrorString(e_));
     const size_t host_bytes = nscal * (3 * sizeof(double) + 3 * sizeof(int)) + 128 + kMaxChunk * sizeof(int);
@@ -721,7 +725,11 @@ struct Solver {
     sc.bnorm2 = d + 5 * nscal;
     sc.relres2 = d + 6 * nscal;
     sc.q = d + 7 * nscal;            // 2 * nscal
-    int* iv = (int*)(d + 9 * nscal);
+    sc.pp = d + 9 * nscal;
+    sc.anorm = d + 10 * nscal;
+    sc.xhn = d + 11 * nscal;
+    sc.dev = d + 12 * nscal;
+    int* iv = (int*)(d + 13 * nscal);
     sc.state = iv;
     sc.iters = iv + nscal;
     sc.restarts = iv + 2 * nscal;
@@ -829,7 +837,8 @@ struct Solver {
     if (tv) TIP_HIP(hipEventRecord(tv->c, st));
     TIP_HIP(launch_reduce_alpha(sc, pl.B, part, gx_m, st, mixed ? 1 : 0, force_breakdown));
     TIP_HIP(launch_update_r(nvec, pl.logB, pl.elem, prec, sc, Rv, W, part + pstride, st));
-    TIP_HIP(launch_reduce_beta(sc, pl.B, part + pstride, gx_u, tol2, max_iter, delta2, st, freeze2));
+    TIP_HIP(launch_reduce_beta(sc, pl.B, part + pstride, gx_u, tol2, max_iter, delta2, st, freeze2, ru_eps,
+                               ru_tau2));
     TIP_HIP(launch_direction(nvec, pl.logB, pl.elem, prec, sc, xdir, Rv, Pv, st));
     if (mixed) {
       tip_status s = reliable(rhs0, nb, 0);

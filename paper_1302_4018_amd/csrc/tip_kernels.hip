@@ -778,6 +778,10 @@ __global__ void k_scalars_init(CgScalars sc, int nb, int B, double bnorm2, int s
   sc.xalpha[j] = 0.0;
   sc.beta[j] = 0.0;
   sc.rho_ref[j] = valid ? bnorm2 : 0.0;
+  sc.pp[j] = valid ? bnorm2 : 0.0;
+  sc.anorm[j] = 0.0;
+  sc.xhn[j] = 0.0;
+  sc.dev[j] = 0.0;
   sc.ru[j] = 0;
   sc.iters[j] = 0;
   sc.restarts[j] = 0;
@@ -805,13 +809,29 @@ __global__ __launch_bounds__(kBlock) void k_reduce_alpha(CgScalars sc, const dou
     return;
   }
   sc.alpha[j] = sc.rho[j] / pAp;
+  const double pp = sc.pp[j];
+  if (pp > 0.0) sc.anorm[j] = fmax(sc.anorm[j], pAp / pp);
 }
 
 // rho' = ||r||^2; beta = rho'/rho; freeze on the recursive residual, or stop
 // at max_iter.  xalpha = the x update the direction pass applies this
 // iteration (alpha for a rhs that iterated, 0 otherwise).
+//
+// Mixed precision (eps = the single-precision unit roundoff; 0 in FP64): the
+// gap between the true residual b - A x and the recursive r grows by the
+// rounding of x_h += alpha p and of r -= alpha A p.  Following van der Vorst &
+// Ye (SIAM J. Sci. Comput. 22 (2000) 835) it is bounded from scalars CG
+// already has, d += eps (||A|| (||x_h|| + |alpha| ||p||) + ||r|| + ||r'||), with
+// ||A|| estimated by the largest Rayleigh quotient, ||p||^2 by its recurrence
+// and ||x_h|| <= sum |alpha| ||p||.  A reliable update (residual replacement)
+// is asked for once d^2 > tau2 ||r'||^2, so the recursive residual stays
+// within a factor 1 +- sqrt(tau2) of the true one, and (delta2 > 0) also
+// when ||r'||^2 has fallen by delta2 since the last update.  An isolated small
+// eigenvalue makes ||x_h|| large: the bound then asks for updates often,
+// where a fixed factor would let r drift off b - A x and CG stall.
 __global__ __launch_bounds__(kBlock) void k_reduce_beta(CgScalars sc, const double* __restrict__ partial, int gx,
-                                                        double tol2, int max_iter, double delta2, double first2) {
+                                                        double tol2, int max_iter, double delta2, double first2,
+                                                        double eps, double tau2) {
   const int j = blockIdx.x;
   if (sc.state[j] != kActive) {                // uniform per workgroup
     if (threadIdx.x == 0) sc.xalpha[j] = 0.0;
@@ -819,11 +839,21 @@ __global__ __launch_bounds__(kBlock) void k_reduce_beta(CgScalars sc, const doub
   }
   const double rho_new = sum_partials(partial + (size_t)j * gx, gx);
   if (threadIdx.x != 0) return;
-  sc.xalpha[j] = sc.alpha[j];
+  const double alpha = sc.alpha[j];
+  sc.xalpha[j] = alpha;
   const int it = sc.iters[j] + 1;
   sc.iters[j] = it;
-  sc.beta[j] = rho_new / sc.rho[j];
+  const double rho_old = sc.rho[j];
+  const double beta = rho_new / rho_old;
+  sc.beta[j] = beta;
   sc.rho[j] = rho_new;
+  const double pp = sc.pp[j];
+  const double step = fabs(alpha) * sqrt(pp);
+  const double xh = sc.xhn[j] + step;
+  const double dev = sc.dev[j] + eps * (sc.anorm[j] * (xh + step) + sqrt(rho_old) + sqrt(rho_new));
+  sc.xhn[j] = xh;
+  sc.dev[j] = dev;
+  sc.pp[j] = rho_new + beta * beta * pp;
   if (!isfinite(rho_new)) {
     sc.state[j] = kBreakdown;
     atomicSub(sc.active, 1);
@@ -833,7 +863,7 @@ __global__ __launch_bounds__(kBlock) void k_reduce_beta(CgScalars sc, const doub
   } else if (it >= max_iter) {
     sc.state[j] = kNoConv;
     atomicSub(sc.active, 1);
-  } else if (rho_new < delta2 * sc.rho_ref[j] && sc.ru[j] == 0) {
+  } else if (sc.ru[j] == 0 && (dev * dev > tau2 * rho_new || rho_new < delta2 * sc.rho_ref[j])) {
     sc.ru[j] = 1;                              // ask for a reliable update
     atomicAdd(sc.n_ru, 1);
   }
@@ -859,6 +889,7 @@ __global__ __launch_bounds__(kBlock) void k_reduce_true(CgScalars sc, const doub
   } else if (sc.restarts[j] < max_restarts && sc.iters[j] < max_iter && isfinite(rt2)) {
     sc.state[j] = kActive;
     sc.rho[j] = rt2;
+    sc.pp[j] = rt2;                            // p = r
     sc.restarts[j] += 1;
     atomicAdd(sc.active, 1);
   } else {
@@ -987,6 +1018,8 @@ __global__ __launch_bounds__(kBlock) void k_reduce_ru(CgScalars sc, const double
     sc.ru[j] = 0;
     atomicSub(sc.n_ru, 1);
   }
+  sc.xhn[j] = 0.0;                             // x_h is in x now; r is the true residual
+  sc.dev[j] = 0.0;
   if (mode == 0) {
     sc.rho[j] = rt2;
     sc.rho_ref[j] = rt2;
@@ -1002,6 +1035,7 @@ __global__ __launch_bounds__(kBlock) void k_reduce_ru(CgScalars sc, const double
     sc.state[j] = kActive;
     sc.rho[j] = rt2;
     sc.rho_ref[j] = rt2;
+    sc.pp[j] = rt2;                            // p = r
     sc.restarts[j] += 1;
     atomicAdd(sc.active, 1);
   } else {
@@ -1543,6 +1577,7 @@ __global__ __launch_bounds__(kBlock) void k_reduce_rho0(CgScalars sc, const doub
   if (threadIdx.x != 0) return;
   sc.rho[j] = v;
   sc.rho_ref[j] = v;
+  sc.pp[j] = v;                                // p = r
 }
 
 size_t march_lds_bytes(const Geom& g, const MarchMap& mm, Prec prec) {
@@ -1858,8 +1893,9 @@ hipError_t launch_reduce_alpha(const CgScalars& sc, int B, const double* partial
 }
 
 hipError_t launch_reduce_beta(const CgScalars& sc, int B, const double* partial, int gx, double tol2, int max_iter,
-                              double delta2, hipStream_t st, double first2) {
-  k_reduce_beta<<<B, kBlock, 0, st>>>(sc, partial, gx, tol2, max_iter, delta2, first2 > 0.0 ? first2 : tol2);
+                              double delta2, hipStream_t st, double first2, double eps, double tau2) {
+  k_reduce_beta<<<B, kBlock, 0, st>>>(sc, partial, gx, tol2, max_iter, delta2, first2 > 0.0 ? first2 : tol2, eps,
+                                      tau2);
   return hipGetLastError();
 }
 

@@ -32,6 +32,10 @@ struct CgScalars {
   double* xalpha;              // x update the direction pass applies this iteration
   double* beta;
   double* rho_ref;             // residual norm^2 at the last reliable update (mixed precision)
+  double* pp;                  // ||p||^2 by the recurrence ||r'||^2 + beta^2 ||p||^2
+  double* anorm;               // largest Rayleigh quotient p^H A p / ||p||^2 seen (estimate of ||A||)
+  double* xhn;                 // bound on ||x_h||, the single-precision x since the last update
+  double* dev;                 // bound on ||(b - A x) - r|| accumulated since the last update
   double* bnorm2;
   double* relres2;
   double* q;
@@ -164,9 +168,11 @@ hipError_t launch_scalars_init(const CgScalars& sc, int nb, int B, double bnorm2
 // soft: freeze instead of failing on p^H A p <= 0 (mixed precision); force_iter: test hook
 hipError_t launch_reduce_alpha(const CgScalars& sc, int B, const double* partial, int gx, hipStream_t st,
                                int soft = 0, int force_iter = 0);
-// first2 > 0: freeze threshold for solves not yet restarted (tol2 otherwise)
+// first2 > 0: freeze threshold for solves not yet restarted (tol2 otherwise);
+// eps, tau2: residual-replacement bound of mixed precision (eps = 0 turns it off)
 hipError_t launch_reduce_beta(const CgScalars& sc, int B, const double* partial, int gx, double tol2, int max_iter,
-                              double delta2, hipStream_t st, double first2 = 0.0);
+                              double delta2, hipStream_t st, double first2 = 0.0, double eps = 0.0,
+                              double tau2 = 0.0);
 hipError_t launch_reduce_true(const CgScalars& sc, int B, const double* partial, int gx, size_t pstride, double tol2,
                               int max_iter, int max_restarts, hipStream_t st, const double* partial2 = nullptr);
 hipError_t launch_hier_perm(const Geom& g, uint32_t* out, hipStream_t st);
