@@ -800,17 +800,17 @@ __global__ __launch_bounds__(kBlock) void k_reduce_alpha(CgScalars sc, const dou
                                                          int soft, int force_iter) {
   const int j = blockIdx.x;
   if (*sc.active == 0 || sc.state[j] != kActive) return;     // uniform per workgroup
+  const double rho = sc.rho[j], pp = sc.pp[j], anorm = sc.anorm[j];
+  const bool forced = force_iter > 0 && sc.restarts[j] == 0 && sc.iters[j] + 1 == force_iter;
   const double pAp = sum_partials(partial + (size_t)j * gx, gx);
   if (threadIdx.x != 0) return;
-  const bool forced = force_iter > 0 && sc.restarts[j] == 0 && sc.iters[j] + 1 == force_iter;
   if (!(pAp > 0.0) || !isfinite(pAp) || forced) {
     sc.state[j] = soft ? kFrozen : kBreakdown;
     atomicSub(sc.active, 1);
     return;
   }
-  sc.alpha[j] = sc.rho[j] / pAp;
-  const double pp = sc.pp[j];
-  if (pp > 0.0) sc.anorm[j] = fmax(sc.anorm[j], pAp / pp);
+  sc.alpha[j] = rho / pAp;
+  if (pp > 0.0) sc.anorm[j] = fmax(anorm, pAp / pp);
 }
 
 // rho' = ||r||^2; beta = rho'/rho; freeze on the recursive residual, or stop
@@ -837,33 +837,35 @@ __global__ __launch_bounds__(kBlock) void k_reduce_beta(CgScalars sc, const doub
     if (threadIdx.x == 0) sc.xalpha[j] = 0.0;
     return;
   }
+  // the lane's scalars are read before the reduction, so their latency
+  // overlaps it (uniform addresses: one load per wave)
+  const double alpha = sc.alpha[j], rho_old = sc.rho[j], pp = sc.pp[j];
+  const double xh0 = sc.xhn[j], dev0 = sc.dev[j], anorm = sc.anorm[j];
+  const double rho_ref = sc.rho_ref[j], bnorm2 = sc.bnorm2[j];
+  const int it = sc.iters[j] + 1, restarted = sc.restarts[j], flagged = sc.ru[j];
   const double rho_new = sum_partials(partial + (size_t)j * gx, gx);
   if (threadIdx.x != 0) return;
-  const double alpha = sc.alpha[j];
   sc.xalpha[j] = alpha;
-  const int it = sc.iters[j] + 1;
   sc.iters[j] = it;
-  const double rho_old = sc.rho[j];
   const double beta = rho_new / rho_old;
   sc.beta[j] = beta;
   sc.rho[j] = rho_new;
-  const double pp = sc.pp[j];
   const double step = fabs(alpha) * sqrt(pp);
-  const double xh = sc.xhn[j] + step;
-  const double dev = sc.dev[j] + eps * (sc.anorm[j] * (xh + step) + sqrt(rho_old) + sqrt(rho_new));
+  const double xh = xh0 + step;
+  const double dev = dev0 + eps * (anorm * (xh + step) + sqrt(rho_old) + sqrt(rho_new));
   sc.xhn[j] = xh;
   sc.dev[j] = dev;
   sc.pp[j] = rho_new + beta * beta * pp;
   if (!isfinite(rho_new)) {
     sc.state[j] = kBreakdown;
     atomicSub(sc.active, 1);
-  } else if (rho_new <= (sc.restarts[j] == 0 ? first2 : tol2) * sc.bnorm2[j]) {
+  } else if (rho_new <= (restarted == 0 ? first2 : tol2) * bnorm2) {
     sc.state[j] = kFrozen;
     atomicSub(sc.active, 1);
   } else if (it >= max_iter) {
     sc.state[j] = kNoConv;
     atomicSub(sc.active, 1);
-  } else if (sc.ru[j] == 0 && (dev * dev > tau2 * rho_new || rho_new < delta2 * sc.rho_ref[j])) {
+  } else if (flagged == 0 && (dev * dev > tau2 * rho_new || rho_new < delta2 * rho_ref)) {
     sc.ru[j] = 1;                              // ask for a reliable update
     atomicAdd(sc.n_ru, 1);
   }

@@ -83,19 +83,20 @@ struct MarchMap {
 //   1: each XCD takes a contiguous range of tiles;
 //   2: 3-D blocks (4-D lattices with whole x1 rows per tile group): XCD k owns
 //      a region of r2 x r3 rows (x2, x3) and runs it in rounds of b2 x b3 rows
-//      (all x1 tiles), so the workgroups resident on one XCD at a time cover a
-//      compact block whose x2 +- 1 and x3 +- 1 neighbour rows they load
-//      themselves (one t-chunk after another).
+//      (all x1 tiles), each round through all its t-chunks before the next,
+//      so the workgroups resident on one XCD at a time cover a compact block
+//      at the same few t slices: they load each other's x2 +- 1 and x3 +- 1
+//      neighbour rows, and the previous chunk's slices, into the same L2.
 __host__ __device__ inline void march_tile(const MarchMap& mm, uint32_t b, uint32_t& q, uint32_t& chunk) {
   if (mm.xcd_order == 2) {
     const uint32_t xcd = b % kNumXcd, slot = b / kNumXcd;
     const uint32_t n1t = (uint32_t)mm.ord_n1t, b2 = (uint32_t)mm.ord_b2, b3 = (uint32_t)mm.ord_b3;
     const uint32_t r2 = (uint32_t)mm.ord_r2, r3 = (uint32_t)mm.ord_r3;
-    const uint32_t per = n1t * r2 * r3;                    // tiles per XCD
-    chunk = slot / per;
-    const uint32_t k = slot % per;
     const uint32_t bs = n1t * b2 * b3;                     // tiles per round
-    const uint32_t blk = k / bs, w = k % bs;
+    const uint32_t span = bs * (uint32_t)(mm.nt / mm.Tc);  // workgroups per round (all chunks)
+    const uint32_t blk = slot / span, k = slot % span;
+    chunk = k / bs;
+    const uint32_t w = k % bs;
     const uint32_t x1t = w % n1t, y = (w / n1t) % b2, z = w / (n1t * b2);
     const uint32_t nb2 = r2 / b2;
     const uint32_t g2 = (uint32_t)mm.ord_g2;
