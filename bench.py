@@ -33,11 +33,13 @@ METRIC = "probing-vector solves/sec (4D 32^4, rel.res 1e-10) + stencil HBM GB/s 
 KERNEL_SOURCES = ["paper_1302_4018_amd/csrc/tip_kernels.hip", "paper_1302_4018_amd/csrc/tip_device.h",
                   "paper_1302_4018_amd/csrc/tip_launch.h"]
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "stencil_traffic.json")
-# the dominant kernel: with the even-odd reduction (FP64), the half-lattice
-# stencil that forms S p; without it (mixed precision), the 4-D marching stencil
+# the dominant kernel: with the even-odd reduction, the half-lattice stencil
+# that forms S p (in single precision the form with two rhs per thread, unless
+# TIP_EO_PAIR=0); without it, the 4-D marching stencil
 STENCIL = {
     (True, "fp64"): "k_eo_hop<tip::CovOp<HIP_vector_type<double, 2u> >, 1, 5>",
-    (True, "fp32"): "k_eo_hop<tip::CovOp<HIP_vector_type<float, 2u> >, 1, 5>",
+    (True, "fp32"): ("k_eo_hop<tip::CovOp<HIP_vector_type<float, 2u> >, 1, 5>" if os.environ.get("TIP_EO_PAIR") == "0"
+                     else "k_eo_hop_pair<1>"),
     (False, "fp64"): "k_stencil_march4<HIP_vector_type<double, 2u>, 5, false>",
     (False, "fp32"): "k_stencil_march4<HIP_vector_type<float, 2u>, 5, false>",
 }

@@ -317,6 +317,8 @@ struct Plan {
   bool use_march;
   bool eo = false;  // CG on the even-odd reduced system
   MarchMap me;      // half-lattice march (valid when eo)
+  bool pair = false;  // single-precision covariant hops with two rhs per thread (B = 32)
+  MarchMap me2;       // their march (16 sites per tile)
 };
 
 bool env_off(const char* name) {
@@ -515,6 +517,7 @@ struct Solver {
   int force_breakdown = 0;      // TIP_FORCE_BREAKDOWN = k (tests): iteration k of a fresh solve breaks down
   size_t vbytes, vbytes64, pstride, nscal, nelem, nvec;
   int gx_m, gx_u, gx_t;       // partials per rhs written by matvec, update, true residual
+  int gx_p;                   // partials per rhs of the iteration's matvec (gx_m unless pair)
   void *X, *Rv, *Pv, *W, *XH; // FP64 path: X, Rv, Pv, W; mixed: X (FP64) + XH, Rv, Pv, W (FP32)
   void *Xe = nullptr, *Tv = nullptr;   // even-odd: x_e and t_o (half lattice)
   void *Bh = nullptr, *T64 = nullptr;  // mixed even-odd: b_hat and an FP64 t_o (half lattice)
@@ -615,6 +618,13 @@ struct Solver {
       // the covariant half-lattice kernel stages its tile's links in LDS
       if (pl.eo && h->kind == TIP_KIND_COVARIANT && (eo_lds_bytes(g, pl.me, prec) > 65536 || !h->has_links_eo))
         pl.eo = false;
+      // mixed precision, 32 rhs, covariant without couplings: the iteration's
+      // two hops load two rhs per thread (TIP_EO_PAIR=0 turns this off);
+      // rounds of 128 of these tiles cover as many sites as 256 of the others
+      pl.pair = pl.eo && mixed && h->kind == TIP_KIND_COVARIANT && !h->has_coupling && pl.B == 32 &&
+                !env_off("TIP_EO_PAIR") &&
+                make_marchmap(g, 4, &pl.me2, true, p->round_tiles > 0 ? p->round_tiles : 128, p->march_tc) &&
+                eo_lds_bytes(g, pl.me2, prec) <= 65536;
     }
     max_iter = p->max_iter > 0 ? p->max_iter : (int)std::min<int64_t>(10 * V * ncomp, 1 << 20);
     tol2 = p->tol * p->tol;
@@ -644,9 +654,10 @@ struct Solver {
     vbytes64 = nelem * esz64;
     nvec = pl.eo ? nelem / 2 : nelem;             // elements the CG vector passes touch
     gx_m = (int)(pl.eo ? pl.me.grid : (pl.use_march ? pl.mm.grid : pl.tm.grid));
+    gx_p = pl.pair ? (int)pl.me2.grid : gx_m;
     gx_u = (int)update_grid(nvec);
     gx_t = (int)ru_grid(pl.tm);
-    pstride = (size_t)B * std::max(gx_m, std::max(gx_u, gx_t));
+    pstride = (size_t)B * std::max(std::max(gx_m, gx_p), std::max(gx_u, gx_t));
     nscal = (size_t)B;
     // FP64: x, r, p, w; mixed: x (FP64) + xh, r, p, w (FP32); even-odd: x on the
     // full lattice + x_e, r, p, w, t on the half lattice
@@ -696,6 +707,8 @@ struct Solver {
       Pv = q + 2 * h32;
       W = q + 3 * h32;
       Tv = q + 4 * h32;
+      if (pl.pair && (((uintptr_t)Pv | (uintptr_t)Tv | (uintptr_t)W) & 15u))
+        return fail(TIP_EDEVICE, "internal: single-precision half vectors not 16-byte aligned");
     } else if (mixed) {
       XH = vb + vbytes64;
       Rv = vb + vbytes64 + vbytes;
@@ -822,7 +835,12 @@ struct Solver {
     const MarchMap* mm = pl.use_march ? &pl.mm : nullptr;
     const double* diag = (const double*)h->diag.p;
     if (tv) TIP_HIP(hipEventRecord(tv->a, st));
-    if (pl.eo) {
+    if (pl.pair) {
+      TIP_HIP(launch_eo_hop_pair(0, od, g, pl.me2, 1, diag, sc.state, sc.active, Pv, nullptr, Tv, nullptr, nullptr,
+                                 st));
+      if (tv) TIP_HIP(hipEventRecord(tv->b, st));
+      TIP_HIP(launch_eo_hop_pair(1, od, g, pl.me2, 0, diag, sc.state, sc.active, Tv, Pv, W, part, ran_dev + it, st));
+    } else if (pl.eo) {
       // w_e = S p_e: t_o = D_o^-1 H_oe p_e, then w_e = D_e p_e - H_eo t_o
       TIP_HIP(launch_eo_hop(0, od, g, pl.me, 1, pl.elem, prec, diag, sc.state, sc.active, Pv, nullptr, Tv,
                             nullptr, nullptr, 0, 0, 0, 0, nullptr, nullptr, st));
@@ -835,7 +853,7 @@ struct Solver {
                              st));
     }
     if (tv) TIP_HIP(hipEventRecord(tv->c, st));
-    TIP_HIP(launch_reduce_alpha(sc, pl.B, part, gx_m, st, mixed ? 1 : 0, force_breakdown));
+    TIP_HIP(launch_reduce_alpha(sc, pl.B, part, gx_p, st, mixed ? 1 : 0, force_breakdown));
     TIP_HIP(launch_update_r(nvec, pl.logB, pl.elem, prec, sc, Rv, W, part + pstride, st));
     TIP_HIP(launch_reduce_beta(sc, pl.B, part + pstride, gx_u, tol2, max_iter, delta2, st, freeze2, ru_eps,
                                ru_tau2));

@@ -1515,6 +1515,181 @@ __global__ __launch_bounds__(kBlock) void k_eo_hop(Geom g, MarchMap mm, int P, O
   }
 }
 
+// Single-precision covariant hops of the CG iteration (modes 0 and 1 of
+// k_eo_hop) with two right-hand sides per thread.  A block of 32 rhs in
+// [ncomp][V/2][32] float2 holds rhs 2l and 2l + 1 of a site and colour in
+// one aligned 16-byte float4, so thread l of a site loads both with one
+// instruction: the same bytes per load as the FP64 kernel, 16 threads per
+// site and 16 sites per workgroup (against 8), which also halves the share of
+// x1 neighbours that lie in the next tile.  Each rhs is computed exactly as
+// in k_eo_hop; the partials of mode 1 are written per rhs.
+typedef float tip_f4 __attribute__((ext_vector_type(4)));
+
+template <bool kNT>
+__device__ __forceinline__ void load_pair(const float2* __restrict__ v, size_t Vh, uint32_t h, int l,
+                                          float2 (&a)[3], float2 (&b)[3]) {
+  const tip_f4* p = reinterpret_cast<const tip_f4*>(v);
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    const tip_f4* q = p + ((((size_t)c * Vh + h)) << 4) + l;
+    tip_f4 x;
+    if constexpr (kNT) x = __builtin_nontemporal_load(q);
+    else x = *q;
+    a[c] = make_float2(x.x, x.y);
+    b[c] = make_float2(x.z, x.w);
+  }
+}
+__device__ __forceinline__ void store_pair_nt(float2* __restrict__ v, size_t Vh, uint32_t h, int l,
+                                              const float2 (&a)[3], const float2 (&b)[3]) {
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    float2* q = v + ((((size_t)c * Vh + h)) << 5) + 2 * l;
+    st_nt(q, a[c]);
+    st_nt(q + 1, b[c]);
+  }
+}
+
+template <int MODE>
+__global__ __launch_bounds__(kBlock) void k_eo_hop_pair(Geom g, MarchMap mm, int P, CovOp<float2> op,
+                                                        const double* __restrict__ diag,
+                                                        const int* __restrict__ state, const int* __restrict__ active,
+                                                        const float2* __restrict__ in,
+                                                        const float2* __restrict__ cin, float2* __restrict__ out,
+                                                        double* __restrict__ partial, int* __restrict__ ran) {
+  static_assert(MODE == 0 || MODE == 1, "pair kernel: the two hops of the CG iteration");
+  constexpr int kLP = 4;                          // 16 pair lanes per site: rhs 2l, 2l + 1
+  constexpr int NL = 1 << kLP;
+  constexpr int TS = kBlock >> kLP;               // 16 sites per workgroup
+  if (active && *active == 0) return;
+  if (ran && blockIdx.x == 0 && threadIdx.x == 0) *ran = 1;
+  __shared__ double lds[2 * 4 * 64];
+  float2* lds_links = reinterpret_cast<float2*>(tip_dyn_lds);   // [2 ndim][9][TS]
+  const int l = threadIdx.x & (NL - 1);
+  const int si = threadIdx.x >> kLP;
+  uint32_t q, chunk;
+  march_tile(mm, blockIdx.x, q, chunk);
+  const uint32_t V3 = mm.V3;
+  const uint32_t Vh = g.V >> 1;
+  const int ndim = g.ndim;
+  const int tdim = ndim - 1;
+  const uint32_t ntau = (1u << g.logn[tdim]) >> 1;
+  const uint32_t s3_first = q * (uint32_t)TS;
+  const uint32_t s3 = s3_first + (uint32_t)si;
+  const uint32_t delta = ((uint32_t)P + spatial_parity(s3, g)) & 1u;
+  const bool live = !state || state[2 * l] == kActive || state[2 * l + 1] == kActive;
+  double acc[2] = {0.0, 0.0};
+  const uint32_t tau0 = chunk * (uint32_t)mm.Tc;
+  float2 pa[3], pb[3];                            // backward t input, carried along the march
+  if (live) load_pair<false>(in, Vh, s3 + V3 * ((tau0 + ntau - 1u + delta) % ntau), l, pa, pb);
+  for (uint32_t tau = tau0; tau < tau0 + (uint32_t)mm.Tc; ++tau) {
+    const uint32_t t = 2u * tau + delta;
+    const uint32_t s = s3 + V3 * t;
+    const uint32_t h = s3 + V3 * tau;
+    // the tile's links, as in k_eo_hop: forward U_mu of the tile's sites,
+    // backward ones at the opposite-parity neighbours
+    __syncthreads();
+    const int nslot = 2 * ndim;
+    for (int it = threadIdx.x; it < nslot * 9 * TS; it += kBlock) {
+      const int site = it % TS;
+      const int es = it / TS;
+      const int e = es % 9;
+      const int slot = es / 9;
+      const uint32_t x3 = s3_first + (uint32_t)site;
+      uint32_t hl, par;
+      int mu;
+      if (slot < ndim) {
+        mu = slot;
+        par = (uint32_t)P;
+        hl = x3 + V3 * tau;
+      } else {
+        mu = slot - ndim;
+        par = 1u - (uint32_t)P;
+        if (mu < tdim) {
+          hl = nbr_bwd_p2(x3, g, mu) + V3 * tau;
+        } else {
+          const uint32_t dl = ((uint32_t)P + spatial_parity(x3, g)) & 1u;
+          hl = x3 + V3 * ((tau + ntau - 1u + dl) % ntau);
+        }
+      }
+      lds_links[it] = op.U[(((size_t)par * ndim + mu) * 9 + e) * Vh + hl];
+    }
+    __syncthreads();
+    if (!live) continue;
+    float2 ha[3], hb[3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) ha[c] = hb[c] = zero<float2>();
+#pragma unroll
+    for (int mu = 0; mu < kMaxDim - 1; ++mu) {
+      if (mu >= tdim) break;
+      const uint32_t nf = nbr_fwd_p2(s3, g, mu), nbk = nbr_bwd_p2(s3, g, mu);
+      float2 xa[3], xb[3], ya[3], yb[3], u[9];
+      load_pair<false>(in, Vh, nf + V3 * tau, l, xa, xb);
+#pragma unroll
+      for (int e = 0; e < 9; ++e) u[e] = lds_links[(mu * 9 + e) * TS + si];
+      mul_u(u, xa, ya);
+      mul_u(u, xb, yb);
+      add_weighted<float2, 3>(1.0, ya, ha);
+      add_weighted<float2, 3>(1.0, yb, hb);
+      load_pair<false>(in, Vh, nbk + V3 * tau, l, xa, xb);
+#pragma unroll
+      for (int e = 0; e < 9; ++e) u[e] = lds_links[((ndim + mu) * 9 + e) * TS + si];
+      mul_uh(u, xa, ya);
+      mul_uh(u, xb, yb);
+      add_weighted<float2, 3>(1.0, ya, ha);
+      add_weighted<float2, 3>(1.0, yb, hb);
+    }
+    {
+      float2 xa[3], xb[3], ya[3], yb[3], u[9];
+      load_pair<false>(in, Vh, s3 + V3 * ((tau + delta) % ntau), l, xa, xb);
+#pragma unroll
+      for (int e = 0; e < 9; ++e) u[e] = lds_links[(tdim * 9 + e) * TS + si];
+      mul_u(u, xa, ya);
+      mul_u(u, xb, yb);
+      add_weighted<float2, 3>(1.0, ya, ha);
+      add_weighted<float2, 3>(1.0, yb, hb);
+#pragma unroll
+      for (int e = 0; e < 9; ++e) u[e] = lds_links[((ndim + tdim) * 9 + e) * TS + si];
+      mul_uh(u, pa, ya);
+      mul_uh(u, pb, yb);
+      add_weighted<float2, 3>(1.0, ya, ha);
+      add_weighted<float2, 3>(1.0, yb, hb);
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        pa[c] = xa[c];
+        pb[c] = xb[c];
+      }
+    }
+    const double d = diag[s];
+    float2 ya[3], yb[3];
+    if constexpr (MODE == 0) {
+      const double f = 1.0 / d;
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        ya[c] = axpy(f, ha[c], zero<float2>());
+        yb[c] = axpy(f, hb[c], zero<float2>());
+      }
+    } else {
+      float2 ca[3], cb[3];
+      load_pair<true>(cin, Vh, h, l, ca, cb);
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        ya[c] = axpy(d, ca[c], axpy(-1.0, ha[c], zero<float2>()));
+        yb[c] = axpy(d, cb[c], axpy(-1.0, hb[c], zero<float2>()));
+        acc[0] += redot(ca[c], ya[c]);
+        acc[1] += redot(cb[c], yb[c]);
+      }
+    }
+    store_pair_nt(out, Vh, h, l, ya, yb);
+  }
+  if constexpr (MODE == 1) {
+    seg_sum<2>(acc, NL, lds);
+    if ((int)threadIdx.x < NL) {
+      partial[(size_t)(2 * threadIdx.x) * gridDim.x + blockIdx.x] = acc[0];
+      partial[(size_t)(2 * threadIdx.x + 1) * gridDim.x + blockIdx.x] = acc[1];
+    }
+  }
+}
+
 // Half-lattice index <-> full-lattice site of parity P (see above).
 __device__ __forceinline__ uint32_t eo_site(uint32_t h, int P, const Geom& g) {
   const int tdim = g.ndim - 1;
@@ -1815,6 +1990,20 @@ hipError_t launch_eo_hop(int mode, const OpDev& od, const Geom& g, const MarchMa
         break;
     }
   });
+}
+
+hipError_t launch_eo_hop_pair(int mode, const OpDev& od, const Geom& g, const MarchMap& mm, int P,
+                              const double* diag, const int* state, const int* active, const void* in,
+                              const void* cin, void* out, double* partial, int* ran, hipStream_t st) {
+  CovOp<float2> op{reinterpret_cast<const float2*>(od.links_eo)};
+  const size_t lds = eo_lds_bytes(g, mm, Prec::kF32);
+  if (mode == 0)
+    k_eo_hop_pair<0><<<mm.grid, kBlock, lds, st>>>(g, mm, P, op, diag, state, active, (const float2*)in, nullptr,
+                                                  (float2*)out, nullptr, ran);
+  else
+    k_eo_hop_pair<1><<<mm.grid, kBlock, lds, st>>>(g, mm, P, op, diag, state, active, (const float2*)in,
+                                                  (const float2*)cin, (float2*)out, partial, ran);
+  return hipGetLastError();
 }
 
 hipError_t launch_eo_init_odd(const Geom& g, Elem elem, Prec prec, int logB, int64_t rhs0, int nb, uint64_t seed,

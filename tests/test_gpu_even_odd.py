@@ -182,3 +182,26 @@ def test_even_odd_gradient_and_solution_assemble_x():
     ax = orc.apply(x.cpu().numpy().reshape(orc.V, 3))
     assert np.linalg.norm(ax - b) <= 1e-12 * np.linalg.norm(b) * 1.01
     assert np.all(gm.cpu().numpy() < 0)
+
+
+@pytest.mark.parametrize("dims,n", [([16, 16, 16, 16], 16), ([8, 8, 8, 8], 12), ([8, 4, 8], 12)])
+def test_mixed_two_rhs_per_thread_matches_one(dims, n):
+    """In mixed precision with 32 rhs per block the covariant iteration's two
+    hops load two rhs per thread (16-byte loads, 16 sites per tile).  Each rhs
+    is computed as with one per thread, so against TIP_EO_PAIR=0 the
+    quadratures agree to rounding and every solve meets tol; 4-D and 3-D
+    lattices, several tiles."""
+    tip = gpu_binding()
+    orc, gop = _ops(tip, dims, 1, seed=470)
+    tol = 1e-11
+    print(f"pair kernel: dims {dims} n {n}", flush=True)
+    est, q, st = tip.trace_inv_probe(gop, n, tol, 4018, mask=MASK_Z4, precision=tip.PREC_MIXED, rhs_block=32)
+    est_1, q_1, st_1 = _with_env("TIP_EO_PAIR", "0", lambda: tip.trace_inv_probe(
+        gop, n, tol, 4018, mask=MASK_Z4, precision=tip.PREC_MIXED, rhs_block=32))
+    assert st["even_odd"] == 1 and st_1["even_odd"] == 1
+    assert st["max_true_relres"] <= tol and st_1["max_true_relres"] <= tol
+    assert _rel(q, q_1) <= REL
+    if orc.V <= 4096:
+        est_o, q_o, _ = oracle_trace(orc, n, tol, 4018, MASK_Z4)
+        assert _rel(q, q_o) <= REL
+    assert abs(st["total_iters"] - st_1["total_iters"]) <= 2 * st["solves"]
