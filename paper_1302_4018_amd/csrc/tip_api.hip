@@ -498,8 +498,9 @@ tip_status check_params(const tip_op_s* h, const tip_params* p, int* mask_out) {
 // CG over blocks of right-hand sides on one prepared operator.
 //   FP64:  x, r, p, w in FP64; one FP64 true-residual check per solve.
 //   mixed: x in FP64; correction xh, r, p, w in FP32 with FP32 links; FP64
-//          reliable updates whenever the FP32 residual has fallen by delta,
-//          and the same FP64 true-residual check at the end.
+//          reliable updates whenever the bound on the drift of the FP32
+//          residual from b - A x asks for one (k_reduce_beta), and the same
+//          FP64 true-residual check at the end.
 struct Solver {
   tip_op_s* h;
   const tip_params* p;
@@ -618,13 +619,15 @@ struct Solver {
       // the covariant half-lattice kernel stages its tile's links in LDS
       if (pl.eo && h->kind == TIP_KIND_COVARIANT && (eo_lds_bytes(g, pl.me, prec) > 65536 || !h->has_links_eo))
         pl.eo = false;
-      // mixed precision, 32 rhs, covariant without couplings: the iteration's
-      // two hops load two rhs per thread (TIP_EO_PAIR=0 turns this off);
-      // rounds of 128 of these tiles cover as many sites as 256 of the others
-      pl.pair = pl.eo && mixed && h->kind == TIP_KIND_COVARIANT && !h->has_coupling && pl.B == 32 &&
-                !env_off("TIP_EO_PAIR") &&
+      // 32 rhs with 8-byte lane elements (single-precision covariant without
+      // couplings, FP64 real scalar): the iteration's two hops load two rhs
+      // per thread (TIP_EO_PAIR=0 turns this off); rounds of 128 of these
+      // tiles cover as many sites as 256 of the others
+      const bool pair_op = (mixed && h->kind == TIP_KIND_COVARIANT && !h->has_coupling) ||
+                           (!mixed && h->kind == TIP_KIND_SCALAR && pl.elem == Elem::kReal);
+      pl.pair = pl.eo && pair_op && pl.B == 32 && !env_off("TIP_EO_PAIR") &&
                 make_marchmap(g, 4, &pl.me2, true, p->round_tiles > 0 ? p->round_tiles : 128, p->march_tc) &&
-                eo_lds_bytes(g, pl.me2, prec) <= 65536;
+                (h->kind != TIP_KIND_COVARIANT || eo_lds_bytes(g, pl.me2, prec) <= 65536);
     }
     max_iter = p->max_iter > 0 ? p->max_iter : (int)std::min<int64_t>(10 * V * ncomp, 1 << 20);
     tol2 = p->tol * p->tol;
@@ -722,6 +725,8 @@ struct Solver {
       Pv = vb + vbytes + 2 * hb;
       W = vb + vbytes + 3 * hb;
       Tv = vb + vbytes + 4 * hb;
+      if (pl.pair && (((uintptr_t)Pv | (uintptr_t)Tv | (uintptr_t)W) & 15u))
+        return fail(TIP_EDEVICE, "internal: half vectors not 16-byte aligned");
     } else {
       XH = nullptr;
       Rv = vb + vbytes;
@@ -836,10 +841,11 @@ struct Solver {
     const double* diag = (const double*)h->diag.p;
     if (tv) TIP_HIP(hipEventRecord(tv->a, st));
     if (pl.pair) {
-      TIP_HIP(launch_eo_hop_pair(0, od, g, pl.me2, 1, diag, sc.state, sc.active, Pv, nullptr, Tv, nullptr, nullptr,
-                                 st));
+      TIP_HIP(launch_eo_hop_pair(0, od, g, pl.me2, 1, prec, diag, sc.state, sc.active, Pv, nullptr, Tv, nullptr,
+                                 nullptr, st));
       if (tv) TIP_HIP(hipEventRecord(tv->b, st));
-      TIP_HIP(launch_eo_hop_pair(1, od, g, pl.me2, 0, diag, sc.state, sc.active, Tv, Pv, W, part, ran_dev + it, st));
+      TIP_HIP(launch_eo_hop_pair(1, od, g, pl.me2, 0, prec, diag, sc.state, sc.active, Tv, Pv, W, part, ran_dev + it,
+                                 st));
     } else if (pl.eo) {
       // w_e = S p_e: t_o = D_o^-1 H_oe p_e, then w_e = D_e p_e - H_eo t_o
       TIP_HIP(launch_eo_hop(0, od, g, pl.me, 1, pl.elem, prec, diag, sc.state, sc.active, Pv, nullptr, Tv,

@@ -1515,61 +1515,90 @@ __global__ __launch_bounds__(kBlock) void k_eo_hop(Geom g, MarchMap mm, int P, O
   }
 }
 
-// Single-precision covariant hops of the CG iteration (modes 0 and 1 of
-// k_eo_hop) with two right-hand sides per thread.  A block of 32 rhs in
-// [ncomp][V/2][32] float2 holds rhs 2l and 2l + 1 of a site and colour in
-// one aligned 16-byte float4, so thread l of a site loads both with one
-// instruction: the same bytes per load as the FP64 kernel, 16 threads per
-// site and 16 sites per workgroup (against 8), which also halves the share of
-// x1 neighbours that lie in the next tile.  Each rhs is computed exactly as
-// in k_eo_hop; the partials of mode 1 are written per rhs.
+// The two hops of the CG iteration (modes 0 and 1 of k_eo_hop) with two
+// right-hand sides per thread, for the operators whose lane element is 8
+// bytes: the single-precision covariant operator (float2) and the FP64 real
+// scalar one (double).  A block of 32 rhs in [ncomp][V/2][32] holds rhs 2l and
+// 2l + 1 of a site and colour in one aligned 16-byte pair, so thread l of a
+// site loads both with one instruction: the bytes per load of the FP64
+// covariant kernel, 16 threads per site and 16 sites per workgroup (against
+// 8), which also halves the share of x1 neighbours that lie in the next tile.
+// Each rhs is computed exactly as in k_eo_hop; the partials of mode 1 are
+// written per rhs.
 typedef float tip_f4 __attribute__((ext_vector_type(4)));
+typedef double tip_d2 __attribute__((ext_vector_type(2)));
+template <class T> struct PairOf;
+template <> struct PairOf<float2> {
+  using V = tip_f4;
+  __device__ static void split(const V& x, float2& a, float2& b) {
+    a = make_float2(x.x, x.y);
+    b = make_float2(x.z, x.w);
+  }
+};
+template <> struct PairOf<double> {
+  using V = tip_d2;
+  __device__ static void split(const V& x, double& a, double& b) {
+    a = x.x;
+    b = x.y;
+  }
+};
 
-template <bool kNT>
-__device__ __forceinline__ void load_pair(const float2* __restrict__ v, size_t Vh, uint32_t h, int l,
-                                          float2 (&a)[3], float2 (&b)[3]) {
-  const tip_f4* p = reinterpret_cast<const tip_f4*>(v);
+template <bool kNT, class T, int NC>
+__device__ __forceinline__ void load_pair(const T* __restrict__ v, size_t Vh, uint32_t h, int l, T (&a)[NC],
+                                          T (&b)[NC]) {
+  using PV = typename PairOf<T>::V;
+  const PV* p = reinterpret_cast<const PV*>(v);
 #pragma unroll
-  for (int c = 0; c < 3; ++c) {
-    const tip_f4* q = p + ((((size_t)c * Vh + h)) << 4) + l;
-    tip_f4 x;
+  for (int c = 0; c < NC; ++c) {
+    const PV* q = p + ((((size_t)c * Vh + h)) << 4) + l;
+    PV x;
     if constexpr (kNT) x = __builtin_nontemporal_load(q);
     else x = *q;
-    a[c] = make_float2(x.x, x.y);
-    b[c] = make_float2(x.z, x.w);
+    PairOf<T>::split(x, a[c], b[c]);
   }
 }
-__device__ __forceinline__ void store_pair_nt(float2* __restrict__ v, size_t Vh, uint32_t h, int l,
-                                              const float2 (&a)[3], const float2 (&b)[3]) {
+// Two 8-byte streaming stores to adjacent addresses (merged into one 16-byte
+// store); packing the pair into one vector first put it on the stack.
+template <class T, int NC>
+__device__ __forceinline__ void store_pair_nt(T* __restrict__ v, size_t Vh, uint32_t h, int l, const T (&a)[NC],
+                                              const T (&b)[NC]) {
 #pragma unroll
-  for (int c = 0; c < 3; ++c) {
-    float2* q = v + ((((size_t)c * Vh + h)) << 5) + 2 * l;
+  for (int c = 0; c < NC; ++c) {
+    T* q = v + ((((size_t)c * Vh + h)) << 5) + 2 * l;
     st_nt(q, a[c]);
     st_nt(q + 1, b[c]);
   }
 }
 
-template <int MODE>
-__global__ __launch_bounds__(kBlock) void k_eo_hop_pair(Geom g, MarchMap mm, int P, CovOp<float2> op,
+template <class Op, int MODE>
+__global__ __launch_bounds__(kBlock) void k_eo_hop_pair(Geom g, MarchMap mm, int P, Op op,
                                                         const double* __restrict__ diag,
+                                                        const double* __restrict__ w,
                                                         const int* __restrict__ state, const int* __restrict__ active,
-                                                        const float2* __restrict__ in,
-                                                        const float2* __restrict__ cin, float2* __restrict__ out,
+                                                        const typename Op::T* __restrict__ in,
+                                                        const typename Op::T* __restrict__ cin,
+                                                        typename Op::T* __restrict__ out,
                                                         double* __restrict__ partial, int* __restrict__ ran) {
   static_assert(MODE == 0 || MODE == 1, "pair kernel: the two hops of the CG iteration");
+  using T = typename Op::T;
+  constexpr int NC = Op::NC;
+  constexpr bool kCov = NC == 3;
+  static_assert(sizeof(T) == 8, "pair kernel: 8-byte lane elements");
   constexpr int kLP = 4;                          // 16 pair lanes per site: rhs 2l, 2l + 1
   constexpr int NL = 1 << kLP;
   constexpr int TS = kBlock >> kLP;               // 16 sites per workgroup
   if (active && *active == 0) return;
   if (ran && blockIdx.x == 0 && threadIdx.x == 0) *ran = 1;
   __shared__ double lds[2 * 4 * 64];
-  float2* lds_links = reinterpret_cast<float2*>(tip_dyn_lds);   // [2 ndim][9][TS]
+  T* lds_links = reinterpret_cast<T*>(tip_dyn_lds);   // covariant: [2 ndim][9][TS]
+  __shared__ double lds_w[kCov ? 1 : 2 * kMaxDim * TS];   // scalar with couplings: [2 ndim][TS]
   const int l = threadIdx.x & (NL - 1);
   const int si = threadIdx.x >> kLP;
   uint32_t q, chunk;
   march_tile(mm, blockIdx.x, q, chunk);
+  const uint32_t V = g.V;
   const uint32_t V3 = mm.V3;
-  const uint32_t Vh = g.V >> 1;
+  const uint32_t Vh = V >> 1;
   const int ndim = g.ndim;
   const int tdim = ndim - 1;
   const uint32_t ntau = (1u << g.logn[tdim]) >> 1;
@@ -1579,107 +1608,124 @@ __global__ __launch_bounds__(kBlock) void k_eo_hop_pair(Geom g, MarchMap mm, int
   const bool live = !state || state[2 * l] == kActive || state[2 * l + 1] == kActive;
   double acc[2] = {0.0, 0.0};
   const uint32_t tau0 = chunk * (uint32_t)mm.Tc;
-  float2 pa[3], pb[3];                            // backward t input, carried along the march
-  if (live) load_pair<false>(in, Vh, s3 + V3 * ((tau0 + ntau - 1u + delta) % ntau), l, pa, pb);
+  T pa[NC], pb[NC];                               // backward t input, carried along the march
+  if (live) load_pair<false, T, NC>(in, Vh, s3 + V3 * ((tau0 + ntau - 1u + delta) % ntau), l, pa, pb);
   for (uint32_t tau = tau0; tau < tau0 + (uint32_t)mm.Tc; ++tau) {
     const uint32_t t = 2u * tau + delta;
     const uint32_t s = s3 + V3 * t;
     const uint32_t h = s3 + V3 * tau;
-    // the tile's links, as in k_eo_hop: forward U_mu of the tile's sites,
-    // backward ones at the opposite-parity neighbours
-    __syncthreads();
     const int nslot = 2 * ndim;
-    for (int it = threadIdx.x; it < nslot * 9 * TS; it += kBlock) {
-      const int site = it % TS;
-      const int es = it / TS;
-      const int e = es % 9;
-      const int slot = es / 9;
-      const uint32_t x3 = s3_first + (uint32_t)site;
-      uint32_t hl, par;
-      int mu;
-      if (slot < ndim) {
-        mu = slot;
-        par = (uint32_t)P;
-        hl = x3 + V3 * tau;
-      } else {
-        mu = slot - ndim;
-        par = 1u - (uint32_t)P;
-        if (mu < tdim) {
-          hl = nbr_bwd_p2(x3, g, mu) + V3 * tau;
+    if constexpr (kCov) {
+      // the tile's links, as in k_eo_hop: forward U_mu of the tile's sites,
+      // backward ones at the opposite-parity neighbours
+      __syncthreads();
+      for (int it = threadIdx.x; it < nslot * 9 * TS; it += kBlock) {
+        const int site = it % TS;
+        const int es = it / TS;
+        const int e = es % 9;
+        const int slot = es / 9;
+        const uint32_t x3 = s3_first + (uint32_t)site;
+        uint32_t hl, par;
+        int mu;
+        if (slot < ndim) {
+          mu = slot;
+          par = (uint32_t)P;
+          hl = x3 + V3 * tau;
         } else {
-          const uint32_t dl = ((uint32_t)P + spatial_parity(x3, g)) & 1u;
-          hl = x3 + V3 * ((tau + ntau - 1u + dl) % ntau);
+          mu = slot - ndim;
+          par = 1u - (uint32_t)P;
+          if (mu < tdim) {
+            hl = nbr_bwd_p2(x3, g, mu) + V3 * tau;
+          } else {
+            const uint32_t dl = ((uint32_t)P + spatial_parity(x3, g)) & 1u;
+            hl = x3 + V3 * ((tau + ntau - 1u + dl) % ntau);
+          }
         }
+        lds_links[it] = op.U[(((size_t)par * ndim + mu) * 9 + e) * Vh + hl];
       }
-      lds_links[it] = op.U[(((size_t)par * ndim + mu) * 9 + e) * Vh + hl];
+      __syncthreads();
+    } else if (w) {
+      // the tile's couplings, as in k_eo_hop: forward w_mu(s), backward w_mu(s - mu)
+      __syncthreads();
+      for (int it = threadIdx.x; it < nslot * TS; it += kBlock) {
+        const int site = it % TS;
+        const int slot = it / TS;
+        const uint32_t x3 = s3_first + (uint32_t)site;
+        const uint32_t dl = ((uint32_t)P + spatial_parity(x3, g)) & 1u;
+        const uint32_t sf = x3 + V3 * (2u * tau + dl);
+        const int mu = slot < ndim ? slot : slot - ndim;
+        lds_w[it] = w[(size_t)mu * V + (slot < ndim ? sf : nbr_bwd_p2(sf, g, mu))];
+      }
+      __syncthreads();
     }
-    __syncthreads();
     if (!live) continue;
-    float2 ha[3], hb[3];
+    T ha[NC], hb[NC];
 #pragma unroll
-    for (int c = 0; c < 3; ++c) ha[c] = hb[c] = zero<float2>();
+    for (int c = 0; c < NC; ++c) ha[c] = hb[c] = zero<T>();
+    // one hop: y = U x (forward) or U^H x (backward) for both rhs, weighted
+    auto hop = [&](int slot, bool fwd, const T (&xa)[NC], const T (&xb)[NC]) {
+      T ya[NC], yb[NC];
+      double wt = 1.0;
+      if constexpr (kCov) {
+        T u[9];
+#pragma unroll
+        for (int e = 0; e < 9; ++e) u[e] = lds_links[(slot * 9 + e) * TS + si];
+        if (fwd) {
+          mul_u(u, xa, ya);
+          mul_u(u, xb, yb);
+        } else {
+          mul_uh(u, xa, ya);
+          mul_uh(u, xb, yb);
+        }
+      } else {
+        if (w) wt = lds_w[slot * TS + si];
+        ya[0] = xa[0];
+        yb[0] = xb[0];
+      }
+      add_weighted<T, NC>(wt, ya, ha);
+      add_weighted<T, NC>(wt, yb, hb);
+    };
 #pragma unroll
     for (int mu = 0; mu < kMaxDim - 1; ++mu) {
       if (mu >= tdim) break;
-      const uint32_t nf = nbr_fwd_p2(s3, g, mu), nbk = nbr_bwd_p2(s3, g, mu);
-      float2 xa[3], xb[3], ya[3], yb[3], u[9];
-      load_pair<false>(in, Vh, nf + V3 * tau, l, xa, xb);
-#pragma unroll
-      for (int e = 0; e < 9; ++e) u[e] = lds_links[(mu * 9 + e) * TS + si];
-      mul_u(u, xa, ya);
-      mul_u(u, xb, yb);
-      add_weighted<float2, 3>(1.0, ya, ha);
-      add_weighted<float2, 3>(1.0, yb, hb);
-      load_pair<false>(in, Vh, nbk + V3 * tau, l, xa, xb);
-#pragma unroll
-      for (int e = 0; e < 9; ++e) u[e] = lds_links[((ndim + mu) * 9 + e) * TS + si];
-      mul_uh(u, xa, ya);
-      mul_uh(u, xb, yb);
-      add_weighted<float2, 3>(1.0, ya, ha);
-      add_weighted<float2, 3>(1.0, yb, hb);
+      T xa[NC], xb[NC];
+      load_pair<false, T, NC>(in, Vh, nbr_fwd_p2(s3, g, mu) + V3 * tau, l, xa, xb);
+      hop(mu, true, xa, xb);
+      load_pair<false, T, NC>(in, Vh, nbr_bwd_p2(s3, g, mu) + V3 * tau, l, xa, xb);
+      hop(ndim + mu, false, xa, xb);
     }
     {
-      float2 xa[3], xb[3], ya[3], yb[3], u[9];
-      load_pair<false>(in, Vh, s3 + V3 * ((tau + delta) % ntau), l, xa, xb);
+      T xa[NC], xb[NC];
+      load_pair<false, T, NC>(in, Vh, s3 + V3 * ((tau + delta) % ntau), l, xa, xb);
+      hop(tdim, true, xa, xb);
+      hop(ndim + tdim, false, pa, pb);
 #pragma unroll
-      for (int e = 0; e < 9; ++e) u[e] = lds_links[(tdim * 9 + e) * TS + si];
-      mul_u(u, xa, ya);
-      mul_u(u, xb, yb);
-      add_weighted<float2, 3>(1.0, ya, ha);
-      add_weighted<float2, 3>(1.0, yb, hb);
-#pragma unroll
-      for (int e = 0; e < 9; ++e) u[e] = lds_links[((ndim + tdim) * 9 + e) * TS + si];
-      mul_uh(u, pa, ya);
-      mul_uh(u, pb, yb);
-      add_weighted<float2, 3>(1.0, ya, ha);
-      add_weighted<float2, 3>(1.0, yb, hb);
-#pragma unroll
-      for (int c = 0; c < 3; ++c) {
+      for (int c = 0; c < NC; ++c) {
         pa[c] = xa[c];
         pb[c] = xb[c];
       }
     }
     const double d = diag[s];
-    float2 ya[3], yb[3];
+    T ya[NC], yb[NC];
     if constexpr (MODE == 0) {
       const double f = 1.0 / d;
 #pragma unroll
-      for (int c = 0; c < 3; ++c) {
-        ya[c] = axpy(f, ha[c], zero<float2>());
-        yb[c] = axpy(f, hb[c], zero<float2>());
+      for (int c = 0; c < NC; ++c) {
+        ya[c] = axpy(f, ha[c], zero<T>());
+        yb[c] = axpy(f, hb[c], zero<T>());
       }
     } else {
-      float2 ca[3], cb[3];
-      load_pair<true>(cin, Vh, h, l, ca, cb);
+      T ca[NC], cb[NC];
+      load_pair<true, T, NC>(cin, Vh, h, l, ca, cb);
 #pragma unroll
-      for (int c = 0; c < 3; ++c) {
-        ya[c] = axpy(d, ca[c], axpy(-1.0, ha[c], zero<float2>()));
-        yb[c] = axpy(d, cb[c], axpy(-1.0, hb[c], zero<float2>()));
+      for (int c = 0; c < NC; ++c) {
+        ya[c] = axpy(d, ca[c], axpy(-1.0, ha[c], zero<T>()));
+        yb[c] = axpy(d, cb[c], axpy(-1.0, hb[c], zero<T>()));
         acc[0] += redot(ca[c], ya[c]);
         acc[1] += redot(cb[c], yb[c]);
       }
     }
-    store_pair_nt(out, Vh, h, l, ya, yb);
+    store_pair_nt<T, NC>(out, Vh, h, l, ya, yb);
   }
   if constexpr (MODE == 1) {
     seg_sum<2>(acc, NL, lds);
@@ -1992,17 +2038,23 @@ hipError_t launch_eo_hop(int mode, const OpDev& od, const Geom& g, const MarchMa
   });
 }
 
-hipError_t launch_eo_hop_pair(int mode, const OpDev& od, const Geom& g, const MarchMap& mm, int P,
+hipError_t launch_eo_hop_pair(int mode, const OpDev& od, const Geom& g, const MarchMap& mm, int P, Prec prec,
                               const double* diag, const int* state, const int* active, const void* in,
                               const void* cin, void* out, double* partial, int* ran, hipStream_t st) {
-  CovOp<float2> op{reinterpret_cast<const float2*>(od.links_eo)};
-  const size_t lds = eo_lds_bytes(g, mm, Prec::kF32);
-  if (mode == 0)
-    k_eo_hop_pair<0><<<mm.grid, kBlock, lds, st>>>(g, mm, P, op, diag, state, active, (const float2*)in, nullptr,
-                                                  (float2*)out, nullptr, ran);
-  else
-    k_eo_hop_pair<1><<<mm.grid, kBlock, lds, st>>>(g, mm, P, op, diag, state, active, (const float2*)in,
-                                                  (const float2*)cin, (float2*)out, partial, ran);
+  auto go = [&](auto op) {
+    using Op = decltype(op);
+    using T = typename Op::T;
+    const size_t lds = Op::NC == 3 ? eo_lds_bytes(g, mm, prec) : 0;
+    if (mode == 0)
+      k_eo_hop_pair<Op, 0><<<mm.grid, kBlock, lds, st>>>(g, mm, P, op, diag, od.coupling, state, active,
+                                                        (const T*)in, nullptr, (T*)out, nullptr, ran);
+    else
+      k_eo_hop_pair<Op, 1><<<mm.grid, kBlock, lds, st>>>(g, mm, P, op, diag, od.coupling, state, active,
+                                                        (const T*)in, (const T*)cin, (T*)out, partial, ran);
+  };
+  if (od.kind == 1 && prec == Prec::kF32) go(CovOp<float2>{reinterpret_cast<const float2*>(od.links_eo)});
+  else if (od.kind == 0 && prec == Prec::kF64) go(ScalarOp<double>{});
+  else return hipErrorInvalidValue;
   return hipGetLastError();
 }
 

@@ -151,9 +151,10 @@ hipError_t launch_grad_accum(const OpDev& od64, const Geom& g, Elem elem, int lo
 hipError_t launch_scale(size_t n, double* a, double f, hipStream_t st);
 // even-odd reduced system (half-lattice vectors [ncomp][V/2][B], see k_eo_hop)
 size_t eo_lds_bytes(const Geom& g, const MarchMap& mm, Prec prec);
-// Single-precision covariant modes 0 and 1 with two rhs per thread (B = 32;
-// the march map built for 16 lanes per site, 16 sites per tile).
-hipError_t launch_eo_hop_pair(int mode, const OpDev& od, const Geom& g, const MarchMap& mm, int P,
+// Modes 0 and 1 with two rhs per thread (B = 32; the march map built for 16
+// lanes per site, 16 sites per tile) for the single-precision covariant and
+// the FP64 real scalar operators; hipErrorInvalidValue for any other.
+hipError_t launch_eo_hop_pair(int mode, const OpDev& od, const Geom& g, const MarchMap& mm, int P, Prec prec,
                               const double* diag, const int* state, const int* active, const void* in,
                               const void* cin, void* out, double* partial, int* ran, hipStream_t st);
 hipError_t launch_eo_hop(int mode, const OpDev& od, const Geom& g, const MarchMap& mm, int P, Elem elem, Prec prec,

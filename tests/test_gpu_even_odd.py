@@ -205,3 +205,26 @@ def test_mixed_two_rhs_per_thread_matches_one(dims, n):
         est_o, q_o, _ = oracle_trace(orc, n, tol, 4018, MASK_Z4)
         assert _rel(q, q_o) <= REL
     assert abs(st["total_iters"] - st_1["total_iters"]) <= 2 * st["solves"]
+
+
+@pytest.mark.parametrize("dims,n,coupled", [([16, 16], 32, True), ([32, 32, 32], 32, True), ([8, 8, 8, 8], 24, False),
+                                            ([8, 4, 8], 20, True)])
+def test_fp64_scalar_two_rhs_per_thread_matches_one(dims, n, coupled):
+    """FP64 real scalar operator, 32 rhs per block: the iteration's two hops
+    load two rhs per thread (one 16-byte load per pair), couplings staged per
+    tile.  Against TIP_EO_PAIR=0 the quadratures agree to rounding, and
+    against the oracle to the 1e-10 bar; 2-D, 3-D and 4-D, several tiles."""
+    tip = gpu_binding()
+    orc, gop = _ops(tip, dims, 0, seed=480, coupled=coupled)
+    tol = 1e-12
+    print(f"scalar pair kernel: dims {dims} n {n} coupled {coupled}", flush=True)
+    est, q, st = tip.trace_inv_probe(gop, n, tol, 4018, mask=MASK_Z2, rhs_block=32)
+    est_1, q_1, st_1 = _with_env("TIP_EO_PAIR", "0", lambda: tip.trace_inv_probe(
+        gop, n, tol, 4018, mask=MASK_Z2, rhs_block=32))
+    assert st["even_odd"] == 1 and st_1["even_odd"] == 1
+    assert st["max_true_relres"] <= tol and st_1["max_true_relres"] <= tol
+    assert _rel(q, q_1) <= REL
+    assert abs(st["total_iters"] - st_1["total_iters"]) <= st["solves"]
+    if orc.V <= 4096:
+        est_o, q_o, _ = oracle_trace(orc, n, tol, 4018, MASK_Z2)
+        assert _rel(q, q_o) <= REL
