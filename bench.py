@@ -170,12 +170,14 @@ def bench_c4(args):
         # timed steps without per-kernel events, so that iteration chunks replay
         # as HIP graphs; one extra profiled step gives the stencil figures
         for _ in range(args.warmup):
-            tip.trace_inv_probe_batch(ops, ns, args.tol, args.seed, mask=tip.MASK_Z2, precision=prec)
+            tip.trace_inv_probe_batch(ops, ns, args.tol, args.seed, mask=tip.MASK_Z2, precision=prec,
+                                      n_streams=args.streams)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         agg = {"iters": 0, "solves": 0, "relres": 0.0, "launches": 0, "seconds": 0.0, "bytes": 0.0}
         for _ in range(args.steps):
-            out = tip.trace_inv_probe_batch(ops, ns, args.tol, args.seed, mask=tip.MASK_Z2, precision=prec)
+            out = tip.trace_inv_probe_batch(ops, ns, args.tol, args.seed, mask=tip.MASK_Z2, precision=prec,
+                                            n_streams=args.streams)
             for _, st in out:
                 agg["iters"] += st["total_iters"]
                 agg["solves"] += st["solves"]
@@ -183,7 +185,8 @@ def bench_c4(args):
         torch.cuda.synchronize()
         el = time.perf_counter() - t0
         tip.tip_set_profiling(True)
-        for _, st in tip.trace_inv_probe_batch(ops, ns, args.tol, args.seed, mask=tip.MASK_Z2, precision=prec):
+        for _, st in tip.trace_inv_probe_batch(ops, ns, args.tol, args.seed, mask=tip.MASK_Z2, precision=prec,
+                                               n_streams=args.streams):
             agg["launches"] += st["stencil_launches"]
             agg["seconds"] += st["stencil_seconds"]
             agg["bytes"] += st["stencil_bytes"]
@@ -199,7 +202,7 @@ def bench_c4(args):
            "config": {"workload": "64 independent 3-D tori, sides iid U{8..48}, scalar Laplacian m~U[0.02,0.2], "
                                   "w~U[0.5,1.5], Z2, 16..256 probes each, tol 1e-10",
                       "rhs_per_step": total, "iters_per_solve": round(agg["iters"] / agg["solves"], 2),
-                      "max_true_relres": agg["relres"], "streams": 8},
+                      "max_true_relres": agg["relres"], "streams": args.streams or 8},
            "roofline": {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                         "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": None, "kernel": "k_stencil (generic sites)",
                         "note": "working sets of a few MB per torus stay in L2/MALL; from one extra profiled step "
@@ -486,6 +489,8 @@ def main():
                          "compare: hierarchical vs natural-order Hadamard vs Monte-Carlo probes on a 32^3 torus "
                          "with a closed-form trace; study: the experiments of Sec. 5 (stopped levels, three "
                          "lattices and condition numbers, variance over 100 masks)")
+    ap.add_argument("--streams", type=int, default=0, help="c4: host threads and streams of the batch call "
+                    "(0 = the library's default, 8)")
     ap.add_argument("--masks", type=int, default=4, help="compare / study B: masks averaged per probe kind")
     ap.add_argument("--sequential", action="store_true",
                     help="c4: solve the tori one after another on one thread instead of the batch call")
