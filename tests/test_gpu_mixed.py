@@ -137,7 +137,7 @@ def test_mixed_converges_on_badly_conditioned_fields(dims, kappa, iter_ratio):
     stall or diverge there (a run to 81648 iterations at kappa = 1e5).  The
     bound on that drift asks for updates in time: every solve meets tol and the
     estimates match FP64.  Single precision costs up to about twice FP64's
-    iterations at kappa = 1e4 and 1e5 (1.7x and 2.0x here) and about four
+    iterations at kappa = 1e4 and 1e5 (1.4x and 2.0x here) and about four
     times at 1e6."""
     tip = gpu_binding()
     d = len(dims)
