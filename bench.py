@@ -515,6 +515,9 @@ def main():
     from paper_1302_4018_amd import binding as tip
     from paper_1302_4018_amd import inputs
 
+    if args.copy_calibration:
+        copy_calibration()
+
     if args.workload == "c4":
         bench_c4(args)
         return
@@ -527,9 +530,6 @@ def main():
     if args.workload == "c2h":
         bench_c2h(args)
         return
-
-    if args.copy_calibration:
-        copy_calibration()
 
     t = time.perf_counter()
     U = inputs.haar_links(DIMS)
