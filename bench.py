@@ -57,17 +57,25 @@ def kernel_source_hash():
     return h.hexdigest()
 
 
-def measured_traffic(kernel_name):
-    """HBM bytes per stencil launch from the committed rocprofv3 counter runs,
-    or None when the kernel sources changed since they were taken."""
+def traffic_records():
+    """The per-kernel records of the traffic file ([] when absent)."""
     try:
         with open(TRAFFIC_FILE) as f:
             t = json.load(f)
     except (OSError, ValueError):
-        return None
-    if t.get("source_sha256") != kernel_source_hash() or t.get("kernel") != kernel_name:
-        return None
-    return t.get("traffic_bytes_per_launch")
+        return []
+    return t.get("records", [t] if "kernel" in t else [])
+
+
+def measured_traffic(kernel_name):
+    """HBM bytes per stencil launch of kernel_name from the committed rocprofv3
+    counter runs, or None when there is no record of it or the kernel sources
+    changed since it was taken."""
+    src = kernel_source_hash()
+    for t in traffic_records():
+        if t.get("kernel") == kernel_name and t.get("source_sha256") == src:
+            return t.get("traffic_bytes_per_launch")
+    return None
 
 
 def write_traffic(fetch_csv, write_csv, kernel_match, command):
@@ -100,8 +108,9 @@ def write_traffic(fetch_csv, write_csv, kernel_match, command):
     out = {"kernel": kernel_match, "source_sha256": kernel_source_hash(),
            "fetch_kib_per_launch": fk, "fetch_scale": fs, "write_kib_per_launch": wk, "write_scale": ws,
            "launches": [nf, nw], "traffic_bytes_per_launch": 1024.0 * (fk * fs + wk * ws), "command": command}
+    records = [t for t in traffic_records() if t.get("kernel") != kernel_match] + [out]
     with open(TRAFFIC_FILE, "w") as f:
-        json.dump(out, f, indent=1)
+        json.dump({"records": records}, f, indent=1)
         f.write("\n")
     print(json.dumps(out))
 
@@ -483,6 +492,8 @@ def main():
                     help="write the stencil's measured HBM bytes per launch from two rocprofv3 --pmc "
                          "counter_collection.csv files, then exit (no GPU work)")
     ap.add_argument("--traffic-command", default="", help="command recorded with --traffic-from")
+    ap.add_argument("--traffic-kernel", choices=["fp64", "fp32"], default="fp64",
+                    help="--traffic-from: the FP64 or the single-precision dominant kernel of the 32^4 workload")
     ap.add_argument("--workload", choices=["c5", "c4", "c2h", "compare", "study"], default="c5",
                     help="c5: the 32^4 covariant probing run (default); c4: the batch of 64 uneven 3-D tori; "
                          "c2h: the scalar stencil's HBM rate on a 256^3 torus; "
@@ -499,7 +510,8 @@ def main():
     ap.add_argument("--variance-masks", type=int, default=100, help="study C: masks")
     args = ap.parse_args()
     if args.traffic_from:
-        write_traffic(args.traffic_from[0], args.traffic_from[1], STENCIL[(True, "fp64")], args.traffic_command)
+        write_traffic(args.traffic_from[0], args.traffic_from[1], STENCIL[(True, args.traffic_kernel)],
+                      args.traffic_command)
         return
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
