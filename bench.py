@@ -34,11 +34,13 @@ KERNEL_SOURCES = ["paper_1302_4018_amd/csrc/tip_kernels.hip", "paper_1302_4018_a
                   "paper_1302_4018_amd/csrc/tip_launch.h"]
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "stencil_traffic.json")
 # the dominant kernel: with the even-odd reduction, the half-lattice stencil
-# that forms S p (in single precision the form with two rhs per thread, unless
-# TIP_EO_PAIR=0); without it, the 4-D marching stencil
+# that forms S p (in FP64 in 512-thread workgroups unless TIP_EO_WIDE=0, in
+# single precision with two rhs per thread unless TIP_EO_PAIR=0); without it,
+# the 4-D marching stencil
 STENCIL = {
-    (True, "fp64"): "k_eo_hop<tip::CovOp<HIP_vector_type<double, 2u> >, 1, 5>",
-    (True, "fp32"): ("k_eo_hop<tip::CovOp<HIP_vector_type<float, 2u> >, 1, 5>" if os.environ.get("TIP_EO_PAIR") == "0"
+    (True, "fp64"): ("k_eo_hop<tip::CovOp<HIP_vector_type<double, 2u> >, 1, 5, 256>" if os.environ.get("TIP_EO_WIDE") == "0"
+                     else "k_eo_hop<tip::CovOp<HIP_vector_type<double, 2u> >, 1, 5, 512>"),
+    (True, "fp32"): ("k_eo_hop<tip::CovOp<HIP_vector_type<float, 2u> >, 1, 5, 256>" if os.environ.get("TIP_EO_PAIR") == "0"
                      else "k_eo_hop_pair<tip::CovOp<HIP_vector_type<float, 2u> >, 1>"),
     (False, "fp64"): "k_stencil_march4<HIP_vector_type<double, 2u>, 5, false>",
     (False, "fp32"): "k_stencil_march4<HIP_vector_type<float, 2u>, 5, false>",
@@ -108,7 +110,9 @@ def write_traffic(fetch_csv, write_csv, kernel_match, command):
     out = {"kernel": kernel_match, "source_sha256": kernel_source_hash(),
            "fetch_kib_per_launch": fk, "fetch_scale": fs, "write_kib_per_launch": wk, "write_scale": ws,
            "launches": [nf, nw], "traffic_bytes_per_launch": 1024.0 * (fk * fs + wk * ws), "command": command}
-    records = [t for t in traffic_records() if t.get("kernel") != kernel_match] + [out]
+    # other kernels' records stay while they were taken on the same sources
+    records = [t for t in traffic_records()
+               if t.get("kernel") != kernel_match and t.get("source_sha256") == out["source_sha256"]] + [out]
     with open(TRAFFIC_FILE, "w") as f:
         json.dump({"records": records}, f, indent=1)
         f.write("\n")
@@ -333,7 +337,7 @@ def bench_c2h(args):
     if not tot["eo"]:
         name = "k_stencil_march<ScalarOp<double>>"
     elif os.environ.get("TIP_EO_PAIR") == "0":
-        name = "k_eo_hop<tip::ScalarOp<double>, 1, 5>"
+        name = "k_eo_hop<tip::ScalarOp<double>, 1, 5, 256>"
     else:
         name = "k_eo_hop_pair<tip::ScalarOp<double>, 1>"
     out = {"metric": "scalar stencil HBM GB/s vs peak (3D 256^3 weighted Laplacian, rel.res 1e-10)",

@@ -318,7 +318,8 @@ struct Plan {
   bool eo = false;  // CG on the even-odd reduced system
   MarchMap me;      // half-lattice march (valid when eo)
   bool pair = false;  // single-precision covariant hops with two rhs per thread (B = 32)
-  MarchMap me2;       // their march (16 sites per tile)
+  bool wide = false;  // FP64 covariant hops with 512-thread workgroups (B = 32)
+  MarchMap me2;       // the march of either (16 sites per tile)
 };
 
 bool env_off(const char* name) {
@@ -628,6 +629,12 @@ struct Solver {
       pl.pair = pl.eo && pair_op && pl.B == 32 && !env_off("TIP_EO_PAIR") &&
                 make_marchmap(g, 4, &pl.me2, true, p->round_tiles > 0 ? p->round_tiles : 128, p->march_tc) &&
                 (h->kind != TIP_KIND_COVARIANT || eo_lds_bytes(g, pl.me2, prec) <= 65536);
+      // FP64 covariant, 32 rhs: the same tiles of 16 sites with one rhs per
+      // lane, in 512-thread workgroups (TIP_EO_WIDE=0 turns this off)
+      pl.wide = !pl.pair && pl.eo && !mixed && h->kind == TIP_KIND_COVARIANT && pl.B == 32 &&
+                !env_off("TIP_EO_WIDE") &&
+                make_marchmap(g, 4, &pl.me2, true, p->round_tiles > 0 ? p->round_tiles : 128, p->march_tc) &&
+                eo_lds_bytes(g, pl.me2, prec) <= 65536;
     }
     max_iter = p->max_iter > 0 ? p->max_iter : (int)std::min<int64_t>(10 * V * ncomp, 1 << 20);
     tol2 = p->tol * p->tol;
@@ -657,7 +664,7 @@ struct Solver {
     vbytes64 = nelem * esz64;
     nvec = pl.eo ? nelem / 2 : nelem;             // elements the CG vector passes touch
     gx_m = (int)(pl.eo ? pl.me.grid : (pl.use_march ? pl.mm.grid : pl.tm.grid));
-    gx_p = pl.pair ? (int)pl.me2.grid : gx_m;
+    gx_p = (pl.pair || pl.wide) ? (int)pl.me2.grid : gx_m;
     gx_u = (int)update_grid(nvec);
     gx_t = (int)ru_grid(pl.tm);
     pstride = (size_t)B * std::max(std::max(gx_m, gx_p), std::max(gx_u, gx_t));
@@ -846,6 +853,11 @@ struct Solver {
       if (tv) TIP_HIP(hipEventRecord(tv->b, st));
       TIP_HIP(launch_eo_hop_pair(1, od, g, pl.me2, 0, prec, diag, sc.state, sc.active, Tv, Pv, W, part, ran_dev + it,
                                  st));
+    } else if (pl.wide) {
+      TIP_HIP(launch_eo_hop_wide(0, od, g, pl.me2, 1, diag, sc.state, sc.active, Pv, nullptr, Tv, nullptr, nullptr,
+                                 st));
+      if (tv) TIP_HIP(hipEventRecord(tv->b, st));
+      TIP_HIP(launch_eo_hop_wide(1, od, g, pl.me2, 0, diag, sc.state, sc.active, Tv, Pv, W, part, ran_dev + it, st));
     } else if (pl.eo) {
       // w_e = S p_e: t_o = D_o^-1 H_oe p_e, then w_e = D_e p_e - H_eo t_o
       TIP_HIP(launch_eo_hop(0, od, g, pl.me, 1, pl.elem, prec, diag, sc.state, sc.active, Pv, nullptr, Tv,

@@ -159,8 +159,8 @@ __device__ __forceinline__ void add_weighted(double wgt, const T (&h)[NC], T (&a
 // Sum per right-hand side over a 256-thread workgroup whose lane l holds rhs
 // l mod B: a shuffle tree inside each wave down to B lanes, then the four
 // wave results through LDS.  Threads tid < B end with the totals of rhs tid.
-template <int N>
-__device__ __forceinline__ void seg_sum(double (&v)[N], int B, double* lds /* [N][4][64] */) {
+template <int N, int W = 4>
+__device__ __forceinline__ void seg_sum(double (&v)[N], int B, double* lds /* [N][W][64] */) {
 #pragma unroll
   for (int i = 0; i < N; ++i)
     for (int off = 32; off >= B; off >>= 1) v[i] += __shfl_down(v[i], off, 64);
@@ -168,15 +168,23 @@ __device__ __forceinline__ void seg_sum(double (&v)[N], int B, double* lds /* [N
   __syncthreads();
   if (lane < B) {
 #pragma unroll
-    for (int i = 0; i < N; ++i) lds[(i * 4 + wave) * 64 + lane] = v[i];
+    for (int i = 0; i < N; ++i) lds[(i * W + wave) * 64 + lane] = v[i];
   }
   __syncthreads();
   if ((int)threadIdx.x < B) {
     const int t = threadIdx.x;
 #pragma unroll
-    for (int i = 0; i < N; ++i)
-      v[i] = (lds[(i * 4 + 0) * 64 + t] + lds[(i * 4 + 1) * 64 + t]) +
-             (lds[(i * 4 + 2) * 64 + t] + lds[(i * 4 + 3) * 64 + t]);
+    for (int i = 0; i < N; ++i) {
+      // pairs of waves, then pairs of pairs: a fixed order for any W
+      double q[W];
+#pragma unroll
+      for (int w = 0; w < W; ++w) q[w] = lds[(i * W + w) * 64 + t];
+#pragma unroll
+      for (int h = 1; h < W; h <<= 1)
+#pragma unroll
+        for (int w = 0; w + h < W; w += 2 * h) q[w] += q[w + h];
+      v[i] = q[0];
+    }
   }
 }
 
@@ -1263,8 +1271,8 @@ static inline unsigned cdiv(size_t a, size_t b) { return (unsigned)((a + b - 1) 
 #ifndef TIP_EO_STREAMING
 #define TIP_EO_STREAMING 1
 #endif
-template <class Op, int MODE, int kLogB>
-__global__ __launch_bounds__(kBlock) void k_eo_hop(Geom g, MarchMap mm, int P, Op op,
+template <class Op, int MODE, int kLogB, int kNT = kBlock>
+__global__ __launch_bounds__(kNT) void k_eo_hop(Geom g, MarchMap mm, int P, Op op,
                                                    const double* __restrict__ diag, const double* __restrict__ w,
                                                    const int* __restrict__ state, const int* __restrict__ active,
                                                    const typename Op::T* __restrict__ in,
@@ -1282,14 +1290,14 @@ __global__ __launch_bounds__(kBlock) void k_eo_hop(Geom g, MarchMap mm, int P, O
   constexpr int NP = kResidual ? 5 : 1;
   const int logB = kLogB >= 0 ? kLogB : mm.logB;
   const int B = 1 << logB;
-  const int TS = kBlock >> logB;
+  const int TS = kNT >> logB;
   if (active && *active == 0) return;
   if (ran && blockIdx.x == 0 && threadIdx.x == 0) *ran = 1;
-  __shared__ double lds[NP * 4 * 64];
+  __shared__ double lds[NP * (kNT / 64) * 64];
   T* lds_links = reinterpret_cast<T*>(tip_dyn_lds);   // covariant: [2 ndim][9][TS]
   // scalar operator with couplings: the tile's weights [2 ndim][TS] (forward
   // w_mu(s), backward w_mu(s - mu)), read once per site instead of per lane
-  __shared__ double lds_w[kCov ? 1 : 2 * kMaxDim * kBlock];
+  __shared__ double lds_w[kCov ? 1 : 2 * kMaxDim * kNT];
   const int j = threadIdx.x & (B - 1);
   const int si = threadIdx.x >> logB;
   uint32_t q, chunk;
@@ -1323,7 +1331,7 @@ __global__ __launch_bounds__(kBlock) void k_eo_hop(Geom g, MarchMap mm, int P, O
       // links of the tile's own sites (parity P, index x + V3 tau), backward
       // ones at the neighbours of parity 1 - P (same slice for spatial mu,
       // slice tau - 1 + delta along t)
-      for (int it = threadIdx.x; it < nslot * 9 * TS; it += kBlock) {
+      for (int it = threadIdx.x; it < nslot * 9 * TS; it += kNT) {
         const int site = it % TS;
         const int es = it / TS;
         const int e = es % 9;
@@ -1352,7 +1360,7 @@ __global__ __launch_bounds__(kBlock) void k_eo_hop(Geom g, MarchMap mm, int P, O
       if (w) {
         __syncthreads();
         const int nslot = 2 * ndim;
-        for (int it = threadIdx.x; it < nslot * TS; it += kBlock) {
+        for (int it = threadIdx.x; it < nslot * TS; it += kNT) {
           const int site = it % TS;
           const int slot = it / TS;
           const uint32_t x3 = s3_first + (uint32_t)site;
@@ -1538,7 +1546,7 @@ __global__ __launch_bounds__(kBlock) void k_eo_hop(Geom g, MarchMap mm, int P, O
     }
   }
   if (partial) {
-    seg_sum<NP>(acc, B, lds);
+    seg_sum<NP, kNT / 64>(acc, B, lds);
     if ((int)threadIdx.x < B) {
 #pragma unroll
       for (int k = 0; k < NP; ++k) partial[k * pstride + (size_t)threadIdx.x * gridDim.x + blockIdx.x] = acc[k];
@@ -2067,6 +2075,29 @@ hipError_t launch_eo_hop(int mode, const OpDev& od, const Geom& g, const MarchMa
         break;
     }
   });
+}
+
+// FP64 covariant modes 0 and 1 with 512-thread workgroups: one rhs per lane as
+// in k_eo_hop, 16 sites per tile (the march map built for that tile size).
+// Measured at 32^4 against 256 threads (8 sites per tile): 749 against 772 us
+// for the dominant hop; 1024 threads (a whole x1 row per tile) gained nothing.
+hipError_t launch_eo_hop_wide(int mode, const OpDev& od, const Geom& g, const MarchMap& mm, int P,
+                              const double* diag, const int* state, const int* active, const void* in,
+                              const void* cin, void* out, double* partial, int* ran, hipStream_t st) {
+  using Op = CovOp<double2>;
+  constexpr int kNT = 2 * kBlock;
+  Op op{reinterpret_cast<const double2*>(od.links_eo)};
+  const size_t lds = eo_lds_bytes(g, mm, Prec::kF64);
+  const double2* x = (const double2*)in;
+  const double2* c = (const double2*)cin;
+  auto go = [&](auto kern) {
+    kern<<<mm.grid, kNT, lds, st>>>(g, mm, P, op, diag, od.coupling, state, active, x, c, (double2*)out, nullptr,
+                                    nullptr, 0, 0, 0, 0, mode == 1 ? partial : nullptr, ran, nullptr, nullptr,
+                                    nullptr, 0);
+  };
+  if (mode == 0) go(k_eo_hop<Op, 0, 5, kNT>);
+  else go(k_eo_hop<Op, 1, 5, kNT>);
+  return hipGetLastError();
 }
 
 hipError_t launch_eo_hop_pair(int mode, const OpDev& od, const Geom& g, const MarchMap& mm, int P, Prec prec,

@@ -154,6 +154,11 @@ size_t eo_lds_bytes(const Geom& g, const MarchMap& mm, Prec prec);
 // Modes 0 and 1 with two rhs per thread (B = 32; the march map built for 16
 // lanes per site, 16 sites per tile) for the single-precision covariant and
 // the FP64 real scalar operators; hipErrorInvalidValue for any other.
+// FP64 covariant modes 0 and 1 with 512-thread workgroups (B = 32, 16 sites per
+// tile; the same march map as the pair kernel).
+hipError_t launch_eo_hop_wide(int mode, const OpDev& od, const Geom& g, const MarchMap& mm, int P,
+                              const double* diag, const int* state, const int* active, const void* in,
+                              const void* cin, void* out, double* partial, int* ran, hipStream_t st);
 hipError_t launch_eo_hop_pair(int mode, const OpDev& od, const Geom& g, const MarchMap& mm, int P, Prec prec,
                               const double* diag, const int* state, const int* active, const void* in,
                               const void* cin, void* out, double* partial, int* ran, hipStream_t st);

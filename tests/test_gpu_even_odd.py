@@ -228,3 +228,25 @@ def test_fp64_scalar_two_rhs_per_thread_matches_one(dims, n, coupled):
     if orc.V <= 4096:
         est_o, q_o, _ = oracle_trace(orc, n, tol, 4018, MASK_Z2)
         assert _rel(q, q_o) <= REL
+
+
+@pytest.mark.parametrize("dims,n", [([16, 16, 16, 16], 16), ([8, 8, 8, 8], 12), ([8, 4, 8], 12)])
+def test_fp64_covariant_512_thread_hops_match_256(dims, n):
+    """FP64 covariant operator, 32 rhs per block: the iteration's two hops run
+    in 512-thread workgroups (16 sites per tile, one rhs per lane).  Each site
+    is computed as in the 256-thread kernel, so against TIP_EO_WIDE=0 the
+    quadratures agree to rounding; 4-D and 3-D lattices, several tiles."""
+    tip = gpu_binding()
+    orc, gop = _ops(tip, dims, 1, seed=490)
+    tol = 1e-12
+    print(f"512-thread hops: dims {dims} n {n}", flush=True)
+    est, q, st = tip.trace_inv_probe(gop, n, tol, 4018, mask=MASK_Z4, rhs_block=32)
+    est_1, q_1, st_1 = _with_env("TIP_EO_WIDE", "0", lambda: tip.trace_inv_probe(
+        gop, n, tol, 4018, mask=MASK_Z4, rhs_block=32))
+    assert st["even_odd"] == 1 and st_1["even_odd"] == 1
+    assert st["max_true_relres"] <= tol and st_1["max_true_relres"] <= tol
+    assert _rel(q, q_1) <= REL
+    assert abs(st["total_iters"] - st_1["total_iters"]) <= st["solves"]
+    if orc.V <= 4096:
+        est_o, q_o, _ = oracle_trace(orc, n, tol, 4018, MASK_Z4)
+        assert _rel(q, q_o) <= REL
