@@ -41,7 +41,7 @@ STENCIL = {
     (True, "fp64"): ("k_eo_hop<tip::CovOp<HIP_vector_type<double, 2u> >, 1, 5, 256>" if os.environ.get("TIP_EO_WIDE") == "0"
                      else "k_eo_hop<tip::CovOp<HIP_vector_type<double, 2u> >, 1, 5, 512>"),
     (True, "fp32"): ("k_eo_hop<tip::CovOp<HIP_vector_type<float, 2u> >, 1, 5, 256>" if os.environ.get("TIP_EO_PAIR") == "0"
-                     else "k_eo_hop_pair<tip::CovOp<HIP_vector_type<float, 2u> >, 1>"),
+                     else "k_eo_hop_pair<tip::CovOp<HIP_vector_type<float, 2u> >, 1, 256>"),
     (False, "fp64"): "k_stencil_march4<HIP_vector_type<double, 2u>, 5, false>",
     (False, "fp32"): "k_stencil_march4<HIP_vector_type<float, 2u>, 5, false>",
 }
@@ -339,7 +339,7 @@ def bench_c2h(args):
     elif os.environ.get("TIP_EO_PAIR") == "0":
         name = "k_eo_hop<tip::ScalarOp<double>, 1, 5, 256>"
     else:
-        name = "k_eo_hop_pair<tip::ScalarOp<double>, 1>"
+        name = "k_eo_hop_pair<tip::ScalarOp<double>, 1, 512>"
     out = {"metric": "scalar stencil HBM GB/s vs peak (3D 256^3 weighted Laplacian, rel.res 1e-10)",
            "value": round(ach, 1), "unit": "GB/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
            "ms_per_step": round(el / args.steps * 1e3, 2), "higher_is_better": True, "scaling": "weak",

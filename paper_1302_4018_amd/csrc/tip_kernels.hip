@@ -1609,8 +1609,8 @@ __device__ __forceinline__ void store_pair_nt(T* __restrict__ v, size_t Vh, uint
   }
 }
 
-template <class Op, int MODE>
-__global__ __launch_bounds__(kBlock) void k_eo_hop_pair(Geom g, MarchMap mm, int P, Op op,
+template <class Op, int MODE, int kNT = kBlock>
+__global__ __launch_bounds__(kNT) void k_eo_hop_pair(Geom g, MarchMap mm, int P, Op op,
                                                         const double* __restrict__ diag,
                                                         const double* __restrict__ w,
                                                         const int* __restrict__ state, const int* __restrict__ active,
@@ -1625,10 +1625,10 @@ __global__ __launch_bounds__(kBlock) void k_eo_hop_pair(Geom g, MarchMap mm, int
   static_assert(sizeof(T) == 8, "pair kernel: 8-byte lane elements");
   constexpr int kLP = 4;                          // 16 pair lanes per site: rhs 2l, 2l + 1
   constexpr int NL = 1 << kLP;
-  constexpr int TS = kBlock >> kLP;               // 16 sites per workgroup
+  constexpr int TS = kNT >> kLP;                  // 16 sites per 256-thread workgroup
   if (active && *active == 0) return;
   if (ran && blockIdx.x == 0 && threadIdx.x == 0) *ran = 1;
-  __shared__ double lds[2 * 4 * 64];
+  __shared__ double lds[2 * (kNT / 64) * 64];
   T* lds_links = reinterpret_cast<T*>(tip_dyn_lds);   // covariant: [2 ndim][9][TS]
   __shared__ double lds_w[kCov ? 1 : 2 * kMaxDim * TS];   // scalar with couplings: [2 ndim][TS]
   const int l = threadIdx.x & (NL - 1);
@@ -1658,7 +1658,7 @@ __global__ __launch_bounds__(kBlock) void k_eo_hop_pair(Geom g, MarchMap mm, int
       // the tile's links, as in k_eo_hop: forward U_mu of the tile's sites,
       // backward ones at the opposite-parity neighbours
       __syncthreads();
-      for (int it = threadIdx.x; it < nslot * 9 * TS; it += kBlock) {
+      for (int it = threadIdx.x; it < nslot * 9 * TS; it += kNT) {
         const int site = it % TS;
         const int es = it / TS;
         const int e = es % 9;
@@ -1686,7 +1686,7 @@ __global__ __launch_bounds__(kBlock) void k_eo_hop_pair(Geom g, MarchMap mm, int
     } else if (w) {
       // the tile's couplings, as in k_eo_hop: forward w_mu(s), backward w_mu(s - mu)
       __syncthreads();
-      for (int it = threadIdx.x; it < nslot * TS; it += kBlock) {
+      for (int it = threadIdx.x; it < nslot * TS; it += kNT) {
         const int site = it % TS;
         const int slot = it / TS;
         const uint32_t x3 = s3_first + (uint32_t)site;
@@ -1767,7 +1767,7 @@ __global__ __launch_bounds__(kBlock) void k_eo_hop_pair(Geom g, MarchMap mm, int
     store_pair_nt<T, NC>(out, Vh, h, l, ya, yb);
   }
   if constexpr (MODE == 1) {
-    seg_sum<2>(acc, NL, lds);
+    seg_sum<2, kNT / 64>(acc, NL, lds);
     if ((int)threadIdx.x < NL) {
       partial[(size_t)(2 * threadIdx.x) * gridDim.x + blockIdx.x] = acc[0];
       partial[(size_t)(2 * threadIdx.x + 1) * gridDim.x + blockIdx.x] = acc[1];
@@ -2107,6 +2107,15 @@ hipError_t launch_eo_hop_pair(int mode, const OpDev& od, const Geom& g, const Ma
     using Op = decltype(op);
     using T = typename Op::T;
     const size_t lds = Op::NC == 3 ? eo_lds_bytes(g, mm, prec) : 0;
+    if (mm.TS == 2 * (kBlock >> 4)) {             // 32-site tiles (the scalar form): 512 threads
+      if (mode == 0)
+        k_eo_hop_pair<Op, 0, 2 * kBlock><<<mm.grid, 2 * kBlock, lds, st>>>(
+            g, mm, P, op, diag, od.coupling, state, active, (const T*)in, nullptr, (T*)out, nullptr, ran);
+      else
+        k_eo_hop_pair<Op, 1, 2 * kBlock><<<mm.grid, 2 * kBlock, lds, st>>>(
+            g, mm, P, op, diag, od.coupling, state, active, (const T*)in, (const T*)cin, (T*)out, partial, ran);
+      return;
+    }
     if (mode == 0)
       k_eo_hop_pair<Op, 0><<<mm.grid, kBlock, lds, st>>>(g, mm, P, op, diag, od.coupling, state, active,
                                                         (const T*)in, nullptr, (T*)out, nullptr, ran);

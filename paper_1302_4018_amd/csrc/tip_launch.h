@@ -151,9 +151,10 @@ hipError_t launch_grad_accum(const OpDev& od64, const Geom& g, Elem elem, int lo
 hipError_t launch_scale(size_t n, double* a, double f, hipStream_t st);
 // even-odd reduced system (half-lattice vectors [ncomp][V/2][B], see k_eo_hop)
 size_t eo_lds_bytes(const Geom& g, const MarchMap& mm, Prec prec);
-// Modes 0 and 1 with two rhs per thread (B = 32; the march map built for 16
-// lanes per site, 16 sites per tile) for the single-precision covariant and
-// the FP64 real scalar operators; hipErrorInvalidValue for any other.
+// Modes 0 and 1 with two rhs per thread (B = 32, 16 lanes per site) for the
+// single-precision covariant and the FP64 real scalar operators, with 256
+// threads when the march map has 16 sites per tile and 512 when it has 32;
+// hipErrorInvalidValue for any other operator.
 // FP64 covariant modes 0 and 1 with 512-thread workgroups (B = 32, 16 sites per
 // tile; the same march map as the pair kernel).
 hipError_t launch_eo_hop_wide(int mode, const OpDev& od, const Geom& g, const MarchMap& mm, int P,
