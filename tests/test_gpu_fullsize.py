@@ -73,3 +73,22 @@ def test_one_quadrature_against_oracle_cg(workload):
         x, qg, _ = h.solve_probe(1, 2, TOL, 4018)
     qo, it, rr = quadrature(orc, 1, 2, TOL, 4018, MASK_Z4, 10000)
     assert abs(qg - qo) <= 1e-10 * abs(qo)
+
+
+@pytest.mark.timeout(900)
+def test_benchmark_blocking_against_oracle(workload):
+    """The benchmark's launch configuration: 32 rhs per block (the FP64 hops in
+    512-thread workgroups, the mixed-precision hops with two rhs per thread),
+    here 11 probes = 33 rhs, so the last block is ragged (one rhs).  Every
+    solve meets tol in both precisions, the two agree, and probe 10 (its three
+    components straddle the two blocks) matches the oracle's own CG solves."""
+    tip, gop, orc = workload
+    print("full-size benchmark blocking: 11 probes, 32-rhs blocks, FP64 and mixed", flush=True)
+    est64, q64, st64 = tip.trace_inv_probe(gop, 11, TOL, 4018)
+    est32, q32, st32 = tip.trace_inv_probe(gop, 11, TOL, 4018, precision=tip.PREC_MIXED)
+    assert st64["even_odd"] == 1 and st32["even_odd"] == 1
+    assert st64["max_true_relres"] <= TOL and st32["max_true_relres"] <= TOL
+    assert np.max(np.abs(q32 - q64) / np.abs(q64)) <= 1e-10
+    qo = sum(quadrature(orc, 10, c, TOL, 4018, MASK_Z4, 10000)[0] for c in range(3))
+    assert abs(q64[10] - qo) <= 1e-10 * abs(qo)
+    assert abs(q32[10] - qo) <= 1e-10 * abs(qo)
