@@ -92,3 +92,31 @@ def test_benchmark_blocking_against_oracle(workload):
     qo = sum(quadrature(orc, 10, c, TOL, 4018, MASK_Z4, 10000)[0] for c in range(3))
     assert abs(q64[10] - qo) <= 1e-10 * abs(qo)
     assert abs(q32[10] - qo) <= 1e-10 * abs(qo)
+
+
+@pytest.mark.timeout(900)
+def test_scalar_256_cubed_benchmark_configuration_against_oracle():
+    """The out-of-cache scalar workload as the benchmark runs it: 256^3 weighted
+    Laplacian (w ~ U[0.5, 1.5], m = 0.05), Z2 mask, 32 probes in one 32-rhs block
+    (the FP64 scalar hops with two rhs per thread in 512-thread workgroups).
+    Probe 31, the last lane, matches the oracle's own CG solve, and the estimate
+    matches the one-rhs-per-thread kernel (TIP_EO_PAIR=0) to rounding."""
+    import os
+    tip = gpu_binding()
+    dims = [256, 256, 256]
+    w = inputs.couplings(dims)
+    gop = tip.Operator(dims, tip.KIND_SCALAR, mass=0.05, coupling=to_dev(w))
+    print("full-size 256^3 scalar, 32 probes", flush=True)
+    est, q, st = tip.trace_inv_probe(gop, 32, TOL, 4018, mask=tip.MASK_Z2)
+    assert st["even_odd"] == 1 and st["max_true_relres"] <= TOL
+    os.environ["TIP_EO_PAIR"] = "0"
+    try:
+        est1, q1, st1 = tip.trace_inv_probe(gop, 32, TOL, 4018, mask=tip.MASK_Z2)
+    finally:
+        del os.environ["TIP_EO_PAIR"]
+    assert np.max(np.abs(q - q1) / np.abs(q1)) <= 1e-10
+    del gop
+    torch.cuda.empty_cache()
+    orc = OracleOp(dims, 0, mass=0.05, coupling=w)
+    qo, it, rr = quadrature(orc, 31, 0, TOL, 4018, tip.MASK_Z2, 10000)
+    assert abs(q[31] - qo) <= 1e-10 * abs(qo)
