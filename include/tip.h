@@ -138,7 +138,7 @@ enum { TIP_PROBE_HIERARCHICAL = 0, TIP_PROBE_NATURAL = 1, TIP_PROBE_RANDOM = 2, 
 /* Operator description.  Arrays are DEVICE pointers, read only. */
 typedef struct {
   int32_t ndim;              /* 1..4                                              */
-  int64_t dims[4];           /* n_1..n_ndim, powers of two                         */
+  int64_t dims[4];           /* n_1..n_ndim >= 1 (see "Lattice" above)             */
   int32_t kind;              /* TIP_KIND_SCALAR or TIP_KIND_COVARIANT              */
   double mass;               /* m(x) = mass when mass_field is NULL                */
   const double* mass_field;  /* [V] m(x), or NULL                                  */
