@@ -294,6 +294,19 @@ tip_status tip_solve_probe(tip_op_handle h, const tip_params* p, int64_t m, int3
 tip_status tip_apply_operator(const tip_operator* op, int32_t nrhs,
                               const double* x, double* y, void* stream);
 
+/* Measurement aid, not part of the method: the practical HBM ceiling of the
+ * device, for stating a kernel's rate against what a kernel that only moves
+ * data reaches on the same machine beside the published peak.  Allocates
+ * `bytes` of device memory split over the arrays of streaming kernel `kind`
+ * (0: read only, one array; 1: copy, two arrays; 2: three arrays read and one
+ * written, d = a + b + c), runs one warm-up pass and `reps` timed passes
+ * (hipEvents on `stream`) with 16-byte accesses and `grid` workgroups of 256
+ * threads (0 = 16 per compute unit), frees everything, and writes the device
+ * time of one pass and the bytes one pass moves (HOST doubles).  bytes >= 1 MiB,
+ * reps >= 1; pick bytes well above the 256 MB last-level cache. */
+tip_status tip_stream_ceiling(int32_t kind, int64_t bytes, int32_t reps, int32_t grid,
+                              double* seconds_per_pass, double* bytes_per_pass, void* stream);
+
 /* P(x) of every site (Alg. 5): DEVICE uint32 [V].  With odd factors in the
  * sides: the binary colour over the B binary levels, in [0, 2^LB). */
 tip_status tip_hier_perm(int32_t ndim, const int64_t* dims, uint32_t* P_out, void* stream);

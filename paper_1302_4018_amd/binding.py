@@ -84,6 +84,8 @@ def _load():
         "tip_probe_vectors": (ctypes.c_int, [ctypes.c_int32, P(ctypes.c_int64), ctypes.c_int32, ctypes.c_int32,
                                              ctypes.c_uint64, ctypes.c_int64, ctypes.c_int64, ctypes.c_int32,
                                              ctypes.c_int32, ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p]),
+        "tip_stream_ceiling": (ctypes.c_int, [ctypes.c_int32, ctypes.c_int64, ctypes.c_int32, ctypes.c_int32,
+                                              P(ctypes.c_double), P(ctypes.c_double), ctypes.c_void_p]),
         "tip_set_profiling": (None, [ctypes.c_int32]),
         "tip_last_error": (ctypes.c_char_p, []),
     }
@@ -396,6 +398,15 @@ def tip_probe_vectors(dims, ncomp, mask, seed, m0, count, comp, stream=None, pro
                                  int(count), int(comp), int(probe), int(stop_levels), _ptr(out), _stream(stream)),
            "tip_probe_vectors")
     return torch.view_as_complex(out)
+
+
+def tip_stream_ceiling(kind, nbytes, reps=10, grid=0, stream=None):
+    """(seconds per pass, bytes per pass) of streaming kernel `kind` (0 read,
+    1 copy, 2 three reads + one write) over `nbytes` of device memory."""
+    sec, byt = ctypes.c_double(), ctypes.c_double()
+    _check(lib.tip_stream_ceiling(int(kind), int(nbytes), int(reps), int(grid), ctypes.byref(sec), ctypes.byref(byt),
+                                  _stream(stream)), "tip_stream_ceiling")
+    return sec.value, byt.value
 
 
 def tip_set_profiling(on):

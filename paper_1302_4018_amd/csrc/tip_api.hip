@@ -150,6 +150,8 @@ struct HostPinned {
 
 }  // namespace
 
+void tip::set_last_error(const char* msg) { g_err = msg; }
+
 struct tip_op_s {
   Geom geom{};                 // ncomp filled from kind
   int kind = 0;

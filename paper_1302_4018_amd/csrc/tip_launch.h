@@ -9,6 +9,9 @@
 
 namespace tip {
 
+// Message returned by tip_last_error() for the calling thread.
+void set_last_error(const char* msg);
+
 enum class Elem { kReal, kComplex };
 enum class Prec { kF64, kF32 };            // storage and arithmetic of the CG vectors and links
 
