@@ -294,6 +294,26 @@ tip_status tip_solve_probe(tip_op_handle h, const tip_params* p, int64_t m, int3
 tip_status tip_apply_operator(const tip_operator* op, int32_t nrhs,
                               const double* x, double* y, void* stream);
 
+/* tip_apply_operator for callers that cannot allocate device memory (code
+ * under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc): the same kernels and arithmetic (results equal bit for bit),
+ * with the caller's mass field and couplings read in place and the
+ * workspace (repacked links and the input and output vectors in the kernels'
+ * layout) in a fixed device array of the library, 64 MiB per GPU, held from
+ * first use until the process ends.  No hipMalloc, hipFree or allocating
+ * library routine is called; the first call on a device also resolves the
+ * array's device address there (hipGetSymbolAddress).  Lattices whose
+ * workspace exceeds 64 MiB (ndim * 9 * V * 16 bytes of links for the
+ * covariant operator plus two vectors of ncomp * V elements, each part
+ * rounded up to 256 bytes) fail with TIP_EINVAL before any device work.
+ * Calls on one GPU share the array: calls that overlap on one GPU (from
+ * several host threads, or on several streams) race and must be serialised
+ * by the caller.  Every byte a call reads from the array it wrote earlier in
+ * the same call, so nothing carries over between calls.  Synchronises
+ * `stream` before returning. */
+tip_status tip_apply_operator_noalloc(const tip_operator* op, int32_t nrhs,
+                                      const double* x, double* y, void* stream);
+
 /* Measurement aid, not part of the method: the practical HBM ceiling of the
  * device, for stating a kernel's rate against what a kernel that only moves
  * data reaches on the same machine beside the published peak.  Allocates

@@ -80,6 +80,8 @@ def _load():
                                            ctypes.c_void_p, P(ctypes.c_double), P(tip_stats)]),
         "tip_apply_operator": (ctypes.c_int, [P(tip_operator), ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p,
                                               ctypes.c_void_p]),
+        "tip_apply_operator_noalloc": (ctypes.c_int, [P(tip_operator), ctypes.c_int32, ctypes.c_void_p,
+                                                      ctypes.c_void_p, ctypes.c_void_p]),
         "tip_hier_perm": (ctypes.c_int, [ctypes.c_int32, P(ctypes.c_int64), ctypes.c_void_p, ctypes.c_void_p]),
         "tip_probe_vectors": (ctypes.c_int, [ctypes.c_int32, P(ctypes.c_int64), ctypes.c_int32, ctypes.c_int32,
                                              ctypes.c_uint64, ctypes.c_int64, ctypes.c_int64, ctypes.c_int32,
@@ -375,6 +377,24 @@ def tip_apply_operator(op, x, stream=None):
     s = op.c_struct()
     _check(lib.tip_apply_operator(ctypes.byref(s), int(x.shape[0]), _ptr(xr), _ptr(y), _stream(stream)),
            "tip_apply_operator")
+    return torch.view_as_complex(y) if x.is_complex() else y
+
+
+def tip_apply_operator_noalloc(op, x, y=None, stream=None):
+    """y = A x as tip_apply_operator, with no device allocation inside the
+    library (its workspace is the library's fixed scratch); y is allocated
+    here unless the caller passes it."""
+    import torch
+    _need_cuda(x, "x")
+    xr = torch.view_as_real(x) if x.is_complex() else x
+    if y is None:
+        y = torch.empty_like(xr)
+    else:
+        _need_cuda(y, "y")
+        y = torch.view_as_real(y) if y.is_complex() else y
+    s = op.c_struct()
+    _check(lib.tip_apply_operator_noalloc(ctypes.byref(s), int(x.shape[0]), _ptr(xr), _ptr(y), _stream(stream)),
+           "tip_apply_operator_noalloc")
     return torch.view_as_complex(y) if x.is_complex() else y
 
 

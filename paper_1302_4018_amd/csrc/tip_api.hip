@@ -1573,6 +1573,105 @@ tip_status tip_apply_operator(const tip_operator* op, int32_t nrhs, const double
   return ret;
 }
 
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// Operator application without allocation.  Its workspace (repacked links and
+// the block-layout input and output vectors) lives in `scratch`, a file-scope
+// device array of kScratchBytes: every GPU the library runs on holds its own
+// copy until the process ends, and calls on one GPU share it (overlapping
+// calls on one GPU race).  In host code the array's name is only a stand-in
+// for the variable; its device address is taken once per device with
+// hipGetSymbolAddress, with that device current, and only that address is
+// handed to kernels.  Every byte a call reads from the scratch was written
+// earlier in the same call, so nothing needs clearing between calls.
+// ---------------------------------------------------------------------------
+
+namespace {
+constexpr size_t kScratchBytes = size_t(64) << 20;     // 64 MiB per device
+constexpr int kMaxScratchDevices = 64;
+}  // namespace
+
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+namespace {
+
+std::mutex g_scratch_mu;
+void* g_scratch_addr[kMaxScratchDevices] = {};
+
+// Device address of `scratch` on the current device.
+tip_status scratch_address(void** out) {
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess) return fail(TIP_EDEVICE, "hipGetDevice failed");
+  if (dev < 0 || dev >= kMaxScratchDevices)
+    return fail(TIP_EUNSUPPORTED, "device %d: the no-allocation scratch covers devices 0..%d", dev,
+                kMaxScratchDevices - 1);
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_addr[dev]) {
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p)
+      return fail(TIP_EDEVICE, "hipGetSymbolAddress(scratch) failed on device %d: %s", dev, hipGetErrorString(e));
+    g_scratch_addr[dev] = p;
+  }
+  *out = g_scratch_addr[dev];
+  return TIP_OK;
+}
+
+size_t align256(size_t n) { return (n + 255) & ~size_t(255); }
+
+}  // namespace
+
+extern "C" {
+
+tip_status tip_apply_operator_noalloc(const tip_operator* op, int32_t nrhs, const double* x, double* y,
+                                      void* stream) {
+  Geom g;
+  tip_status s = validate_op(op, &g);
+  if (s != TIP_OK) return s;
+  if (nrhs < 1) return fail(TIP_EINVAL, "nrhs = %d must be >= 1", nrhs);
+  if (!x || !y) return fail(TIP_EINVAL, "x or y is NULL");
+  const bool cov = op->kind == TIP_KIND_COVARIANT;
+  const Elem elem = cov ? Elem::kComplex : Elem::kReal;
+  const size_t esz = cov ? sizeof(double2) : sizeof(double);
+  const size_t bytes = (size_t)g.ncomp * g.V * esz;                   // one vector
+  const size_t link_bytes = cov ? (size_t)g.ndim * 9 * g.V * sizeof(double2) : 0;
+  const size_t need = align256(link_bytes) + 2 * align256(bytes);
+  if (need > kScratchBytes)
+    return fail(TIP_EINVAL, "lattice needs %zu bytes of workspace; the no-allocation scratch holds %zu", need,
+                kScratchBytes);
+  void* base = nullptr;
+  s = scratch_address(&base);
+  if (s != TIP_OK) return s;
+  hipStream_t st = (hipStream_t)stream;
+  char* links = (char*)base;
+  char* in = links + align256(link_bytes);
+  char* out = in + align256(bytes);
+  // the caller's mass field and couplings are read in place; the links are
+  // repacked into the scratch ([ndim][9][V], as the kernels read them)
+  OpDev od{};
+  od.kind = op->kind;
+  od.mass = op->mass;
+  od.mass_field = op->mass_field;
+  od.coupling = op->coupling;
+  od.links = cov ? (const double*)links : nullptr;
+  od.links_eo = nullptr;
+  if (cov && launch_repack_links(g, (const double2*)op->links, (double2*)links, st) != hipSuccess)
+    return fail(TIP_EDEVICE, "link repack launch failed");
+  const TileMap tm = make_tilemap(g, 0);
+  for (int k = 0; k < nrhs; ++k) {
+    const char* xk = (const char*)x + k * bytes;
+    char* yk = (char*)y + k * bytes;
+    if (launch_layout(g, elem, 0, 0, xk, in, true, st) != hipSuccess ||
+        launch_stencil(od, g, tm, nullptr, elem, Prec::kF64, nullptr, nullptr, in, out, nullptr, nullptr, st) !=
+            hipSuccess ||
+        launch_layout(g, elem, 0, 0, out, yk, false, st) != hipSuccess)
+      return fail(TIP_EDEVICE, "apply launch failed");
+  }
+  if (hipStreamSynchronize(st) != hipSuccess) return fail(TIP_EDEVICE, "apply failed on the device");
+  return TIP_OK;
+}
+
 tip_status tip_hier_perm(int32_t ndim, const int64_t* dims, uint32_t* P_out, void* stream) {
   Geom g;
   tip_status s = make_geom(ndim, dims, 1, &g);
