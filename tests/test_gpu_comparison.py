@@ -63,5 +63,5 @@ def test_study_workload_first_probes_against_oracle():
     for probe in (general.PROBE_HIERARCHICAL, general.PROBE_NATURAL, general.PROBE_RANDOM):
         est, q, st = tip.trace_inv_probe(gop, 4, 1e-10, 7, mask=MASK_Z2, probe=probe)
         est_o, _, _ = general.trace_inv_probe(orc, 4, 1e-10, 7, MASK_Z2, probe=probe)
-        assert np.max(np.abs(est - est_o) / np.abs(est_o)) <= 1e-9, probe
+        assert np.max(np.abs(est - est_o) / np.abs(est_o)) <= REL, probe
         assert abs(est[-1] - tr) / tr < 0.5

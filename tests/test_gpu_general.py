@@ -5,7 +5,7 @@ bit against the oracle, and the whole probing run against the oracle's CG."""
 import numpy as np
 import pytest
 
-from conftest import gpu_binding, to_dev
+from conftest import assert_gradient_entries, gpu_binding, to_dev
 from oracle import general
 from oracle.gradient import trace_inv_probe_grad as oracle_grad
 from oracle.mask import MASK_NONE, MASK_Z2, MASK_Z4
@@ -74,10 +74,8 @@ def test_gradient_on_an_odd_torus():
     with tip.OpHandle(gop) as h:
         est, q, gm, gw, st = h.trace_inv_probe_grad(30, 1e-12, 4018)
     T, gm_o, gw_o, _ = oracle_grad(orc, 30, 1e-12, 4018, MASK_Z2)
-    kappa = (0.3 + 0.06 + 4 * 3 * 1.5) / (0.3 - 0.06)
     assert abs(est[-1] - T) <= REL * abs(T)
-    for a, b in ((gm.cpu().numpy(), gm_o), (gw.cpu().numpy(), gw_o)):
-        assert np.sum(np.abs(a - b)) <= 4 * kappa * 1e-12 * np.sum(np.abs(b))
+    assert_gradient_entries(gm.cpu().numpy(), gw.cpu().numpy(), gm_o, gw_o, 1e-12, orc.V, float(np.min(mf)))
 
 
 def _no_split(tip, fn):

@@ -4,9 +4,9 @@ determinism, resume, blocking independence and the error paths."""
 import numpy as np
 import pytest
 
-from conftest import gpu_binding, to_dev
+from conftest import gpu_binding, read_quadratures, to_dev
 from oracle import exact
-from oracle.estimator import trace_inv_probe as oracle_trace, quadrature
+from oracle.estimator import estimates_from_quadratures, trace_inv_probe as oracle_trace, quadrature
 from oracle.mask import MASK_NONE, MASK_Z2, MASK_Z4
 from oracle.operators import Operator as OracleOp
 from paper_1302_4018_amd import inputs
@@ -46,25 +46,47 @@ def test_c1_16x16_all_vectors():
     assert st["solves"] == 256
 
 
-def test_c2_32cubed_weighted_subset():
-    """3-D 32^3, w ~ U[0.5, 1.5], m = 0.05, Z2, tol 1e-10: first 16 probes."""
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_c2_32cubed_weighted_all_512_probes(precision):
+    """3-D 32^3, w ~ U[0.5, 1.5], m = 0.05, Z2, tol 1e-10: all 512 probes (the
+    3-D completion points s = 2, 16, 128 and s = 512) against the stored oracle
+    quadratures, every q_m and every estimate."""
     tip = gpu_binding()
-    orc, gop = _ops(tip, [32, 32, 32], 0, mass=0.05, coupled=True)
-    est, q, st = tip.trace_inv_probe(gop, 16, 1e-10, 4018)
-    est_o, q_o, _ = oracle_trace(orc, 16, 1e-10, 4018, MASK_Z2)
-    assert _rel(est, est_o) <= REL
+    _, gop = _ops(tip, [32, 32, 32], 0, mass=0.05, coupled=True)
+    prec = tip.PREC_MIXED if precision == "mixed" else tip.PREC_FP64
+    est, q, st = tip.trace_inv_probe(gop, 512, 1e-10, 4018, precision=prec)
+    q_o = read_quadratures("quadratures_c2_32x32x32.txt")["c2"]
+    assert st["solves"] == 512 and st["max_true_relres"] <= 1e-10
     assert _rel(q, q_o) <= REL
+    assert _rel(est, estimates_from_quadratures(q_o)) <= REL
 
 
-def test_c3_16to4_covariant_subset():
-    """4-D 16^4 covariant, Haar U(3), m = 0.1, Z4: first 4 probes (12 solves)."""
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_c3_16to4_covariant_64_probes(precision):
+    """4-D 16^4 covariant, Haar U(3), m = 0.1, Z4, tol 1e-10: 64 probes (192
+    solves, past the 4-D completion point s = 32) against the stored oracle
+    quadratures."""
+    tip = gpu_binding()
+    _, gop = _ops(tip, [16, 16, 16, 16], 1)
+    prec = tip.PREC_MIXED if precision == "mixed" else tip.PREC_FP64
+    est, q, st = tip.trace_inv_probe(gop, 64, 1e-10, 4018, precision=prec)
+    q_o = read_quadratures("quadratures_c3_16x16x16x16.txt")["c3"]
+    assert st["solves"] == 192 and st["max_true_relres"] <= 1e-10
+    assert _rel(q, q_o) <= REL
+    assert _rel(est, estimates_from_quadratures(q_o)) <= REL
+    assert np.abs(est.imag).max() <= 1e-9 * np.abs(est.real).max()
+
+
+def test_c3_16to4_first_probes_against_a_live_oracle_run():
+    """The same workload's first 4 probes (12 solves) with the oracle run here,
+    so the stored quadratures are checked against the oracle as it stands."""
     tip = gpu_binding()
     orc, gop = _ops(tip, [16, 16, 16, 16], 1)
     est, q, st = tip.trace_inv_probe(gop, 4, 1e-10, 4018)
     est_o, q_o, _ = oracle_trace(orc, 4, 1e-10, 4018, MASK_Z4)
     assert _rel(est, est_o) <= REL
     assert _rel(q, q_o) <= REL
-    assert np.abs(est.imag).max() <= 1e-9 * np.abs(est.real).max()
+    assert _rel(q_o, read_quadratures("quadratures_c3_16x16x16x16.txt")["c3"][:4]) <= REL
 
 
 @pytest.mark.parametrize("dims", [[4, 4, 4, 4], [2, 8, 4, 2]])

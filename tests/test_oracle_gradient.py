@@ -137,3 +137,31 @@ def test_c1_uniform_mass_gradient_closed_form():
     T, gm, gw, _ = trace_inv_probe_grad(op, 256, 1e-13, 4018, mask.MASK_Z2)
     assert abs(gm.sum() - (-231.195071582666)) <= 1e-9 * 231.195071582666
     assert abs(T.real - 116.949743403339) <= 1e-10 * 116.949743403339
+
+
+@pytest.mark.parametrize("kind", [0, 1])
+def test_entry_bounds_hold_and_catch_one_wrong_entry(kind):
+    """The per-entry bound the GPU gradient tests use (conftest) holds between
+    the oracle's CG gradient at s = V and the dense exact one, and a single
+    entry off by one part in 10^6 (a planted mistake in the oracle's result)
+    breaks it, for the mass and for the coupling gradient."""
+    from conftest import assert_gradient_entries
+    dims = [2, 2, 4, 2] if kind == 1 else [8, 8]
+    mf = inputs.mass_field(dims, m0=0.3, seed=71)
+    w = inputs.couplings(dims, seed=72)
+    U = inputs.haar_links(dims, seed=73) if kind == 1 else None
+    op = Operator(dims, kind, mass_field=mf, coupling=w, links=U)
+    V = op.V
+    tol = 1e-12
+    _, gm, gw, _ = trace_inv_probe_grad(op, V, tol, 5, mask.MASK_NONE)
+    dm, dw = dense_trace_inverse_grad(op)
+    lam = float(np.min(mf))
+    assert_gradient_entries(gm, gw, dm, dw, tol, V, lam)
+    bad = gm.copy()
+    bad[V // 3] *= 1.0 + 1e-6
+    with pytest.raises(AssertionError, match="mass gradient entry"):
+        assert_gradient_entries(bad, gw, dm, dw, tol, V, lam)
+    bad = gw.copy()
+    bad[1, V // 2] *= 1.0 - 1e-6
+    with pytest.raises(AssertionError, match="coupling gradient entry"):
+        assert_gradient_entries(gm, bad, dm, dw, tol, V, lam)
