@@ -119,9 +119,57 @@ def write_traffic(fetch_csv, write_csv, kernel_match, command):
     print(json.dumps(out))
 
 
-def cpu_baseline(U, mf, seed, tol, n_rhs):
+_ORACLE = {}
+
+
+def _oracle_worker_init(seed, tol, barrier):
+    """Worker of the all-cores oracle run: builds the same 32^4 operator
+    (numpy on one thread), then waits for every other worker."""
+    from threadpoolctl import threadpool_limits
+
+    from oracle.hierperm import hier_perm
+    from oracle.operators import Operator
+    from paper_1302_4018_amd import inputs
+
+    _ORACLE["limits"] = threadpool_limits(limits=1)
+    _ORACLE["op"] = Operator(DIMS, 1, mass_field=inputs.mass_field(DIMS), links=inputs.haar_links(DIMS))
+    _ORACLE["P"] = hier_perm(DIMS)
+    _ORACLE["seed"], _ORACLE["tol"] = seed, tol
+    barrier.wait()
+
+
+def _oracle_worker_solve(k):
+    """One complete oracle CG solve of right-hand side k; (start, end, iterations)."""
+    from oracle.cg import cg_solve
+    from oracle.mask import MASK_Z4
+    from oracle.probing import rhs
+
+    op = _ORACLE["op"]
+    b = rhs(DIMS, 3, k // 3, k % 3, _ORACLE["seed"], MASK_Z4, _ORACLE["P"])
+    t0 = time.time()
+    _, it, _ = cg_solve(op.apply, b, _ORACLE["tol"], 10 * op.V * 3)
+    return t0, time.time(), it
+
+
+def host_cores():
+    """CPUs this process may run on, capped at the 16-core share a one-GPU
+    node gives each GPU."""
+    try:
+        n = len(os.sched_getaffinity(0))
+    except AttributeError:
+        n = os.cpu_count() or 1
+    return max(1, min(n, 16))
+
+
+def cpu_baseline(U, mf, seed, tol, n_rhs, all_cores=True):
     """The CPU oracle on a bounded sample: complete solves (textbook CG to the
-    same true residual) of the first n_rhs right-hand sides of this workload."""
+    same true residual) of the first right-hand sides of this workload, on one
+    host thread; then one solve per core on every core at once (one oracle
+    process per core, each on one thread, distinct right-hand sides), timed
+    from the moment all of them have their operator."""
+    import multiprocessing as mp
+
+    import numpy as np
     from threadpoolctl import threadpool_limits
 
     from oracle.cg import cg_solve
@@ -135,14 +183,53 @@ def cpu_baseline(U, mf, seed, tol, n_rhs):
         P = hier_perm(DIMS)
         bs = [rhs(DIMS, 3, k // 3, k % 3, seed, MASK_Z4, P) for k in range(n_rhs)]
         iters = []
+        q = 0.0 + 0.0j
         t0 = time.perf_counter()
-        for b in bs:
-            _, it, _ = cg_solve(op.apply, b, tol, 10 * op.V * 3)
+        for k, b in enumerate(bs):
+            x, it, _ = cg_solve(op.apply, b, tol, 10 * op.V * 3)
             iters.append(it)
+            if k < 3:
+                q += complex(np.vdot(b, x))           # q_0 = sum_c b_{0,c}^H x_{0,c}
         dt = time.perf_counter() - t0
-    return {"value": n_rhs / dt, "unit": "solves/s", "cores": 1, "kind": "oracle",
-            "sample": f"{n_rhs} complete oracle CG solves ({dt:.1f} s, {sum(iters) / len(iters):.1f} iterations each) "
-                      f"of the first right-hand sides of the same 32^4 workload"}
+    out = {"value": n_rhs / dt, "unit": "solves/s", "cores": 1, "kind": "oracle",
+           "sample": f"{n_rhs} complete oracle CG solves ({dt:.1f} s, {sum(iters) / len(iters):.1f} iterations each) "
+                     f"of the first right-hand sides of the same 32^4 workload, one host thread",
+           "nproc": os.cpu_count()}
+    if n_rhs >= 3:
+        out["_q0"] = q                                # probe 0 (three solves): the oracle's T_1
+    if all_cores:
+        n = host_cores()
+        ctx = mp.get_context("spawn")                 # fresh processes: numpy only, nothing of the GPU
+        barrier = ctx.Barrier(n)
+        with ctx.Pool(n, initializer=_oracle_worker_init, initargs=(seed, tol, barrier)) as pool:
+            res = pool.map(_oracle_worker_solve, range(n), chunksize=1)
+        span = max(e for _, e, _ in res) - min(s0 for s0, _, _ in res)
+        out["all_cores"] = {"value": n / span, "unit": "solves/s", "cores": n, "kind": "oracle",
+                            "sample": f"{n} oracle processes on one thread each, one complete solve each (right-hand "
+                                      f"sides 0..{n - 1}), all at once: {span:.1f} s from the first start to the "
+                                      f"last end", "nproc": os.cpu_count()}
+    return out
+
+
+def per_estimate_errors(mixed, fp64, lam_lb, q0_oracle=None):
+    """For every estimate T_k (s = 2^k) of the mixed-precision run: its relative
+    difference from the FP64 run's, and the bound on its own error, (1/s)
+    sum_{m<s,c} ||r||^2 / lambda_lb relative to T_k (its quadratures are the
+    variational b^H x + x^H r, whose error is r^H A^-1 r; ||r||^2 = V res^2
+    with the per-solve true residuals); at s = 1 both runs against the
+    oracle's T_1 from its own solves of probe 0."""
+    import numpy as np
+    V = float(np.prod(DIMS))
+    rows = []
+    for k, (tm, tf) in enumerate(zip(mixed["est"], fp64["est"])):
+        s = 1 << k
+        bm = float(np.sum(V * mixed["residuals"][:s] ** 2) / lam_lb / s)
+        row = {"s": s, "rel_diff_vs_fp64": float(abs(tm - tf) / abs(tf)), "bound_rel": bm / abs(tm)}
+        if k == 0 and q0_oracle is not None:
+            row["rel_err_vs_oracle_mixed"] = float(abs(tm - q0_oracle) / abs(q0_oracle))
+            row["rel_err_vs_oracle_fp64"] = float(abs(tf - q0_oracle) / abs(q0_oracle))
+        rows.append(row)
+    return rows
 
 
 def copy_calibration():
@@ -160,11 +247,15 @@ def copy_calibration():
 def bench_c4(args):
     """The batch of 64 independent uneven 3-D tori (sides iid in [8, 48], scalar
     weighted Laplacian with m ~ U[0.02, 0.2], w ~ U[0.5, 1.5], Z2 mask, 16..256
-    probes each) in one trace_inv_probe_batch call per step, with FP32 CG and
-    FP64 reliable updates (and FP64 beside it).  The tori are a few MB each, so
-    the stencil works from L2 / MALL: no HBM roofline applies to this line."""
+    probes each) in one trace_inv_probe_batch call per step: every CG phase of
+    every torus is one launch per group (real / complex probe classes), a
+    chunk of iterations of the whole batch is one HIP graph.  FP32 CG with
+    FP64 reliable updates (the headline of this line) and FP64 beside it.  The
+    block size and work-item size come from tip_autotune_batch (cached).  The
+    stencil roofline comes from one extra step with per-launch timing."""
     import torch
 
+    from paper_1302_4018_amd import autotune
     from paper_1302_4018_amd import binding as tip
     from paper_1302_4018_amd import inputs
 
@@ -180,48 +271,59 @@ def bench_c4(args):
         return
     res = {}
     for name, prec in (("mixed", tip.PREC_MIXED), ("fp64", tip.PREC_FP64)):
-        # timed steps without per-kernel events, so that iteration chunks replay
-        # as HIP graphs; one extra profiled step gives the stencil figures
+        kw = {}
+        if not args.no_autotune:
+            t0 = time.perf_counter()
+            kw = autotune.tuned_batch(ops, ns, args.tol, args.seed, mask=tip.MASK_Z2, precision=prec)
+            log(f"[c4 {name}] tuning {kw} ({time.perf_counter() - t0:.1f} s)")
         for _ in range(args.warmup):
-            tip.trace_inv_probe_batch(ops, ns, args.tol, args.seed, mask=tip.MASK_Z2, precision=prec,
-                                      n_streams=args.streams)
+            tip.trace_inv_probe_batch(ops, ns, args.tol, args.seed, mask=tip.MASK_Z2, precision=prec, **kw)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        agg = {"iters": 0, "solves": 0, "relres": 0.0, "launches": 0, "seconds": 0.0, "bytes": 0.0}
-        for _ in range(args.steps):
-            out = tip.trace_inv_probe_batch(ops, ns, args.tol, args.seed, mask=tip.MASK_Z2, precision=prec,
-                                            n_streams=args.streams)
+        agg = {"iters": 0, "solves": 0, "relres": 0.0, "reused": 0, "ru": 0}
+        for k in range(args.steps):
+            out = tip.trace_inv_probe_batch(ops, ns, args.tol, args.seed, mask=tip.MASK_Z2, precision=prec, **kw)
             for _, st in out:
                 agg["iters"] += st["total_iters"]
                 agg["solves"] += st["solves"]
+                agg["reused"] += st["reused"]
+                agg["ru"] += st["reliable_updates"]
                 agg["relres"] = max(agg["relres"], st["max_true_relres"])
+            log(f"[c4 {name}] step {k}: {out[0][1]['seconds']:.3f} s")
         torch.cuda.synchronize()
         el = time.perf_counter() - t0
         tip.tip_set_profiling(True)
-        for _, st in tip.trace_inv_probe_batch(ops, ns, args.tol, args.seed, mask=tip.MASK_Z2, precision=prec,
-                                               n_streams=args.streams):
-            agg["launches"] += st["stencil_launches"]
-            agg["seconds"] += st["stencil_seconds"]
-            agg["bytes"] += st["stencil_bytes"]
+        st0 = tip.trace_inv_probe_batch(ops, ns, args.tol, args.seed, mask=tip.MASK_Z2, precision=prec, **kw)[0][1]
         tip.tip_set_profiling(False)
-        res[name] = (total * args.steps / el, el, agg)
-        log(f"[c4 {name}] {el / args.steps:.3f} s/step, {agg['iters'] / agg['solves']:.1f} it/solve")
-    value, el, agg = res["mixed"]
-    ach = agg["bytes"] / agg["seconds"] / 1e9 if agg["seconds"] > 0 else 0.0
-    out = {"metric": "probing-vector solves/sec (batch of 64 uneven 3-D tori, rel.res 1e-10)", "value": round(value, 2),
-           "unit": "solves/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        res[name] = (total * args.steps / el, el, agg, st0, kw)
+        log(f"[c4 {name}] {el / args.steps:.3f} s/step, {agg['iters'] / agg['solves']:.1f} it/solve, "
+            f"{agg['ru'] / max(agg['solves'], 1):.2f} reliable updates/solve")
+    value, el, agg, st0, kw = res["mixed"]
+
+    def roof(st):
+        sec, byt, n = st["stencil_seconds"], st["stencil_bytes"], st["stencil_launches"]
+        ach = byt / sec / 1e9 if sec > 0 else 0.0
+        return {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": None,
+                "kernel": "kb_stencil (batched generic site stencil, real and complex groups)",
+                "alg_bytes_per_launch": byt / max(n, 1), "avg_launch_us": round(sec / max(n, 1) * 1e6, 2),
+                "launches": n,
+                "note": "algorithmic bytes of the live work items only (couplings once per site, p read and "
+                        "w written per live rhs), counted on the device; from one extra step with eager launches"}
+    out = {"metric": "probe quadratures/sec (batch of 64 uneven 3-D tori, rel.res 1e-10)", "value": round(value, 2),
+           "unit": "quadratures/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
            "ms_per_step": round(el / args.steps * 1e3, 2), "higher_is_better": True, "scaling": "weak",
            "vs_baseline": None, "dtype": "f32 CG + f64 reliable updates", "data": "synthetic",
            "config": {"workload": "64 independent 3-D tori, sides iid U{8..48}, scalar Laplacian m~U[0.02,0.2], "
                                   "w~U[0.5,1.5], Z2, 16..256 probes each, tol 1e-10",
-                      "rhs_per_step": total, "iters_per_solve": round(agg["iters"] / agg["solves"], 2),
-                      "max_true_relres": agg["relres"], "streams": args.streams or 8},
-           "roofline": {"bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                        "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": None, "kernel": "k_stencil (generic sites)",
-                        "note": "working sets of a few MB per torus stay in L2/MALL; from one extra profiled step "
-                                "(eager launches, concurrent streams)"},
-           "cpu_baseline": None,
-           "fp64": {"value": round(res["fp64"][0], 2), "ms_per_step": round(res["fp64"][1] / args.steps * 1e3, 2)}}
+                      "quadratures_per_step": total, "solves_per_step": agg["solves"] // args.steps,
+                      "reused_conjugates_per_step": agg["reused"] // args.steps,
+                      "iters_per_solve": round(agg["iters"] / agg["solves"], 2),
+                      "max_true_relres": agg["relres"], "tuning": kw},
+           "roofline": roof(st0), "cpu_baseline": None,
+           "fp64": {"value": round(res["fp64"][0], 2), "ms_per_step": round(res["fp64"][1] / args.steps * 1e3, 2),
+                    "iters_per_solve": round(res["fp64"][2]["iters"] / res["fp64"][2]["solves"], 2),
+                    "tuning": res["fp64"][4], "roofline": roof(res["fp64"][3])}}
     print(json.dumps(out), flush=True)
 
 
@@ -488,6 +590,7 @@ def main():
     ap.add_argument("--seed", type=int, default=4018)
     ap.add_argument("--cpu-solves", type=int, default=3, help="right-hand sides the CPU oracle solves")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-one-core", action="store_true", help="time the oracle on one host thread only")
     ap.add_argument("--copy-calibration", action="store_true")
     ap.add_argument("--precision", choices=["both", "fp64", "mixed"], default="both",
                     help="FP64 is the headline value; 'both' adds the mixed-precision solver beside it")
@@ -504,8 +607,8 @@ def main():
                          "compare: hierarchical vs natural-order Hadamard vs Monte-Carlo probes on a 32^3 torus "
                          "with a closed-form trace; study: the experiments of Sec. 5 (stopped levels, three "
                          "lattices and condition numbers, variance over 100 masks)")
-    ap.add_argument("--streams", type=int, default=0, help="c4: host threads and streams of the batch call "
-                    "(0 = the library's default, 8)")
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="c4: the library's default block and work-item sizes instead of tip_autotune_batch")
     ap.add_argument("--masks", type=int, default=4, help="compare / study B: masks averaged per probe kind")
     ap.add_argument("--sequential", action="store_true",
                     help="c4: solve the tori one after another on one thread instead of the batch call")
@@ -607,6 +710,7 @@ def main():
                                 "alg_bytes": tot["mv_bytes"] / tot["mv"],
                                 "achieved": round(tot["mv_bytes"] / tot["mv_seconds"] / 1e9, 1)}
         return {"value": n_rhs * args.steps / elapsed, "elapsed": elapsed, "roofline": roof, "est": est, "eo": tot["eo"],
+                "q": q, "residuals": st["residuals"],
                 "iters_per_solve": tot["iters"] / max(tot["solves"], 1), "max_true_relres": tot["relres"],
                 "reliable_updates_per_step": tot["ru"] / args.steps, "max_quad_err_bound": tot["bound"]}
 
@@ -635,7 +739,10 @@ def main():
 
     cpu = None
     if not args.no_cpu_baseline:
-        cpu = cpu_baseline(U, mf, args.seed, args.tol, args.cpu_solves)
+        cpu = cpu_baseline(U, mf, args.seed, args.tol, args.cpu_solves, all_cores=not args.cpu_one_core)
+    q0_oracle = cpu.pop("_q0", None) if cpu else None
+    if mixed is not None:
+        mixed["per_estimate"] = per_estimate_errors(res[tip.PREC_MIXED], main, float(np.min(mf)), q0_oracle)
 
     out = {"metric": METRIC, "value": round(value, 2), "unit": "solves/s", "n_gpus": 1, "steps": args.steps,
            "warmup": args.warmup, "ms_per_step": round(elapsed / args.steps * 1e3, 2), "higher_is_better": True,

@@ -173,6 +173,15 @@ typedef struct {
   int32_t march_tc;      /* lattice slices one stencil workgroup marches (power of two;
                             0 = library choice)                                    */
   int32_t stop_levels;   /* TIP_PROBE_STOPPED: bit-levels of the colouring kept (>= 0) */
+  int32_t item_sites;    /* trace_inv_probe_batch: lattice sites one workgroup walks per
+                            work item (rounded up to a power of two >= 256; 0 = library
+                            choice, 512; see tip_autotune_batch); ignored elsewhere  */
+  double* residuals;     /* HOST [n_vectors][ncomp] or NULL: entries [m_begin, n_vectors)
+                            receive ||b - A x|| / ||b|| of each solve's accepted FP64 true
+                            residual (the partner's for a reused conjugate; NaN for a solve
+                            that was not accepted).  With ||b||^2 = V and lambda_lb of
+                            tip_stats.max_quad_err_bound, (1/s) sum_{m<s,c} V res^2 /
+                            lambda_lb bounds the error of the estimate at s.         */
 } tip_params;
 
 typedef struct {
@@ -214,15 +223,29 @@ tip_status trace_inv_probe(const tip_operator* op, const tip_params* p,
                            double* estimates, tip_stats* stats);
 
 /* Many independent problems in one call, e.g. a batch of uneven 3-D tori.
- * Problem i is ops[i] with params[i] (its stream field is ignored) and writes
- * estimates[i] (HOST [tip_num_checkpoints(params[i].n_vectors)][2]) and, when
- * stats is not NULL, stats[i].  The library runs n_streams host threads (0 =
- * 8), each with a HIP stream of its own on the caller's current device, that
- * take the problems largest first (V n_vectors ncomp); every problem gets
- * exactly the arithmetic of a trace_inv_probe call.  statuses: HOST [count]
- * per-problem status, or NULL.  All arguments are validated before any work
- * starts (TIP_EINVAL names the problem); otherwise the return value is TIP_OK
- * or the status of the lowest-numbered failing problem. */
+ * Problem i is ops[i] with params[i] and writes estimates[i] (HOST
+ * [tip_num_checkpoints(params[i].n_vectors)][2]) and, when stats is not NULL,
+ * stats[i].  All problems are solved together on params[0].stream (NULL: a
+ * stream of the call's own, after the null stream has been synchronised):
+ * each problem's right-hand sides are cut into blocks as trace_inv_probe
+ * cuts them (params[i].rhs_block, default 32, fewer when the problem has
+ * fewer right-hand sides; the conjugate F_3 columns of real odd-sided
+ * problems are reused the same way), and every CG phase of every block of
+ * every problem that shares the operator kind, element type and precision
+ * is one kernel launch over work items of params[0].item_sites sites.  A
+ * chunk of CG iterations of the whole batch is captured once as a HIP graph
+ * and replayed; the host polls one counter per chunk.  Solves stop on each
+ * problem's own tol and max_iter and are accepted on the FP64 true residual;
+ * the batch runs plain CG (no even-odd reduction), so results agree with
+ * separate trace_inv_probe calls to the solver tolerance, not bit for bit.
+ * stats[i].seconds is the wall time of the whole call; stats[i].stencil_*
+ * describe the batch's shared stencil launches (the same in every entry;
+ * timed only with tip_set_profiling(1), which also turns the graph off).
+ * n_streams is kept for compatibility and ignored (must be >= 0).
+ * statuses: HOST [count] per-problem status, or NULL.  All arguments are
+ * validated before any device work (TIP_EINVAL names the problem); otherwise
+ * the return value is TIP_OK or the status of the lowest-numbered failing
+ * problem. */
 tip_status trace_inv_probe_batch(const tip_operator* ops, const tip_params* params, int32_t count,
                                  int32_t n_streams, double* const* estimates, tip_stats* stats,
                                  int32_t* statuses);
@@ -244,6 +267,7 @@ typedef struct {
   int32_t round_tiles;        /* tiles per XCD round (0 = library choice)           */
   int32_t march_tc;           /* marched slices (0 = library choice)                */
   double seconds_per_solve;   /* measured on the sample                             */
+  int32_t item_sites;         /* tip_autotune_batch: sites per work item            */
 } tip_tuning;
 
 /* Times trace_inv_probe_op on the first sample_vectors probes (0 = 64) for each
@@ -258,6 +282,18 @@ typedef struct {
  * between block sizes in rounding only. */
 tip_status tip_autotune(tip_op_handle h, const tip_params* p, int64_t sample_vectors, tip_tuning* best,
                         tip_tuning* tried, int32_t max_tried, int32_t* n_tried);
+
+/* Times trace_inv_probe_batch on the first sample_vectors probes of every
+ * problem (0 = 16) for each candidate launch configuration: right-hand sides
+ * per block in {16, 32, 64} unless params[0].rhs_block fixes it, times sites
+ * per work item in {256, 512, 1024, 2048} unless params[0].item_sites fixes
+ * it.  Every candidate runs twice (the first run warms up); the fastest goes
+ * to best (its rhs_block and item_sites; round_tiles and march_tc are 0).
+ * tried / max_tried / n_tried as in tip_autotune.  Copy the result into every
+ * params[i].rhs_block and params[0].item_sites. */
+tip_status tip_autotune_batch(const tip_operator* ops, const tip_params* params, int32_t count,
+                              int64_t sample_vectors, tip_tuning* best, tip_tuning* tried,
+                              int32_t max_tried, int32_t* n_tried);
 
 /* trace_inv_probe_op plus the gradient of the last estimate, T = (1/s) sum_{m<s} q_m
  * at s = n_vectors, with respect to the operator's parameters, the probes held

@@ -49,3 +49,29 @@ def tuned(handle, tol=1e-10, seed=0, mask=tip.MASK_DEFAULT, precision=tip.PREC_F
         os.replace(tmp, path)
     b = table[key]["best"]
     return {"rhs_block": b["rhs_block"], "round_tiles": b["round_tiles"], "march_tc": b["march_tc"]}
+
+
+def _batch_key(ops, n_vectors, precision, mask):
+    return json.dumps({"batch": [[op.dims, op.kind, op.coupling is not None, int(n)] for op, n in zip(ops, n_vectors)],
+                       "precision": int(precision), "mask": mask if isinstance(mask, int) else list(mask)},
+                      sort_keys=True)
+
+
+def tuned_batch(ops, n_vectors, tol=1e-10, seed=0, mask=tip.MASK_DEFAULT, precision=tip.PREC_FP64,
+                sample_vectors=16, path=None, retune=False):
+    """kwargs (rhs_block, item_sites) for trace_inv_probe_batch on these problems,
+    from tip_autotune_batch, cached like tuned() under the batch's shapes."""
+    path = path or cache_path()
+    key = _batch_key(ops, n_vectors, precision, mask)
+    table = _load(path)
+    if key not in table or retune:
+        best, tried = tip.tip_autotune_batch(ops, n_vectors, tol, seed, sample_vectors=sample_vectors, mask=mask,
+                                             precision=precision)
+        table[key] = {"best": best, "tried": tried}
+        os.makedirs(os.path.dirname(path) or ".", exist_ok=True)
+        tmp = path + ".tmp"
+        with open(tmp, "w") as f:
+            json.dump(table, f, indent=1, sort_keys=True)
+        os.replace(tmp, path)
+    b = table[key]["best"]
+    return {"rhs_block": b["rhs_block"], "item_sites": b["item_sites"]}

@@ -36,12 +36,13 @@ class tip_params(ctypes.Structure):
                 ("rhs_block", ctypes.c_int32), ("precision", ctypes.c_int32), ("stream", ctypes.c_void_p),
                 ("quadratures", ctypes.POINTER(ctypes.c_double)), ("reliable_delta", ctypes.c_double),
                 ("probe", ctypes.c_int32), ("round_tiles", ctypes.c_int32), ("march_tc", ctypes.c_int32),
-                ("stop_levels", ctypes.c_int32)]
+                ("stop_levels", ctypes.c_int32), ("item_sites", ctypes.c_int32),
+                ("residuals", ctypes.POINTER(ctypes.c_double))]
 
 
 class tip_tuning(ctypes.Structure):
     _fields_ = [("rhs_block", ctypes.c_int32), ("round_tiles", ctypes.c_int32), ("march_tc", ctypes.c_int32),
-                ("seconds_per_solve", ctypes.c_double)]
+                ("seconds_per_solve", ctypes.c_double), ("item_sites", ctypes.c_int32)]
 
 
 class tip_stats(ctypes.Structure):
@@ -71,6 +72,8 @@ def _load():
                                                  P(P(ctypes.c_double)), P(tip_stats), P(ctypes.c_int32)]),
         "tip_autotune": (ctypes.c_int, [ctypes.c_void_p, P(tip_params), ctypes.c_int64, P(tip_tuning), P(tip_tuning),
                                         ctypes.c_int32, P(ctypes.c_int32)]),
+        "tip_autotune_batch": (ctypes.c_int, [P(tip_operator), P(tip_params), ctypes.c_int32, ctypes.c_int64,
+                                              P(tip_tuning), P(tip_tuning), ctypes.c_int32, P(ctypes.c_int32)]),
         "tip_op_create": (ctypes.c_int, [P(tip_operator), ctypes.c_void_p, P(ctypes.c_void_p)]),
         "tip_op_destroy": (ctypes.c_int, [ctypes.c_void_p]),
         "trace_inv_probe_op": (ctypes.c_int, [ctypes.c_void_p, P(tip_params), P(ctypes.c_double), P(tip_stats)]),
@@ -173,7 +176,7 @@ class Operator:
 
 
 def _params(n_vectors, tol, seed, mask, max_iter, rhs_block, m_begin, quadratures, stream, precision=PREC_FP64,
-            reliable_delta=0.0, probe=PROBE_HIERARCHICAL, round_tiles=0, march_tc=0, stop_levels=0):
+            reliable_delta=0.0, probe=PROBE_HIERARCHICAL, round_tiles=0, march_tc=0, stop_levels=0, item_sites=0):
     p = tip_params()
     p.n_vectors = int(n_vectors)
     p.m_begin = int(m_begin)
@@ -191,6 +194,7 @@ def _params(n_vectors, tol, seed, mask, max_iter, rhs_block, m_begin, quadrature
     p.round_tiles = int(round_tiles)
     p.march_tc = int(march_tc)
     p.stop_levels = int(stop_levels)
+    p.item_sites = int(item_sites)
     return p
 
 
@@ -204,18 +208,21 @@ def tip_num_checkpoints(n_vectors):
 
 def _run(fn, first, n_vectors, tol, seed, mask, max_iter, rhs_block, m_begin, quadratures, stream, raise_on_error,
          precision=PREC_FP64, reliable_delta=0.0, probe=PROBE_HIERARCHICAL, round_tiles=0, march_tc=0,
-         stop_levels=0):
+         stop_levels=0, ncomp=1):
     nck = tip_num_checkpoints(n_vectors)
     est = np.zeros((nck, 2), dtype=np.float64)
     q = np.zeros((int(n_vectors), 2), dtype=np.float64)
+    res = np.full((int(n_vectors), int(ncomp)), np.nan)
     if quadratures is not None:
         q[:m_begin] = np.asarray(quadratures, dtype=np.complex128)[:m_begin].view(np.float64).reshape(-1, 2)
     p = _params(n_vectors, tol, seed, mask, max_iter, rhs_block, m_begin, q, stream, precision, reliable_delta, probe,
                 round_tiles, march_tc, stop_levels)
+    p.residuals = res.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
     st = tip_stats()
     status = fn(first, ctypes.byref(p), est.ctypes.data_as(ctypes.POINTER(ctypes.c_double)), ctypes.byref(st))
     stats = _stats_dict(st)
     stats["status"] = status
+    stats["residuals"] = res
     if raise_on_error:
         _check(status, fn.__name__)
     done = stats["n_checkpoints_done"]
@@ -229,26 +236,37 @@ def trace_inv_probe(op, n_vectors, tol, seed, mask=MASK_DEFAULT, max_iter=0, rhs
     """Estimates at s = 2^k (complex numpy), quadratures q_m (complex numpy), stats dict."""
     s = op.c_struct()
     return _run(lib.trace_inv_probe, ctypes.byref(s), n_vectors, tol, seed, mask, max_iter, rhs_block, m_begin,
-                quadratures, stream, raise_on_error, precision, reliable_delta, probe, stop_levels=stop_levels)
+                quadratures, stream, raise_on_error, precision, reliable_delta, probe, stop_levels=stop_levels,
+                ncomp=op.ncomp)
 
 
-def trace_inv_probe_batch(ops, n_vectors, tol, seed, mask=MASK_DEFAULT, max_iter=0, rhs_block=0,
-                          precision=PREC_FP64, reliable_delta=0.0, n_streams=0, raise_on_error=True,
-                          probe=PROBE_HIERARCHICAL, stop_levels=0):
-    """Independent problems in one call: ops and n_vectors are sequences of
-    equal length.  Returns a list of (estimates complex numpy, stats dict)."""
+def _batch_structs(ops, n_vectors, tol, seed, mask, max_iter, rhs_block, precision, reliable_delta, probe,
+                   stop_levels, item_sites, stream):
     count = len(ops)
     if len(n_vectors) != count:
         raise ValueError("ops and n_vectors differ in length")
     structs = (tip_operator * count)(*[op.c_struct() for op in ops])
     params = (tip_params * count)()
-    ests, qs = [], []
+    qs = []
+    masks = list(mask) if isinstance(mask, (list, tuple)) else [mask] * count
     for i, n in enumerate(n_vectors):
         q = np.zeros((int(n), 2))
         qs.append(q)
-        params[i] = _params(n, tol, seed, mask, max_iter, rhs_block, 0, q, None, precision, reliable_delta, probe,
-                            stop_levels=stop_levels)
-        ests.append(np.zeros((tip_num_checkpoints(n), 2)))
+        params[i] = _params(n, tol, seed, masks[i], max_iter, rhs_block, 0, q, stream, precision, reliable_delta,
+                            probe, stop_levels=stop_levels, item_sites=item_sites)
+    return structs, params, qs
+
+
+def trace_inv_probe_batch(ops, n_vectors, tol, seed, mask=MASK_DEFAULT, max_iter=0, rhs_block=0,
+                          precision=PREC_FP64, reliable_delta=0.0, n_streams=0, raise_on_error=True,
+                          probe=PROBE_HIERARCHICAL, stop_levels=0, item_sites=0, stream=None):
+    """Independent problems solved together: ops and n_vectors (and mask, when
+    a sequence) have one entry per problem.  Returns a list of (estimates complex numpy, stats dict with
+    "status" and "quadratures")."""
+    count = len(ops)
+    structs, params, qs = _batch_structs(ops, n_vectors, tol, seed, mask, max_iter, rhs_block, precision,
+                                         reliable_delta, probe, stop_levels, item_sites, stream)
+    ests = [np.zeros((tip_num_checkpoints(n), 2)) for n in n_vectors]
     est_ptrs = (ctypes.POINTER(ctypes.c_double) * count)(*[e.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
                                                           for e in ests])
     stats = (tip_stats * count)()
@@ -260,8 +278,27 @@ def trace_inv_probe_batch(ops, n_vectors, tol, seed, mask=MASK_DEFAULT, max_iter
     for i in range(count):
         st = _stats_dict(stats[i])
         st["status"] = statuses[i]
+        st["quadratures"] = qs[i][:, 0] + 1j * qs[i][:, 1]
         out.append((ests[i][:, 0] + 1j * ests[i][:, 1], st))
     return out
+
+
+def tip_autotune_batch(ops, n_vectors, tol, seed, sample_vectors=16, mask=MASK_DEFAULT, precision=PREC_FP64,
+                       rhs_block=0, item_sites=0, stream=None):
+    """Fastest (rhs_block, item_sites) of trace_inv_probe_batch on a sample:
+    returns (best dict, list of tried dicts)."""
+    count = len(ops)
+    structs, params, _ = _batch_structs(ops, n_vectors, tol, seed, mask, 0, rhs_block, precision, 0.0,
+                                        PROBE_HIERARCHICAL, 0, item_sites, stream)
+    best = tip_tuning()
+    tried = (tip_tuning * 16)()
+    n_tried = ctypes.c_int32()
+    _check(lib.tip_autotune_batch(structs, params, count, int(sample_vectors), ctypes.byref(best), tried, 16,
+                                  ctypes.byref(n_tried)), "tip_autotune_batch")
+
+    def d(t):
+        return {"rhs_block": t.rhs_block, "item_sites": t.item_sites, "seconds_per_solve": t.seconds_per_solve}
+    return d(best), [d(tried[k]) for k in range(min(n_tried.value, 16))]
 
 
 class OpHandle:
@@ -278,7 +315,7 @@ class OpHandle:
                         probe=PROBE_HIERARCHICAL, round_tiles=0, march_tc=0, stop_levels=0):
         return _run(lib.trace_inv_probe_op, self._h, n_vectors, tol, seed, mask, max_iter, rhs_block, m_begin,
                     quadratures, stream, raise_on_error, precision, reliable_delta, probe, round_tiles, march_tc,
-                    stop_levels)
+                    stop_levels, ncomp=self.op.ncomp)
 
     def autotune(self, tol, seed, sample_vectors=64, mask=MASK_DEFAULT, precision=PREC_FP64, probe=PROBE_HIERARCHICAL,
                  rhs_block=0, round_tiles=0, stream=None):

@@ -17,7 +17,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(HERE, "libtip.so")
-SOURCES = ["tip_kernels.hip", "tip_api.hip", "tip_bandwidth.hip"]
+SOURCES = ["tip_kernels.hip", "tip_api.hip", "tip_bandwidth.hip", "tip_batch.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["-O3", "-std=c++17", "--offload-arch=gfx950", "-fPIC",

@@ -21,10 +21,11 @@
 #include <string>
 #include <vector>
 #include <atomic>
+#include <memory>
 #include <mutex>
-#include <thread>
 
 #include "../../include/tip.h"
+#include "tip_batch.h"
 #include "tip_launch.h"
 
 using namespace tip;
@@ -770,6 +771,7 @@ struct Solver {
     sc.active = iv + 4 * nscal;
     sc.n_ru = sc.active + 1;
     sc.ru_count = sc.active + 2;
+    sc.ru_lanes = nullptr;
     ran_dev = sc.active + 32;
     char* hb = (char*)h->host.p;
     h_q = (double*)hb;
@@ -1112,6 +1114,170 @@ tip_status tip_op_destroy(tip_op_handle h) {
 
 namespace {
 
+// Per-rhs results of one probing run: slot k = (m - m_begin) * ncomp + c for
+// probe m and component c.
+struct RunResult {
+  std::vector<double> qre, qim, relres;
+  std::vector<int> state, iters;
+  std::vector<char> copied;        // quadrature taken from the conjugate partner, not solved
+  tip_stats acc{};                 // stencil / matvec timing, reliable updates, restarts, even_odd
+  explicit RunResult(int64_t n_rhs)
+      : qre((size_t)n_rhs, 0.0), qim((size_t)n_rhs, 0.0), relres((size_t)n_rhs, 0.0),
+        state((size_t)n_rhs, kPadding), iters((size_t)n_rhs, 0), copied((size_t)n_rhs, 0) {}
+};
+
+// Conjugate F_3 columns (Sec. 3.4, eq. Hperm-general-recursive): for a real
+// operator and a real mask, probe column j3 = 2 of a sweep is the complex
+// conjugate of column j3 = 1 (w^2 = conj w), so its quadrature is the
+// conjugate of that one, and the j3 = 0 columns are real.  Then the j3 = 0
+// probes are solved in real arithmetic, the j3 = 1 ones in complex, and the
+// j3 = 2 ones take conj(q) of their partner probe m - 2^LB: half the work of
+// complex solves for all of them.  Not with the gradient (it needs every x).
+bool conj_split(const Geom& gg, int kind, int mask, const tip_params* p, bool want_grad) {
+  const int64_t nb_cols = int64_t(1) << gg.LB;
+  return gg.has3 && kind == TIP_KIND_SCALAR && (mask == TIP_MASK_Z2 || mask == TIP_MASK_NONE) &&
+         p->probe == TIP_PROBE_HIERARCHICAL && !want_grad && p->n_vectors > nb_cols && !env_off("TIP_CONJ_SPLIT");
+}
+
+// The classes of the split: class j3 numbers its probes i = 0, 1, ...
+// (class_probe); the members in [m_begin, n_vectors) have consecutive i.
+struct ClassMap {
+  int64_t gam, nbc;
+  int64_t index(int64_t m, int j3) const { return (m / gam) * nbc + (m % gam - j3 * nbc); }
+  int64_t first_member(int64_t m, int j3) const {      // smallest member >= m
+    const int64_t r = m / gam, j = m % gam;
+    if (j < j3 * nbc) return r * gam + j3 * nbc;
+    if (j < (j3 + 1) * nbc) return m;
+    return (r + 1) * gam + j3 * nbc;
+  }
+};
+
+// The j3 = 2 probes of a split run: the conjugate of the partner's quadrature
+// (and its state); from the earlier call's quadratures when the partner lies
+// before m_begin.
+void conj_copies(const Geom& gg, const tip_params* p, int ncomp, RunResult& rr) {
+  const int64_t gam = (int64_t)gg.gamma, nb_cols = int64_t(1) << gg.LB;
+  for (int64_t m = p->m_begin; m < p->n_vectors; ++m) {
+    if ((m % gam) / nb_cols != 2) continue;
+    for (int c = 0; c < ncomp; ++c) {
+      const size_t k = (size_t)((m - p->m_begin) * ncomp + c);
+      const int64_t mp = m - nb_cols;                   // same sweep, column j3 = 1
+      rr.copied[k] = 1;
+      if (mp < p->m_begin) {                              // from the earlier call's quadratures
+        if (ncomp != 1) { rr.state[k] = kNoConv; continue; }
+        rr.qre[k] = p->quadratures[2 * mp];
+        rr.qim[k] = -p->quadratures[2 * mp + 1];
+        rr.state[k] = kAccepted;
+        continue;
+      }
+      const size_t kp = (size_t)((mp - p->m_begin) * ncomp + c);
+      rr.qre[k] = rr.qre[kp];
+      rr.qim[k] = -rr.qim[kp];
+      rr.state[k] = rr.state[kp] == kPadding ? kNoConv : rr.state[kp];
+      rr.relres[k] = rr.relres[kp];
+    }
+  }
+}
+
+// Quadratures per probe, compensated sums into the estimates at s = 2^k,
+// stats, and the status of the first probe (in probe order) that was not
+// accepted.
+tip_status finish_run(const tip_op_s* h, const tip_params* p, const RunResult& rr, double* estimates,
+                      tip_stats* stats, std::chrono::steady_clock::time_point t_start) {
+  const int ncomp = h->geom.ncomp;
+  const int64_t probes = p->n_vectors - p->m_begin;
+  const int64_t n_rhs = probes * ncomp;
+  int64_t first_bad_rhs = -1;
+  tip_status bad_status = TIP_OK;
+  for (int64_t k = 0; k < n_rhs; ++k)
+    if (rr.state[(size_t)k] != kAccepted) {
+      first_bad_rhs = k;
+      bad_status = rr.state[(size_t)k] == kBreakdown ? TIP_EBREAKDOWN : TIP_ENOCONV;
+      break;
+    }
+  const int64_t n = p->n_vectors;
+  const int64_t good_probes = first_bad_rhs < 0 ? probes : first_bad_rhs / ncomp;
+  const int64_t m_end = p->m_begin + good_probes;      // probes [0, m_end) are valid
+  std::vector<double> q_all_re((size_t)m_end), q_all_im((size_t)m_end);
+  for (int64_t m = 0; m < p->m_begin; ++m) {
+    q_all_re[m] = p->quadratures[2 * m];
+    q_all_im[m] = p->quadratures[2 * m + 1];
+  }
+  for (int64_t m = p->m_begin; m < m_end; ++m) {
+    double re = 0.0, im = 0.0;
+    for (int c = 0; c < ncomp; ++c) {
+      re += rr.qre[(size_t)((m - p->m_begin) * ncomp + c)];
+      im += rr.qim[(size_t)((m - p->m_begin) * ncomp + c)];
+    }
+    q_all_re[m] = re;
+    q_all_im[m] = im;
+  }
+  if (p->quadratures)
+    for (int64_t m = p->m_begin; m < m_end; ++m) {
+      p->quadratures[2 * m] = q_all_re[m];
+      p->quadratures[2 * m + 1] = q_all_im[m];
+    }
+  if (p->residuals)
+    for (int64_t k = 0; k < n_rhs; ++k)
+      p->residuals[p->m_begin * ncomp + k] = rr.state[(size_t)k] == kAccepted ? rr.relres[(size_t)k] : std::nan("");
+  const int nck = num_checkpoints(n);
+  int done = 0;
+  {
+    Compensated sre, sim;
+    int64_t m = 0;
+    for (int k = 0; k < nck; ++k) {
+      const int64_t sz = checkpoint_size(n, k);
+      if (sz > m_end) break;
+      for (; m < sz; ++m) {
+        sre.add(q_all_re[m]);
+        sim.add(q_all_im[m]);
+      }
+      estimates[2 * k] = sre.value() / (double)sz;
+      estimates[2 * k + 1] = sim.value() / (double)sz;
+      done = k + 1;
+    }
+  }
+  if (stats) {
+    std::memset(stats, 0, sizeof *stats);
+    double mx_rr = 0.0;
+    int64_t tot = 0;
+    int mx_it = 0, solved = 0;
+    for (int64_t k = 0; k < n_rhs; ++k) {
+      if (rr.state[k] == kPadding || rr.copied[(size_t)k]) continue;
+      ++solved;
+      tot += rr.iters[k];
+      mx_it = std::max(mx_it, rr.iters[k]);
+      if (rr.state[k] == kAccepted) mx_rr = std::max(mx_rr, rr.relres[k]);
+    }
+    stats->solves = solved;
+    stats->total_iters = tot;
+    stats->max_iters = mx_it;
+    stats->n_checkpoints_done = done;
+    stats->max_true_relres = mx_rr;
+    // error of one quadrature: r^H A^-1 r <= ||r||^2 / lambda_min, ||b||^2 = V
+    stats->max_quad_err_bound = mx_rr * mx_rr * (double)h->geom.V / h->lambda_lb;
+    stats->stencil_launches = rr.acc.stencil_launches;
+    stats->stencil_seconds = rr.acc.stencil_seconds;
+    stats->stencil_bytes = rr.acc.stencil_bytes;
+    stats->matvecs = rr.acc.matvecs;
+    stats->matvec_seconds = rr.acc.matvec_seconds;
+    stats->matvec_bytes = rr.acc.matvec_bytes;
+    stats->reliable_updates = rr.acc.reliable_updates;
+    stats->restarts = rr.acc.restarts;
+    stats->even_odd = rr.acc.even_odd;
+    int64_t reused = 0;
+    for (char c : rr.copied) reused += c ? 1 : 0;
+    stats->reused = reused;
+    stats->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t_start).count();
+  }
+  if (first_bad_rhs >= 0) {
+    const int64_t bad_m = p->m_begin + first_bad_rhs / ncomp;
+    return fail(bad_status, "solve of probe %lld component %d %s", (long long)bad_m, (int)(first_bad_rhs % ncomp),
+                bad_status == TIP_EBREAKDOWN ? "broke down (p^H A p <= 0)" : "did not converge within max_iter");
+  }
+  return TIP_OK;
+}
+
 // The probing run behind trace_inv_probe_op and trace_inv_probe_grad; grad_mass
 // and grad_coupling (device, or NULL) receive the gradient of the estimate at
 // s = n_vectors, accumulated block by block from the solutions in the workspace.
@@ -1131,10 +1297,7 @@ tip_status run_probe(tip_op_handle h, const tip_params* p, double* estimates, do
   const int64_t n_rhs = probes * ncomp;
   const Geom& gg = h->geom;
   const size_t V = gg.V;
-  std::vector<double> qre((size_t)n_rhs, 0.0), qim((size_t)n_rhs, 0.0), rhs_relres((size_t)n_rhs, 0.0);
-  std::vector<int> rhs_state((size_t)n_rhs, kPadding), rhs_iters((size_t)n_rhs, 0);
-  tip_stats acc_stats;
-  std::memset(&acc_stats, 0, sizeof acc_stats);
+  RunResult rr(n_rhs);
   bool failed = false;
   hipStream_t st_used = nullptr;
   // Solve right-hand sides [r0, r1) in blocks: rhs r (lane rhs of the kernels)
@@ -1148,11 +1311,11 @@ tip_status run_probe(tip_op_handle h, const tip_params* p, double* estimates, do
         TIP_HIP(launch_grad_accum(sv.od64, gg, sv.pl.elem, sv.pl.logB, nb, sv.X, grad_mass, grad_coupling, sv.st));
       for (int j = 0; j < nb; ++j) {
         const size_t k = slot(blk0 + j);
-        qre[k] = sv.h_q[2 * j];
-        qim[k] = sv.h_q[2 * j + 1];
-        rhs_state[k] = sv.h_state[j];
-        rhs_iters[k] = sv.h_iters[j];
-        rhs_relres[k] = std::sqrt(sv.h_relres2[j]);
+        rr.qre[k] = sv.h_q[2 * j];
+        rr.qim[k] = sv.h_q[2 * j + 1];
+        rr.state[k] = sv.h_state[j];
+        rr.iters[k] = sv.h_iters[j];
+        rr.relres[k] = std::sqrt(sv.h_relres2[j]);
         if (sv.h_state[j] != kAccepted) failed = true;
       }
     }
@@ -1162,29 +1325,17 @@ tip_status run_probe(tip_op_handle h, const tip_params* p, double* estimates, do
     tip_stats t;
     std::memset(&t, 0, sizeof t);
     sv.fill_stats(&t);
-    acc_stats.stencil_launches += t.stencil_launches;
-    acc_stats.stencil_seconds += t.stencil_seconds;
-    acc_stats.stencil_bytes += t.stencil_bytes;
-    acc_stats.matvecs += t.matvecs;
-    acc_stats.matvec_seconds += t.matvec_seconds;
-    acc_stats.matvec_bytes += t.matvec_bytes;
-    acc_stats.reliable_updates += t.reliable_updates;
-    acc_stats.restarts += t.restarts;
-    acc_stats.even_odd = acc_stats.even_odd || t.even_odd;
+    rr.acc.stencil_launches += t.stencil_launches;
+    rr.acc.stencil_seconds += t.stencil_seconds;
+    rr.acc.stencil_bytes += t.stencil_bytes;
+    rr.acc.matvecs += t.matvecs;
+    rr.acc.matvec_seconds += t.matvec_seconds;
+    rr.acc.matvec_bytes += t.matvec_bytes;
+    rr.acc.reliable_updates += t.reliable_updates;
+    rr.acc.restarts += t.restarts;
+    rr.acc.even_odd = rr.acc.even_odd || t.even_odd;
   };
-  // Conjugate F_3 columns (Sec. 3.4, eq. Hperm-general-recursive): for a real
-  // operator and a real mask, probe column j3 = 2 of a sweep is the complex
-  // conjugate of column j3 = 1 (w^2 = conj w), so its quadrature is the
-  // conjugate of that one, and the j3 = 0 columns are real.  Then the j3 = 0
-  // probes are solved in real arithmetic, the j3 = 1 ones in complex, and the
-  // j3 = 2 ones take conj(q) of their partner probe m - 2^LB: half the work of
-  // complex solves for all of them.  Not with the gradient (it needs every x).
-  const int64_t nb_cols = int64_t(1) << gg.LB;
-  const bool split = gg.has3 && h->kind == TIP_KIND_SCALAR && (mask == TIP_MASK_Z2 || mask == TIP_MASK_NONE) &&
-                     p->probe == TIP_PROBE_HIERARCHICAL && !want_grad && p->n_vectors > nb_cols &&
-                     !env_off("TIP_CONJ_SPLIT");
-  std::vector<char> copied((size_t)n_rhs, 0);
-  if (!split) {
+  if (!conj_split(gg, h->kind, mask, p, want_grad)) {
     Solver sv;
     sv.need_x = want_grad;
     s = sv.setup(h, p, mask);
@@ -1197,31 +1348,22 @@ tip_status run_probe(tip_op_handle h, const tip_params* p, double* estimates, do
     if (s != TIP_OK) return s;
     add_stats(sv);
   } else {
-    // each class of F_3 digit j3 numbers its probes i = 0, 1, ... (class_probe);
-    // the class members in [m_begin, n_vectors) have consecutive i
-    const int64_t gam = (int64_t)gg.gamma;
-    auto class_index = [&](int64_t m, int j3) { return (m / gam) * nb_cols + (m % gam - j3 * nb_cols); };
-    auto first_member = [&](int64_t m, int j3) {      // smallest member >= m
-      const int64_t r = m / gam, j = m % gam;
-      if (j < j3 * nb_cols) return r * gam + j3 * nb_cols;
-      if (j < (j3 + 1) * nb_cols) return m;
-      return (r + 1) * gam + j3 * nb_cols;
-    };
+    const ClassMap cm{(int64_t)gg.gamma, int64_t(1) << gg.LB};
     // each class runs up to its own first failure; the checkpoints then stop
     // at the first probe, in probe order, that is not accepted
     for (int pass = 0; pass < 2; ++pass) {
       failed = false;
-      const int64_t m0 = first_member(p->m_begin, pass);
+      const int64_t m0 = cm.first_member(p->m_begin, pass);
       if (m0 >= p->n_vectors) continue;
-      const int64_t i0 = class_index(m0, pass);
-      const int64_t i1 = class_index(first_member(p->n_vectors, pass), pass);   // one past the last member
+      const int64_t i0 = cm.index(m0, pass);
+      const int64_t i1 = cm.index(cm.first_member(p->n_vectors, pass), pass);   // one past the last member
       Solver sv;
       sv.force_elem = pass;          // j3 = 0: real, j3 = 1: complex
       sv.rhs_hint = (i1 - i0) * ncomp;
       s = sv.setup(h, p, mask);
       if (s != TIP_OK) return s;
-      sv.geom.cls_gamma = (int32_t)gam;
-      sv.geom.cls_nbc = (int32_t)nb_cols;
+      sv.geom.cls_gamma = (int32_t)cm.gam;
+      sv.geom.cls_nbc = (int32_t)cm.nbc;
       sv.geom.cls_j3 = pass;
       st_used = sv.st;
       s = run_range(sv, i0 * ncomp, i1 * ncomp, [&](int64_t r) {
@@ -1231,123 +1373,485 @@ tip_status run_probe(tip_op_handle h, const tip_params* p, double* estimates, do
       if (s != TIP_OK) return s;
       add_stats(sv);
     }
-    // j3 = 2: the conjugate of the partner's quadrature (and its state)
-    for (int64_t m = p->m_begin; m < p->n_vectors; ++m) {
-      if ((m % gam) / nb_cols != 2) continue;
-        for (int c = 0; c < ncomp; ++c) {
-          const size_t k = (size_t)((m - p->m_begin) * ncomp + c);
-          const int64_t mp = m - nb_cols;                   // same sweep, column j3 = 1
-          copied[k] = 1;
-          if (mp < p->m_begin) {                              // from the earlier call's quadratures
-            if (ncomp != 1) { rhs_state[k] = kNoConv; failed = true; continue; }
-            qre[k] = p->quadratures[2 * mp];
-            qim[k] = -p->quadratures[2 * mp + 1];
-            rhs_state[k] = kAccepted;
-            continue;
-          }
-          const size_t kp = (size_t)((mp - p->m_begin) * ncomp + c);
-          qre[k] = qre[kp];
-          qim[k] = -qim[kp];
-          rhs_state[k] = rhs_state[kp] == kPadding ? kNoConv : rhs_state[kp];
-          rhs_relres[k] = rhs_relres[kp];
-          if (rhs_state[k] != kAccepted) failed = true;
-        }
-    }
+    conj_copies(gg, p, ncomp, rr);
   }
-  int64_t first_bad_rhs = -1;
-  tip_status bad_status = TIP_OK;
-  for (int64_t k = 0; k < n_rhs; ++k)
-    if (rhs_state[(size_t)k] != kAccepted) {
-      first_bad_rhs = k;
-      bad_status = rhs_state[(size_t)k] == kBreakdown ? TIP_EBREAKDOWN : TIP_ENOCONV;
-      break;
-    }
-
-  // ---- quadratures per probe, compensated sums, checkpoints ---------------
-  const int64_t n = p->n_vectors;
-  const int64_t good_probes = first_bad_rhs < 0 ? probes : first_bad_rhs / ncomp;
-  const int64_t m_end = p->m_begin + good_probes;      // probes [0, m_end) are valid
-  std::vector<double> q_all_re((size_t)m_end), q_all_im((size_t)m_end);
-  for (int64_t m = 0; m < p->m_begin; ++m) {
-    q_all_re[m] = p->quadratures[2 * m];
-    q_all_im[m] = p->quadratures[2 * m + 1];
-  }
-  for (int64_t m = p->m_begin; m < m_end; ++m) {
-    double re = 0.0, im = 0.0;
-    for (int c = 0; c < ncomp; ++c) {
-      re += qre[(size_t)((m - p->m_begin) * ncomp + c)];
-      im += qim[(size_t)((m - p->m_begin) * ncomp + c)];
-    }
-    q_all_re[m] = re;
-    q_all_im[m] = im;
-  }
-  if (p->quadratures)
-    for (int64_t m = p->m_begin; m < m_end; ++m) {
-      p->quadratures[2 * m] = q_all_re[m];
-      p->quadratures[2 * m + 1] = q_all_im[m];
-    }
-  const int nck = num_checkpoints(n);
-  int done = 0;
-  {
-    Compensated sre, sim;
-    int64_t m = 0;
-    for (int k = 0; k < nck; ++k) {
-      const int64_t sz = checkpoint_size(n, k);
-      if (sz > m_end) break;
-      for (; m < sz; ++m) {
-        sre.add(q_all_re[m]);
-        sim.add(q_all_im[m]);
-      }
-      estimates[2 * k] = sre.value() / (double)sz;
-      estimates[2 * k + 1] = sim.value() / (double)sz;
-      done = k + 1;
-    }
-  }
-
-  if (stats) {
-    std::memset(stats, 0, sizeof *stats);
-    double mx_rr = 0.0;
-    int64_t tot = 0;
-    int mx_it = 0, solved = 0;
-    for (int64_t k = 0; k < n_rhs; ++k) {
-      if (rhs_state[k] == kPadding || copied[(size_t)k]) continue;
-      ++solved;
-      tot += rhs_iters[k];
-      mx_it = std::max(mx_it, rhs_iters[k]);
-      if (rhs_state[k] == kAccepted) mx_rr = std::max(mx_rr, rhs_relres[k]);
-    }
-    stats->solves = solved;
-    stats->total_iters = tot;
-    stats->max_iters = mx_it;
-    stats->n_checkpoints_done = done;
-    stats->max_true_relres = mx_rr;
-    // error of one quadrature: r^H A^-1 r <= ||r||^2 / lambda_min, ||b||^2 = V
-    stats->max_quad_err_bound = mx_rr * mx_rr * (double)h->geom.V / h->lambda_lb;
-    stats->stencil_launches = acc_stats.stencil_launches;
-    stats->stencil_seconds = acc_stats.stencil_seconds;
-    stats->stencil_bytes = acc_stats.stencil_bytes;
-    stats->matvecs = acc_stats.matvecs;
-    stats->matvec_seconds = acc_stats.matvec_seconds;
-    stats->matvec_bytes = acc_stats.matvec_bytes;
-    stats->reliable_updates = acc_stats.reliable_updates;
-    stats->restarts = acc_stats.restarts;
-    stats->even_odd = acc_stats.even_odd;
-    int64_t reused = 0;
-    for (char c : copied) reused += c ? 1 : 0;
-    stats->reused = reused;
-    stats->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t_start).count();
-  }
-  if (want_grad && first_bad_rhs < 0) {
-    const double f = -1.0 / (double)n;
+  s = finish_run(h, p, rr, estimates, stats, t_start);
+  if (s == TIP_OK && want_grad) {
+    const double f = -1.0 / (double)p->n_vectors;
     if (grad_mass) TIP_HIP(launch_scale(V, grad_mass, f, st_used));
-    if (grad_coupling) TIP_HIP(launch_scale((size_t)h->geom.ndim * V, grad_coupling, f, st_used));
+    if (grad_coupling) TIP_HIP(launch_scale((size_t)gg.ndim * V, grad_coupling, f, st_used));
     TIP_HIP(hipStreamSynchronize(st_used));
   }
-  if (first_bad_rhs >= 0) {
-    const int64_t bad_m = p->m_begin + first_bad_rhs / ncomp;
-    return fail(bad_status, "solve of probe %lld component %d %s", (long long)bad_m, (int)(first_bad_rhs % ncomp),
-                bad_status == TIP_EBREAKDOWN ? "broke down (p^H A p <= 0)" : "did not converge within max_iter");
+  return s;
+}
+
+// ---------------------------------------------------------------------------
+// Many independent problems solved together (trace_inv_probe_batch).
+//
+// Every problem's right-hand sides are cut into blocks (jobs) exactly as a
+// single call would solve them (probe classes of the conjugate F_3 split
+// included), and all jobs of one (operator kind, element type, precision)
+// group advance together: each CG phase is one launch over the work items
+// of every job of the group (tip_batch.hip), and one chunk of iterations for
+// the whole batch is captured once as a HIP graph and replayed.  One host
+// thread and one stream do all of it; the host polls one counter per chunk.
+// ---------------------------------------------------------------------------
+
+struct HandleDel {
+  void operator()(tip_op_s* h) const { delete h; }
+};
+
+// Batch arguments valid for every problem (estimates may be NULL when only
+// the parameters are checked).
+tip_status validate_batch(const tip_operator* ops, const tip_params* params, int32_t count, double* const* estimates) {
+  if (count < 0) return fail(TIP_EINVAL, "count = %d must be >= 0", count);
+  if (count > 0 && (!ops || !params)) return fail(TIP_EINVAL, "ops or params is NULL");
+  for (int32_t i = 0; i < count; ++i) {
+    Geom g;
+    tip_status s = validate_op(&ops[i], &g);
+    if (s != TIP_OK) return fail(s, "torus %d: %s", i, g_err.c_str());
+    if (estimates && !estimates[i]) return fail(TIP_EINVAL, "torus %d: estimates is NULL", i);
+    if (params[i].n_vectors < 1 || params[i].n_vectors > (int64_t)g.V)
+      return fail(TIP_EINVAL, "torus %d: n_vectors = %lld must be in [1, V = %u]", i,
+                  (long long)params[i].n_vectors, g.V);
+    if (params[i].m_begin > 0 && !params[i].quadratures)
+      return fail(TIP_EINVAL, "torus %d: m_begin > 0 needs the earlier quadratures", i);
+    if (params[i].item_sites < 0) return fail(TIP_EINVAL, "torus %d: item_sites must be >= 0", i);
   }
+  return TIP_OK;
+}
+
+// A range of right-hand sides of one problem solved in one element type.
+struct BatchClass {
+  int prob;
+  int j3;                      // F_3 class of the conjugate split, -1 for none
+  Elem elem;
+  Prec prec;
+  int64_t r0, r1;              // right-hand sides (class-local with a class)
+  int B;
+};
+
+constexpr int kBatchChunk = 8;              // CG iterations per poll of the active counter
+constexpr int kBatchItemSites = 512;        // default sites per work item
+
+tip_status run_batch(const tip_operator* ops, const tip_params* params, int32_t count, double* const* estimates,
+                     tip_stats* stats, int32_t* statuses, const tip_tuning* tune) {
+  const auto t_start = std::chrono::steady_clock::now();
+  // one stream for the whole batch: the first problem's, or one of the call's own
+  hipStream_t st = (hipStream_t)params[0].stream;
+  struct OwnStream {
+    hipStream_t s = nullptr;
+    ~OwnStream() {
+      if (!s) return;
+      std::lock_guard<std::mutex> lk(g_device_mu);
+      (void)hipStreamSynchronize(s);
+      (void)hipStreamDestroy(s);
+    }
+  } own;
+  if (!st) {
+    {
+      std::lock_guard<std::mutex> lk(g_device_mu);
+      if (hipStreamCreateWithFlags(&own.s, hipStreamNonBlocking) != hipSuccess)
+        return fail(TIP_EDEVICE, "hipStreamCreateWithFlags failed");
+    }
+    TIP_HIP(hipStreamSynchronize(nullptr));        // work queued on the null stream comes first
+    st = own.s;
+  }
+  // operators: link repack, diagonal, lower spectral bound; the call's masks
+  std::vector<std::unique_ptr<tip_op_s, HandleDel>> hs((size_t)count);
+  std::vector<int> masks((size_t)count);
+  for (int32_t i = 0; i < count; ++i) {
+    tip_op_s* h = nullptr;
+    tip_status s = create_handle(&ops[i], st, &h);
+    if (s != TIP_OK) return fail(s, "torus %d: %s", i, g_err.c_str());
+    hs[(size_t)i].reset(h);
+    s = check_params(h, &params[i], &masks[(size_t)i]);
+    if (s != TIP_OK) return fail(s, "torus %d: %s", i, g_err.c_str());
+    if (params[i].precision == TIP_PREC_MIXED && h->kind == TIP_KIND_COVARIANT && !h->has_links32) {
+      const size_t n = (size_t)h->geom.ndim * 9 * h->geom.V;
+      if (const hipError_t e_ = h->links32.ensure(n * sizeof(float2)); e_ != hipSuccess)
+        return fail(TIP_ENOMEM, "torus %d: hipMalloc FP32 links: %s", i, hipGetErrorString(e_));
+      TIP_HIP(launch_cast_links(n, (const double2*)h->links.p, (float2*)h->links32.p, st));
+      h->has_links32 = true;
+    }
+  }
+  // classes of right-hand sides
+  std::vector<BatchClass> classes;
+  for (int32_t i = 0; i < count; ++i) {
+    const tip_op_s* h = hs[(size_t)i].get();
+    const tip_params& p = params[i];
+    const Geom& g = h->geom;
+    const int ncomp = g.ncomp;
+    const Prec prec = p.precision == TIP_PREC_MIXED ? Prec::kF32 : Prec::kF64;
+    const int rb = tune ? tune->rhs_block : p.rhs_block;
+    auto pick_b = [&](int64_t nrhs) {
+      int b = 1;
+      if (rb > 0) {
+        while (b < rb && b < 64) b *= 2;
+      } else {
+        b = 32;
+      }
+      while (b > 1 && b / 2 >= nrhs) b /= 2;
+      return b;
+    };
+    if (conj_split(g, h->kind, masks[(size_t)i], &p, false)) {
+      const ClassMap cm{(int64_t)g.gamma, int64_t(1) << g.LB};
+      for (int pass = 0; pass < 2; ++pass) {
+        const int64_t m0 = cm.first_member(p.m_begin, pass);
+        if (m0 >= p.n_vectors) continue;
+        const int64_t i0 = cm.index(m0, pass), i1 = cm.index(cm.first_member(p.n_vectors, pass), pass);
+        classes.push_back({i, pass, pass ? Elem::kComplex : Elem::kReal, prec, i0 * ncomp, i1 * ncomp,
+                           pick_b((i1 - i0) * ncomp)});
+      }
+    } else {
+      const bool f3 = g.has3 && p.n_vectors > (int64_t(1) << g.LB);
+      const bool cplx = h->kind == TIP_KIND_COVARIANT || masks[(size_t)i] == TIP_MASK_Z4 || f3 ||
+                        p.probe == TIP_PROBE_FOURIER;
+      if (p.n_vectors > p.m_begin)
+        classes.push_back({i, -1, cplx ? Elem::kComplex : Elem::kReal, prec, p.m_begin * ncomp, p.n_vectors * ncomp,
+                           pick_b((p.n_vectors - p.m_begin) * ncomp)});
+    }
+  }
+  // groups and jobs; work items of item_sites sites
+  int item_sites = tune && tune->item_sites > 0 ? tune->item_sites
+                   : params[0].item_sites > 0   ? params[0].item_sites
+                                                : kBatchItemSites;
+  if (const char* e = std::getenv("TIP_BATCH_ITEM")) item_sites = std::max(1, std::atoi(e));   // experiments
+  {
+    int v = 256;
+    while (v < item_sites && v < (1 << 20)) v *= 2;
+    item_sites = v;                              // a power of two >= 256: whole tiles for every B
+  }
+  std::vector<int> order(classes.size());
+  for (size_t c = 0; c < classes.size(); ++c) order[c] = (int)c;
+  auto key = [&](const BatchClass& c) {
+    return hs[(size_t)c.prob]->kind * 4 + (c.elem == Elem::kComplex ? 2 : 0) + (c.prec == Prec::kF32 ? 1 : 0);
+  };
+  std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return key(classes[x]) < key(classes[y]); });
+  std::vector<BatchJob> jobs;
+  std::vector<int> job_class;
+  std::vector<uint32_t> item_job;
+  std::vector<int32_t> lane_job;
+  std::vector<BatchGroup> groups;
+  std::vector<size_t> group_elems;
+  size_t PI = 1;
+  for (size_t oi = 0; oi < order.size();) {
+    const BatchClass& c0 = classes[(size_t)order[oi]];
+    BatchGroup gr{hs[(size_t)c0.prob]->kind, c0.elem, c0.prec, (uint32_t)item_job.size(), 0, (int)lane_job.size(), 0};
+    uint64_t off = 0;
+    for (; oi < order.size() && key(classes[(size_t)order[oi]]) == key(c0); ++oi) {
+      const BatchClass& c = classes[(size_t)order[oi]];
+      const tip_op_s* h = hs[(size_t)c.prob].get();
+      const tip_params& p = params[c.prob];
+      Geom gj = h->geom;
+      gj.probe = p.probe;
+      gj.stop = p.stop_levels;
+      gj.cls_gamma = c.j3 >= 0 ? (int32_t)gj.gamma : 0;
+      gj.cls_nbc = c.j3 >= 0 ? (int32_t)(1u << gj.LB) : 0;
+      gj.cls_j3 = c.j3 >= 0 ? c.j3 : 0;
+      int logB = 0;
+      while ((1 << logB) < c.B) ++logB;
+      const uint32_t nitems = (uint32_t)((gj.V + (uint32_t)item_sites - 1) / (uint32_t)item_sites);
+      PI = std::max<size_t>(PI, nitems);
+      const bool single = c.prec == Prec::kF32;
+      uint32_t site_bytes = 0;
+      if (h->kind == TIP_KIND_COVARIANT) site_bytes += (uint32_t)gj.ndim * 9 * 2 * (single ? 4 : 8);
+      if (h->has_coupling) site_bytes += (uint32_t)gj.ndim * 8;
+      if (h->has_mass_field) site_bytes += 8;
+      const uint32_t esz = (c.elem == Elem::kComplex ? 2u : 1u) * (single ? 4u : 8u);
+      for (int64_t blk0 = c.r0; blk0 < c.r1; blk0 += c.B) {
+        BatchJob J{};
+        J.g = gj;
+        J.prob = c.prob;
+        J.logB = logB;
+        J.nb = (int32_t)std::min<int64_t>(c.B, c.r1 - blk0);
+        J.rhs0 = blk0;
+        J.item0 = (uint32_t)item_job.size();
+        J.nitems = nitems;
+        J.lane0 = (int32_t)lane_job.size();
+        J.site_bytes = site_bytes;
+        J.esz = esz;
+        J.off = off;
+        const uint32_t jidx = (uint32_t)jobs.size();
+        jobs.push_back(J);
+        job_class.push_back(order[oi]);
+        item_job.insert(item_job.end(), nitems, jidx);
+        lane_job.insert(lane_job.end(), (size_t)c.B, (int32_t)jidx);
+        off += (uint64_t)gj.ncomp * gj.V * (uint64_t)c.B;
+      }
+    }
+    gr.nitems = (uint32_t)item_job.size() - gr.item_base;
+    gr.nlanes = (int)lane_job.size() - gr.lane_base;
+    groups.push_back(gr);
+    group_elems.push_back(off);
+  }
+  const int L = (int)lane_job.size();
+  std::vector<RunResult> results;
+  results.reserve((size_t)count);
+  for (int32_t i = 0; i < count; ++i)
+    results.emplace_back((params[i].n_vectors - params[i].m_begin) * hs[(size_t)i]->geom.ncomp);
+  if (L > 0) {
+    // device memory: per group x (FP64) and r, p, w (and x_h in mixed precision)
+    // in the working precision; 6 partial rows; the CG scalars; the tables
+    auto al = [](size_t n) { return (n + 255) & ~size_t(255); };
+    struct GroupVec { size_t x, xh, r, p, w; };
+    std::vector<GroupVec> gv(groups.size());
+    size_t vec_bytes = 0;
+    for (size_t gi = 0; gi < groups.size(); ++gi) {
+      const size_t e64 = groups[gi].elem == Elem::kComplex ? 16 : 8;
+      const size_t ew = groups[gi].prec == Prec::kF32 ? e64 / 2 : e64;
+      const size_t n = group_elems[gi];
+      gv[gi].x = vec_bytes;
+      vec_bytes += al(n * e64);
+      gv[gi].xh = vec_bytes;
+      if (groups[gi].prec == Prec::kF32) vec_bytes += al(n * ew);
+      gv[gi].r = vec_bytes;
+      vec_bytes += al(n * ew);
+      gv[gi].p = vec_bytes;
+      vec_bytes += al(n * ew);
+      gv[gi].w = vec_bytes;
+      vec_bytes += al(n * ew);
+    }
+    const size_t rowstride = (size_t)L * PI;
+    DevBuf vec, part, scal, tab;
+    if (const hipError_t e_ = vec.ensure(vec_bytes); e_ != hipSuccess)
+      return fail(TIP_ENOMEM, "hipMalloc of %zu bytes of batch vectors failed: %s", vec_bytes, hipGetErrorString(e_));
+    if (const hipError_t e_ = part.ensure(6 * rowstride * sizeof(double)); e_ != hipSuccess)
+      return fail(TIP_ENOMEM, "hipMalloc batch partials: %s", hipGetErrorString(e_));
+    const size_t scal_bytes = (size_t)L * (13 * sizeof(double) + 5 * sizeof(int)) + 256;
+    if (const hipError_t e_ = scal.ensure(scal_bytes); e_ != hipSuccess)
+      return fail(TIP_ENOMEM, "hipMalloc batch scalars: %s", hipGetErrorString(e_));
+    std::vector<BatchProb> probs((size_t)count);
+    for (int32_t i = 0; i < count; ++i) {
+      const tip_op_s* h = hs[(size_t)i].get();
+      BatchProb& P = probs[(size_t)i];
+      P.mass_field = h->has_mass_field ? (const double*)h->mass_field.p : nullptr;
+      P.mass = h->mass;
+      P.coupling = h->has_coupling ? (const double*)h->coupling.p : nullptr;
+      P.links = h->kind == TIP_KIND_COVARIANT ? h->links.p : nullptr;
+      P.links32 = h->has_links32 ? h->links32.p : nullptr;
+      P.seed = params[i].seed;
+      P.mask = masks[(size_t)i];
+      P.max_iter = params[i].max_iter > 0 ? params[i].max_iter
+                                          : (int)std::min<int64_t>(10 * (int64_t)h->geom.V * h->geom.ncomp, 1 << 20);
+      P.tol2 = params[i].tol * params[i].tol;
+    }
+    const size_t t_jobs = 0, t_probs = al(jobs.size() * sizeof(BatchJob));
+    const size_t t_items = t_probs + al(probs.size() * sizeof(BatchProb));
+    const size_t t_lanes = t_items + al(item_job.size() * sizeof(uint32_t));
+    const size_t t_bytes = t_lanes + al(lane_job.size() * sizeof(int32_t));
+    if (const hipError_t e_ = tab.ensure(t_bytes + 256); e_ != hipSuccess)
+      return fail(TIP_ENOMEM, "hipMalloc batch tables: %s", hipGetErrorString(e_));
+    char* tb = (char*)tab.p;
+    TIP_HIP(hipMemcpyAsync(tb + t_jobs, jobs.data(), jobs.size() * sizeof(BatchJob), hipMemcpyHostToDevice, st));
+    TIP_HIP(hipMemcpyAsync(tb + t_probs, probs.data(), probs.size() * sizeof(BatchProb), hipMemcpyHostToDevice, st));
+    TIP_HIP(hipMemcpyAsync(tb + t_items, item_job.data(), item_job.size() * sizeof(uint32_t), hipMemcpyHostToDevice,
+                           st));
+    TIP_HIP(hipMemcpyAsync(tb + t_lanes, lane_job.data(), lane_job.size() * sizeof(int32_t), hipMemcpyHostToDevice,
+                           st));
+    BatchArgs args{};
+    args.jobs = (const BatchJob*)(tb + t_jobs);
+    args.probs = (const BatchProb*)(tb + t_probs);
+    args.item_job = (const uint32_t*)(tb + t_items);
+    args.lane_job = (const int32_t*)(tb + t_lanes);
+    args.item_sites = item_sites;
+    args.PI = PI;
+    args.bytes = g_profiling ? (unsigned long long*)(tb + t_bytes) : nullptr;
+    CgScalars sc{};
+    double* d = (double*)scal.p;
+    sc.rho = d;
+    sc.alpha = d + L;
+    sc.xalpha = d + 2 * (size_t)L;
+    sc.beta = d + 3 * (size_t)L;
+    sc.rho_ref = d + 4 * (size_t)L;
+    sc.bnorm2 = d + 5 * (size_t)L;
+    sc.relres2 = d + 6 * (size_t)L;
+    sc.q = d + 7 * (size_t)L;                      // 2 L
+    sc.pp = d + 9 * (size_t)L;
+    sc.anorm = d + 10 * (size_t)L;
+    sc.xhn = d + 11 * (size_t)L;
+    sc.dev = d + 12 * (size_t)L;
+    int* iv = (int*)(d + 13 * (size_t)L);
+    sc.state = iv;
+    sc.iters = iv + L;
+    sc.restarts = iv + 2 * (size_t)L;
+    sc.ru = iv + 3 * (size_t)L;
+    sc.ru_lanes = iv + 4 * (size_t)L;
+    sc.active = iv + 5 * (size_t)L;
+    sc.n_ru = sc.active + 1;
+    sc.ru_count = sc.active + 2;
+    TIP_HIP(hipMemsetAsync(sc.ru_lanes, 0, (size_t)L * sizeof(int) + 64, st));
+    if (args.bytes) TIP_HIP(hipMemsetAsync(args.bytes, 0, sizeof(unsigned long long), st));
+    int live_lanes = 0;
+    for (const BatchJob& J : jobs) live_lanes += J.nb;
+    HostPinned host;
+    if (const hipError_t e_ = host.ensure((size_t)L * (3 * sizeof(double) + 4 * sizeof(int)) + 256); e_ != hipSuccess)
+      return fail(TIP_ENOMEM, "hipHostMalloc: %s", hipGetErrorString(e_));
+    int* h_active = (int*)host.p;
+    h_active[0] = live_lanes;
+    TIP_HIP(launch_batch_scalars_init(args, sc, L, st));
+    TIP_HIP(hipMemcpyAsync(sc.active, h_active, sizeof(int), hipMemcpyHostToDevice, st));
+    char* vb = (char*)vec.p;
+    for (size_t gi = 0; gi < groups.size(); ++gi) {
+      BatchArgs ga = args;
+      ga.item_base = groups[gi].item_base;
+      const bool mixed = groups[gi].prec == Prec::kF32;
+      TIP_HIP(launch_batch_init(ga, groups[gi], vb + gv[gi].x, mixed ? vb + gv[gi].xh : nullptr, vb + gv[gi].r,
+                                vb + gv[gi].p, st));
+    }
+    double* pt = (double*)part.p;
+    // residual replacement in single precision: the constants of the single-problem solver
+    const double eps32 = 0x1p-24, tau2 = 0x1p-10;
+    int64_t stencil_launches = 0;
+    double stencil_seconds = 0.0;
+    std::vector<hipEvent_t> evs;
+    auto enqueue_chunk = [&](int chunk, bool timed) -> tip_status {
+      for (int it = 0; it < chunk; ++it)
+        for (size_t gi = 0; gi < groups.size(); ++gi) {
+          BatchArgs ga = args;
+          ga.item_base = groups[gi].item_base;
+          const bool mixed = groups[gi].prec == Prec::kF32;
+          hipEvent_t e0 = nullptr, e1 = nullptr;
+          if (timed) {
+            TIP_HIP(hipEventCreate(&e0));
+            evs.push_back(e0);
+            TIP_HIP(hipEventCreate(&e1));
+            evs.push_back(e1);
+          }
+          TIP_HIP(launch_batch_iteration(ga, groups[gi], sc, vb + (mixed ? gv[gi].xh : gv[gi].x), vb + gv[gi].r,
+                                         vb + gv[gi].p, vb + gv[gi].w, pt, rowstride, mixed ? eps32 : 0.0,
+                                         mixed ? tau2 : 0.0, st, e0, e1));
+          if (mixed)
+            TIP_HIP(launch_batch_reliable(ga, groups[gi], sc, 0, vb + gv[gi].x, vb + gv[gi].xh, vb + gv[gi].r,
+                                          vb + gv[gi].p, pt + rowstride, rowstride, st));
+        }
+      return TIP_OK;
+    };
+    // chunks of iterations replayed as one HIP graph for the whole batch
+    hipGraphExec_t graph = nullptr;
+    struct GraphDel {
+      hipGraphExec_t* g;
+      ~GraphDel() {
+        if (*g) (void)hipGraphExecDestroy(*g);
+      }
+    } graph_del{&graph};
+    bool use_graph = !g_profiling && !env_off("TIP_GRAPH");
+    auto poll = [&]() -> tip_status {
+      TIP_HIP(hipMemcpyAsync(h_active, sc.active, sizeof(int), hipMemcpyDeviceToHost, st));
+      TIP_HIP(hipStreamSynchronize(st));
+      return TIP_OK;
+    };
+    for (;;) {
+      for (;;) {
+        if (use_graph && !graph) {
+          std::lock_guard<std::mutex> lk(g_device_mu);
+          if (hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal) != hipSuccess) {
+            use_graph = false;
+            (void)hipGetLastError();
+          } else {
+            const tip_status cs = enqueue_chunk(kBatchChunk, false);
+            hipGraph_t gr = nullptr;
+            const hipError_t e = hipStreamEndCapture(st, &gr);
+            hipError_t ei = hipErrorUnknown;
+            if (cs == TIP_OK && e == hipSuccess && gr) ei = hipGraphInstantiate(&graph, gr, nullptr, nullptr, 0);
+            if (gr) (void)hipGraphDestroy(gr);
+            if (ei != hipSuccess) {
+              graph = nullptr;
+              use_graph = false;
+              (void)hipGetLastError();
+            }
+          }
+        }
+        if (use_graph && graph) {
+          TIP_HIP(hipGraphLaunch(graph, st));
+        } else {
+          tip_status cs = enqueue_chunk(kBatchChunk, g_profiling != 0);
+          if (cs != TIP_OK) return cs;
+        }
+        tip_status ps = poll();
+        if (ps != TIP_OK) return ps;
+        for (size_t k = 0; k + 1 < evs.size(); k += 2) {
+          float ms = 0.f;
+          TIP_HIP(hipEventElapsedTime(&ms, evs[k], evs[k + 1]));
+          stencil_seconds += ms * 1e-3;
+          ++stencil_launches;
+        }
+        for (hipEvent_t e : evs) (void)hipEventDestroy(e);
+        evs.clear();
+        if (h_active[0] == 0) break;
+      }
+      // the FP64 check of every frozen solve: accept, or restart CG from x
+      for (size_t gi = 0; gi < groups.size(); ++gi) {
+        BatchArgs ga = args;
+        ga.item_base = groups[gi].item_base;
+        if (groups[gi].prec == Prec::kF32)
+          TIP_HIP(launch_batch_reliable(ga, groups[gi], sc, 1, vb + gv[gi].x, vb + gv[gi].xh, vb + gv[gi].r,
+                                        vb + gv[gi].p, pt + rowstride, rowstride, st));
+        else
+          TIP_HIP(launch_batch_true_residual(ga, groups[gi], sc, vb + gv[gi].x, vb + gv[gi].r, vb + gv[gi].p,
+                                             pt + rowstride, rowstride, st));
+      }
+      tip_status ps = poll();
+      if (ps != TIP_OK) return ps;
+      if (h_active[0] == 0) break;
+    }
+    // per-lane results back to the problems
+    double* h_q = (double*)((char*)host.p + 64);
+    double* h_rr = h_q + 2 * (size_t)L;
+    int* h_state = (int*)(h_rr + L);
+    int* h_iters = h_state + L;
+    int* h_restarts = h_iters + L;
+    int* h_ru = h_restarts + L;
+    TIP_HIP(hipMemcpyAsync(h_q, sc.q, 2 * (size_t)L * sizeof(double), hipMemcpyDeviceToHost, st));
+    TIP_HIP(hipMemcpyAsync(h_rr, sc.relres2, (size_t)L * sizeof(double), hipMemcpyDeviceToHost, st));
+    TIP_HIP(hipMemcpyAsync(h_state, sc.state, (size_t)L * sizeof(int), hipMemcpyDeviceToHost, st));
+    TIP_HIP(hipMemcpyAsync(h_iters, sc.iters, (size_t)L * sizeof(int), hipMemcpyDeviceToHost, st));
+    TIP_HIP(hipMemcpyAsync(h_restarts, sc.restarts, (size_t)L * sizeof(int), hipMemcpyDeviceToHost, st));
+    TIP_HIP(hipMemcpyAsync(h_ru, sc.ru_lanes, (size_t)L * sizeof(int), hipMemcpyDeviceToHost, st));
+    unsigned long long bytes_moved = 0;
+    if (args.bytes) TIP_HIP(hipMemcpyAsync(&bytes_moved, args.bytes, sizeof bytes_moved, hipMemcpyDeviceToHost, st));
+    TIP_HIP(hipStreamSynchronize(st));
+    for (size_t ji = 0; ji < jobs.size(); ++ji) {
+      const BatchJob& J = jobs[ji];
+      const BatchClass& c = classes[(size_t)job_class[ji]];
+      const tip_params& p = params[J.prob];
+      const int ncomp = J.g.ncomp;
+      RunResult& rr = results[(size_t)J.prob];
+      for (int j = 0; j < J.nb; ++j) {
+        const int lane = J.lane0 + j;
+        const int64_t r = J.rhs0 + j;
+        const int64_t m = c.j3 >= 0 ? (int64_t)class_probe((uint64_t)(r / ncomp), J.g) : r / ncomp;
+        const size_t k = (size_t)((m - p.m_begin) * ncomp + r % ncomp);
+        rr.qre[k] = h_q[2 * lane];
+        rr.qim[k] = h_q[2 * lane + 1];
+        rr.state[k] = h_state[lane];
+        rr.iters[k] = h_iters[lane];
+        rr.relres[k] = std::sqrt(h_rr[lane]);
+        rr.acc.restarts += h_restarts[lane];
+        rr.acc.reliable_updates += h_ru[lane];
+      }
+    }
+    for (int32_t i = 0; i < count; ++i) {
+      tip_stats& a = results[(size_t)i].acc;
+      a.stencil_launches = stencil_launches;
+      a.stencil_seconds = g_profiling ? stencil_seconds : 0.0;
+      a.stencil_bytes = (double)bytes_moved;
+    }
+  }
+  // estimates and stats per problem; conjugate F_3 columns from their partners
+  tip_status first = TIP_OK;
+  int32_t first_i = -1;
+  std::string first_msg;
+  for (int32_t i = 0; i < count; ++i) {
+    const tip_op_s* h = hs[(size_t)i].get();
+    if (conj_split(h->geom, h->kind, masks[(size_t)i], &params[i], false))
+      conj_copies(h->geom, &params[i], h->geom.ncomp, results[(size_t)i]);
+    const tip_status si =
+        finish_run(h, &params[i], results[(size_t)i], estimates[i], stats ? &stats[i] : nullptr, t_start);
+    if (statuses) statuses[i] = si;
+    if (si != TIP_OK && first_i < 0) first = si, first_i = i, first_msg = g_err;
+  }
+  if (first_i >= 0) return fail(first, "torus %d: %s", first_i, first_msg.c_str());
   return TIP_OK;
 }
 
@@ -1474,71 +1978,57 @@ tip_status trace_inv_probe(const tip_operator* op, const tip_params* p, double* 
 
 tip_status trace_inv_probe_batch(const tip_operator* ops, const tip_params* params, int32_t count, int32_t n_streams,
                                  double* const* estimates, tip_stats* stats, int32_t* statuses) {
-  if (count < 0) return fail(TIP_EINVAL, "count = %d must be >= 0", count);
-  if (count > 0 && (!ops || !params || !estimates)) return fail(TIP_EINVAL, "ops, params or estimates is NULL");
   if (n_streams < 0) return fail(TIP_EINVAL, "n_streams = %d must be >= 0", n_streams);
+  tip_status s = validate_batch(ops, params, count, estimates);
+  if (s != TIP_OK || count == 0) return s;
+  return run_batch(ops, params, count, estimates, stats, statuses, nullptr);
+}
+
+tip_status tip_autotune_batch(const tip_operator* ops, const tip_params* params, int32_t count,
+                              int64_t sample_vectors, tip_tuning* best, tip_tuning* tried, int32_t max_tried,
+                              int32_t* n_tried) {
+  if (!best) return fail(TIP_EINVAL, "best is NULL");
+  if (max_tried < 0 || (max_tried > 0 && !tried)) return fail(TIP_EINVAL, "tried is NULL");
+  tip_status s = validate_batch(ops, params, count, nullptr);
+  if (s != TIP_OK) return s;
+  if (count == 0) return fail(TIP_EINVAL, "count = 0: nothing to tune");
+  // the sample: the first sample_vectors probes of every problem, fresh runs
+  const int64_t want = sample_vectors > 0 ? sample_vectors : 16;
+  std::vector<tip_params> q(params, params + count);
+  std::vector<std::vector<double>> est((size_t)count);
+  std::vector<double*> est_ptr((size_t)count);
+  int64_t solves = 0;
   for (int32_t i = 0; i < count; ++i) {
-    Geom g;
-    tip_status s = validate_op(&ops[i], &g);
-    if (s != TIP_OK) return fail(s, "torus %d: %s", i, g_err.c_str());
-    if (!estimates[i]) return fail(TIP_EINVAL, "torus %d: estimates is NULL", i);
-    if (params[i].n_vectors < 1 || params[i].n_vectors > (int64_t)g.V)
-      return fail(TIP_EINVAL, "torus %d: n_vectors = %lld must be in [1, V = %u]", i,
-                  (long long)params[i].n_vectors, g.V);
+    q[(size_t)i].n_vectors = std::max<int64_t>(1, std::min<int64_t>(want, params[i].n_vectors));
+    q[(size_t)i].m_begin = 0;
+    q[(size_t)i].quadratures = nullptr;
+    est[(size_t)i].assign((size_t)num_checkpoints(q[(size_t)i].n_vectors) * 2, 0.0);
+    est_ptr[(size_t)i] = est[(size_t)i].data();
+    solves += q[(size_t)i].n_vectors * (ops[i].kind == TIP_KIND_COVARIANT ? 3 : 1);
   }
-  if (count == 0) return TIP_OK;
-  int device = 0;
-  if (hipGetDevice(&device) != hipSuccess) return fail(TIP_EDEVICE, "hipGetDevice failed");
-  // longest first: work ~ V * n_vectors * ncomp
-  std::vector<int32_t> order((size_t)count);
-  std::vector<double> work((size_t)count);
-  for (int32_t i = 0; i < count; ++i) {
-    double v = (double)params[i].n_vectors * (ops[i].kind == TIP_KIND_COVARIANT ? 3.0 : 1.0);
-    for (int j = 0; j < ops[i].ndim; ++j) v *= (double)ops[i].dims[j];
-    work[(size_t)i] = v;
-    order[(size_t)i] = i;
-  }
-  std::stable_sort(order.begin(), order.end(), [&](int32_t a, int32_t b) { return work[(size_t)a] > work[(size_t)b]; });
-  // 8 by default: twice the hardware queues a process gets here, so that one
-  // worker's host-side polling overlaps another's kernels (measured on the
-  // batch of 64 uneven 3-D tori: +3% over 4)
-  const int workers = std::max(1, std::min<int>(n_streams > 0 ? n_streams : 8, count));
-  std::vector<tip_status> st((size_t)count, TIP_OK);
-  std::vector<std::string> msg((size_t)count);
-  std::atomic<int32_t> next{0};
-  auto run = [&]() {
-    (void)hipSetDevice(device);
-    hipStream_t stream = nullptr;
-    // non-blocking: no implicit ordering with the null stream or the other workers
-    {
-      std::lock_guard<std::mutex> lk(g_device_mu);
-      if (hipStreamCreateWithFlags(&stream, hipStreamNonBlocking) != hipSuccess) stream = nullptr;
+  std::vector<int> blocks = params[0].rhs_block > 0 ? std::vector<int>{params[0].rhs_block} : std::vector<int>{16, 32, 64};
+  std::vector<int> items = params[0].item_sites > 0 ? std::vector<int>{params[0].item_sites}
+                                                    : std::vector<int>{256, 512, 1024, 2048};
+  int cnt = 0;
+  double best_t = 1e300;
+  for (int bsz : blocks)
+    for (int it : items) {
+      tip_tuning t{};
+      t.rhs_block = bsz;
+      t.item_sites = it;
+      double secs = 0.0;
+      for (int rep = 0; rep < 2; ++rep) {                 // the first run warms up
+        const auto t0 = std::chrono::steady_clock::now();
+        s = run_batch(ops, q.data(), count, est_ptr.data(), nullptr, nullptr, &t);
+        if (s != TIP_OK) return s;
+        secs = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+      }
+      t.seconds_per_solve = secs / (double)std::max<int64_t>(1, solves);
+      if (cnt < max_tried) tried[cnt] = t;
+      ++cnt;
+      if (t.seconds_per_solve < best_t) best_t = t.seconds_per_solve, *best = t;
     }
-    for (;;) {
-      const int32_t k = next.fetch_add(1);
-      if (k >= count) break;
-      const int32_t i = order[(size_t)k];
-      tip_params p = params[i];
-      p.stream = stream;
-      st[(size_t)i] = trace_inv_probe(&ops[i], &p, estimates[i], stats ? &stats[i] : nullptr);
-      if (st[(size_t)i] != TIP_OK) msg[(size_t)i] = g_err;
-    }
-    if (stream) {
-      std::lock_guard<std::mutex> lk(g_device_mu);
-      (void)hipStreamDestroy(stream);
-    }
-  };
-  std::vector<std::thread> pool;
-  for (int w = 1; w < workers; ++w) pool.emplace_back(run);
-  run();
-  for (auto& t : pool) t.join();
-  tip_status first = TIP_OK;
-  int32_t first_i = -1;
-  for (int32_t i = 0; i < count; ++i) {
-    if (statuses) statuses[i] = st[(size_t)i];
-    if (st[(size_t)i] != TIP_OK && first_i < 0) first = st[(size_t)i], first_i = i;
-  }
-  if (first_i >= 0) return fail(first, "torus %d: %s", first_i, msg[(size_t)first_i].c_str());
+  if (n_tried) *n_tried = cnt;
   return TIP_OK;
 }
 

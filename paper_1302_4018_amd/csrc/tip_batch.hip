@@ -1,0 +1,503 @@
+// Batched kernels: many independent problems (e.g. 64 tori of uneven sides,
+// Sec. 3.4) solved together, one launch per CG phase for every problem of a
+// group.
+//
+// Each problem's right-hand sides are split into jobs: blocks of B = 2^logB
+// right-hand sides in the block layout [ncomp][V][B] of that problem, placed
+// one after another in the group's vector arrays.  A job's sites are cut
+// into work items of `item_sites` consecutive sites (a multiple of the tile
+// of 256 / B sites); workgroup b of a launch takes item item_base + b, finds
+// its job in item_job[] and walks the item one tile (256 threads = 256 / B
+// sites x B rhs) at a time.  Lanes are numbered globally (job lane0 + j), so
+// one array of CG scalars serves every problem, and the partials of a
+// per-rhs reduction are stored per lane: partial[lane * PI + item - item0],
+// PI = the most items any job has.  The scalar steps are those of the
+// single-problem solver (lane_alpha, lane_beta, lane_true, lane_ru), with each
+// problem's own tolerance and iteration cap.
+//
+// A workgroup none of whose rhs is live returns at once, so problems that
+// have converged cost a launch slot each, not memory traffic.
+
+#include <type_traits>
+
+#include "tip_batch.h"
+#include "tip_kernel_common.h"
+
+namespace tip {
+
+namespace {
+
+// CG scalars of job J (lane j of the job is entry j of every array).
+__device__ __forceinline__ CgScalars job_scalars(const CgScalars& sc, int lane0) {
+  CgScalars s = sc;
+  s.rho += lane0;
+  s.alpha += lane0;
+  s.xalpha += lane0;
+  s.beta += lane0;
+  s.rho_ref += lane0;
+  s.pp += lane0;
+  s.anorm += lane0;
+  s.xhn += lane0;
+  s.dev += lane0;
+  s.bnorm2 += lane0;
+  s.relres2 += lane0;
+  s.q += 2 * lane0;
+  s.state += lane0;
+  s.iters += lane0;
+  s.restarts += lane0;
+  s.ru += lane0;
+  return s;
+}
+
+// Operator policy of a problem: the links in the vector type's precision.
+template <class Op> struct BatchOpOf;
+template <class TT> struct BatchOpOf<ScalarOp<TT>> {
+  __device__ static ScalarOp<TT> get(const BatchProb&) { return ScalarOp<TT>{}; }
+};
+template <class C> struct BatchOpOf<CovOp<C>> {
+  __device__ static CovOp<C> get(const BatchProb& P) {
+    return CovOp<C>{(const C*)(sizeof(C) == sizeof(float2) ? P.links32 : P.links)};
+  }
+};
+
+// Per-lane sum of a workgroup's values, stored as partial row entry of lane
+// lane0 + j and item `local` (threads j < B hold the totals after seg_sum).
+template <int N>
+__device__ __forceinline__ void store_partials(double (&acc)[N], int B, double* lds, double* __restrict__ partial,
+                                               size_t rowstride, size_t PI, int lane0, uint32_t local) {
+  seg_sum<N, kBlock / 64>(acc, B, lds);
+  if ((int)threadIdx.x < B) {
+#pragma unroll
+    for (int k = 0; k < N; ++k) partial[k * rowstride + (size_t)(lane0 + (int)threadIdx.x) * PI + local] = acc[k];
+  }
+}
+
+}  // namespace
+
+// x = 0 and r = p = b (FP64); mixed: x64 = 0, xh = 0, r = p = single(b).
+template <class T64, class TW, int NC>
+__global__ __launch_bounds__(kBlock) void kb_init(BatchArgs a, T64* __restrict__ x64, TW* __restrict__ xh,
+                                                  TW* __restrict__ r, TW* __restrict__ p) {
+  const uint32_t item = a.item_base + blockIdx.x;
+  const BatchJob& J = a.jobs[a.item_job[item]];
+  const BatchProb& P = a.probs[J.prob];
+  const Geom& g = J.g;
+  const int logB = J.logB, B = 1 << logB;
+  const int j = threadIdx.x & (B - 1), si = threadIdx.x >> logB;
+  const uint32_t s0 = (item - J.item0) * (uint32_t)a.item_sites;
+  const uint32_t s1 = min(g.V, s0 + (uint32_t)a.item_sites);
+  T64* xj = x64 + J.off;
+  for (uint32_t s = s0 + (uint32_t)si; s < s1; s += (uint32_t)(kBlock >> logB)) {
+    TW b[NC], zw[NC];
+    T64 z64[NC];
+    rhs_at<TW, NC>(g, s, J.rhs0, j, J.nb, P.seed, P.mask, b);
+#pragma unroll
+    for (int c = 0; c < NC; ++c) {
+      zw[c] = zero<TW>();
+      z64[c] = zero<T64>();
+    }
+    store_vec<T64, NC>(xj, g.V, logB, s, j, z64);
+    if (xh) store_vec<TW, NC>(xh + J.off, g.V, logB, s, j, zw);
+    store_vec<TW, NC>(r + J.off, g.V, logB, s, j, b);
+    store_vec<TW, NC>(p + J.off, g.V, logB, s, j, b);
+  }
+}
+
+// w = A p for the live lanes, partial p^H w per lane.
+template <class Op>
+__global__ __launch_bounds__(kBlock) void kb_stencil(BatchArgs a, CgScalars sc, const typename Op::T* __restrict__ in,
+                                                     typename Op::T* __restrict__ out, double* __restrict__ partial) {
+  using T = typename Op::T;
+  constexpr int NC = Op::NC;
+  __shared__ double lds[4 * 64];
+  const uint32_t item = a.item_base + blockIdx.x;
+  const BatchJob& J = a.jobs[a.item_job[item]];
+  const BatchProb& P = a.probs[J.prob];
+  const Geom& g = J.g;
+  const int logB = J.logB, B = 1 << logB;
+  const int j = threadIdx.x & (B - 1), si = threadIdx.x >> logB;
+  const bool live = sc.state[J.lane0 + j] == kActive;
+  // live rhs of the job (threads si == 0 hold lanes 0..B-1); none: its partials are not read
+  const int nlive = __syncthreads_count(live && si == 0);
+  if (nlive == 0) return;
+  const Op op = BatchOpOf<Op>::get(P);
+  const uint32_t s0 = (item - J.item0) * (uint32_t)a.item_sites;
+  const uint32_t s1 = min(g.V, s0 + (uint32_t)a.item_sites);
+  if (a.bytes && threadIdx.x == 0)   // each link, coupling and mass read once, p read and w written per live rhs
+    atomicAdd(a.bytes, (unsigned long long)(s1 - s0) * (J.site_bytes + 2ull * (unsigned)NC * (unsigned)nlive * J.esz));
+  const T* inj = in + J.off;
+  T* outj = out + J.off;
+  double dot[1] = {0.0};
+  if (live) {
+    for (uint32_t s = s0 + (uint32_t)si; s < s1; s += (uint32_t)(kBlock >> logB)) {
+      T xs[NC], y[NC];
+      stencil_site(op, g, logB, s, j, P.mass_field, P.mass, P.coupling, inj, xs, y);
+      store_vec<T, NC>(outj, g.V, logB, s, j, y);
+#pragma unroll
+      for (int c = 0; c < NC; ++c) dot[0] += redot(xs[c], y[c]);
+    }
+  }
+  store_partials<1>(dot, B, lds, partial, 0, a.PI, J.lane0, item - J.item0);
+}
+
+// r -= alpha w for the live lanes, partial ||r||^2.
+template <class T>
+__global__ __launch_bounds__(kBlock) void kb_update_r(BatchArgs a, CgScalars sc, T* __restrict__ r,
+                                                      const T* __restrict__ w, double* __restrict__ partial) {
+  __shared__ double lds[4 * 64];
+  const uint32_t item = a.item_base + blockIdx.x;
+  const BatchJob& J = a.jobs[a.item_job[item]];
+  const Geom& gp = J.g;
+  const uint32_t V = gp.V;
+  const int nc = gp.ncomp;
+  const int logB = J.logB, B = 1 << logB;
+  const int j = threadIdx.x & (B - 1), si = threadIdx.x >> logB;
+  const bool live = sc.state[J.lane0 + j] == kActive;
+  if (!__syncthreads_or(live)) return;
+  const uint32_t s0 = (item - J.item0) * (uint32_t)a.item_sites;
+  const uint32_t s1 = min(V, s0 + (uint32_t)a.item_sites);
+  double acc[1] = {0.0};
+  if (live) {
+    const double al = sc.alpha[J.lane0 + j];
+    T* rj = r + J.off;
+    const T* wj = w + J.off;
+    for (int c = 0; c < nc; ++c)
+      for (uint32_t s = s0 + (uint32_t)si; s < s1; s += (uint32_t)(kBlock >> logB)) {
+        const size_t i = (((size_t)c * V + s) << logB) + j;
+        const T ri = axpy(-al, wj[i], rj[i]);
+        rj[i] = ri;
+        acc[0] += norm2(ri);
+      }
+  }
+  store_partials<1>(acc, B, lds, partial, 0, a.PI, J.lane0, item - J.item0);
+}
+
+// x += xalpha p (also for a rhs that converged this iteration); p = r + beta p
+// for the lanes still iterating.
+template <class T>
+__global__ __launch_bounds__(kBlock) void kb_direction(BatchArgs a, CgScalars sc, T* __restrict__ x,
+                                                       const T* __restrict__ r, T* __restrict__ p) {
+  const uint32_t item = a.item_base + blockIdx.x;
+  const BatchJob& J = a.jobs[a.item_job[item]];
+  const Geom& gp = J.g;
+  const uint32_t V = gp.V;
+  const int nc = gp.ncomp;
+  const int logB = J.logB, B = 1 << logB;
+  const int j = threadIdx.x & (B - 1), si = threadIdx.x >> logB;
+  const double xa = sc.xalpha[J.lane0 + j];
+  const bool live = sc.state[J.lane0 + j] == kActive;
+  if (!__syncthreads_or(live || xa != 0.0)) return;
+  if (!live && xa == 0.0) return;
+  const double be = sc.beta[J.lane0 + j];
+  const uint32_t s0 = (item - J.item0) * (uint32_t)a.item_sites;
+  const uint32_t s1 = min(V, s0 + (uint32_t)a.item_sites);
+  T* xj = x + J.off;
+  const T* rj = r + J.off;
+  T* pj = p + J.off;
+  for (int c = 0; c < nc; ++c)
+    for (uint32_t s = s0 + (uint32_t)si; s < s1; s += (uint32_t)(kBlock >> logB)) {
+      const size_t i = (((size_t)c * V + s) << logB) + j;
+      const T pi = pj[i];
+      if (xa != 0.0) xj[i] = axpy(xa, pi, xj[i]);
+      if (live) pj[i] = axpy(be, pi, rj[i]);
+    }
+}
+
+// FP64 check of the frozen lanes: rt = b - A x with b regenerated; r = p = rt
+// (the restart direction); partial rows ||rt||^2, Re b^H x, Im b^H x.
+template <class Op>
+__global__ __launch_bounds__(kBlock) void kb_true_residual(BatchArgs a, CgScalars sc,
+                                                           const typename Op::T* __restrict__ x,
+                                                           typename Op::T* __restrict__ r,
+                                                           typename Op::T* __restrict__ p, double* __restrict__ partial,
+                                                           size_t rowstride) {
+  using T = typename Op::T;
+  constexpr int NC = Op::NC;
+  __shared__ double lds[3 * 4 * 64];
+  const uint32_t item = a.item_base + blockIdx.x;
+  const BatchJob& J = a.jobs[a.item_job[item]];
+  const BatchProb& P = a.probs[J.prob];
+  const Geom& g = J.g;
+  const int logB = J.logB, B = 1 << logB;
+  const int j = threadIdx.x & (B - 1), si = threadIdx.x >> logB;
+  const bool live = sc.state[J.lane0 + j] == kFrozen;
+  if (!__syncthreads_or(live)) return;
+  const Op op = BatchOpOf<Op>::get(P);
+  const uint32_t s0 = (item - J.item0) * (uint32_t)a.item_sites;
+  const uint32_t s1 = min(g.V, s0 + (uint32_t)a.item_sites);
+  double acc[3] = {0.0, 0.0, 0.0};
+  if (live) {
+    const T* xj = x + J.off;
+    for (uint32_t s = s0 + (uint32_t)si; s < s1; s += (uint32_t)(kBlock >> logB)) {
+      T xs[NC], ax[NC], b[NC], rt[NC];
+      stencil_site(op, g, logB, s, j, P.mass_field, P.mass, P.coupling, xj, xs, ax);
+      rhs_at<T, NC>(g, s, J.rhs0, j, J.nb, P.seed, P.mask, b);
+#pragma unroll
+      for (int c = 0; c < NC; ++c) {
+        rt[c] = axpy(-1.0, ax[c], b[c]);
+        acc[0] += norm2(rt[c]);
+        acc[1] += redot(b[c], xs[c]);
+        acc[2] += imdot(b[c], xs[c]);
+      }
+      store_vec<T, NC>(r + J.off, g.V, logB, s, j, rt);
+      store_vec<T, NC>(p + J.off, g.V, logB, s, j, rt);
+    }
+  }
+  store_partials<3>(acc, B, lds, partial, rowstride, a.PI, J.lane0, item - J.item0);
+}
+
+// Mixed precision: x64 += xh, xh = 0 for the selected lanes (mode 0 flagged
+// for a reliable update, mode 1 frozen).  Mode 0 runs after every iteration
+// and returns at once while no update is pending.
+template <class T64, class T32>
+__global__ __launch_bounds__(kBlock) void kb_ru_accumulate(BatchArgs a, CgScalars sc, int mode,
+                                                           T64* __restrict__ x, T32* __restrict__ xh) {
+  if (mode == 0 && *sc.n_ru == 0) return;
+  const uint32_t item = a.item_base + blockIdx.x;
+  const BatchJob& J = a.jobs[a.item_job[item]];
+  const Geom& gp = J.g;
+  const uint32_t V = gp.V;
+  const int nc = gp.ncomp;
+  const int logB = J.logB, B = 1 << logB;
+  const int j = threadIdx.x & (B - 1), si = threadIdx.x >> logB;
+  const CgScalars sj = job_scalars(sc, J.lane0);
+  if (!ru_selected(sj, mode, j)) return;
+  const uint32_t s0 = (item - J.item0) * (uint32_t)a.item_sites;
+  const uint32_t s1 = min(V, s0 + (uint32_t)a.item_sites);
+  T64* xj = x + J.off;
+  T32* hj = xh + J.off;
+  for (int c = 0; c < nc; ++c)
+    for (uint32_t s = s0 + (uint32_t)si; s < s1; s += (uint32_t)(kBlock >> logB)) {
+      const size_t i = (((size_t)c * V + s) << logB) + j;
+      xj[i] = axpy(1.0, from_c<T64>(to_c(hj[i])), xj[i]);
+      hj[i] = zero<T32>();
+    }
+}
+
+// Mixed precision: r = b - A x64 with the FP64 operator for the selected lanes,
+// rh = single(r), in mode 1 also ph = rh; partial rows ||r||^2, Re/Im b^H x,
+// Re/Im x^H r.
+template <class Op64, class T32>
+__global__ __launch_bounds__(kBlock) void kb_ru_residual(BatchArgs a, CgScalars sc, int mode,
+                                                         const typename Op64::T* __restrict__ x,
+                                                         T32* __restrict__ rh, T32* __restrict__ ph,
+                                                         double* __restrict__ partial, size_t rowstride) {
+  using T = typename Op64::T;
+  constexpr int NC = Op64::NC;
+  if (mode == 0 && *sc.n_ru == 0) return;
+  __shared__ double lds[5 * 4 * 64];
+  const uint32_t item = a.item_base + blockIdx.x;
+  const BatchJob& J = a.jobs[a.item_job[item]];
+  const BatchProb& P = a.probs[J.prob];
+  const Geom& g = J.g;
+  const int logB = J.logB, B = 1 << logB;
+  const int j = threadIdx.x & (B - 1), si = threadIdx.x >> logB;
+  const CgScalars sj = job_scalars(sc, J.lane0);
+  const bool live = ru_selected(sj, mode, j);
+  if (!__syncthreads_or(live)) return;
+  const Op64 op = BatchOpOf<Op64>::get(P);
+  const uint32_t s0 = (item - J.item0) * (uint32_t)a.item_sites;
+  const uint32_t s1 = min(g.V, s0 + (uint32_t)a.item_sites);
+  double acc[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+  if (live) {
+    const T* xj = x + J.off;
+    for (uint32_t s = s0 + (uint32_t)si; s < s1; s += (uint32_t)(kBlock >> logB)) {
+      T xs[NC], ax[NC], b[NC];
+      T32 r32[NC];
+      stencil_site(op, g, logB, s, j, P.mass_field, P.mass, P.coupling, xj, xs, ax);
+      rhs_at<T, NC>(g, s, J.rhs0, j, J.nb, P.seed, P.mask, b);
+#pragma unroll
+      for (int c = 0; c < NC; ++c) {
+        const T rt = axpy(-1.0, ax[c], b[c]);
+        acc[0] += norm2(rt);
+        acc[1] += redot(b[c], xs[c]);
+        acc[2] += imdot(b[c], xs[c]);
+        acc[3] += redot(xs[c], rt);
+        acc[4] += imdot(xs[c], rt);
+        r32[c] = to_single(rt);
+      }
+      store_vec<T32, NC>(rh + J.off, g.V, logB, s, j, r32);
+      if (mode == 1) store_vec<T32, NC>(ph + J.off, g.V, logB, s, j, r32);
+    }
+  }
+  store_partials<5>(acc, B, lds, partial, rowstride, a.PI, J.lane0, item - J.item0);
+}
+
+// ---- per-lane scalar steps, one workgroup per lane of a group -------------
+
+__global__ void kb_scalars_init(BatchArgs a, CgScalars sc, int nlanes) {
+  const int L = blockIdx.x * blockDim.x + threadIdx.x;
+  if (L >= nlanes) return;
+  const BatchJob& J = a.jobs[a.lane_job[L]];
+  const int j = L - J.lane0;
+  const bool valid = j < J.nb;
+  const double bnorm2 = (double)J.g.V;   // unit-modulus entries on one component per site
+  sc.state[L] = valid ? kActive : kPadding;
+  sc.bnorm2[L] = valid ? bnorm2 : 0.0;
+  sc.rho[L] = valid ? bnorm2 : 0.0;
+  sc.alpha[L] = 0.0;
+  sc.xalpha[L] = 0.0;
+  sc.beta[L] = 0.0;
+  sc.rho_ref[L] = valid ? bnorm2 : 0.0;
+  sc.pp[L] = valid ? bnorm2 : 0.0;
+  sc.anorm[L] = 0.0;
+  sc.xhn[L] = 0.0;
+  sc.dev[L] = 0.0;
+  sc.ru[L] = 0;
+  sc.iters[L] = 0;
+  sc.restarts[L] = 0;
+  sc.relres2[L] = 0.0;
+  sc.q[2 * L] = 0.0;
+  sc.q[2 * L + 1] = 0.0;
+}
+
+__global__ __launch_bounds__(kBlock) void kb_reduce_alpha(BatchArgs a, CgScalars sc, int lane_base,
+                                                          const double* __restrict__ partial, int soft) {
+  const int L = lane_base + blockIdx.x;
+  if (*sc.active == 0 || sc.state[L] != kActive) return;     // uniform per workgroup
+  const BatchJob& J = a.jobs[a.lane_job[L]];
+  const double pAp = sum_partials(partial + (size_t)L * a.PI, (int)J.nitems);
+  if (threadIdx.x != 0) return;
+  lane_alpha(sc, L, pAp, soft, false);
+}
+
+__global__ __launch_bounds__(kWideBlock) void kb_reduce_beta(BatchArgs a, CgScalars sc, int lane_base,
+                                                         const double* __restrict__ partial, double eps,
+                                                         double tau2) {
+  const int L = lane_base + blockIdx.x;
+  if (sc.state[L] != kActive) {                // uniform per workgroup
+    if (threadIdx.x == 0) sc.xalpha[L] = 0.0;
+    return;
+  }
+  const BatchJob& J = a.jobs[a.lane_job[L]];
+  const BatchProb& P = a.probs[J.prob];
+  const BetaIn in = lane_beta_read(sc, L);
+  const double rho_new = sum_partials_wide(partial + (size_t)L * a.PI, (int)J.nitems);
+  if (threadIdx.x != 0) return;
+  lane_beta(sc, L, in, rho_new, P.tol2, P.max_iter, 0.0, P.tol2, eps, tau2);
+}
+
+__global__ __launch_bounds__(kBlock) void kb_reduce_true(BatchArgs a, CgScalars sc, int lane_base,
+                                                         const double* __restrict__ partial, size_t rowstride) {
+  const int L = lane_base + blockIdx.x;
+  if (threadIdx.x == 0) sc.xalpha[L] = 0.0;
+  if (sc.state[L] != kFrozen) return;
+  const BatchJob& J = a.jobs[a.lane_job[L]];
+  const BatchProb& P = a.probs[J.prob];
+  const double* row = partial + (size_t)L * a.PI;
+  const double rt2 = sum_partials(row, (int)J.nitems);
+  const double qre = sum_partials(row + rowstride, (int)J.nitems);
+  const double qim = sum_partials(row + 2 * rowstride, (int)J.nitems);
+  if (threadIdx.x != 0) return;
+  lane_true(sc, L, rt2, qre, qim, P.tol2, P.max_iter, kBatchMaxRestarts);
+}
+
+__global__ __launch_bounds__(kBlock) void kb_reduce_ru(BatchArgs a, CgScalars sc, int lane_base,
+                                                       const double* __restrict__ partial, size_t rowstride, int mode) {
+  const int L = lane_base + blockIdx.x;
+  if (mode == 0 && *sc.n_ru == 0) return;
+  if (!ru_selected(sc, mode, L)) return;      // uniform per workgroup
+  const BatchJob& J = a.jobs[a.lane_job[L]];
+  const BatchProb& P = a.probs[J.prob];
+  double v[5];
+#pragma unroll
+  for (int k = 0; k < 5; ++k) v[k] = sum_partials(partial + k * rowstride + (size_t)L * a.PI, (int)J.nitems);
+  if (threadIdx.x != 0) return;
+  lane_ru(sc, L, v, mode, P.tol2, P.max_iter, kBatchMaxRestarts);
+}
+
+// ---- launchers -------------------------------------------------------------
+
+namespace {
+
+// Operator policy for a group: (kind, element type, precision).
+template <class F>
+hipError_t batch_dispatch(int kind, Elem elem, Prec prec, F&& f) {
+  if (kind == 1) {
+    if (prec == Prec::kF32) f(CovOp<float2>{nullptr});
+    else f(CovOp<double2>{nullptr});
+  } else if (elem == Elem::kReal) {
+    if (prec == Prec::kF32) f(ScalarOp<float>{});
+    else f(ScalarOp<double>{});
+  } else {
+    if (prec == Prec::kF32) f(ScalarOp<float2>{});
+    else f(ScalarOp<double2>{});
+  }
+  return hipGetLastError();
+}
+
+template <class T> struct Wide;
+template <> struct Wide<float> { using type = double; };
+template <> struct Wide<double> { using type = double; };
+template <> struct Wide<float2> { using type = double2; };
+template <> struct Wide<double2> { using type = double2; };
+
+template <class T> struct is_single
+    : std::integral_constant<bool, std::is_same<T, float>::value || std::is_same<T, float2>::value> {};
+
+template <class Op> struct FP64Op;
+template <class TT> struct FP64Op<ScalarOp<TT>> { using type = ScalarOp<typename Wide<TT>::type>; };
+template <class C> struct FP64Op<CovOp<C>> { using type = CovOp<typename Wide<C>::type>; };
+
+}  // namespace
+
+hipError_t launch_batch_init(const BatchArgs& a, const BatchGroup& gr, void* x64, void* xh, void* r, void* p,
+                             hipStream_t st) {
+  return batch_dispatch(gr.kind, gr.elem, gr.prec, [&](auto op) {
+    using Op = decltype(op);
+    using TW = typename Op::T;
+    using T64 = typename Wide<TW>::type;
+    kb_init<T64, TW, Op::NC><<<gr.nitems, kBlock, 0, st>>>(a, (T64*)x64, (TW*)xh, (TW*)r, (TW*)p);
+  });
+}
+
+hipError_t launch_batch_iteration(const BatchArgs& a, const BatchGroup& gr, const CgScalars& sc, void* x, void* r,
+                                  void* p, void* w, double* partial, size_t rowstride, double eps, double tau2,
+                                  hipStream_t st, hipEvent_t ev0, hipEvent_t ev1) {
+  return batch_dispatch(gr.kind, gr.elem, gr.prec, [&](auto op) {
+    using Op = decltype(op);
+    using T = typename Op::T;
+    if (ev0) (void)hipEventRecord(ev0, st);
+    kb_stencil<Op><<<gr.nitems, kBlock, 0, st>>>(a, sc, (const T*)p, (T*)w, partial);
+    if (ev1) (void)hipEventRecord(ev1, st);
+    kb_reduce_alpha<<<gr.nlanes, kBlock, 0, st>>>(a, sc, gr.lane_base, partial, gr.prec == Prec::kF32 ? 1 : 0);
+    kb_update_r<T><<<gr.nitems, kBlock, 0, st>>>(a, sc, (T*)r, (const T*)w, partial + rowstride);
+    kb_reduce_beta<<<gr.nlanes, kWideBlock, 0, st>>>(a, sc, gr.lane_base, partial + rowstride, eps, tau2);
+    kb_direction<T><<<gr.nitems, kBlock, 0, st>>>(a, sc, (T*)x, (const T*)r, (T*)p);
+  });
+}
+
+hipError_t launch_batch_reliable(const BatchArgs& a, const BatchGroup& gr, const CgScalars& sc, int mode, void* x64,
+                                 void* xh, void* r, void* p, double* partial, size_t rowstride, hipStream_t st) {
+  return batch_dispatch(gr.kind, gr.elem, Prec::kF32, [&](auto op) {
+    using Op = decltype(op);
+    using T32 = typename Op::T;
+    if constexpr (is_single<T32>::value) {
+      using Op64 = typename FP64Op<Op>::type;
+      using T64 = typename Op64::T;
+      kb_ru_accumulate<T64, T32><<<gr.nitems, kBlock, 0, st>>>(a, sc, mode, (T64*)x64, (T32*)xh);
+      kb_ru_residual<Op64, T32><<<gr.nitems, kBlock, 0, st>>>(a, sc, mode, (const T64*)x64, (T32*)r, (T32*)p,
+                                                                partial, rowstride);
+      kb_reduce_ru<<<gr.nlanes, kBlock, 0, st>>>(a, sc, gr.lane_base, partial, rowstride, mode);
+    }
+  });
+}
+
+hipError_t launch_batch_true_residual(const BatchArgs& a, const BatchGroup& gr, const CgScalars& sc, void* x,
+                                      void* r, void* p, double* partial, size_t rowstride, hipStream_t st) {
+  return batch_dispatch(gr.kind, gr.elem, Prec::kF64, [&](auto op) {
+    using Op = decltype(op);
+    using T = typename Op::T;
+    if constexpr (!is_single<T>::value) {
+      kb_true_residual<Op><<<gr.nitems, kBlock, 0, st>>>(a, sc, (const T*)x, (T*)r, (T*)p, partial, rowstride);
+      kb_reduce_true<<<gr.nlanes, kBlock, 0, st>>>(a, sc, gr.lane_base, partial, rowstride);
+    }
+  });
+}
+
+hipError_t launch_batch_scalars_init(const BatchArgs& a, const CgScalars& sc, int nlanes, hipStream_t st) {
+  kb_scalars_init<<<(nlanes + 255) / 256, 256, 0, st>>>(a, sc, nlanes);
+  return hipGetLastError();
+}
+
+}  // namespace tip

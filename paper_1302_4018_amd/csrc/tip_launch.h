@@ -49,6 +49,7 @@ struct CgScalars {
   int* ru;                     // reliable update requested (mixed precision)
   int* n_ru;                   // number of such right-hand sides
   int* ru_count;               // reliable updates done in the block
+  int* ru_lanes;               // reliable updates per rhs (batched solver), or null
 };
 
 // Generic site kernels: workgroup b owns TS = 256/B sites (tile_first_site).

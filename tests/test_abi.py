@@ -46,7 +46,9 @@ int main(void) {
   P(tip_operator, dims) P(tip_operator, kind) P(tip_operator, mass) P(tip_operator, links)
   P(tip_params, tol) P(tip_params, seed) P(tip_params, mask) P(tip_params, stream) P(tip_params, quadratures)
   P(tip_params, reliable_delta) P(tip_params, probe) P(tip_params, round_tiles) P(tip_params, march_tc)
-  P(tip_params, stop_levels)
+  P(tip_params, stop_levels) P(tip_params, item_sites) P(tip_params, residuals)
+  printf("tip_tuning %zu\\n", sizeof(tip_tuning));
+  P(tip_tuning, seconds_per_solve) P(tip_tuning, item_sites)
   P(tip_stats, max_true_relres) P(tip_stats, stencil_launches) P(tip_stats, stencil_bytes)
   P(tip_stats, reliable_updates) P(tip_stats, max_quad_err_bound) P(tip_stats, matvecs)
   P(tip_stats, matvec_seconds) P(tip_stats, matvec_bytes) P(tip_stats, even_odd) P(tip_stats, restarts) P(tip_stats, reused)
@@ -57,7 +59,8 @@ int main(void) {
     subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
     out = dict(line.rsplit(" ", 1) for line in subprocess.run([str(exe)], capture_output=True, text=True,
                                                              check=True).stdout.split("\n") if line)
-    classes = {"tip_operator": b.tip_operator, "tip_params": b.tip_params, "tip_stats": b.tip_stats}
+    classes = {"tip_operator": b.tip_operator, "tip_params": b.tip_params, "tip_stats": b.tip_stats,
+               "tip_tuning": b.tip_tuning}
     for key, val in out.items():
         if "." in key:
             cls, field = key.split(".")

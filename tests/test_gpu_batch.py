@@ -1,14 +1,17 @@
-"""Batches of independent tori in one call (trace_inv_probe_batch): each
-problem bit for bit as its own trace_inv_probe call, against the oracle, and
-the batch of 64 uneven 3-D tori (sides 8..48, Z2, FP32 CG with FP64 reliable
-updates) checked on its first probes against the oracle."""
+"""Batches of independent problems solved together (trace_inv_probe_batch:
+one launch per CG phase for every problem of a group): every problem against
+its own trace_inv_probe call and against the oracle, batches that mix
+operator kinds, element types, probe classes and precisions, the batch
+autotuner, and the 64 uneven 3-D tori (sides 8..48) against the stored
+oracle quadratures."""
 
 import numpy as np
 import pytest
 
-from conftest import gpu_binding, to_dev
+from conftest import gpu_binding, read_quadratures, to_dev
 from oracle import general
-from oracle.mask import MASK_Z2
+from oracle.estimator import estimates_from_quadratures
+from oracle.mask import MASK_Z2, MASK_Z4
 from oracle.operators import Operator as OracleOp
 from paper_1302_4018_amd import inputs
 
@@ -34,11 +37,59 @@ def test_batch_equals_single_calls_and_oracle(precision):
     prec = tip.PREC_MIXED if precision == "mixed" else tip.PREC_FP64
     orcs, gops = _ops(tip, SMALL)
     ns = [n for _, _, n in SMALL]
-    out = tip.trace_inv_probe_batch(gops, ns, 1e-12, 4018, precision=prec, n_streams=3)
+    print(f"batch of {len(ns)} small tori, {precision}", flush=True)
+    out = tip.trace_inv_probe_batch(gops, ns, 1e-12, 4018, precision=prec)
     for i, (est, st) in enumerate(out):
         assert st["status"] == 0 and st["max_true_relres"] <= 1e-12
-        single, _, _ = tip.trace_inv_probe(gops[i], ns[i], 1e-12, 4018, precision=prec)
-        assert np.array_equal(est, single), i
+        single, q1, st1 = tip.trace_inv_probe(gops[i], ns[i], 1e-12, 4018, precision=prec)
+        assert st["reused"] == st1["reused"] and st["solves"] == st1["solves"], i
+        assert np.max(np.abs(est - single) / np.abs(single)) <= REL, i
+        assert np.max(np.abs(st["quadratures"] - q1) / np.abs(q1)) <= REL, i
+        est_o, _, _ = general.trace_inv_probe(orcs[i], ns[i], 1e-12, 4018, MASK_Z2)
+        assert np.max(np.abs(est - est_o) / np.abs(est_o)) <= REL, i
+
+
+def test_batch_mixing_kinds_masks_and_precisions():
+    """Covariant and scalar problems, Z4 and Z2 masks, real and complex
+    solves, FP64 and mixed precision in one call: one group per (kind,
+    element type, precision), each against the oracle."""
+    tip = gpu_binding()
+    cases = [  # dims, kind, mass, n, mask, coupled
+        ([4, 4, 4, 4], 1, 0.1, 6, MASK_Z4, False),
+        ([6, 4, 3, 2], 1, 0.2, 5, MASK_Z4, True),
+        ([8, 8], 0, 0.05, 10, MASK_Z4, True),
+        ([5, 9, 7], 0, 0.2, 12, MASK_Z2, True),
+        ([16, 16], 0, 0.1, 33, MASK_Z2, False),
+    ]
+    for prec in (tip.PREC_FP64, tip.PREC_MIXED):
+        gops, orcs, ns = [], [], []
+        for k, (dims, kind, m, n, mask, coupled) in enumerate(cases):
+            w = inputs.couplings(dims, seed=700 + k) if coupled else None
+            U = inputs.haar_links(dims, seed=710 + k) if kind == 1 else None
+            orcs.append(OracleOp(dims, kind, mass=m, coupling=w, links=U))
+            gops.append(tip.Operator(dims, kind, mass=m, coupling=to_dev(w), links=to_dev(U)))
+            ns.append(n)
+        masks = [c[4] for c in cases]
+        print(f"mixed batch, precision {prec}", flush=True)
+        out = tip.trace_inv_probe_batch(gops, ns, 1e-12, 99, mask=masks, precision=prec)
+        for i, (est, st) in enumerate(out):
+            assert st["status"] == 0, i
+            est_o, q_o, _ = general.trace_inv_probe(orcs[i], ns[i], 1e-12, 99, masks[i])
+            assert np.max(np.abs(est - est_o) / np.abs(est_o)) <= REL, (prec, i)
+            assert np.max(np.abs(st["quadratures"] - q_o) / np.abs(q_o)) <= REL, (prec, i)
+
+
+def test_batch_autotuner_picks_a_candidate():
+    tip = gpu_binding()
+    orcs, gops = _ops(tip, SMALL)
+    ns = [n for _, _, n in SMALL]
+    best, tried = tip.tip_autotune_batch(gops, ns, 1e-10, 4018, sample_vectors=8)
+    assert len(tried) == 12
+    assert best["rhs_block"] in (16, 32, 64) and best["item_sites"] in (256, 512, 1024, 2048)
+    assert best["seconds_per_solve"] == min(t["seconds_per_solve"] for t in tried)
+    out = tip.trace_inv_probe_batch(gops, ns, 1e-12, 4018, rhs_block=best["rhs_block"],
+                                    item_sites=best["item_sites"])
+    for i, (est, st) in enumerate(out):
         est_o, _, _ = general.trace_inv_probe(orcs[i], ns[i], 1e-12, 4018, MASK_Z2)
         assert np.max(np.abs(est - est_o) / np.abs(est_o)) <= REL, i
 
@@ -51,22 +102,23 @@ def test_batch_validates_every_problem_first():
     assert "torus 1" in str(e.value) or "torus 1" in tip.tip_last_error()
 
 
-def test_uneven_tori_batch_first_probes_against_oracle():
-    """The 64 uneven 3-D tori: every problem converges; on the two smallest,
-    the estimates at s = 1, 2, 4 (which use the first 4 probes only) match the
-    oracle."""
+@pytest.mark.parametrize("precision", ["mixed", "fp64"])
+def test_uneven_tori_batch_first_probes_against_oracle(precision):
+    """The 64 uneven 3-D tori in one batch call: every problem converges, and
+    on every torus the estimates at s = 1, 2, 4 (which use probes 0..3 only,
+    F_3 columns included on tori with odd sides) match the stored oracle
+    quadratures."""
     tip = gpu_binding()
     tori = inputs.uneven_tori()
-    gops, orcs = [], []
+    gops = []
     for i, t in enumerate(tori):
         w = inputs.uneven_torus_couplings(t["dims"], i)
         gops.append(tip.Operator(t["dims"], tip.KIND_SCALAR, mass=t["mass"], coupling=to_dev(w)))
-        orcs.append((t["dims"], t["mass"], w))
     ns = [t["n_vectors"] for t in tori]
-    out = tip.trace_inv_probe_batch(gops, ns, 1e-10, 4018, mask=MASK_Z2, precision=tip.PREC_MIXED)
+    prec = tip.PREC_MIXED if precision == "mixed" else tip.PREC_FP64
+    out = tip.trace_inv_probe_batch(gops, ns, 1e-10, 4018, mask=MASK_Z2, precision=prec)
     assert all(st["status"] == 0 and st["max_true_relres"] <= 1e-10 for _, st in out)
-    vol = [int(np.prod(t["dims"])) for t in tori]
-    for i in sorted(range(len(tori)), key=lambda k: vol[k])[:2]:
-        dims, m, w = orcs[i]
-        est_o, _, _ = general.trace_inv_probe(OracleOp(dims, 0, mass=m, coupling=w), 4, 1e-10, 4018, MASK_Z2)
-        assert np.max(np.abs(out[i][0][:3] - est_o) / np.abs(est_o)) <= 1e-9, (i, dims)
+    golden = read_quadratures("quadratures_c4_uneven_tori.txt")
+    for i, t in enumerate(tori):
+        est_o = estimates_from_quadratures(golden[f"torus{i}"])
+        assert np.max(np.abs(out[i][0][:3] - est_o) / np.abs(est_o)) <= REL, (i, t["dims"])
