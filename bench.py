@@ -8,7 +8,8 @@ relative residual of 1e-10 (FP64).  One step is one trace_inv_probe call over
 all 768 right-hand sides, with the operator already resident on the GPU.
 The headline value is the FP64 solver; the mixed-precision solver (FP32 CG,
 FP64 reliable updates, same FP64 true-residual acceptance) is timed beside
-it and reported under "mixed_precision".
+it and reported under "mixed_precision", and the same run with the gradient
+of the last estimate (dT/dm and dT/dw, FP64) under "gradient".
 
 Prints one JSON line: solves/s, the stencil kernel's achieved HBM bandwidth
 against the MI355X peak (hipEvent timing of every stencil launch inside the
@@ -31,17 +32,23 @@ DIMS = [32, 32, 32, 32]
 HBM_PEAK_GBS = 8000.0
 METRIC = "probing-vector solves/sec (4D 32^4, rel.res 1e-10) + stencil HBM GB/s vs peak"
 KERNEL_SOURCES = ["paper_1302_4018_amd/csrc/tip_kernels.hip", "paper_1302_4018_amd/csrc/tip_device.h",
-                  "paper_1302_4018_amd/csrc/tip_launch.h"]
+                  "paper_1302_4018_amd/csrc/tip_launch.h", "paper_1302_4018_amd/csrc/tip_kernel_common.h"]
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "stencil_traffic.json")
 # the dominant kernel: with the even-odd reduction, the half-lattice stencil
 # that forms S p (in FP64 in 512-thread workgroups unless TIP_EO_WIDE=0, in
 # single precision with two rhs per thread unless TIP_EO_PAIR=0); without it,
 # the 4-D marching stencil
 STENCIL = {
-    (True, "fp64"): ("k_eo_hop<tip::CovOp<HIP_vector_type<double, 2u> >, 1, 5, 256>" if os.environ.get("TIP_EO_WIDE") == "0"
-                     else "k_eo_hop<tip::CovOp<HIP_vector_type<double, 2u> >, 1, 5, 512>"),
-    (True, "fp32"): ("k_eo_hop<tip::CovOp<HIP_vector_type<float, 2u> >, 1, 5, 256>" if os.environ.get("TIP_EO_PAIR") == "0"
+    (True, "fp64"): ("k_eo_hop<tip::CovOp<HIP_vector_type<double, 2u> >, 1, 5, 256, false>" if os.environ.get("TIP_EO_WIDE") == "0"
+                     else "k_eo_hop<tip::CovOp<HIP_vector_type<double, 2u> >, 1, 5, 512, false>"),
+    (True, "fp32"): ("k_eo_hop<tip::CovOp<HIP_vector_type<float, 2u> >, 1, 5, 256, false>" if os.environ.get("TIP_EO_PAIR") == "0"
                      else "k_eo_hop_pair<tip::CovOp<HIP_vector_type<float, 2u> >, 1, 256>"),
+    (True, "fp64_odd"): ("k_eo_hop<tip::CovOp<HIP_vector_type<double, 2u> >, 0, 5, 256, false>"
+                         if os.environ.get("TIP_EO_WIDE") == "0"
+                         else "k_eo_hop<tip::CovOp<HIP_vector_type<double, 2u> >, 0, 5, 512, false>"),
+    (True, "fp32_odd"): ("k_eo_hop<tip::CovOp<HIP_vector_type<float, 2u> >, 0, 5, 256, false>"
+                         if os.environ.get("TIP_EO_PAIR") == "0"
+                         else "k_eo_hop_pair<tip::CovOp<HIP_vector_type<float, 2u> >, 0, 256>"),
     (False, "fp64"): "k_stencil_march4<HIP_vector_type<double, 2u>, 5, false>",
     (False, "fp32"): "k_stencil_march4<HIP_vector_type<float, 2u>, 5, false>",
 }
@@ -579,6 +586,42 @@ def bench_study(args):
     print(json.dumps(out), flush=True)
 
 
+def practical_ceiling(tip):
+    """The HBM rate hand-written streaming kernels reach on this GPU (tip_stream_ceiling:
+    4 GiB, 8192 workgroups of 256 threads, 16-byte accesses), read only and three reads
+    per write, in GB/s; measured outside the timed steps."""
+    out = {"unit": "GB/s", "bytes": 4 << 30}
+    for kind, key in ((0, "read_only"), (2, "three_reads_one_write")):
+        sec, byt = tip.tip_stream_ceiling(kind, 4 << 30, 10, 8192)
+        out[key] = round(byt / sec / 1e9, 1)
+    return out
+
+
+def timed_gradient(handle, args, n_rhs, forward):
+    """The same probing run with the gradient of the last estimate with respect
+    to the mass field and the couplings (trace_inv_probe_grad, FP64): W warmup
+    and K timed calls, reported as solves/s beside the forward-only rate."""
+    import numpy as np
+    import torch
+
+    kw = dict(rhs_block=args.rhs_block)
+    for w in range(args.warmup):
+        handle.trace_inv_probe_grad(args.n_vectors, args.tol, args.seed, **kw)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        est, _, gm, gw, st = handle.trace_inv_probe_grad(args.n_vectors, args.tol, args.seed, **kw)
+        log(f"[gradient] step {k}: {st['seconds']:.3f} s, {st['solves']} solves")
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    value = n_rhs * args.steps / elapsed
+    return {"value": round(value, 2), "unit": "solves/s", "ms_per_step": round(elapsed / args.steps * 1e3, 2),
+            "vs_forward_fp64": round(value / forward["value"], 3), "dtype": "f64",
+            "outputs": "estimates, dT/dm [V] and dT/dw [ndim][V] of the last estimate",
+            "max_rel_diff_estimates_vs_forward": float(np.max(np.abs(est - forward["est"]) / np.abs(forward["est"]))),
+            "grad_mass_sum": float(gm.sum()), "grad_coupling_sum": float(gw.sum())}
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -592,6 +635,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-one-core", action="store_true", help="time the oracle on one host thread only")
     ap.add_argument("--copy-calibration", action="store_true")
+    ap.add_argument("--no-gradient", action="store_true",
+                    help="skip the leg that times the estimate together with dT/dm and dT/dw")
     ap.add_argument("--precision", choices=["both", "fp64", "mixed"], default="both",
                     help="FP64 is the headline value; 'both' adds the mixed-precision solver beside it")
     ap.add_argument("--reliable-delta", type=float, default=0.0)
@@ -599,7 +644,7 @@ def main():
                     help="write the stencil's measured HBM bytes per launch from two rocprofv3 --pmc "
                          "counter_collection.csv files, then exit (no GPU work)")
     ap.add_argument("--traffic-command", default="", help="command recorded with --traffic-from")
-    ap.add_argument("--traffic-kernel", choices=["fp64", "fp32"], default="fp64",
+    ap.add_argument("--traffic-kernel", choices=["fp64", "fp32", "fp64_odd", "fp32_odd"], default="fp64",
                     help="--traffic-from: the FP64 or the single-precision dominant kernel of the 32^4 workload")
     ap.add_argument("--workload", choices=["c5", "c4", "c2h", "compare", "study"], default="c5",
                     help="c5: the 32^4 covariant probing run (default); c4: the batch of 64 uneven 3-D tori; "
@@ -709,6 +754,16 @@ def main():
             roof["operator"] = {"applications": tot["mv"], "avg_us": round(tot["mv_seconds"] / tot["mv"] * 1e6, 2),
                                 "alg_bytes": tot["mv_bytes"] / tot["mv"],
                                 "achieved": round(tot["mv_bytes"] / tot["mv_seconds"] / 1e9, 1)}
+            if tot["eo"] and tot["mv"] == tot["launches"]:
+                # the other half-lattice kernel of each application (t_o = D_o^-1 H_oe p_e),
+                # timed between the same events: the operator minus the dominant kernel
+                odd_s = (tot["mv_seconds"] - tot["seconds"]) / tot["mv"]
+                odd_b = (tot["mv_bytes"] - tot["bytes"]) / tot["mv"]
+                odd_name = STENCIL[(True, ("fp64" if precision == tip.PREC_FP64 else "fp32") + "_odd")]
+                roof["odd_hop"] = {"kernel": odd_name, "avg_launch_us": round(odd_s * 1e6, 2),
+                                   "alg_bytes_per_launch": odd_b, "achieved": round(odd_b / odd_s / 1e9, 1),
+                                   "frac": round(odd_b / odd_s / 1e9 / HBM_PEAK_GBS, 4),
+                                   "traffic": measured_traffic(odd_name)}
         return {"value": n_rhs * args.steps / elapsed, "elapsed": elapsed, "roofline": roof, "est": est, "eo": tot["eo"],
                 "q": q, "residuals": st["residuals"],
                 "iters_per_solve": tot["iters"] / max(tot["solves"], 1), "max_true_relres": tot["relres"],
@@ -717,7 +772,14 @@ def main():
     precisions = {"fp64": [tip.PREC_FP64], "mixed": [tip.PREC_MIXED],
                   "both": [tip.PREC_FP64, tip.PREC_MIXED]}[args.precision]
     res = {pr: timed(pr) for pr in precisions}
+    grad = None if args.no_gradient else timed_gradient(handle, args, n_rhs, res[precisions[0]])
     handle.close()
+    ceiling = practical_ceiling(tip)
+    log(f"practical HBM ceiling: {ceiling}")
+    for r in res.values():
+        # the dominant kernel reads about four bytes for each one it writes
+        r["roofline"]["practical_ceiling"] = ceiling
+        r["roofline"]["frac_of_practical"] = round(r["roofline"]["achieved"] / ceiling["three_reads_one_write"], 4)
     main_pr = precisions[0]
     main = res[main_pr]
     value = main["value"]
@@ -754,7 +816,7 @@ def main():
                       "mask": "Z4", "iters_per_solve": round(iters_per_solve, 2),
                       "solver": "CG on the even-odd reduced system" if main["eo"] else "CG",
                       "max_true_relres": main["max_true_relres"], "repack_ms": round(repack_s * 1e3, 2)},
-           "roofline": roofline, "cpu_baseline": cpu, "mixed_precision": mixed}
+           "roofline": roofline, "cpu_baseline": cpu, "mixed_precision": mixed, "gradient": grad}
     print(json.dumps(out), flush=True)
 
 

@@ -323,6 +323,7 @@ struct Plan {
   bool pair = false;  // single-precision covariant hops with two rhs per thread (B = 32)
   bool wide = false;  // FP64 covariant hops with 512-thread workgroups (B = 32)
   MarchMap me2;       // the march of either (16 sites per tile)
+  bool eo512 = false; // FP64 once-per-block and reliable-update passes in 512-thread workgroups on me2
 };
 
 bool env_off(const char* name) {
@@ -644,6 +645,11 @@ struct Solver {
                 !env_off("TIP_EO_WIDE") &&
                 make_marchmap(g, 4, &pl.me2, true, p->round_tiles > 0 ? p->round_tiles : 128, p->march_tc) &&
                 eo_lds_bytes(g, pl.me2, prec) <= 65536;
+      // the FP64 passes outside the iteration (reduced right-hand side, true
+      // residual, reliable updates) on the same 16-site tiles in 512-thread
+      // workgroups (TIP_EO_WIDE_ONCE=0 keeps them at 256 threads)
+      pl.eo512 = (pl.wide || pl.pair) && h->kind == TIP_KIND_COVARIANT && pl.B == 32 &&
+                 eo_lds_bytes(g, pl.me2, Prec::kF64) <= 65536 && !env_off("TIP_EO_WIDE_ONCE");
     }
     max_iter = p->max_iter > 0 ? p->max_iter : (int)std::min<int64_t>(10 * V * ncomp, 1 << 20);
     tol2 = p->tol * p->tol;
@@ -806,6 +812,20 @@ struct Solver {
     return TIP_OK;
   }
 
+  // An FP64 even-odd pass (the operator's FP64 form) and the workgroups, that
+  // is the partials per rhs, it writes.
+  hipError_t eo_pass(int mode, int P, const int* state, const int* active, const void* in, const void* cin,
+                     void* out, void* out2, void* out3, int64_t rhs0, int nb, double* partial,
+                     const int* ru = nullptr, const void* cin2 = nullptr, void* out32 = nullptr) {
+    const double* diag = (const double*)h->diag.p;
+    if (pl.eo512)
+      return launch_eo_hop512(mode, od64, geom, pl.me2, P, diag, state, active, in, cin, out, out2, out3, rhs0, nb,
+                              p->seed, pl.mask, partial, nullptr, st, ru, cin2, out32, pstride);
+    return launch_eo_hop(mode, od64, geom, pl.me, P, pl.elem, Prec::kF64, diag, state, active, in, cin, out, out2,
+                         out3, rhs0, nb, p->seed, pl.mask, partial, nullptr, st, ru, cin2, out32, pstride);
+  }
+  int gx_eo() const { return pl.eo512 ? (int)pl.me2.grid : gx_m; }
+
   // Reliable updates of flagged right-hand sides (mode 0, enqueued after
   // every iteration; the kernels return at once when none is pending) or the
   // final check of frozen ones (mode 1) in the mixed solver.
@@ -818,24 +838,18 @@ struct Solver {
         // r_e = b_hat - S x_e in FP64 for the flagged lanes (the kernels return
         // at once while no reliable update is pending: n_ru doubles as the
         // active counter)
-        TIP_HIP(launch_eo_hop(0, od64, g, pl.me, 1, pl.elem, Prec::kF64, diag, sc.state, sc.n_ru, Xe, nullptr, T64,
-                              nullptr, nullptr, 0, 0, 0, 0, nullptr, nullptr, st, sc.ru));
-        TIP_HIP(launch_eo_hop(4, od64, g, pl.me, 0, pl.elem, Prec::kF64, diag, sc.state, sc.n_ru, T64, Xe, nullptr,
-                              nullptr, nullptr, 0, 0, 0, 0, part, nullptr, st, sc.ru, Bh, Rv));
-        TIP_HIP(launch_reduce_ru(sc, pl.B, part, gx_m, pstride, 0, tol2, max_iter, max_restarts, st));
+        TIP_HIP(eo_pass(0, 1, sc.state, sc.n_ru, Xe, nullptr, T64, nullptr, nullptr, 0, 0, nullptr, sc.ru));
+        TIP_HIP(eo_pass(4, 0, sc.state, sc.n_ru, T64, Xe, nullptr, nullptr, nullptr, 0, 0, part, sc.ru, Bh, Rv));
+        TIP_HIP(launch_reduce_ru(sc, pl.B, part, gx_eo(), pstride, 0, tol2, max_iter, max_restarts, st));
         return TIP_OK;
       }
       // final check: the FP64 true residual b - A x in two half-lattice passes,
       // x_o = D_o^-1 (b_o + H_oe x_e) with the odd sites' part, then the even
       // sites' part (restart_residual stores r_e for lanes that fail)
-      TIP_HIP(launch_eo_hop(3, od64, g, pl.me, 1, pl.elem, Prec::kF64, diag, nullptr, nullptr, Xe, nullptr, T64,
-                            need_x ? X : nullptr, nullptr, rhs0, nb, p->seed, pl.mask, part, nullptr, st, nullptr,
-                            nullptr, nullptr, pstride));
+      TIP_HIP(eo_pass(3, 1, nullptr, nullptr, Xe, nullptr, T64, need_x ? X : nullptr, nullptr, rhs0, nb, part));
       if (need_x) TIP_HIP(launch_eo_scatter_even(g, pl.elem, Prec::kF64, pl.logB, Xe, X, st));
-      TIP_HIP(launch_eo_hop(5, od64, g, pl.me, 0, pl.elem, Prec::kF64, diag, nullptr, nullptr, T64, Xe, nullptr,
-                            nullptr, nullptr, rhs0, nb, p->seed, pl.mask, part + 5 * pstride, nullptr, st, nullptr,
-                            nullptr, nullptr, pstride));
-      TIP_HIP(launch_reduce_ru(sc, pl.B, part, gx_m, pstride, 1, tol2, max_iter, max_restarts, st,
+      TIP_HIP(eo_pass(5, 0, nullptr, nullptr, T64, Xe, nullptr, nullptr, nullptr, rhs0, nb, part + 5 * pstride));
+      TIP_HIP(launch_reduce_ru(sc, pl.B, part, gx_eo(), pstride, 1, tol2, max_iter, max_restarts, st,
                                part + 5 * pstride));
       return TIP_OK;
     }
@@ -950,16 +964,14 @@ struct Solver {
     if (pl.eo && mixed) {
       // b_hat in FP64 (kept for the reliable updates), x_e = 0; r = p = single(b_hat), x_h = 0
       TIP_HIP(launch_eo_init_odd(g, pl.elem, Prec::kF64, pl.logB, rhs0, nb, p->seed, pl.mask, diag, T64, st));
-      TIP_HIP(launch_eo_hop(2, od64, g, pl.me, 0, pl.elem, Prec::kF64, diag, nullptr, nullptr, T64, nullptr, Bh,
-                            nullptr, Xe, rhs0, nb, p->seed, pl.mask, part, nullptr, st));
-      TIP_HIP(launch_reduce_rho0(sc, pl.B, part, gx_m, st));
+      TIP_HIP(eo_pass(2, 0, nullptr, nullptr, T64, nullptr, Bh, nullptr, Xe, rhs0, nb, part));
+      TIP_HIP(launch_reduce_rho0(sc, pl.B, part, gx_eo(), st));
       TIP_HIP(launch_eo_cast_init(nvec, pl.elem, Bh, Rv, Pv, XH, st));
     } else if (pl.eo) {
       // reduced right-hand side b_e + H_eo D_o^-1 b_o; x_e = 0, r = p = it
       TIP_HIP(launch_eo_init_odd(g, pl.elem, prec, pl.logB, rhs0, nb, p->seed, pl.mask, diag, Tv, st));
-      TIP_HIP(launch_eo_hop(2, od, g, pl.me, 0, pl.elem, prec, diag, nullptr, nullptr, Tv, nullptr, Rv, Pv, Xe, rhs0,
-                            nb, p->seed, pl.mask, part, nullptr, st));
-      TIP_HIP(launch_reduce_rho0(sc, pl.B, part, gx_m, st));
+      TIP_HIP(eo_pass(2, 0, nullptr, nullptr, Tv, nullptr, Rv, Pv, Xe, rhs0, nb, part));
+      TIP_HIP(launch_reduce_rho0(sc, pl.B, part, gx_eo(), st));
     } else if (mixed) {
       TIP_HIP(launch_init_mixed(g, pl.elem, pl.logB, rhs0, nb, p->seed, pl.mask, X, XH, Rv, Pv, st));
     } else {
@@ -1022,14 +1034,10 @@ struct Solver {
           // (b_o + H_oe x_e) with the odd sites' part, then the even sites'
           // part r_e = b_e - D_e x_e + H_eo x_o (the restart r = p for lanes
           // that fail); x on the full lattice only when the caller reads it
-          TIP_HIP(launch_eo_hop(3, od, g, pl.me, 1, pl.elem, prec, diag, nullptr, nullptr, Xe, nullptr, Tv,
-                                need_x ? X : nullptr, nullptr, rhs0, nb, p->seed, pl.mask, part, nullptr, st, nullptr,
-                                nullptr, nullptr, pstride));
+          TIP_HIP(eo_pass(3, 1, nullptr, nullptr, Xe, nullptr, Tv, need_x ? X : nullptr, nullptr, rhs0, nb, part));
           if (need_x) TIP_HIP(launch_eo_scatter_even(g, pl.elem, prec, pl.logB, Xe, X, st));
-          TIP_HIP(launch_eo_hop(5, od, g, pl.me, 0, pl.elem, prec, diag, nullptr, nullptr, Tv, Xe, nullptr, nullptr,
-                                nullptr, rhs0, nb, p->seed, pl.mask, part + 5 * pstride, nullptr, st, nullptr, nullptr,
-                                nullptr, pstride));
-          TIP_HIP(launch_reduce_true(sc, pl.B, part, gx_m, pstride, tol2, max_iter, max_restarts, st,
+          TIP_HIP(eo_pass(5, 0, nullptr, nullptr, Tv, Xe, nullptr, nullptr, nullptr, rhs0, nb, part + 5 * pstride));
+          TIP_HIP(launch_reduce_true(sc, pl.B, part, gx_eo(), pstride, tol2, max_iter, max_restarts, st,
                                      part + 5 * pstride));
         } else {
           TIP_HIP(launch_true_residual(od, g, pl.tm, pl.elem, sc.state, rhs0, nb, p->seed, pl.mask, X, Rv, Pv, part,
@@ -1046,12 +1054,10 @@ struct Solver {
         // the x_o of the check is still in the t buffer)
         const double* diag = (const double*)h->diag.p;
         if (mixed)
-          TIP_HIP(launch_eo_hop(5, od64, g, pl.me, 0, pl.elem, Prec::kF64, diag, sc.state, nullptr, T64, Xe, nullptr,
-                                nullptr, Pv, rhs0, nb, p->seed, pl.mask, nullptr, nullptr, st, nullptr, nullptr, Rv,
-                                pstride));
+          TIP_HIP(eo_pass(5, 0, sc.state, nullptr, T64, Xe, nullptr, nullptr, Pv, rhs0, nb, nullptr, nullptr, nullptr,
+                          Rv));
         else
-          TIP_HIP(launch_eo_hop(5, od, g, pl.me, 0, pl.elem, prec, diag, sc.state, nullptr, Tv, Xe, Rv, Pv, nullptr,
-                                rhs0, nb, p->seed, pl.mask, nullptr, nullptr, st, nullptr, nullptr, nullptr, pstride));
+          TIP_HIP(eo_pass(5, 0, sc.state, nullptr, Tv, Xe, Rv, Pv, nullptr, rhs0, nb, nullptr));
       }
     }
     TIP_HIP(hipMemcpyAsync(h_q, sc.q, 2 * nb * sizeof(double), hipMemcpyDeviceToHost, st));

@@ -112,8 +112,10 @@ __global__ __launch_bounds__(kBlock) void kb_stencil(BatchArgs a, CgScalars sc, 
   __shared__ double lds[4 * 64];
   const uint32_t item = a.item_base + blockIdx.x;
   const BatchJob& J = a.jobs[a.item_job[item]];
-  const BatchProb& P = a.probs[J.prob];
-  const Geom& g = J.g;
+  // the geometry and operator in registers: read through the tables, every
+  // field would be reloaded after each store (the tables might alias it)
+  const Geom g = J.g;
+  const BatchProb P = a.probs[J.prob];
   const int logB = J.logB, B = 1 << logB;
   const int j = threadIdx.x & (B - 1), si = threadIdx.x >> logB;
   const bool live = sc.state[J.lane0 + j] == kActive;
@@ -129,10 +131,14 @@ __global__ __launch_bounds__(kBlock) void kb_stencil(BatchArgs a, CgScalars sc, 
   T* outj = out + J.off;
   double dot[1] = {0.0};
   if (live) {
-    for (uint32_t s = s0 + (uint32_t)si; s < s1; s += (uint32_t)(kBlock >> logB)) {
+    const uint32_t step = (uint32_t)(kBlock >> logB);
+    SiteWalk w(s0 + (uint32_t)si, g);
+    auto nbr = [&](int mu, bool fwd) { return w.nbr(mu, fwd, g); };
+#pragma unroll 2
+    for (; w.s < s1; w.advance(step, g)) {
       T xs[NC], y[NC];
-      stencil_site(op, g, logB, s, j, P.mass_field, P.mass, P.coupling, inj, xs, y);
-      store_vec<T, NC>(outj, g.V, logB, s, j, y);
+      stencil_site_at(op, g, logB, w.s, j, P.mass_field, P.mass, P.coupling, inj, nbr, xs, y);
+      store_vec<T, NC>(outj, g.V, logB, w.s, j, y);
 #pragma unroll
       for (int c = 0; c < NC; ++c) dot[0] += redot(xs[c], y[c]);
     }
@@ -159,15 +165,34 @@ __global__ __launch_bounds__(kBlock) void kb_update_r(BatchArgs a, CgScalars sc,
   double acc[1] = {0.0};
   if (live) {
     const double al = sc.alpha[J.lane0 + j];
-    T* rj = r + J.off;
-    const T* wj = w + J.off;
-    for (int c = 0; c < nc; ++c)
-      for (uint32_t s = s0 + (uint32_t)si; s < s1; s += (uint32_t)(kBlock >> logB)) {
-        const size_t i = (((size_t)c * V + s) << logB) + j;
+    // the item's elements of one component are contiguous: walk them flat,
+    // four loads in flight per thread (256 is a multiple of B, so the lane of
+    // element threadIdx.x + 256 k is always j)
+    const size_t n = (size_t)(s1 - s0) << logB;
+    for (int c = 0; c < nc; ++c) {
+      T* rj = r + J.off + (((size_t)c * V + s0) << logB);
+      const T* wj = w + J.off + (((size_t)c * V + s0) << logB);
+      size_t i = threadIdx.x;
+      for (; i + 3 * kBlock < n; i += 4 * kBlock) {
+        T rr[4], ww[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          rr[u] = rj[i + u * kBlock];
+          ww[u] = wj[i + u * kBlock];
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          rr[u] = axpy(-al, ww[u], rr[u]);
+          rj[i + u * kBlock] = rr[u];
+          acc[0] += norm2(rr[u]);
+        }
+      }
+      for (; i < n; i += kBlock) {
         const T ri = axpy(-al, wj[i], rj[i]);
         rj[i] = ri;
         acc[0] += norm2(ri);
       }
+    }
   }
   store_partials<1>(acc, B, lds, partial, 0, a.PI, J.lane0, item - J.item0);
 }
@@ -191,16 +216,33 @@ __global__ __launch_bounds__(kBlock) void kb_direction(BatchArgs a, CgScalars sc
   const double be = sc.beta[J.lane0 + j];
   const uint32_t s0 = (item - J.item0) * (uint32_t)a.item_sites;
   const uint32_t s1 = min(V, s0 + (uint32_t)a.item_sites);
-  T* xj = x + J.off;
-  const T* rj = r + J.off;
-  T* pj = p + J.off;
-  for (int c = 0; c < nc; ++c)
-    for (uint32_t s = s0 + (uint32_t)si; s < s1; s += (uint32_t)(kBlock >> logB)) {
-      const size_t i = (((size_t)c * V + s) << logB) + j;
+  const size_t n = (size_t)(s1 - s0) << logB;        // flat, as in kb_update_r
+  for (int c = 0; c < nc; ++c) {
+    const size_t base = J.off + (((size_t)c * V + s0) << logB);
+    T* xj = x + base;
+    const T* rj = r + base;
+    T* pj = p + base;
+    size_t i = threadIdx.x;
+    for (; i + 3 * kBlock < n; i += 4 * kBlock) {
+      T pp[4], xx[4], rr[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        pp[u] = pj[i + u * kBlock];
+        if (xa != 0.0) xx[u] = xj[i + u * kBlock];
+        if (live) rr[u] = rj[i + u * kBlock];
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        if (xa != 0.0) xj[i + u * kBlock] = axpy(xa, pp[u], xx[u]);
+        if (live) pj[i + u * kBlock] = axpy(be, pp[u], rr[u]);
+      }
+    }
+    for (; i < n; i += kBlock) {
       const T pi = pj[i];
       if (xa != 0.0) xj[i] = axpy(xa, pi, xj[i]);
       if (live) pj[i] = axpy(be, pi, rj[i]);
     }
+  }
 }
 
 // FP64 check of the frozen lanes: rt = b - A x with b regenerated; r = p = rt
@@ -228,9 +270,13 @@ __global__ __launch_bounds__(kBlock) void kb_true_residual(BatchArgs a, CgScalar
   double acc[3] = {0.0, 0.0, 0.0};
   if (live) {
     const T* xj = x + J.off;
-    for (uint32_t s = s0 + (uint32_t)si; s < s1; s += (uint32_t)(kBlock >> logB)) {
+    const uint32_t step = (uint32_t)(kBlock >> logB);
+    SiteWalk w(s0 + (uint32_t)si, g);
+    auto nbr = [&](int mu, bool fwd) { return w.nbr(mu, fwd, g); };
+    for (; w.s < s1; w.advance(step, g)) {
+      const uint32_t s = w.s;
       T xs[NC], ax[NC], b[NC], rt[NC];
-      stencil_site(op, g, logB, s, j, P.mass_field, P.mass, P.coupling, xj, xs, ax);
+      stencil_site_at(op, g, logB, s, j, P.mass_field, P.mass, P.coupling, xj, nbr, xs, ax);
       rhs_at<T, NC>(g, s, J.rhs0, j, J.nb, P.seed, P.mask, b);
 #pragma unroll
       for (int c = 0; c < NC; ++c) {
@@ -301,10 +347,14 @@ __global__ __launch_bounds__(kBlock) void kb_ru_residual(BatchArgs a, CgScalars 
   double acc[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
   if (live) {
     const T* xj = x + J.off;
-    for (uint32_t s = s0 + (uint32_t)si; s < s1; s += (uint32_t)(kBlock >> logB)) {
+    const uint32_t step = (uint32_t)(kBlock >> logB);
+    SiteWalk w(s0 + (uint32_t)si, g);
+    auto nbr = [&](int mu, bool fwd) { return w.nbr(mu, fwd, g); };
+    for (; w.s < s1; w.advance(step, g)) {
+      const uint32_t s = w.s;
       T xs[NC], ax[NC], b[NC];
       T32 r32[NC];
-      stencil_site(op, g, logB, s, j, P.mass_field, P.mass, P.coupling, xj, xs, ax);
+      stencil_site_at(op, g, logB, s, j, P.mass_field, P.mass, P.coupling, xj, nbr, xs, ax);
       rhs_at<T, NC>(g, s, J.rhs0, j, J.nb, P.seed, P.mask, b);
 #pragma unroll
       for (int c = 0; c < NC; ++c) {
@@ -323,7 +373,7 @@ __global__ __launch_bounds__(kBlock) void kb_ru_residual(BatchArgs a, CgScalars 
   store_partials<5>(acc, B, lds, partial, rowstride, a.PI, J.lane0, item - J.item0);
 }
 
-// ---- per-lane scalar steps, one workgroup per lane of a group -------------
+// ---- per-lane scalar steps -------------------------------------------------
 
 __global__ void kb_scalars_init(BatchArgs a, CgScalars sc, int nlanes) {
   const int L = blockIdx.x * blockDim.x + threadIdx.x;
@@ -351,58 +401,88 @@ __global__ void kb_scalars_init(BatchArgs a, CgScalars sc, int nlanes) {
   sc.q[2 * L + 1] = 0.0;
 }
 
-__global__ __launch_bounds__(kBlock) void kb_reduce_alpha(BatchArgs a, CgScalars sc, int lane_base,
+// One wave per lane: four lanes per 256-thread workgroup.  Each wave sums its
+// lane's partials in a fixed order (four running sums per thread, then a
+// shuffle tree), so the result is reproducible; the lane's scalar step runs
+// on the wave's first thread.
+constexpr int kLanesPerBlock = kBlock / 64;
+
+__device__ __forceinline__ double wave_sum(const double* __restrict__ part, int n) {
+  const int t = threadIdx.x & 63;
+  double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+  int i = t;
+  for (; i + 192 < n; i += 256) {
+    a0 += part[i];
+    a1 += part[i + 64];
+    a2 += part[i + 128];
+    a3 += part[i + 192];
+  }
+  for (; i < n; i += 64) a0 += part[i];
+  double v = (a0 + a1) + (a2 + a3);
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+  return v;
+}
+
+__global__ __launch_bounds__(kBlock) void kb_reduce_alpha(BatchArgs a, CgScalars sc, int lane_base, int nlanes,
                                                           const double* __restrict__ partial, int soft) {
-  const int L = lane_base + blockIdx.x;
-  if (*sc.active == 0 || sc.state[L] != kActive) return;     // uniform per workgroup
+  const int l = blockIdx.x * kLanesPerBlock + (int)(threadIdx.x >> 6);
+  if (l >= nlanes) return;
+  const int L = lane_base + l;
+  if (*sc.active == 0 || sc.state[L] != kActive) return;     // uniform per wave
   const BatchJob& J = a.jobs[a.lane_job[L]];
-  const double pAp = sum_partials(partial + (size_t)L * a.PI, (int)J.nitems);
-  if (threadIdx.x != 0) return;
+  const double pAp = wave_sum(partial + (size_t)L * a.PI, (int)J.nitems);
+  if ((threadIdx.x & 63) != 0) return;
   lane_alpha(sc, L, pAp, soft, false);
 }
 
-__global__ __launch_bounds__(kWideBlock) void kb_reduce_beta(BatchArgs a, CgScalars sc, int lane_base,
-                                                         const double* __restrict__ partial, double eps,
-                                                         double tau2) {
-  const int L = lane_base + blockIdx.x;
-  if (sc.state[L] != kActive) {                // uniform per workgroup
-    if (threadIdx.x == 0) sc.xalpha[L] = 0.0;
+__global__ __launch_bounds__(kBlock) void kb_reduce_beta(BatchArgs a, CgScalars sc, int lane_base, int nlanes,
+                                                         const double* __restrict__ partial, double eps, double tau2) {
+  const int l = blockIdx.x * kLanesPerBlock + (int)(threadIdx.x >> 6);
+  if (l >= nlanes) return;
+  const int L = lane_base + l;
+  if (sc.state[L] != kActive) {                // uniform per wave
+    if ((threadIdx.x & 63) == 0) sc.xalpha[L] = 0.0;
     return;
   }
   const BatchJob& J = a.jobs[a.lane_job[L]];
   const BatchProb& P = a.probs[J.prob];
   const BetaIn in = lane_beta_read(sc, L);
-  const double rho_new = sum_partials_wide(partial + (size_t)L * a.PI, (int)J.nitems);
-  if (threadIdx.x != 0) return;
+  const double rho_new = wave_sum(partial + (size_t)L * a.PI, (int)J.nitems);
+  if ((threadIdx.x & 63) != 0) return;
   lane_beta(sc, L, in, rho_new, P.tol2, P.max_iter, 0.0, P.tol2, eps, tau2);
 }
 
-__global__ __launch_bounds__(kBlock) void kb_reduce_true(BatchArgs a, CgScalars sc, int lane_base,
+__global__ __launch_bounds__(kBlock) void kb_reduce_true(BatchArgs a, CgScalars sc, int lane_base, int nlanes,
                                                          const double* __restrict__ partial, size_t rowstride) {
-  const int L = lane_base + blockIdx.x;
-  if (threadIdx.x == 0) sc.xalpha[L] = 0.0;
+  const int l = blockIdx.x * kLanesPerBlock + (int)(threadIdx.x >> 6);
+  if (l >= nlanes) return;
+  const int L = lane_base + l;
+  if ((threadIdx.x & 63) == 0) sc.xalpha[L] = 0.0;
   if (sc.state[L] != kFrozen) return;
   const BatchJob& J = a.jobs[a.lane_job[L]];
   const BatchProb& P = a.probs[J.prob];
   const double* row = partial + (size_t)L * a.PI;
-  const double rt2 = sum_partials(row, (int)J.nitems);
-  const double qre = sum_partials(row + rowstride, (int)J.nitems);
-  const double qim = sum_partials(row + 2 * rowstride, (int)J.nitems);
-  if (threadIdx.x != 0) return;
+  const double rt2 = wave_sum(row, (int)J.nitems);
+  const double qre = wave_sum(row + rowstride, (int)J.nitems);
+  const double qim = wave_sum(row + 2 * rowstride, (int)J.nitems);
+  if ((threadIdx.x & 63) != 0) return;
   lane_true(sc, L, rt2, qre, qim, P.tol2, P.max_iter, kBatchMaxRestarts);
 }
 
-__global__ __launch_bounds__(kBlock) void kb_reduce_ru(BatchArgs a, CgScalars sc, int lane_base,
+__global__ __launch_bounds__(kBlock) void kb_reduce_ru(BatchArgs a, CgScalars sc, int lane_base, int nlanes,
                                                        const double* __restrict__ partial, size_t rowstride, int mode) {
-  const int L = lane_base + blockIdx.x;
+  const int l = blockIdx.x * kLanesPerBlock + (int)(threadIdx.x >> 6);
+  if (l >= nlanes) return;
+  const int L = lane_base + l;
   if (mode == 0 && *sc.n_ru == 0) return;
-  if (!ru_selected(sc, mode, L)) return;      // uniform per workgroup
+  if (!ru_selected(sc, mode, L)) return;      // uniform per wave
   const BatchJob& J = a.jobs[a.lane_job[L]];
   const BatchProb& P = a.probs[J.prob];
   double v[5];
 #pragma unroll
-  for (int k = 0; k < 5; ++k) v[k] = sum_partials(partial + k * rowstride + (size_t)L * a.PI, (int)J.nitems);
-  if (threadIdx.x != 0) return;
+  for (int k = 0; k < 5; ++k) v[k] = wave_sum(partial + k * rowstride + (size_t)L * a.PI, (int)J.nitems);
+  if ((threadIdx.x & 63) != 0) return;
   lane_ru(sc, L, v, mode, P.tol2, P.max_iter, kBatchMaxRestarts);
 }
 
@@ -439,6 +519,8 @@ template <class Op> struct FP64Op;
 template <class TT> struct FP64Op<ScalarOp<TT>> { using type = ScalarOp<typename Wide<TT>::type>; };
 template <class C> struct FP64Op<CovOp<C>> { using type = CovOp<typename Wide<C>::type>; };
 
+unsigned lane_grid(const BatchGroup& gr) { return (unsigned)((gr.nlanes + kLanesPerBlock - 1) / kLanesPerBlock); }
+
 }  // namespace
 
 hipError_t launch_batch_init(const BatchArgs& a, const BatchGroup& gr, void* x64, void* xh, void* r, void* p,
@@ -460,9 +542,11 @@ hipError_t launch_batch_iteration(const BatchArgs& a, const BatchGroup& gr, cons
     if (ev0) (void)hipEventRecord(ev0, st);
     kb_stencil<Op><<<gr.nitems, kBlock, 0, st>>>(a, sc, (const T*)p, (T*)w, partial);
     if (ev1) (void)hipEventRecord(ev1, st);
-    kb_reduce_alpha<<<gr.nlanes, kBlock, 0, st>>>(a, sc, gr.lane_base, partial, gr.prec == Prec::kF32 ? 1 : 0);
+    kb_reduce_alpha<<<lane_grid(gr), kBlock, 0, st>>>(a, sc, gr.lane_base, gr.nlanes, partial,
+                                                         gr.prec == Prec::kF32 ? 1 : 0);
     kb_update_r<T><<<gr.nitems, kBlock, 0, st>>>(a, sc, (T*)r, (const T*)w, partial + rowstride);
-    kb_reduce_beta<<<gr.nlanes, kWideBlock, 0, st>>>(a, sc, gr.lane_base, partial + rowstride, eps, tau2);
+    kb_reduce_beta<<<lane_grid(gr), kBlock, 0, st>>>(a, sc, gr.lane_base, gr.nlanes, partial + rowstride, eps,
+                                                        tau2);
     kb_direction<T><<<gr.nitems, kBlock, 0, st>>>(a, sc, (T*)x, (const T*)r, (T*)p);
   });
 }
@@ -478,7 +562,7 @@ hipError_t launch_batch_reliable(const BatchArgs& a, const BatchGroup& gr, const
       kb_ru_accumulate<T64, T32><<<gr.nitems, kBlock, 0, st>>>(a, sc, mode, (T64*)x64, (T32*)xh);
       kb_ru_residual<Op64, T32><<<gr.nitems, kBlock, 0, st>>>(a, sc, mode, (const T64*)x64, (T32*)r, (T32*)p,
                                                                 partial, rowstride);
-      kb_reduce_ru<<<gr.nlanes, kBlock, 0, st>>>(a, sc, gr.lane_base, partial, rowstride, mode);
+      kb_reduce_ru<<<lane_grid(gr), kBlock, 0, st>>>(a, sc, gr.lane_base, gr.nlanes, partial, rowstride, mode);
     }
   });
 }
@@ -490,7 +574,7 @@ hipError_t launch_batch_true_residual(const BatchArgs& a, const BatchGroup& gr, 
     using T = typename Op::T;
     if constexpr (!is_single<T>::value) {
       kb_true_residual<Op><<<gr.nitems, kBlock, 0, st>>>(a, sc, (const T*)x, (T*)r, (T*)p, partial, rowstride);
-      kb_reduce_true<<<gr.nlanes, kBlock, 0, st>>>(a, sc, gr.lane_base, partial, rowstride);
+      kb_reduce_true<<<lane_grid(gr), kBlock, 0, st>>>(a, sc, gr.lane_base, gr.nlanes, partial, rowstride);
     }
   });
 }

@@ -187,11 +187,13 @@ __device__ __forceinline__ uint32_t tile_first_site(uint32_t b, const TileMap& t
 // Stencil at one (site, rhs): y = diag x(s) - sum_mu [w_mu(s) U_mu(s) x(s+mu)
 // + w_mu(s-mu) U_mu(s-mu)^H x(s-mu)], with the hop terms summed in the order
 // mu = 0..ndim-1, forward before backward (the marching kernel keeps it).
-template <class Op>
-__device__ __forceinline__ void stencil_site(const Op& op, const Geom& g, int logB, uint32_t s, int j,
-                                             const double* __restrict__ mass_field, double mass,
-                                             const double* __restrict__ w, const typename Op::T* __restrict__ in,
-                                             typename Op::T (&xs)[Op::NC], typename Op::T (&y)[Op::NC]) {
+// Nbr gives the periodic neighbours of s: nbr(mu, fwd).
+template <class Op, class Nbr>
+__device__ __forceinline__ void stencil_site_at(const Op& op, const Geom& g, int logB, uint32_t s, int j,
+                                                const double* __restrict__ mass_field, double mass,
+                                                const double* __restrict__ w, const typename Op::T* __restrict__ in,
+                                                const Nbr& nbr, typename Op::T (&xs)[Op::NC],
+                                                typename Op::T (&y)[Op::NC]) {
   using T = typename Op::T;
   constexpr int NC = Op::NC;
   const size_t V = g.V;
@@ -199,9 +201,11 @@ __device__ __forceinline__ void stencil_site(const Op& op, const Geom& g, int lo
 #pragma unroll
   for (int c = 0; c < NC; ++c) hop[c] = zero<T>();
   double diag = mass_field ? mass_field[s] : mass;
-  for (int mu = 0; mu < g.ndim; ++mu) {
-    const uint32_t sf = nbr_fwd(s, g, mu);
-    const uint32_t sb = nbr_bwd(s, g, mu);
+#pragma unroll
+  for (int mu = 0; mu < kMaxDim; ++mu) {
+    if (mu >= g.ndim) break;
+    const uint32_t sf = nbr(mu, true);
+    const uint32_t sb = nbr(mu, false);
     const double wf = w ? w[(size_t)mu * V + s] : 1.0;
     const double wb = w ? w[(size_t)mu * V + sb] : 1.0;
     diag += wf + wb;
@@ -217,6 +221,54 @@ __device__ __forceinline__ void stencil_site(const Op& op, const Geom& g, int lo
 #pragma unroll
   for (int c = 0; c < NC; ++c) y[c] = axpy(diag, xs[c], axpy(-1.0, hop[c], zero<T>()));
 }
+
+template <class Op>
+__device__ __forceinline__ void stencil_site(const Op& op, const Geom& g, int logB, uint32_t s, int j,
+                                             const double* __restrict__ mass_field, double mass,
+                                             const double* __restrict__ w, const typename Op::T* __restrict__ in,
+                                             typename Op::T (&xs)[Op::NC], typename Op::T (&y)[Op::NC]) {
+  auto nbr = [&](int mu, bool fwd) { return fwd ? nbr_fwd(s, g, mu) : nbr_bwd(s, g, mu); };
+  stencil_site_at(op, g, logB, s, j, mass_field, mass, w, in, nbr, xs, y);
+}
+
+// A site index with its coordinates, stepped forward without division on
+// any sides: the periodic neighbours then follow from the coordinates.
+struct SiteWalk {
+  uint32_t s;
+  uint32_t x[kMaxDim];
+  __device__ __forceinline__ SiteWalk(uint32_t s0, const Geom& g) : s(s0) {
+#pragma unroll
+    for (int mu = 0; mu < kMaxDim; ++mu) x[mu] = mu < g.ndim ? coord(s0, g, mu) : 0u;
+  }
+  // s += d with the carries through the coordinates (d >= 0)
+  __device__ __forceinline__ void advance(uint32_t d, const Geom& g) {
+    s += d;
+    uint32_t carry = d;
+#pragma unroll
+    for (int mu = 0; mu < kMaxDim; ++mu) {
+      if (mu >= g.ndim || carry == 0u) break;
+      uint32_t v = x[mu] + carry;
+      const uint32_t n = g.n[mu];
+      carry = 0u;
+      if (v >= n) {
+        if (v < 2u * n) {
+          v -= n;
+          carry = 1u;
+        } else {
+          carry = v / n;
+          v -= carry * n;
+        }
+      }
+      x[mu] = v;
+    }
+  }
+  // periodic neighbour of s along mu
+  __device__ __forceinline__ uint32_t nbr(int mu, bool fwd, const Geom& g) const {
+    const uint32_t n = g.n[mu], st = g.stride[mu];
+    if (fwd) return x[mu] == n - 1u ? s - (n - 1u) * st : s + st;
+    return x[mu] == 0u ? s + (n - 1u) * st : s - st;
+  }
+};
 
 
 // Entry (s, c) of right-hand side rhs0 + j (spatial probe (rhs0 + j) / ncomp
@@ -234,6 +286,53 @@ __device__ __forceinline__ void rhs_at(const Geom& g, uint32_t s, int64_t rhs0, 
 #pragma unroll
   for (int c = 0; c < NC; ++c)
     if (c == cj) b[c] = v;
+}
+
+// The part of a hierarchical probe entry that depends on the site only
+// (power-of-two sides, mask sweep 0, i.e. probes m < V): the site's location
+// P(x) and, per component c, the mask value z0(x, c) = i^code (Z2: code 0 or
+// 2; no mask: 0), two bits per component.
+struct ProbeSiteCode {
+  uint32_t P;
+  uint32_t codes;
+};
+__device__ __forceinline__ ProbeSiteCode probe_site_code(uint32_t s, const Geom& g, uint64_t seed, int mask) {
+  ProbeSiteCode pc;
+  pc.P = hier_perm(s, g);
+  pc.codes = 0u;
+  if (mask != kMaskNone)
+    for (int c = 0; c < g.ncomp; ++c) {
+      const uint64_t u = splitmix64_at(seed, (uint64_t)s * (uint64_t)g.ncomp + (uint64_t)c);
+      const uint32_t code = mask == kMaskZ2 ? ((u >> 63) ? 2u : 0u) : (uint32_t)(u >> 62);
+      pc.codes |= code << (2 * c);
+    }
+  return pc;
+}
+
+// b of lane j from its site's ProbeSiteCode: z0(x, c) H(P(x), bitrev_L(m)) on
+// component c of right-hand side rhs0 + j = m ncomp + c (the same exact value
+// rhs_at computes).
+template <class T, int NC>
+__device__ __forceinline__ void rhs_from_code(const ProbeSiteCode& pc, const Geom& g, int64_t rhs0, int j, int nb,
+                                              T (&b)[NC]) {
+#pragma unroll
+  for (int c = 0; c < NC; ++c) b[c] = zero<T>();
+  if (j >= nb) return;
+  const int64_t rg = rhs0 + j;
+  const int cj = (int)(rg % NC);
+  const uint32_t col = hadamard_column((uint32_t)(rg / NC), g.L);
+  const double h = (__popc(pc.P & col) & 1) ? -1.0 : 1.0;
+  double2 v;
+  switch ((pc.codes >> (2 * cj)) & 3u) {            // i^code h
+    case 0: v = make_double2(h, 0.0); break;
+    case 1: v = make_double2(0.0, h); break;
+    case 2: v = make_double2(-h, 0.0); break;
+    default: v = make_double2(0.0, -h); break;
+  }
+  const T e = from_c<T>(v);
+#pragma unroll
+  for (int c = 0; c < NC; ++c)
+    if (c == cj) b[c] = e;
 }
 
 // ---------------------------------------------------------------------------

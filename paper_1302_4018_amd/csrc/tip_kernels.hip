@@ -890,10 +890,74 @@ static inline unsigned cdiv(size_t a, size_t b) { return (unsigned)((a + b - 1) 
 // b is the probing right-hand side, regenerated from site indices.
 // ---------------------------------------------------------------------------
 
+// The link staging of the half-lattice hops with the address arithmetic done
+// once per workgroup instead of once per march step.  At step tau the tile's
+// links [2 ndim][9][TS] (slots 0..ndim-1 forward U_mu(s), ndim..2 ndim-1
+// backward U_mu(s - mu)) come from the even-odd link layout
+// [parity][mu][9][V/2] at half-lattice index x + V3 tau' with x the tile
+// site or its backward spatial neighbour, and tau' = tau except for the
+// backward t-link of a site with delta = 0, which sits one slice behind
+// (tau' = tau - 1, wrapping to ntau - 1 at tau = 0).  Thread tid copies
+// elements it = tid + k kNT, k < KMAX; each keeps its element index at
+// tau' = 0 and whether it is such a trailing t-link.
+template <int KMAX>
+struct EoLinkStage {
+  uint32_t base[KMAX];
+  uint32_t trail;                 // bit k: element k trails by one slice
+  int n;                          // 2 ndim 9 TS
+  __device__ __forceinline__ EoLinkStage(const Geom& g, uint32_t V3, int P, uint32_t s3_first, int TS, int kNT) {
+    const int ndim = g.ndim, tdim = ndim - 1;
+    const uint32_t Vh = g.V >> 1;
+    n = 2 * ndim * 9 * TS;
+    trail = 0u;
+#pragma unroll
+    for (int k = 0; k < KMAX; ++k) {
+      const int it = (int)threadIdx.x + k * kNT;
+      base[k] = 0u;
+      if (it >= n) continue;
+      const int site = it % TS;
+      const int es = it / TS;
+      const int e = es % 9;
+      const int slot = es / 9;
+      const uint32_t x3 = s3_first + (uint32_t)site;
+      uint32_t hl, par;
+      int mu;
+      if (slot < ndim) {
+        mu = slot;
+        par = (uint32_t)P;
+        hl = x3;
+      } else {
+        mu = slot - ndim;
+        par = 1u - (uint32_t)P;
+        if (mu < tdim) {
+          hl = nbr_bwd_p2(x3, g, mu);
+        } else {
+          hl = x3;
+          const uint32_t dl = ((uint32_t)P + spatial_parity(x3, g)) & 1u;
+          if (dl == 0u) trail |= 1u << k;
+        }
+      }
+      base[k] = (((par * (uint32_t)ndim + (uint32_t)mu) * 9u + (uint32_t)e) * Vh) + hl;
+    }
+  }
+  // copy step tau's links into lds (the caller synchronises around it)
+  template <class C>
+  __device__ __forceinline__ void stage(const C* __restrict__ U, C* lds, uint32_t V3, uint32_t tau, uint32_t ntau,
+                                        int kNT) const {
+#pragma unroll
+    for (int k = 0; k < KMAX; ++k) {
+      const int it = (int)threadIdx.x + k * kNT;
+      if (it >= n) break;
+      const uint32_t tt = (trail >> k) & 1u ? (tau == 0u ? ntau : tau) - 1u : tau;
+      lds[it] = U[base[k] + V3 * tt];
+    }
+  }
+};
+
 #ifndef TIP_EO_STREAMING
 #define TIP_EO_STREAMING 1
 #endif
-template <class Op, int MODE, int kLogB, int kNT = kBlock>
+template <class Op, int MODE, int kLogB, int kNT = kBlock, bool kCacheProbe = false>
 __global__ __launch_bounds__(kNT) void k_eo_hop(Geom g, MarchMap mm, int P, Op op,
                                                    const double* __restrict__ diag, const double* __restrict__ w,
                                                    const int* __restrict__ state, const int* __restrict__ active,
@@ -920,6 +984,11 @@ __global__ __launch_bounds__(kNT) void k_eo_hop(Geom g, MarchMap mm, int P, Op o
   // scalar operator with couplings: the tile's weights [2 ndim][TS] (forward
   // w_mu(s), backward w_mu(s - mu)), read once per site instead of per lane
   __shared__ double lds_w[kCov ? 1 : 2 * kMaxDim * kNT];
+  // kCacheProbe (passes that regenerate b, hierarchical probes): P(x) and the
+  // mask of each of the tile's sites, computed once per site and march step
+  // (instead of once per rhs lane) and read by the site's B lanes
+  static_assert(!kCacheProbe || MODE == 2 || kResidual, "only the passes that regenerate b cache probes");
+  __shared__ ProbeSiteCode lds_probe[kCacheProbe ? kNT : 1];
   const int j = threadIdx.x & (B - 1);
   const int si = threadIdx.x >> logB;
   uint32_t q, chunk;
@@ -935,6 +1004,9 @@ __global__ __launch_bounds__(kNT) void k_eo_hop(Geom g, MarchMap mm, int P, Op o
   const uint32_t s3 = s3_first + (uint32_t)si;
   const uint32_t delta = ((uint32_t)P + spatial_parity(s3, g)) & 1u;
   const bool live = kResidual || ((!state || state[j] == kActive) && (!ru || ru[j] != 0));
+  // compile-time B: the link staging's addresses once per workgroup
+  constexpr int kStageK = kLogB >= 0 ? (2 * kMaxDim * 9 * (kNT >> (kLogB >= 0 ? kLogB : 0)) + kNT - 1) / kNT : 1;
+  const EoLinkStage<kStageK> stage(g, V3, P, s3_first, TS, kNT);
   double acc[NP];
 #pragma unroll
   for (int k = 0; k < NP; ++k) acc[k] = 0.0;
@@ -945,7 +1017,11 @@ __global__ __launch_bounds__(kNT) void k_eo_hop(Geom g, MarchMap mm, int P, Op o
     const uint32_t t = 2u * tau + delta;
     const uint32_t s = s3 + V3 * t;                     // full-lattice output site
     const uint32_t h = s3 + V3 * tau;                   // its half-lattice index
-    if constexpr (kCov) {
+    if constexpr (kCov && kLogB >= 0) {
+      __syncthreads();
+      stage.stage(op.U, lds_links, V3, tau, ntau, kNT);
+      __syncthreads();
+    } else if constexpr (kCov) {
       // stage the tile's links: slots 0..ndim-1 forward U_mu(s), ndim..2ndim-1 backward U_mu(s - mu)
       __syncthreads();
       const int nslot = 2 * ndim;
@@ -993,6 +1069,15 @@ __global__ __launch_bounds__(kNT) void k_eo_hop(Geom g, MarchMap mm, int P, Op o
         }
         __syncthreads();
       }
+    }
+    if constexpr (kCacheProbe) {
+      __syncthreads();                                  // the previous step's readers are done
+      if ((int)threadIdx.x < TS) {
+        const uint32_t x3 = s3_first + threadIdx.x;
+        const uint32_t dl = ((uint32_t)P + spatial_parity(x3, g)) & 1u;
+        lds_probe[threadIdx.x] = probe_site_code(x3 + V3 * (2u * tau + dl), g, seed, mask);
+      }
+      __syncthreads();
     }
     if (!live) continue;
     T hop[NC];
@@ -1109,7 +1194,8 @@ __global__ __launch_bounds__(kNT) void k_eo_hop(Geom g, MarchMap mm, int P, Op o
       }
     } else {
       T b[NC];
-      rhs_at<T, NC>(g, s, rhs0, j, nb, seed, mask, b);
+      if constexpr (kCacheProbe) rhs_from_code<T, NC>(lds_probe[si], g, rhs0, j, nb, b);
+      else rhs_at<T, NC>(g, s, rhs0, j, nb, seed, mask, b);
       if constexpr (MODE == 2) {
 #pragma unroll
         for (int c = 0; c < NC; ++c) {
@@ -1267,6 +1353,7 @@ __global__ __launch_bounds__(kNT) void k_eo_hop_pair(Geom g, MarchMap mm, int P,
   const uint32_t s3 = s3_first + (uint32_t)si;
   const uint32_t delta = ((uint32_t)P + spatial_parity(s3, g)) & 1u;
   const bool live = !state || state[2 * l] == kActive || state[2 * l + 1] == kActive;
+  const EoLinkStage<(2 * kMaxDim * 9 * TS + kNT - 1) / kNT> stage(g, V3, P, s3_first, TS, kNT);
   double acc[2] = {0.0, 0.0};
   const uint32_t tau0 = chunk * (uint32_t)mm.Tc;
   T pa[NC], pb[NC];                               // backward t input, carried along the march
@@ -1280,30 +1367,7 @@ __global__ __launch_bounds__(kNT) void k_eo_hop_pair(Geom g, MarchMap mm, int P,
       // the tile's links, as in k_eo_hop: forward U_mu of the tile's sites,
       // backward ones at the opposite-parity neighbours
       __syncthreads();
-      for (int it = threadIdx.x; it < nslot * 9 * TS; it += kNT) {
-        const int site = it % TS;
-        const int es = it / TS;
-        const int e = es % 9;
-        const int slot = es / 9;
-        const uint32_t x3 = s3_first + (uint32_t)site;
-        uint32_t hl, par;
-        int mu;
-        if (slot < ndim) {
-          mu = slot;
-          par = (uint32_t)P;
-          hl = x3 + V3 * tau;
-        } else {
-          mu = slot - ndim;
-          par = 1u - (uint32_t)P;
-          if (mu < tdim) {
-            hl = nbr_bwd_p2(x3, g, mu) + V3 * tau;
-          } else {
-            const uint32_t dl = ((uint32_t)P + spatial_parity(x3, g)) & 1u;
-            hl = x3 + V3 * ((tau + ntau - 1u + dl) % ntau);
-          }
-        }
-        lds_links[it] = op.U[(((size_t)par * ndim + mu) * 9 + e) * Vh + hl];
-      }
+      stage.stage(op.U, lds_links, V3, tau, ntau, kNT);
       __syncthreads();
     } else if (w) {
       // the tile's couplings, as in k_eo_hop: forward w_mu(s), backward w_mu(s - mu)
@@ -1683,12 +1747,22 @@ hipError_t launch_eo_hop(int mode, const OpDev& od, const Geom& g, const MarchMa
                                           ran, ru, (const T*)cin2, out32, pstride);
     };
     const bool b32 = mm.logB == 5;
+    const bool hier = g.probe == kProbeHierarchical;     // b from the per-site probe cache
     switch (mode) {
       case 0: b32 ? go(k_eo_hop<Op, 0, 5>) : go(k_eo_hop<Op, 0, -1>); break;
       case 1: b32 ? go(k_eo_hop<Op, 1, 5>) : go(k_eo_hop<Op, 1, -1>); break;
-      case 2: b32 ? go(k_eo_hop<Op, 2, 5>) : go(k_eo_hop<Op, 2, -1>); break;
-      case 3: b32 ? go(k_eo_hop<Op, 3, 5>) : go(k_eo_hop<Op, 3, -1>); break;
-      case 5: b32 ? go(k_eo_hop<Op, 5, 5>) : go(k_eo_hop<Op, 5, -1>); break;
+      case 2:
+        if (hier) b32 ? go(k_eo_hop<Op, 2, 5, kBlock, true>) : go(k_eo_hop<Op, 2, -1, kBlock, true>);
+        else b32 ? go(k_eo_hop<Op, 2, 5>) : go(k_eo_hop<Op, 2, -1>);
+        break;
+      case 3:
+        if (hier) b32 ? go(k_eo_hop<Op, 3, 5, kBlock, true>) : go(k_eo_hop<Op, 3, -1, kBlock, true>);
+        else b32 ? go(k_eo_hop<Op, 3, 5>) : go(k_eo_hop<Op, 3, -1>);
+        break;
+      case 5:
+        if (hier) b32 ? go(k_eo_hop<Op, 5, 5, kBlock, true>) : go(k_eo_hop<Op, 5, -1, kBlock, true>);
+        else b32 ? go(k_eo_hop<Op, 5, 5>) : go(k_eo_hop<Op, 5, -1>);
+        break;
       default:
         if constexpr (sizeof(typename SingleOf<T>::type) * 2 == sizeof(T)) {
           if (b32) go(k_eo_hop<Op, 4, 5>);
@@ -1719,6 +1793,36 @@ hipError_t launch_eo_hop_wide(int mode, const OpDev& od, const Geom& g, const Ma
   };
   if (mode == 0) go(k_eo_hop<Op, 0, 5, kNT>);
   else go(k_eo_hop<Op, 1, 5, kNT>);
+  return hipGetLastError();
+}
+
+// Every FP64 covariant mode in 512-thread workgroups (B = 32, 16 sites per
+// tile, on the march map built for that tile size): the iteration's hops of
+// the FP64 solver, and the once-per-block passes and reliable updates of both
+// solvers.
+hipError_t launch_eo_hop512(int mode, const OpDev& od, const Geom& g, const MarchMap& mm, int P, const double* diag,
+                            const int* state, const int* active, const void* in, const void* cin, void* out,
+                            void* out2, void* out3, int64_t rhs0, int nb, uint64_t seed, int mask, double* partial,
+                            int* ran, hipStream_t st, const int* ru, const void* cin2, void* out32, size_t pstride) {
+  using Op = CovOp<double2>;
+  constexpr int kNT = 2 * kBlock;
+  Op op{reinterpret_cast<const double2*>(od.links_eo)};
+  const size_t lds = eo_lds_bytes(g, mm, Prec::kF64);
+  using T = double2;
+  auto go = [&](auto kern) {
+    kern<<<mm.grid, kNT, lds, st>>>(g, mm, P, op, diag, od.coupling, state, active, (const T*)in, (const T*)cin,
+                                    (T*)out, (T*)out2, (T*)out3, rhs0, nb, seed, mask, partial, ran, ru,
+                                    (const T*)cin2, out32, pstride);
+  };
+  const bool hier = g.probe == kProbeHierarchical;     // b from the per-site probe cache
+  switch (mode) {
+    case 0: go(k_eo_hop<Op, 0, 5, kNT>); break;
+    case 1: go(k_eo_hop<Op, 1, 5, kNT>); break;
+    case 2: hier ? go(k_eo_hop<Op, 2, 5, kNT, true>) : go(k_eo_hop<Op, 2, 5, kNT>); break;
+    case 3: hier ? go(k_eo_hop<Op, 3, 5, kNT, true>) : go(k_eo_hop<Op, 3, 5, kNT>); break;
+    case 4: go(k_eo_hop<Op, 4, 5, kNT>); break;
+    default: hier ? go(k_eo_hop<Op, 5, 5, kNT, true>) : go(k_eo_hop<Op, 5, 5, kNT>); break;
+  }
   return hipGetLastError();
 }
 

@@ -164,6 +164,12 @@ size_t eo_lds_bytes(const Geom& g, const MarchMap& mm, Prec prec);
 hipError_t launch_eo_hop_wide(int mode, const OpDev& od, const Geom& g, const MarchMap& mm, int P,
                               const double* diag, const int* state, const int* active, const void* in,
                               const void* cin, void* out, double* partial, int* ran, hipStream_t st);
+// Any FP64 covariant mode (as launch_eo_hop) with 512-thread workgroups, B = 32,
+// on a march map of 16-site tiles.
+hipError_t launch_eo_hop512(int mode, const OpDev& od, const Geom& g, const MarchMap& mm, int P, const double* diag,
+                            const int* state, const int* active, const void* in, const void* cin, void* out,
+                            void* out2, void* out3, int64_t rhs0, int nb, uint64_t seed, int mask, double* partial,
+                            int* ran, hipStream_t st, const int* ru, const void* cin2, void* out32, size_t pstride);
 hipError_t launch_eo_hop_pair(int mode, const OpDev& od, const Geom& g, const MarchMap& mm, int P, Prec prec,
                               const double* diag, const int* state, const int* active, const void* in,
                               const void* cin, void* out, double* partial, int* ran, hipStream_t st);
