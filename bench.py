@@ -91,7 +91,9 @@ def write_traffic(fetch_csv, write_csv, kernel_match, command):
     """Derive HBM bytes per stencil launch from two rocprofv3 --pmc runs (FETCH_SIZE,
     then WRITE_SIZE, each taken with --copy-calibration) and store them with the
     hash of the kernel sources.  Each counter is scaled by what it reads for the
-    plain 1 GiB device copy of the same run (read 2^30 bytes, written 2^30 bytes)."""
+    plain 1 GiB device copy of the same run (read 2^30 bytes, written 2^30 bytes).
+    Launches that moved under 1% of the largest one's bytes returned at once
+    and are left out of the average."""
     import csv
 
     def per_launch(path, counter):
@@ -107,6 +109,9 @@ def write_traffic(fetch_csv, write_csv, kernel_match, command):
                     vals.append(v)
         if not vals or not copies:
             raise SystemExit(f"{path}: no {counter} rows for {kernel_match!r} or for the calibration copy")
+        # launches that returned at once (every rhs of the block already stopped)
+        # are not stencil work: bench.py does not time them either
+        vals = [v for v in vals if v > 0.01 * max(vals)]
         top = max(copies)
         calib = [c for c in copies if c > 0.9 * top]
         scale = float(1 << 30) / (1024.0 * sum(calib) / len(calib))
