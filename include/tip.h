@@ -284,7 +284,9 @@ tip_status tip_autotune(tip_op_handle h, const tip_params* p, int64_t sample_vec
                         tip_tuning* tried, int32_t max_tried, int32_t* n_tried);
 
 /* Times trace_inv_probe_batch on the first sample_vectors probes of every
- * problem (0 = 16) for each candidate launch configuration: right-hand sides
+ * problem (0 = 64; a sample that keeps the sizes of the probe classes, and so
+ * the padding each block size leaves, close to the full run's) for each
+ * candidate launch configuration: right-hand sides
  * per block in {16, 32, 64} unless params[0].rhs_block fixes it, times sites
  * per work item in {256, 512, 1024, 2048} unless params[0].item_sites fixes
  * it.  Every candidate runs twice (the first run warms up); the fastest goes

@@ -58,7 +58,7 @@ def _batch_key(ops, n_vectors, precision, mask):
 
 
 def tuned_batch(ops, n_vectors, tol=1e-10, seed=0, mask=tip.MASK_DEFAULT, precision=tip.PREC_FP64,
-                sample_vectors=16, path=None, retune=False):
+                sample_vectors=64, path=None, retune=False):
     """kwargs (rhs_block, item_sites) for trace_inv_probe_batch on these problems,
     from tip_autotune_batch, cached like tuned() under the batch's shapes."""
     path = path or cache_path()

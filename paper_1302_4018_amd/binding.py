@@ -283,7 +283,7 @@ def trace_inv_probe_batch(ops, n_vectors, tol, seed, mask=MASK_DEFAULT, max_iter
     return out
 
 
-def tip_autotune_batch(ops, n_vectors, tol, seed, sample_vectors=16, mask=MASK_DEFAULT, precision=PREC_FP64,
+def tip_autotune_batch(ops, n_vectors, tol, seed, sample_vectors=64, mask=MASK_DEFAULT, precision=PREC_FP64,
                        rhs_block=0, item_sites=0, stream=None):
     """Fastest (rhs_block, item_sites) of trace_inv_probe_batch on a sample:
     returns (best dict, list of tried dicts)."""

@@ -159,7 +159,7 @@ struct tip_op_s {
   double mass = 0.0;
   DevBuf links, mass_field, coupling;
   DevBuf links32;              // single-precision copy, made on first mixed-precision use
-  DevBuf diag;                 // D(x) = m(x) + sum_mu [w_mu(x) + w_mu(x - mu)], FP64
+  DevBuf diag;                 // [2][V] FP64: D(x) = m(x) + sum_mu [w_mu(x) + w_mu(x - mu)], then 1 / D(x)
   DevBuf links_eo;             // covariant, every side even: links by parity (see k_repack_links_eo)
   DevBuf links_eo32;           // its single-precision copy, made on first mixed-precision use
   bool has_links_eo = false, has_links_eo32 = false;
@@ -252,7 +252,7 @@ tip_status create_handle(const tip_operator* op, hipStream_t st, tip_op_s** out)
       h->has_links_eo = true;
     }
   }
-  if (const hipError_t e_ = h->diag.ensure(V * sizeof(double)); e_ != hipSuccess)
+  if (const hipError_t e_ = h->diag.ensure(2 * V * sizeof(double)); e_ != hipSuccess)
       return bail(fail(TIP_ENOMEM, "hipMalloc diagonal: %s", hipGetErrorString(e_)));
   if (launch_diag(g, h->has_mass_field ? (const double*)h->mass_field.p : nullptr, op->mass,
                   h->has_coupling ? (const double*)h->coupling.p : nullptr, (double*)h->diag.p, st) != hipSuccess)
@@ -646,10 +646,12 @@ struct Solver {
                 make_marchmap(g, 4, &pl.me2, true, p->round_tiles > 0 ? p->round_tiles : 128, p->march_tc) &&
                 eo_lds_bytes(g, pl.me2, prec) <= 65536;
       // the FP64 passes outside the iteration (reduced right-hand side, true
-      // residual, reliable updates) on the same 16-site tiles in 512-thread
-      // workgroups (TIP_EO_WIDE_ONCE=0 keeps them at 256 threads)
+      // residual, reliable updates) stay in 256-thread workgroups: with 180-200
+      // VGPRs they run 2 waves per SIMD, i.e. two 256-thread workgroups per CU
+      // against one of 512, and measured 10-12% faster that way.
+      // TIP_EO_WIDE_ONCE=1 puts them on the 16-site tiles in 512 threads.
       pl.eo512 = (pl.wide || pl.pair) && h->kind == TIP_KIND_COVARIANT && pl.B == 32 &&
-                 eo_lds_bytes(g, pl.me2, Prec::kF64) <= 65536 && !env_off("TIP_EO_WIDE_ONCE");
+                 eo_lds_bytes(g, pl.me2, Prec::kF64) <= 65536 && env_on("TIP_EO_WIDE_ONCE");
     }
     max_iter = p->max_iter > 0 ? p->max_iter : (int)std::min<int64_t>(10 * V * ncomp, 1 << 20);
     tol2 = p->tol * p->tol;
@@ -1999,7 +2001,7 @@ tip_status tip_autotune_batch(const tip_operator* ops, const tip_params* params,
   if (s != TIP_OK) return s;
   if (count == 0) return fail(TIP_EINVAL, "count = 0: nothing to tune");
   // the sample: the first sample_vectors probes of every problem, fresh runs
-  const int64_t want = sample_vectors > 0 ? sample_vectors : 16;
+  const int64_t want = sample_vectors > 0 ? sample_vectors : 64;
   std::vector<tip_params> q(params, params + count);
   std::vector<std::vector<double>> est((size_t)count);
   std::vector<double*> est_ptr((size_t)count);

@@ -103,7 +103,43 @@ __global__ __launch_bounds__(kBlock) void kb_init(BatchArgs a, T64* __restrict__
   }
 }
 
-// w = A p for the live lanes, partial p^H w per lane.
+// The iteration's stencil visits a job's sites in march order.  The job's
+// plane (its first ndim - 1 dimensions, Vp sites) is cut into columns of TS =
+// 256 / B consecutive plane sites; march index o runs through column c, slice
+// t (the last coordinate) and offset i as o = (c nt + t) TS + i, and through
+// the last column, when TS does not divide Vp, as o = F + t wl + i (wl its
+// width, F the indices of the whole columns).  A thread that starts at o0 + i
+// and steps by TS keeps its plane site and moves one slice per step: the
+// workgroup marches its column through the slices, so a site's t-neighbours
+// are the sites of its previous and next steps, and the plane neighbours lie
+// in the columns that the neighbouring work items march at the same time.
+struct MarchOrder {
+  uint32_t nt, Vp, TS, full, F, wl;
+  __device__ __forceinline__ MarchOrder(const Geom& g, uint32_t TS_) : TS(TS_) {
+    nt = 1u;
+#pragma unroll
+    for (int mu = 0; mu < kMaxDim; ++mu)   // constant indices keep g in registers
+      if (mu == g.ndim - 1) nt = g.n[mu];
+    Vp = g.V / nt;
+    full = Vp / TS * TS;
+    F = full * nt;
+    wl = Vp - full;
+  }
+  // site of march index o, and its slice
+  __device__ __forceinline__ uint32_t site(uint32_t o, uint32_t& t) const {
+    if (o < F) {
+      const uint32_t c = o / (TS * nt), rem = o - c * TS * nt;
+      t = rem / TS;
+      return c * TS + (rem - t * TS) + Vp * t;
+    }
+    const uint32_t r = o - F;
+    t = r / wl;
+    return full + (r - t * wl) + Vp * t;
+  }
+};
+
+// w = A p for the live lanes, partial p^H w per lane (per work item of
+// item_sites march indices).
 template <class Op>
 __global__ __launch_bounds__(kBlock) void kb_stencil(BatchArgs a, CgScalars sc, const typename Op::T* __restrict__ in,
                                                      typename Op::T* __restrict__ out, double* __restrict__ partial) {
@@ -123,24 +159,50 @@ __global__ __launch_bounds__(kBlock) void kb_stencil(BatchArgs a, CgScalars sc, 
   const int nlive = __syncthreads_count(live && si == 0);
   if (nlive == 0) return;
   const Op op = BatchOpOf<Op>::get(P);
-  const uint32_t s0 = (item - J.item0) * (uint32_t)a.item_sites;
-  const uint32_t s1 = min(g.V, s0 + (uint32_t)a.item_sites);
+  const uint32_t o0 = (item - J.item0) * (uint32_t)a.item_sites;
+  const uint32_t o1 = min(g.V, o0 + (uint32_t)a.item_sites);
   if (a.bytes && threadIdx.x == 0)   // each link, coupling and mass read once, p read and w written per live rhs
-    atomicAdd(a.bytes, (unsigned long long)(s1 - s0) * (J.site_bytes + 2ull * (unsigned)NC * (unsigned)nlive * J.esz));
+    atomicAdd(a.bytes, (unsigned long long)(o1 - o0) * (J.site_bytes + 2ull * (unsigned)NC * (unsigned)nlive * J.esz));
   const T* inj = in + J.off;
   T* outj = out + J.off;
   double dot[1] = {0.0};
   if (live) {
-    const uint32_t step = (uint32_t)(kBlock >> logB);
-    SiteWalk w(s0 + (uint32_t)si, g);
+    const uint32_t TS = (uint32_t)(kBlock >> logB);
+    const MarchOrder mo(g, TS);
+    const int last = g.ndim - 1;
+    uint32_t o = o0 + (uint32_t)si, t;
+    SiteWalk w(mo.site(o, t), g);
     auto nbr = [&](int mu, bool fwd) { return w.nbr(mu, fwd, g); };
-#pragma unroll 2
-    for (; w.s < s1; w.advance(step, g)) {
+    while (o < o1) {
       T xs[NC], y[NC];
-      stencil_site_at(op, g, logB, w.s, j, P.mass_field, P.mass, P.coupling, inj, nbr, xs, y);
+      // scalar operators: every load of the site first (the covariant one
+      // would need about twice the registers that way and keeps the plain form)
+      if constexpr (NC == 1)
+        stencil_site_gather(op, g, logB, w.s, j, P.mass_field, P.mass, P.coupling, inj, nbr, xs, y);
+      else
+        stencil_site_at(op, g, logB, w.s, j, P.mass_field, P.mass, P.coupling, inj, nbr, xs, y);
       store_vec<T, NC>(outj, g.V, logB, w.s, j, y);
 #pragma unroll
       for (int c = 0; c < NC; ++c) dot[0] += redot(xs[c], y[c]);
+      o += TS;
+      if (o >= o1) break;
+      if (o < mo.F) {
+        if (t + 1u < mo.nt) {                    // next slice of the column
+          ++t;
+          w.s += mo.Vp;
+        } else {                                 // first slice of the next column
+          t = 0u;
+          w.s -= mo.Vp * (mo.nt - 1u);
+        }
+#pragma unroll
+        for (int mu = 0; mu < kMaxDim; ++mu)
+          if (mu == last) w.x[mu] = t;
+        // the plane site moves on by TS when the column changes; it stays
+        // below full <= Vp, so no carry reaches the last coordinate
+        if (t == 0u) w.advance(TS, g);
+      } else {
+        w = SiteWalk(mo.site(o, t), g);          // the last, narrower column
+      }
     }
   }
   store_partials<1>(dot, B, lds, partial, 0, a.PI, J.lane0, item - J.item0);

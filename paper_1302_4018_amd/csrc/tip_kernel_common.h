@@ -222,6 +222,53 @@ __device__ __forceinline__ void stencil_site_at(const Op& op, const Geom& g, int
   for (int c = 0; c < NC; ++c) y[c] = axpy(diag, xs[c], axpy(-1.0, hop[c], zero<T>()));
 }
 
+// The same site, with every load of the site (the 2 ndim neighbours, the
+// site itself, the couplings and the mass) issued before any arithmetic, so a
+// wave has them all in flight at once instead of one round trip per
+// neighbour.  The arithmetic and its order are stencil_site_at's, so the
+// result is the same bit for bit.  (The covariant operator's links are still
+// loaded inside hop_term.)
+template <class Op, class Nbr>
+__device__ __forceinline__ void stencil_site_gather(const Op& op, const Geom& g, int logB, uint32_t s, int j,
+                                                    const double* __restrict__ mass_field, double mass,
+                                                    const double* __restrict__ w,
+                                                    const typename Op::T* __restrict__ in, const Nbr& nbr,
+                                                    typename Op::T (&xs)[Op::NC], typename Op::T (&y)[Op::NC]) {
+  using T = typename Op::T;
+  constexpr int NC = Op::NC;
+  const size_t V = g.V;
+  T xf[kMaxDim][NC], xb[kMaxDim][NC];
+  double wf[kMaxDim], wb[kMaxDim];
+  uint32_t sbk[kMaxDim];
+#pragma unroll
+  for (int mu = 0; mu < kMaxDim; ++mu) {
+    if (mu >= g.ndim) break;
+    const uint32_t sf = nbr(mu, true);
+    sbk[mu] = nbr(mu, false);
+    wf[mu] = w ? w[(size_t)mu * V + s] : 1.0;
+    wb[mu] = w ? w[(size_t)mu * V + sbk[mu]] : 1.0;
+    load_vec<T, NC>(in, V, logB, sf, j, xf[mu]);
+    load_vec<T, NC>(in, V, logB, sbk[mu], j, xb[mu]);
+  }
+  load_vec<T, NC>(in, V, logB, s, j, xs);
+  double diag = mass_field ? mass_field[s] : mass;
+  T hop[NC];
+#pragma unroll
+  for (int c = 0; c < NC; ++c) hop[c] = zero<T>();
+#pragma unroll
+  for (int mu = 0; mu < kMaxDim; ++mu) {
+    if (mu >= g.ndim) break;
+    diag += wf[mu] + wb[mu];
+    T h[NC];
+    hop_term(op, V, mu, s, false, xf[mu], h);
+    add_weighted<T, NC>(wf[mu], h, hop);
+    hop_term(op, V, mu, sbk[mu], true, xb[mu], h);
+    add_weighted<T, NC>(wb[mu], h, hop);
+  }
+#pragma unroll
+  for (int c = 0; c < NC; ++c) y[c] = axpy(diag, xs[c], axpy(-1.0, hop[c], zero<T>()));
+}
+
 template <class Op>
 __device__ __forceinline__ void stencil_site(const Op& op, const Geom& g, int logB, uint32_t s, int j,
                                              const double* __restrict__ mass_field, double mass,
@@ -309,21 +356,34 @@ __device__ __forceinline__ ProbeSiteCode probe_site_code(uint32_t s, const Geom&
   return pc;
 }
 
-// b of lane j from its site's ProbeSiteCode: z0(x, c) H(P(x), bitrev_L(m)) on
-// component c of right-hand side rhs0 + j = m ncomp + c (the same exact value
-// rhs_at computes).
+// The part of the same entry that depends on the lane only: right-hand side
+// rhs0 + j = m ncomp + c has its component c and Hadamard column bitrev_L(m);
+// cj < 0 marks a padding lane (j >= nb).  Computed once per thread.
+struct LaneProbe {
+  int cj;
+  uint32_t col;
+};
+template <int NC>
+__device__ __forceinline__ LaneProbe lane_probe(const Geom& g, int64_t rhs0, int j, int nb) {
+  LaneProbe lp{-1, 0u};
+  if (j < nb) {
+    const int64_t rg = rhs0 + j;
+    lp.cj = (int)(rg % NC);
+    lp.col = hadamard_column((uint32_t)(rg / NC), g.L);
+  }
+  return lp;
+}
+
+// b of a lane from its site's ProbeSiteCode: z0(x, c) H(P(x), bitrev_L(m)) on
+// component c (the same exact value rhs_at computes), zero elsewhere.
 template <class T, int NC>
-__device__ __forceinline__ void rhs_from_code(const ProbeSiteCode& pc, const Geom& g, int64_t rhs0, int j, int nb,
-                                              T (&b)[NC]) {
+__device__ __forceinline__ void rhs_from_code(const ProbeSiteCode& pc, const LaneProbe& lp, T (&b)[NC]) {
 #pragma unroll
   for (int c = 0; c < NC; ++c) b[c] = zero<T>();
-  if (j >= nb) return;
-  const int64_t rg = rhs0 + j;
-  const int cj = (int)(rg % NC);
-  const uint32_t col = hadamard_column((uint32_t)(rg / NC), g.L);
-  const double h = (__popc(pc.P & col) & 1) ? -1.0 : 1.0;
+  if (lp.cj < 0) return;
+  const double h = (__popc(pc.P & lp.col) & 1) ? -1.0 : 1.0;
   double2 v;
-  switch ((pc.codes >> (2 * cj)) & 3u) {            // i^code h
+  switch ((pc.codes >> (2 * lp.cj)) & 3u) {            // i^code h
     case 0: v = make_double2(h, 0.0); break;
     case 1: v = make_double2(0.0, h); break;
     case 2: v = make_double2(-h, 0.0); break;
@@ -332,7 +392,7 @@ __device__ __forceinline__ void rhs_from_code(const ProbeSiteCode& pc, const Geo
   const T e = from_c<T>(v);
 #pragma unroll
   for (int c = 0; c < NC; ++c)
-    if (c == cj) b[c] = e;
+    if (c == lp.cj) b[c] = e;
 }
 
 // ---------------------------------------------------------------------------

@@ -1007,6 +1007,7 @@ __global__ __launch_bounds__(kNT) void k_eo_hop(Geom g, MarchMap mm, int P, Op o
   // compile-time B: the link staging's addresses once per workgroup
   constexpr int kStageK = kLogB >= 0 ? (2 * kMaxDim * 9 * (kNT >> (kLogB >= 0 ? kLogB : 0)) + kNT - 1) / kNT : 1;
   const EoLinkStage<kStageK> stage(g, V3, P, s3_first, TS, kNT);
+  const LaneProbe lane = lane_probe<NC>(g, rhs0, j, nb);
   double acc[NP];
 #pragma unroll
   for (int k = 0; k < NP; ++k) acc[k] = 0.0;
@@ -1158,7 +1159,7 @@ __global__ __launch_bounds__(kNT) void k_eo_hop(Geom g, MarchMap mm, int P, Op o
     const double d = diag[s];
     T y[NC];
     if constexpr (MODE == 0) {
-      const double f = 1.0 / d;
+      const double f = diag[(size_t)V + s];
 #pragma unroll
       for (int c = 0; c < NC; ++c) y[c] = axpy(f, hop[c], zero<T>());
       if constexpr (TIP_EO_STREAMING) store_vec_nt<T, NC>(out, Vh, logB, h, j, y);
@@ -1194,7 +1195,7 @@ __global__ __launch_bounds__(kNT) void k_eo_hop(Geom g, MarchMap mm, int P, Op o
       }
     } else {
       T b[NC];
-      if constexpr (kCacheProbe) rhs_from_code<T, NC>(lds_probe[si], g, rhs0, j, nb, b);
+      if constexpr (kCacheProbe) rhs_from_code<T, NC>(lds_probe[si], lane, b);
       else rhs_at<T, NC>(g, s, rhs0, j, nb, seed, mask, b);
       if constexpr (MODE == 2) {
 #pragma unroll
@@ -1209,7 +1210,7 @@ __global__ __launch_bounds__(kNT) void k_eo_hop(Geom g, MarchMap mm, int P, Op o
         if (out2) store_vec<T, NC>(out2, Vh, logB, h, j, y);
         if (out3) store_vec<T, NC>(out3, Vh, logB, h, j, z);
       } else if constexpr (MODE == 3) {
-        const double f = 1.0 / d;
+        const double f = diag[(size_t)V + s];
 #pragma unroll
         for (int c = 0; c < NC; ++c) {
           const T yv = axpy(1.0, hop[c], b[c]);              // b_o + H_oe x_e
@@ -1433,7 +1434,7 @@ __global__ __launch_bounds__(kNT) void k_eo_hop_pair(Geom g, MarchMap mm, int P,
     const double d = diag[s];
     T ya[NC], yb[NC];
     if constexpr (MODE == 0) {
-      const double f = 1.0 / d;
+      const double f = diag[(size_t)V + s];
 #pragma unroll
       for (int c = 0; c < NC; ++c) {
         ya[c] = axpy(f, ha[c], zero<T>());
@@ -1483,7 +1484,7 @@ __global__ __launch_bounds__(kBlock) void k_eo_init_odd(Geom g, int logB, int64_
   const uint32_t s = eo_site(h, 1, g);
   T b[NC];
   rhs_at<T, NC>(g, s, rhs0, j, nb, seed, mask, b);
-  const double f = 1.0 / diag[s];
+  const double f = diag[(size_t)g.V + s];
 #pragma unroll
   for (int c = 0; c < NC; ++c) b[c] = axpy(f, b[c], zero<T>());
   store_vec<T, NC>(to, Vh, logB, h, j, b);
@@ -1515,6 +1516,7 @@ __global__ __launch_bounds__(kBlock) void k_diag(Geom g, const double* __restric
     d += wf + wb;
   }
   out[s] = d;
+  out[(size_t)g.V + s] = 1.0 / d;   // D^-1 of the even-odd passes, rounded once here
 }
 
 // rho = rho_ref = ||r||^2 of the reduced start residual.

@@ -183,6 +183,7 @@ hipError_t launch_eo_init_odd(const Geom& g, Elem elem, Prec prec, int logB, int
                               int mask, const double* diag, void* to, hipStream_t st);
 hipError_t launch_eo_scatter_even(const Geom& g, Elem elem, Prec prec, int logB, const void* xe, void* x,
                                   hipStream_t st);
+// out [2][V]: D(x), then 1 / D(x)
 hipError_t launch_diag(const Geom& g, const double* mass_field, double mass, const double* w, double* out,
                        hipStream_t st);
 hipError_t launch_reduce_rho0(const CgScalars& sc, int B, const double* partial, int gx, hipStream_t st);

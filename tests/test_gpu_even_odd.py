@@ -230,6 +230,30 @@ def test_fp64_scalar_two_rhs_per_thread_matches_one(dims, n, coupled):
         assert _rel(q, q_o) <= REL
 
 
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+@pytest.mark.parametrize("dims,n", [([16, 16, 16, 16], 16), ([8, 4, 8], 12)])
+def test_once_per_block_passes_in_512_threads_match_256(dims, n, prec):
+    """The FP64 passes outside the iteration (reduced right-hand side, true
+    residual, reliable updates) run in 256-thread workgroups by default;
+    TIP_EO_WIDE_ONCE=1 puts them on 16-site tiles in 512 threads.  Each site
+    is computed the same way, so the quadratures agree to rounding, in FP64
+    and in the mixed solver, and both match the oracle."""
+    tip = gpu_binding()
+    orc, gop = _ops(tip, dims, 1, seed=493)
+    tol = 1e-12
+    pr = tip.PREC_MIXED if prec == "mixed" else tip.PREC_FP64
+    print(f"512-thread once-per-block passes: dims {dims} n {n} {prec}", flush=True)
+    est, q, st = tip.trace_inv_probe(gop, n, tol, 4018, mask=MASK_Z4, rhs_block=32, precision=pr)
+    est_1, q_1, st_1 = _with_env("TIP_EO_WIDE_ONCE", "1", lambda: tip.trace_inv_probe(
+        gop, n, tol, 4018, mask=MASK_Z4, rhs_block=32, precision=pr))
+    assert st["even_odd"] == 1 and st_1["even_odd"] == 1
+    assert st["max_true_relres"] <= tol and st_1["max_true_relres"] <= tol
+    assert _rel(q, q_1) <= REL
+    if orc.V <= 4096:
+        est_o, q_o, _ = oracle_trace(orc, n, tol, 4018, MASK_Z4)
+        assert _rel(q, q_o) <= REL and _rel(q_1, q_o) <= REL
+
+
 @pytest.mark.parametrize("dims,n", [([16, 16, 16, 16], 16), ([8, 8, 8, 8], 12), ([8, 4, 8], 12)])
 def test_fp64_covariant_512_thread_hops_match_256(dims, n):
     """FP64 covariant operator, 32 rhs per block: the iteration's two hops run
