@@ -451,7 +451,7 @@ def bench_c2h(args):
     if not tot["eo"]:
         name = "k_stencil_march<ScalarOp<double>>"
     elif os.environ.get("TIP_EO_PAIR") == "0":
-        name = "k_eo_hop<tip::ScalarOp<double>, 1, 5, 256>"
+        name = "k_eo_hop<tip::ScalarOp<double>, 1, 5, 256, false>"
     else:
         name = "k_eo_hop_pair<tip::ScalarOp<double>, 1, 512>"
     out = {"metric": "scalar stencil HBM GB/s vs peak (3D 256^3 weighted Laplacian, rel.res 1e-10)",
@@ -467,6 +467,90 @@ def bench_c2h(args):
                         "alg_bytes_per_launch": bpl, "avg_launch_us": round(avg * 1e6, 2),
                         "launches": tot["launches"]},
            "estimate": [float(np.real(est[-1]))]}
+    print(json.dumps(out), flush=True)
+
+
+def _configs_oracle_sample(cfg, n_probe, seed):
+    """The oracle on the first n_probe probes of a small configuration, on
+    this thread: (seconds, solves, estimates)."""
+    import numpy as np
+
+    from oracle.estimator import trace_inv_probe as oracle_trace
+
+    t = time.perf_counter()
+    est, _, st = oracle_trace(cfg["oracle_op"](), n_probe, cfg["tol"], seed, cfg["mask_o"])
+    return time.perf_counter() - t, len(st["iters"]), np.asarray(est)
+
+
+
+def bench_configs(args):
+    """The three small configurations beside the 32^4 one: C1 (2-D 16^2 free
+    scalar Laplacian, m = 0.1, all 256 probes, tol 1e-12: the estimate is then
+    Tr(A^-1) itself), C2 (3-D 32^3 weighted Laplacian, w ~ U[0.5, 1.5],
+    m = 0.05, 512 probes, tol 1e-10), C3 (4-D 16^4 covariant Laplacian, Haar
+    U(3) links, m = 0.1, Z4, 1024 probes x 3 components, tol 1e-10).  Each
+    runs on the GPU (one warm-up call, then K timed calls with the operator
+    resident) and in the oracle on one host thread (C1 whole, C2 and C3 on a
+    sample of their first probes), and the GPU's estimates at the sample's
+    checkpoints are compared with the oracle's.  These working sets sit in
+    L2 / MALL, so no HBM roofline is quoted for them.  Prints one JSON line."""
+    import numpy as np
+    import torch
+
+    from oracle.mask import MASK_Z2 as OZ2, MASK_Z4 as OZ4
+    from oracle.operators import Operator as OOp
+    from paper_1302_4018_amd import binding as tip
+    from paper_1302_4018_amd import inputs
+
+    d1, d2, d3 = [16, 16], [32, 32, 32], [16, 16, 16, 16]
+    w2 = inputs.couplings(d2, seed=1)
+    U3 = inputs.haar_links(d3, seed=3)
+    cfgs = [
+        {"name": "C1", "workload": "2D 16^2 scalar Laplacian, m=0.1, Z2, 256 probes (all sites), tol 1e-12",
+         "op": lambda: tip.Operator(d1, tip.KIND_SCALAR, mass=0.1), "oracle_op": lambda: OOp(d1, 0, mass=0.1),
+         "n": 256, "tol": 1e-12, "mask": tip.MASK_Z2, "mask_o": OZ2, "sample": 256},
+        {"name": "C2", "workload": "3D 32^3 weighted Laplacian, w~U[0.5,1.5], m=0.05, Z2, 512 probes, tol 1e-10",
+         "op": lambda: tip.Operator(d2, tip.KIND_SCALAR, mass=0.05, coupling=torch.from_numpy(w2).cuda()),
+         "oracle_op": lambda: OOp(d2, 0, mass=0.05, coupling=w2),
+         "n": 512, "tol": 1e-10, "mask": tip.MASK_Z2, "mask_o": OZ2, "sample": 32},
+        {"name": "C3", "workload": "4D 16^4 covariant Laplacian x3, Haar U(3) links, m=0.1, Z4, 1024 probes x 3, "
+                                   "tol 1e-10",
+         "op": lambda: tip.Operator(d3, tip.KIND_COVARIANT, mass=0.1, links=torch.from_numpy(U3).cuda()),
+         "oracle_op": lambda: OOp(d3, 1, mass=0.1, links=U3),
+         "n": 1024, "tol": 1e-10, "mask": tip.MASK_Z4, "mask_o": OZ4, "sample": 2},
+    ]
+    rows = []
+    for c in cfgs:
+        with tip.OpHandle(c["op"]()) as h:
+            for _ in range(max(args.warmup, 1)):
+                h.trace_inv_probe(c["n"], c["tol"], args.seed, mask=c["mask"])
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            solves = iters = 0
+            relres = 0.0
+            for _ in range(args.steps):
+                est, _, st = h.trace_inv_probe(c["n"], c["tol"], args.seed, mask=c["mask"])
+                solves += st["solves"]
+                iters += st["total_iters"]
+                relres = max(relres, st["max_true_relres"])
+            torch.cuda.synchronize()
+            el = time.perf_counter() - t0
+        sec, n_o, est_o = _configs_oracle_sample(c, c["sample"], args.seed)
+        k = len(est_o)
+        parity = float(np.max(np.abs(est[:k] - est_o) / np.abs(est_o)))
+        log(f"[{c['name']}] GPU {solves / el:.1f} solves/s, oracle {n_o / sec:.3f} solves/s ({c['sample']} probes, "
+            f"{sec:.1f} s), max rel. diff of T_s up to s = {c['sample']}: {parity:.2e}")
+        rows.append({"config": c["name"], "workload": c["workload"],
+                     "gpu": {"solves_per_s": round(solves / el, 2), "ms_per_call": round(el / args.steps * 1e3, 2),
+                             "iters_per_solve": round(iters / max(solves, 1), 2), "max_true_relres": relres,
+                             "even_odd": bool(st["even_odd"]), "estimate": float(np.real(est[-1]))},
+                     "oracle": {"solves_per_s": round(n_o / sec, 4), "cores": 1, "kind": "oracle",
+                                "sample": f"probes 0..{c['sample'] - 1} ({n_o} complete CG solves, {sec:.1f} s), "
+                                          "one host thread"},
+                     "parity_max_rel_diff_T_s": parity})
+    out = {"metric": "probing-vector solves/sec on the small configurations (GPU and oracle)",
+           "value": None, "unit": "solves/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+           "higher_is_better": True, "data": "synthetic", "dtype": "f64", "configs": rows}
     print(json.dumps(out), flush=True)
 
 
@@ -651,9 +735,10 @@ def main():
     ap.add_argument("--traffic-command", default="", help="command recorded with --traffic-from")
     ap.add_argument("--traffic-kernel", choices=["fp64", "fp32", "fp64_odd", "fp32_odd"], default="fp64",
                     help="--traffic-from: the FP64 or the single-precision dominant kernel of the 32^4 workload")
-    ap.add_argument("--workload", choices=["c5", "c4", "c2h", "compare", "study"], default="c5",
+    ap.add_argument("--workload", choices=["c5", "c4", "c2h", "configs", "compare", "study"], default="c5",
                     help="c5: the 32^4 covariant probing run (default); c4: the batch of 64 uneven 3-D tori; "
-                         "c2h: the scalar stencil's HBM rate on a 256^3 torus; "
+                         "c2h: the scalar stencil's HBM rate on a 256^3 torus; configs: C1, C2, C3 on the GPU "
+                         "and in the oracle; "
                          "compare: hierarchical vs natural-order Hadamard vs Monte-Carlo probes on a 32^3 torus "
                          "with a closed-form trace; study: the experiments of Sec. 5 (stopped levels, three "
                          "lattices and condition numbers, variance over 100 masks)")
@@ -698,6 +783,9 @@ def main():
         return
     if args.workload == "c2h":
         bench_c2h(args)
+        return
+    if args.workload == "configs":
+        bench_configs(args)
         return
 
     t = time.perf_counter()
@@ -818,6 +906,7 @@ def main():
            "config": {"workload": "4D 32^4 covariant Laplacian x3 (Haar U(3) links, m(x)=0.1+0.02clip(xi)), "
                                   f"{args.n_vectors} hierarchical probes x 3 = {n_rhs} CG solves, tol {args.tol:g}",
                       "lattice": DIMS, "n_vectors": args.n_vectors, "rhs_per_step": n_rhs, "tol": args.tol,
+                      "spatial_probes_per_s": round(value / 3, 2),
                       "mask": "Z4", "iters_per_solve": round(iters_per_solve, 2),
                       "solver": "CG on the even-odd reduced system" if main["eo"] else "CG",
                       "max_true_relres": main["max_true_relres"], "repack_ms": round(repack_s * 1e3, 2)},

@@ -72,25 +72,75 @@ __device__ __forceinline__ void store_partials(double (&acc)[N], int B, double* 
   }
 }
 
+// Hierarchical probes on any sides, split like the even-odd passes' probe
+// cache: the part of an entry that depends on the site (P(x) and the colour
+// of the three-colouring level) once per site and step, shared by the site's
+// B lanes through LDS, and the part that depends on the lane (its component,
+// its column through class_probe and probe_column) once per thread.  The
+// entry is then probe_value's, bit for bit.
+struct SiteCode {
+  uint32_t P, c3;
+};
+__device__ __forceinline__ SiteCode site_code(uint32_t s, const Geom& g) {
+  return {hier_perm(s, g), g.has3 ? three_colour(s, g) : 0u};
+}
+struct LaneCode {
+  int cj;                      // component; -1 for a padding lane
+  ProbeCol pc;
+};
+template <int NC>
+__device__ __forceinline__ LaneCode lane_code(const Geom& g, int64_t rhs0, int j, int nb) {
+  LaneCode lc{-1, {0u, 0u, 0u}};
+  if (j < nb) {
+    const int64_t rg = rhs0 + j;
+    lc.cj = (int)(rg % NC);
+    lc.pc = probe_column(class_probe((uint64_t)(rg / NC), g), g);
+  }
+  return lc;
+}
+template <class T, int NC>
+__device__ __forceinline__ void rhs_coded(const SiteCode& sc, const LaneCode& lc, uint32_t s, const Geom& g,
+                                          uint64_t seed, int mask, T (&b)[NC]) {
+#pragma unroll
+  for (int c = 0; c < NC; ++c) b[c] = zero<T>();
+  if (lc.cj < 0) return;
+  const T v = from_c<T>(probe_value_c3(s, sc.P, sc.c3, lc.pc, lc.cj, g, seed, mask));
+#pragma unroll
+  for (int c = 0; c < NC; ++c)
+    if (c == lc.cj) b[c] = v;
+}
+
 }  // namespace
 
 // x = 0 and r = p = b (FP64); mixed: x64 = 0, xh = 0, r = p = single(b).
 template <class T64, class TW, int NC>
 __global__ __launch_bounds__(kBlock) void kb_init(BatchArgs a, T64* __restrict__ x64, TW* __restrict__ xh,
                                                   TW* __restrict__ r, TW* __restrict__ p) {
+  __shared__ SiteCode lds_code[kBlock];
   const uint32_t item = a.item_base + blockIdx.x;
   const BatchJob& J = a.jobs[a.item_job[item]];
-  const BatchProb& P = a.probs[J.prob];
-  const Geom& g = J.g;
+  const BatchProb P = a.probs[J.prob];
+  const Geom g = J.g;
   const int logB = J.logB, B = 1 << logB;
   const int j = threadIdx.x & (B - 1), si = threadIdx.x >> logB;
   const uint32_t s0 = (item - J.item0) * (uint32_t)a.item_sites;
   const uint32_t s1 = min(g.V, s0 + (uint32_t)a.item_sites);
+  const uint32_t TS = (uint32_t)(kBlock >> logB);
+  const bool hier = g.probe == kProbeHierarchical;
+  const LaneCode lc = lane_code<NC>(g, J.rhs0, j, J.nb);
   T64* xj = x64 + J.off;
-  for (uint32_t s = s0 + (uint32_t)si; s < s1; s += (uint32_t)(kBlock >> logB)) {
+  for (uint32_t base = s0; base < s1; base += TS) {
+    const uint32_t s = base + (uint32_t)si;
+    if (hier) {
+      __syncthreads();
+      if (j == 0 && s < s1) lds_code[si] = site_code(s, g);
+      __syncthreads();
+    }
+    if (s >= s1) continue;
     TW b[NC], zw[NC];
     T64 z64[NC];
-    rhs_at<TW, NC>(g, s, J.rhs0, j, J.nb, P.seed, P.mask, b);
+    if (hier) rhs_coded<TW, NC>(lds_code[si], lc, s, g, P.seed, P.mask, b);
+    else rhs_at<TW, NC>(g, s, J.rhs0, j, J.nb, P.seed, P.mask, b);
 #pragma unroll
     for (int c = 0; c < NC; ++c) {
       zw[c] = zero<TW>();
@@ -318,38 +368,50 @@ __global__ __launch_bounds__(kBlock) void kb_true_residual(BatchArgs a, CgScalar
   using T = typename Op::T;
   constexpr int NC = Op::NC;
   __shared__ double lds[3 * 4 * 64];
+  __shared__ SiteCode lds_code[kBlock];
   const uint32_t item = a.item_base + blockIdx.x;
   const BatchJob& J = a.jobs[a.item_job[item]];
-  const BatchProb& P = a.probs[J.prob];
-  const Geom& g = J.g;
   const int logB = J.logB, B = 1 << logB;
   const int j = threadIdx.x & (B - 1), si = threadIdx.x >> logB;
   const bool live = sc.state[J.lane0 + j] == kFrozen;
   if (!__syncthreads_or(live)) return;
+  const Geom g = J.g;                            // in registers (see kb_stencil)
+  const BatchProb P = a.probs[J.prob];
   const Op op = BatchOpOf<Op>::get(P);
   const uint32_t s0 = (item - J.item0) * (uint32_t)a.item_sites;
   const uint32_t s1 = min(g.V, s0 + (uint32_t)a.item_sites);
+  const uint32_t TS = (uint32_t)(kBlock >> logB);
+  const bool hier = g.probe == kProbeHierarchical;
+  const LaneCode lc = lane_code<NC>(g, J.rhs0, j, J.nb);
+  const T* xj = x + J.off;
   double acc[3] = {0.0, 0.0, 0.0};
-  if (live) {
-    const T* xj = x + J.off;
-    const uint32_t step = (uint32_t)(kBlock >> logB);
-    SiteWalk w(s0 + (uint32_t)si, g);
-    auto nbr = [&](int mu, bool fwd) { return w.nbr(mu, fwd, g); };
-    for (; w.s < s1; w.advance(step, g)) {
-      const uint32_t s = w.s;
-      T xs[NC], ax[NC], b[NC], rt[NC];
-      stencil_site_at(op, g, logB, s, j, P.mass_field, P.mass, P.coupling, xj, nbr, xs, ax);
-      rhs_at<T, NC>(g, s, J.rhs0, j, J.nb, P.seed, P.mask, b);
-#pragma unroll
-      for (int c = 0; c < NC; ++c) {
-        rt[c] = axpy(-1.0, ax[c], b[c]);
-        acc[0] += norm2(rt[c]);
-        acc[1] += redot(b[c], xs[c]);
-        acc[2] += imdot(b[c], xs[c]);
-      }
-      store_vec<T, NC>(r + J.off, g.V, logB, s, j, rt);
-      store_vec<T, NC>(p + J.off, g.V, logB, s, j, rt);
+  SiteWalk w(s0 + (uint32_t)si, g);
+  auto nbr = [&](int mu, bool fwd) { return w.nbr(mu, fwd, g); };
+  for (uint32_t base = s0; base < s1; base += TS, w.advance(TS, g)) {
+    const bool in = w.s < s1;
+    if (hier) {
+      __syncthreads();
+      if (j == 0 && in) lds_code[si] = site_code(w.s, g);
+      __syncthreads();
     }
+    if (!live || !in) continue;
+    const uint32_t s = w.s;
+    T xs[NC], ax[NC], b[NC], rt[NC];
+    if constexpr (NC == 1)
+      stencil_site_gather(op, g, logB, s, j, P.mass_field, P.mass, P.coupling, xj, nbr, xs, ax);
+    else
+      stencil_site_at(op, g, logB, s, j, P.mass_field, P.mass, P.coupling, xj, nbr, xs, ax);
+    if (hier) rhs_coded<T, NC>(lds_code[si], lc, s, g, P.seed, P.mask, b);
+    else rhs_at<T, NC>(g, s, J.rhs0, j, J.nb, P.seed, P.mask, b);
+#pragma unroll
+    for (int c = 0; c < NC; ++c) {
+      rt[c] = axpy(-1.0, ax[c], b[c]);
+      acc[0] += norm2(rt[c]);
+      acc[1] += redot(b[c], xs[c]);
+      acc[2] += imdot(b[c], xs[c]);
+    }
+    store_vec<T, NC>(r + J.off, g.V, logB, s, j, rt);
+    store_vec<T, NC>(p + J.off, g.V, logB, s, j, rt);
   }
   store_partials<3>(acc, B, lds, partial, rowstride, a.PI, J.lane0, item - J.item0);
 }
@@ -394,43 +456,56 @@ __global__ __launch_bounds__(kBlock) void kb_ru_residual(BatchArgs a, CgScalars 
   constexpr int NC = Op64::NC;
   if (mode == 0 && *sc.n_ru == 0) return;
   __shared__ double lds[5 * 4 * 64];
+  __shared__ SiteCode lds_code[kBlock];
   const uint32_t item = a.item_base + blockIdx.x;
   const BatchJob& J = a.jobs[a.item_job[item]];
-  const BatchProb& P = a.probs[J.prob];
-  const Geom& g = J.g;
   const int logB = J.logB, B = 1 << logB;
   const int j = threadIdx.x & (B - 1), si = threadIdx.x >> logB;
   const CgScalars sj = job_scalars(sc, J.lane0);
   const bool live = ru_selected(sj, mode, j);
   if (!__syncthreads_or(live)) return;
+  const Geom g = J.g;                            // in registers (see kb_stencil)
+  const BatchProb P = a.probs[J.prob];
   const Op64 op = BatchOpOf<Op64>::get(P);
   const uint32_t s0 = (item - J.item0) * (uint32_t)a.item_sites;
   const uint32_t s1 = min(g.V, s0 + (uint32_t)a.item_sites);
+  const uint32_t TS = (uint32_t)(kBlock >> logB);
+  const bool hier = g.probe == kProbeHierarchical;
+  const LaneCode lc = lane_code<NC>(g, J.rhs0, j, J.nb);
+  const T* xj = x + J.off;
   double acc[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
-  if (live) {
-    const T* xj = x + J.off;
-    const uint32_t step = (uint32_t)(kBlock >> logB);
-    SiteWalk w(s0 + (uint32_t)si, g);
-    auto nbr = [&](int mu, bool fwd) { return w.nbr(mu, fwd, g); };
-    for (; w.s < s1; w.advance(step, g)) {
-      const uint32_t s = w.s;
-      T xs[NC], ax[NC], b[NC];
-      T32 r32[NC];
-      stencil_site_at(op, g, logB, s, j, P.mass_field, P.mass, P.coupling, xj, nbr, xs, ax);
-      rhs_at<T, NC>(g, s, J.rhs0, j, J.nb, P.seed, P.mask, b);
-#pragma unroll
-      for (int c = 0; c < NC; ++c) {
-        const T rt = axpy(-1.0, ax[c], b[c]);
-        acc[0] += norm2(rt);
-        acc[1] += redot(b[c], xs[c]);
-        acc[2] += imdot(b[c], xs[c]);
-        acc[3] += redot(xs[c], rt);
-        acc[4] += imdot(xs[c], rt);
-        r32[c] = to_single(rt);
-      }
-      store_vec<T32, NC>(rh + J.off, g.V, logB, s, j, r32);
-      if (mode == 1) store_vec<T32, NC>(ph + J.off, g.V, logB, s, j, r32);
+  SiteWalk w(s0 + (uint32_t)si, g);
+  auto nbr = [&](int mu, bool fwd) { return w.nbr(mu, fwd, g); };
+  // every thread takes every step (the probe codes are shared through LDS)
+  for (uint32_t base = s0; base < s1; base += TS, w.advance(TS, g)) {
+    const bool in = w.s < s1;
+    if (hier) {
+      __syncthreads();
+      if (j == 0 && in) lds_code[si] = site_code(w.s, g);
+      __syncthreads();
     }
+    if (!live || !in) continue;
+    const uint32_t s = w.s;
+    T xs[NC], ax[NC], b[NC];
+    T32 r32[NC];
+    if constexpr (NC == 1)
+      stencil_site_gather(op, g, logB, s, j, P.mass_field, P.mass, P.coupling, xj, nbr, xs, ax);
+    else
+      stencil_site_at(op, g, logB, s, j, P.mass_field, P.mass, P.coupling, xj, nbr, xs, ax);
+    if (hier) rhs_coded<T, NC>(lds_code[si], lc, s, g, P.seed, P.mask, b);
+    else rhs_at<T, NC>(g, s, J.rhs0, j, J.nb, P.seed, P.mask, b);
+#pragma unroll
+    for (int c = 0; c < NC; ++c) {
+      const T rt = axpy(-1.0, ax[c], b[c]);
+      acc[0] += norm2(rt);
+      acc[1] += redot(b[c], xs[c]);
+      acc[2] += imdot(b[c], xs[c]);
+      acc[3] += redot(xs[c], rt);
+      acc[4] += imdot(xs[c], rt);
+      r32[c] = to_single(rt);
+    }
+    store_vec<T32, NC>(rh + J.off, g.V, logB, s, j, r32);
+    if (mode == 1) store_vec<T32, NC>(ph + J.off, g.V, logB, s, j, r32);
   }
   store_partials<5>(acc, B, lds, partial, rowstride, a.PI, J.lane0, item - J.item0);
 }

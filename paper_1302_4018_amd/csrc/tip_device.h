@@ -261,8 +261,10 @@ __device__ __forceinline__ uint32_t fourier_exponent(uint32_t s, uint64_t m, con
 // (re, im), each exactly 0 or +-1 except the F_3 factor w^k, whose parts are
 // -1/2 and +-(the double nearest sqrt(3)/2).  z0_r takes outputs
 // (r V + s) ncomp + comp of SplitMix64(seed).
-__device__ __forceinline__ double2 probe_value(uint32_t s, uint32_t P, ProbeCol pc, int comp, const Geom& g,
-                                               uint64_t seed, int mask) {
+// c3 is the site's colour of the three-colouring level (three_colour), read
+// only when pc.j3 != 0.
+__device__ __forceinline__ double2 probe_value_c3(uint32_t s, uint32_t P, uint32_t c3, ProbeCol pc, int comp,
+                                                  const Geom& g, uint64_t seed, int mask) {
   const double h = hadamard_sign(P, pc.col);
   double2 v = make_double2(h, 0.0);
   if (mask != kMaskNone) {
@@ -280,13 +282,18 @@ __device__ __forceinline__ double2 probe_value(uint32_t s, uint32_t P, ProbeCol 
     }
   }
   if (pc.j3 != 0u) {
-    const uint32_t k = (three_colour(s, g) * pc.j3) % 3u;
+    const uint32_t k = (c3 * pc.j3) % 3u;
     if (k != 0u) {
       const double wr = -0.5, wi = k == 1u ? 0.8660254037844386 : -0.8660254037844386;
       v = make_double2(v.x * wr - v.y * wi, v.x * wi + v.y * wr);
     }
   }
   return v;
+}
+
+__device__ __forceinline__ double2 probe_value(uint32_t s, uint32_t P, ProbeCol pc, int comp, const Geom& g,
+                                               uint64_t seed, int mask) {
+  return probe_value_c3(s, P, pc.j3 != 0u ? three_colour(s, g) : 0u, pc, comp, g, seed, mask);
 }
 
 // Entry (s, comp) of right-hand side m for the call's probe kind.
