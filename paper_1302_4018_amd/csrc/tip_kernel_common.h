@@ -59,6 +59,24 @@ __device__ __forceinline__ void mul_uh(const C (&u)[9], const C (&x)[3], C (&y)[
   }
 }
 
+// y += U x and y += U^H x, accumulated straight into y (one FMA chain per
+// component, no separate product and add); the single-precision pair hops
+// use them.
+template <class C>
+__device__ __forceinline__ void mul_u_acc(const C (&u)[9], const C (&x)[3], C (&y)[3]) {
+#pragma unroll
+  for (int a = 0; a < 3; ++a)
+#pragma unroll
+    for (int b = 0; b < 3; ++b) y[a] = cfma(u[3 * a + b], x[b], y[a]);
+}
+template <class C>
+__device__ __forceinline__ void mul_uh_acc(const C (&u)[9], const C (&x)[3], C (&y)[3]) {
+#pragma unroll
+  for (int a = 0; a < 3; ++a)
+#pragma unroll
+    for (int b = 0; b < 3; ++b) y[a] = cfma_conj(u[3 * b + a], x[b], y[a]);
+}
+
 template <class C>
 __device__ __forceinline__ void load_link(const CovOp<C>& op, size_t V, int mu, uint32_t s, C (&u)[9]) {
   const C* Um = op.U + (size_t)mu * 9 * V;

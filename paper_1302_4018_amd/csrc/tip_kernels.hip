@@ -1358,7 +1358,8 @@ __global__ __launch_bounds__(kNT) void k_eo_hop_pair(Geom g, MarchMap mm, int P,
   double acc[2] = {0.0, 0.0};
   const uint32_t tau0 = chunk * (uint32_t)mm.Tc;
   T pa[NC], pb[NC];                               // backward t input, carried along the march
-  if (live) load_pair<false, T, NC>(in, Vh, s3 + V3 * ((tau0 + ntau - 1u + delta) % ntau), l, pa, pb);
+  auto ld = [&](uint32_t hh, T (&xa)[NC], T (&xb)[NC]) { load_pair<false, T, NC>(in, Vh, hh, l, xa, xb); };
+  if (live) ld(s3 + V3 * ((tau0 + ntau - 1u + delta) % ntau), pa, pb);
   for (uint32_t tau = tau0; tau < tau0 + (uint32_t)mm.Tc; ++tau) {
     const uint32_t t = 2u * tau + delta;
     const uint32_t s = s3 + V3 * t;
@@ -1390,39 +1391,40 @@ __global__ __launch_bounds__(kNT) void k_eo_hop_pair(Geom g, MarchMap mm, int P,
     for (int c = 0; c < NC; ++c) ha[c] = hb[c] = zero<T>();
     // one hop: y = U x (forward) or U^H x (backward) for both rhs, weighted
     auto hop = [&](int slot, bool fwd, const T (&xa)[NC], const T (&xb)[NC]) {
-      T ya[NC], yb[NC];
-      double wt = 1.0;
       if constexpr (kCov) {
+        // unit weights: the products go straight into the sums
         T u[9];
 #pragma unroll
         for (int e = 0; e < 9; ++e) u[e] = lds_links[(slot * 9 + e) * TS + si];
         if (fwd) {
-          mul_u(u, xa, ya);
-          mul_u(u, xb, yb);
+          mul_u_acc(u, xa, ha);
+          mul_u_acc(u, xb, hb);
         } else {
-          mul_uh(u, xa, ya);
-          mul_uh(u, xb, yb);
+          mul_uh_acc(u, xa, ha);
+          mul_uh_acc(u, xb, hb);
         }
       } else {
+        double wt = 1.0;
         if (w) wt = lds_w[slot * TS + si];
+        T ya[NC], yb[NC];
         ya[0] = xa[0];
         yb[0] = xb[0];
+        add_weighted<T, NC>(wt, ya, ha);
+        add_weighted<T, NC>(wt, yb, hb);
       }
-      add_weighted<T, NC>(wt, ya, ha);
-      add_weighted<T, NC>(wt, yb, hb);
     };
 #pragma unroll
     for (int mu = 0; mu < kMaxDim - 1; ++mu) {
       if (mu >= tdim) break;
       T xa[NC], xb[NC];
-      load_pair<false, T, NC>(in, Vh, nbr_fwd_p2(s3, g, mu) + V3 * tau, l, xa, xb);
+      ld(nbr_fwd_p2(s3, g, mu) + V3 * tau, xa, xb);
       hop(mu, true, xa, xb);
-      load_pair<false, T, NC>(in, Vh, nbr_bwd_p2(s3, g, mu) + V3 * tau, l, xa, xb);
+      ld(nbr_bwd_p2(s3, g, mu) + V3 * tau, xa, xb);
       hop(ndim + mu, false, xa, xb);
     }
     {
       T xa[NC], xb[NC];
-      load_pair<false, T, NC>(in, Vh, s3 + V3 * ((tau + delta) % ntau), l, xa, xb);
+      ld(s3 + V3 * ((tau + delta) % ntau), xa, xb);
       hop(tdim, true, xa, xb);
       hop(ndim + tdim, false, pa, pb);
 #pragma unroll

@@ -122,3 +122,33 @@ def test_uneven_tori_batch_first_probes_against_oracle(precision):
     for i, t in enumerate(tori):
         est_o = estimates_from_quadratures(golden[f"torus{i}"])
         assert np.max(np.abs(out[i][0][:3] - est_o) / np.abs(est_o)) <= REL, (i, t["dims"])
+
+
+@pytest.mark.parametrize("probe,precision", [(general.PROBE_NATURAL, "fp64"), (general.PROBE_RANDOM, "fp64"),
+                                             (general.PROBE_RANDOM, "mixed")])
+def test_batch_comparison_probe_kinds_against_oracle(probe, precision):
+    """The batch with the comparison probes of Sec. 5 (natural-order Hadamard,
+    plain Monte Carlo), whose right-hand sides the batch kernels regenerate
+    per lane rather than from per-site probe codes: every torus against the
+    oracle, scalar and covariant; odd sides with the random probes (natural
+    order takes power-of-two sides)."""
+    tip = gpu_binding()
+    if probe == general.PROBE_NATURAL:
+        cases = [([16, 16], 0, 0.2, 24), ([8, 4, 8], 1, 0.15, 6), ([8, 8, 8], 0, 0.1, 32), ([4, 4, 4, 8], 1, 0.2, 5)]
+    else:
+        cases = [([6, 10], 0, 0.2, 24), ([8, 4, 8], 1, 0.15, 6), ([16, 16], 0, 0.1, 32), ([5, 9, 7], 0, 0.2, 12)]
+    gops, orcs, ns = [], [], []
+    for k, (dims, kind, m, n) in enumerate(cases):
+        w = inputs.couplings(dims, seed=720 + k)
+        U = inputs.haar_links(dims, seed=730 + k) if kind == 1 else None
+        orcs.append(OracleOp(dims, kind, mass=m, coupling=w, links=U))
+        gops.append(tip.Operator(dims, kind, mass=m, coupling=to_dev(w), links=to_dev(U)))
+        ns.append(n)
+    prec = tip.PREC_MIXED if precision == "mixed" else tip.PREC_FP64
+    print(f"batch with probe kind {probe}, {precision}", flush=True)
+    out = tip.trace_inv_probe_batch(gops, ns, 1e-12, 31, mask=MASK_Z4, precision=prec, probe=probe)
+    for i, (est, st) in enumerate(out):
+        assert st["status"] == 0, i
+        est_o, q_o, _ = general.trace_inv_probe(orcs[i], ns[i], 1e-12, 31, MASK_Z4, probe=probe)
+        assert np.max(np.abs(est - est_o) / np.abs(est_o)) <= REL, (probe, i)
+        assert np.max(np.abs(st["quadratures"] - q_o) / np.abs(q_o)) <= REL, (probe, i)
