@@ -31,8 +31,10 @@ sys.path.insert(0, ROOT)
 DIMS = [32, 32, 32, 32]
 HBM_PEAK_GBS = 8000.0
 METRIC = "probing-vector solves/sec (4D 32^4, rel.res 1e-10) + stencil HBM GB/s vs peak"
+# the kernels and the host code that picks their launch shapes and tile order
 KERNEL_SOURCES = ["paper_1302_4018_amd/csrc/tip_kernels.hip", "paper_1302_4018_amd/csrc/tip_device.h",
-                  "paper_1302_4018_amd/csrc/tip_launch.h", "paper_1302_4018_amd/csrc/tip_kernel_common.h"]
+                  "paper_1302_4018_amd/csrc/tip_launch.h", "paper_1302_4018_amd/csrc/tip_kernel_common.h",
+                  "paper_1302_4018_amd/csrc/tip_api.hip"]
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "stencil_traffic.json")
 # the dominant kernel: with the even-odd reduction, the half-lattice stencil
 # that forms S p (in FP64 in 512-thread workgroups unless TIP_EO_WIDE=0, in

@@ -358,22 +358,24 @@ bool env_on(const char* name) {
 }
 
 // Parameters of tile order 2 (see march_tile) for a 4-D lattice marched
-// along x4: split the (x2, x3) rows over the 8 XCDs into regions as square as
-// the sides allow, then pick the round (b2 x b3 rows of n1/TS tiles each) of at
-// most `round_tiles` tiles that leaves the fewest x2 / x3 neighbour rows
-// outside it.  TIP_MARCH_ORDER="g2,b2,b3" overrides the choice.
+// along x4: split the (x2, x3) rows over the 8 XCDs into slabs as thin along x2
+// (and so as long along x3) as the sides allow, then pick the round (b2 x b3
+// rows of n1/TS tiles each) of at most `round_tiles` tiles that leaves the
+// fewest x2 / x3 neighbour rows outside it.  Measured at 32^4 (FP64 / mixed
+// solves/s, one box): slabs of 4 x 32 rows with rounds of 4 x 16 rows 951-953 /
+// 1492 against 940-941 / 1479 for the squarest regions (8 x 16 rows, rounds of
+// 8 x 8), and 902-920 for regions of 16 x 8 rows.  TIP_MARCH_ORDER="g2,b2,b3"
+// overrides the choice.
 bool plan_block_order(const Geom& g, int TS, MarchMap* mm, int round_tiles) {
   const int n1 = 1 << g.logn[0], n2 = 1 << g.logn[1], n3 = 1 << g.logn[2];
   if (TS > n1 || n1 % TS != 0) return false;
   const int n1t = n1 / TS;
   if (const char* e = std::getenv("TIP_ROUND_TILES")) round_tiles = std::max(1, std::atoi(e));   // experiments
   int best_g2 = -1;
-  double best_shape = 1e30;
   for (int g2 = 1; g2 <= kNumXcd; g2 *= 2) {
     const int g3 = kNumXcd / g2;
     if (g2 > n2 || g3 > n3) continue;
-    const double shape = std::fabs(std::log2((double)(n2 / g2) / (double)(n3 / g3)));
-    if (shape <= best_shape) best_shape = shape, best_g2 = g2;   // ties: longer regions along x3
+    best_g2 = g2;                                   // the largest split of x2 that fits
   }
   if (best_g2 < 0) return false;
   int g2 = best_g2, b2 = 0, b3 = 0;
