@@ -8,8 +8,9 @@ relative residual of 1e-10 (FP64).  One step is one trace_inv_probe call over
 all 768 right-hand sides, with the operator already resident on the GPU.
 The headline value is the FP64 solver; the mixed-precision solver (FP32 CG,
 FP64 reliable updates, same FP64 true-residual acceptance) is timed beside
-it and reported under "mixed_precision", and the same run with the gradient
-of the last estimate (dT/dm and dT/dw, FP64) under "gradient".
+it and reported under "mixed_precision", the same run with the gradient
+of the last estimate (dT/dm and dT/dw, FP64) under "gradient", and the
+batched solver on 64 uneven 3-D tori under "batch_c4".
 
 Prints one JSON line: solves/s, the stencil kernel's achieved HBM bandwidth
 against the MI355X peak (hipEvent timing of every stencil launch inside the
@@ -258,7 +259,7 @@ def copy_calibration():
     log(f"copy calibration: 3 copies of {n * 8} bytes")
 
 
-def bench_c4(args):
+def bench_c4(args, emit=True):
     """The batch of 64 independent uneven 3-D tori (sides iid in [8, 48], scalar
     weighted Laplacian with m ~ U[0.02, 0.2], w ~ U[0.5, 1.5], Z2 mask, 16..256
     probes each) in one trace_inv_probe_batch call per step: every CG phase of
@@ -266,7 +267,8 @@ def bench_c4(args):
     chunk of iterations of the whole batch is one HIP graph.  FP32 CG with
     FP64 reliable updates (the headline of this line) and FP64 beside it.  The
     block size and work-item size come from tip_autotune_batch (cached).  The
-    stencil roofline comes from one extra step with per-launch timing."""
+    stencil roofline comes from one extra step with per-launch timing.
+    Prints one JSON line (emit) or returns it."""
     import torch
 
     from paper_1302_4018_amd import autotune
@@ -338,7 +340,9 @@ def bench_c4(args):
            "fp64": {"value": round(res["fp64"][0], 2), "ms_per_step": round(res["fp64"][1] / args.steps * 1e3, 2),
                     "iters_per_solve": round(res["fp64"][2]["iters"] / res["fp64"][2]["solves"], 2),
                     "tuning": res["fp64"][4], "roofline": roof(res["fp64"][3])}}
-    print(json.dumps(out), flush=True)
+    if emit:
+        print(json.dumps(out), flush=True)
+    return out
 
 
 def bench_c4_sequential(args, tip, ops, ns):
@@ -726,6 +730,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-one-core", action="store_true", help="time the oracle on one host thread only")
     ap.add_argument("--copy-calibration", action="store_true")
+    ap.add_argument("--no-batch", action="store_true",
+                    help="skip the batch of 64 uneven 3-D tori that the default line reports under batch_c4")
     ap.add_argument("--no-gradient", action="store_true",
                     help="skip the leg that times the estimate together with dT/dm and dT/dw")
     ap.add_argument("--precision", choices=["both", "fp64", "mixed"], default="both",
@@ -869,6 +875,15 @@ def main():
     res = {pr: timed(pr) for pr in precisions}
     grad = None if args.no_gradient else timed_gradient(handle, args, n_rhs, res[precisions[0]])
     handle.close()
+    batch = None
+    if not args.no_batch:
+        # the batched solver on the 64 uneven 3-D tori, beside the 32^4 line
+        c4 = bench_c4(args, emit=False)
+        batch = {"metric": c4["metric"], "value": c4["value"], "unit": c4["unit"], "ms_per_step": c4["ms_per_step"],
+                 "dtype": c4["dtype"], "workload": c4["config"]["workload"], "tuning": c4["config"]["tuning"],
+                 "iters_per_solve": c4["config"]["iters_per_solve"], "max_true_relres": c4["config"]["max_true_relres"],
+                 "fp64": {"value": c4["fp64"]["value"], "ms_per_step": c4["fp64"]["ms_per_step"]},
+                 "roofline": c4["roofline"]}
     ceiling = practical_ceiling(tip)
     log(f"practical HBM ceiling: {ceiling}")
     for r in res.values():
@@ -912,7 +927,8 @@ def main():
                       "mask": "Z4", "iters_per_solve": round(iters_per_solve, 2),
                       "solver": "CG on the even-odd reduced system" if main["eo"] else "CG",
                       "max_true_relres": main["max_true_relres"], "repack_ms": round(repack_s * 1e3, 2)},
-           "roofline": roofline, "cpu_baseline": cpu, "mixed_precision": mixed, "gradient": grad}
+           "roofline": roofline, "cpu_baseline": cpu, "mixed_precision": mixed, "gradient": grad,
+           "batch_c4": batch}
     print(json.dumps(out), flush=True)
 
 
