@@ -288,7 +288,12 @@ def bench_c4(args, emit=True):
     res = {}
     for name, prec in (("mixed", tip.PREC_MIXED), ("fp64", tip.PREC_FP64)):
         kw = {}
-        if not args.no_autotune:
+        if args.no_autotune:
+            if args.rhs_block > 0:
+                kw["rhs_block"] = args.rhs_block
+            if args.item_sites > 0:
+                kw["item_sites"] = args.item_sites
+        else:
             t0 = time.perf_counter()
             kw = autotune.tuned_batch(ops, ns, args.tol, args.seed, mask=tip.MASK_Z2, precision=prec)
             log(f"[c4 {name}] tuning {kw} ({time.perf_counter() - t0:.1f} s)")
@@ -725,6 +730,8 @@ def main():
     ap.add_argument("--n-vectors", type=int, default=256)
     ap.add_argument("--tol", type=float, default=1e-10)
     ap.add_argument("--rhs-block", type=int, default=0)
+    ap.add_argument("--item-sites", type=int, default=0,
+                    help="c4 with --no-autotune: sites per work item of the batched solver (0 = library default)")
     ap.add_argument("--seed", type=int, default=4018)
     ap.add_argument("--cpu-solves", type=int, default=3, help="right-hand sides the CPU oracle solves")
     ap.add_argument("--no-cpu-baseline", action="store_true")

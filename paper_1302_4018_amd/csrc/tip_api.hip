@@ -1547,12 +1547,14 @@ tip_status run_batch(const tip_operator* ops, const tip_params* params, int32_t 
   size_t PI = 1;
   for (size_t oi = 0; oi < order.size();) {
     const BatchClass& c0 = classes[(size_t)order[oi]];
-    BatchGroup gr{hs[(size_t)c0.prob]->kind, c0.elem, c0.prec, (uint32_t)item_job.size(), 0, (int)lane_job.size(), 0};
+    BatchGroup gr{hs[(size_t)c0.prob]->kind, c0.elem, c0.prec, (uint32_t)item_job.size(), 0, (int)lane_job.size(), 0,
+                  hs[(size_t)c0.prob]->geom.ndim};
     uint64_t off = 0;
     for (; oi < order.size() && key(classes[(size_t)order[oi]]) == key(c0); ++oi) {
       const BatchClass& c = classes[(size_t)order[oi]];
       const tip_op_s* h = hs[(size_t)c.prob].get();
       const tip_params& p = params[c.prob];
+      if (h->geom.ndim != gr.ndim) gr.ndim = 0;
       Geom gj = h->geom;
       gj.probe = p.probe;
       gj.stop = p.stop_levels;

@@ -62,6 +62,7 @@ struct BatchGroup {
   Prec prec;
   uint32_t item_base, nitems;
   int lane_base, nlanes;
+  int ndim;                    // the dimension every job of the group has, or 0 when they differ
 };
 
 hipError_t launch_batch_scalars_init(const BatchArgs& a, const CgScalars& sc, int nlanes, hipStream_t st);

@@ -188,9 +188,186 @@ struct MarchOrder {
   }
 };
 
+// A site of a D-dimensional lattice with its coordinates (D known at
+// compile time: the coordinate and neighbour arithmetic stays in registers
+// with no per-dimension branch).
+template <int D>
+struct WalkD {
+  uint32_t s;
+  uint32_t x[D];
+  __device__ __forceinline__ void set(uint32_t s0, const Geom& g) {
+    s = s0;
+#pragma unroll
+    for (int mu = 0; mu < D; ++mu) x[mu] = (s0 / g.stride[mu]) % g.n[mu];
+  }
+  // s += d (d >= 0) within the plane of the first D - 1 coordinates, with
+  // the carries; the last coordinate is left alone (s stays below the plane)
+  __device__ __forceinline__ void advance_plane(uint32_t d, const Geom& g) {
+    s += d;
+    uint32_t carry = d;
+#pragma unroll
+    for (int mu = 0; mu + 1 < D; ++mu) {
+      uint32_t v = x[mu] + carry;
+      const uint32_t n = g.n[mu];
+      carry = 0u;
+      if (v >= n) {
+        if (v < 2u * n) {
+          v -= n;
+          carry = 1u;
+        } else {
+          carry = v / n;
+          v -= carry * n;
+        }
+      }
+      x[mu] = v;
+    }
+  }
+  __device__ __forceinline__ uint32_t fwd(int mu, const Geom& g) const {
+    return x[mu] == g.n[mu] - 1u ? s - (g.n[mu] - 1u) * g.stride[mu] : s + g.stride[mu];
+  }
+  __device__ __forceinline__ uint32_t bwd(int mu, const Geom& g) const {
+    return x[mu] == 0u ? s + (g.n[mu] - 1u) * g.stride[mu] : s - g.stride[mu];
+  }
+};
+
+// The march of kb_stencil for the scalar operators on a D-dimensional job.
+//
+// A site needs 2D + 1 scalars besides its vector entries: the couplings
+// w_mu(x) and w_mu(x - e_mu) and the mass m(x).  Read by every lane of the
+// site, each would cost the address unit as much as a vector entry while
+// carrying 8 bytes for B lanes; here lane k of the site's B lanes reads value
+// k (lanes k, k + B, ... when B < 2D + 1) and the site's lanes take them from
+// LDS.  The B lanes of a site sit in one wave, so the exchange needs only a
+// wave-level barrier.  Along the march a thread also keeps p at its site and
+// at its forward t-neighbour, which are the next step's backward neighbour
+// and site: a step in the middle of a column loads 2D - 1 vector entries
+// instead of 2D + 1.  The arithmetic is stencil_site_gather's, in the same
+// order, so w is the same bit for bit.
+constexpr int kScalarSiteStride = 10;         // LDS doubles per site: 2 kMaxDim + 1, rounded up to pairs
+static_assert(kScalarSiteStride >= ((2 * kMaxDim + 2) & ~1), "LDS stride of the scalar march");
+
+template <class Op, int D>
+__device__ __forceinline__ void march_scalar(const Geom& g, const BatchProb& P, int logB, int j, int si, bool live,
+                                             uint32_t o0, uint32_t o1, const typename Op::T* __restrict__ inj,
+                                             typename Op::T* __restrict__ outj, double* __restrict__ lds_site,
+                                             double& dot) {
+  using T = typename Op::T;
+  constexpr int NV = 2 * D + 1;
+  constexpr int NVS = (NV + 1) & ~1;                 // per-site LDS stride: pairs stay 16-byte aligned
+  const int B = 1 << logB;
+  const size_t V = g.V;
+  const double* __restrict__ w = P.coupling;
+  const double* __restrict__ mf = P.mass_field;
+  double* my = lds_site + si * NVS;
+  const uint32_t TS = (uint32_t)(kBlock >> logB);
+  const uint32_t nt = g.n[D - 1], Vp = g.stride[D - 1];
+  const uint32_t full = Vp & ~(TS - 1u), F = full * nt, wl = Vp - full;
+  uint32_t o = o0 + (uint32_t)si, t;
+  auto site_of = [&](uint32_t oo, uint32_t& tt) -> uint32_t {
+    if (oo < F) {
+      const uint32_t c = oo / (TS * nt), rem = oo - c * TS * nt;
+      tt = rem >> (8 - logB);
+      return c * TS + (rem & (TS - 1u)) + Vp * tt;
+    }
+    const uint32_t r = oo - F;
+    tt = r / wl;
+    return full + (r - tt * wl) + Vp * tt;
+  };
+  WalkD<D> wk;
+  wk.set(site_of(o, t), g);
+  bool carry = false;
+  T xs = zero<T>(), xft = zero<T>();
+  while (o < o1) {
+    const uint32_t s = wk.s;
+    uint32_t sb[D];
+    T xf[D], xb[D];
+#pragma unroll
+    for (int mu = 0; mu < D; ++mu) sb[mu] = wk.bwd(mu, g);
+    if (live) {                                // lanes whose solve has stopped load and store nothing
+#pragma unroll
+      for (int mu = 0; mu + 1 < D; ++mu) {
+        xf[mu] = inj[((size_t)wk.fwd(mu, g) << logB) + j];
+        xb[mu] = inj[((size_t)sb[mu] << logB) + j];
+      }
+      xf[D - 1] = inj[((size_t)wk.fwd(D - 1, g) << logB) + j];
+      if (carry) {
+        xb[D - 1] = xs;
+        xs = xft;
+      } else {
+        xb[D - 1] = inj[((size_t)sb[D - 1] << logB) + j];
+        xs = inj[((size_t)s << logB) + j];
+      }
+      xft = xf[D - 1];
+    }
+    for (int k = j; k < NV; k += B) {          // every lane of the site takes part
+      double v;
+      if (k < 2 * D) {
+        uint32_t sk = s;
+        int mk = k;
+#pragma unroll
+        for (int mu = 0; mu < D; ++mu)
+          if (k == D + mu) {
+            sk = sb[mu];
+            mk = mu;
+          }
+        v = w ? w[(size_t)mk * V + sk] : 1.0;
+      } else {
+        v = mf ? mf[s] : P.mass;
+      }
+      my[k] = v;
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    if (live) {
+      double diag = my[2 * D];
+      T hop = zero<T>();
+#pragma unroll
+      for (int mu = 0; mu < D; ++mu) {
+        const double wf = my[mu], wb = my[D + mu];
+        diag += wf + wb;
+        hop = axpy(wf, xf[mu], hop);
+        hop = axpy(wb, xb[mu], hop);
+      }
+      const T y = axpy(diag, xs, axpy(-1.0, hop, zero<T>()));
+      outj[((size_t)s << logB) + j] = y;
+      dot += redot(xs, y);
+    }
+    // every lane has read the site's values before the next step writes them
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    o += TS;
+    if (o >= o1) break;
+    if (o < F) {
+      if (t + 1u < nt) {                       // next slice of the column: p there was loaded as xf[D - 1]
+        ++t;
+        wk.s += Vp;
+        wk.x[D - 1] = t;
+        carry = true;
+      } else {                                 // first slice of the next column
+        t = 0u;
+        wk.s -= Vp * (nt - 1u);
+        wk.x[D - 1] = 0u;
+        wk.advance_plane(TS, g);
+        carry = false;
+      }
+    } else {
+      wk.set(site_of(o, t), g);                // the last, narrower column
+      carry = false;
+    }
+  }
+}
+
 // w = A p for the live lanes, partial p^H w per lane (per work item of
 // item_sites march indices).
-template <class Op>
+//
+// D > 0 (scalar operators, every job of the launch D-dimensional): the march
+// of march_scalar.  D = 0: any dimension, every lane loading its site's
+// values itself (stencil_site_gather; the covariant operator keeps the plain
+// form, which needs about half the registers).  One kernel for all D would
+// hold every D's registers: 80-108 VGPRs against 60-84 for D = 3 alone.
+template <class Op, int D>
 __global__ __launch_bounds__(kBlock) void kb_stencil(BatchArgs a, CgScalars sc, const typename Op::T* __restrict__ in,
                                                      typename Op::T* __restrict__ out, double* __restrict__ partial) {
   using T = typename Op::T;
@@ -216,7 +393,11 @@ __global__ __launch_bounds__(kBlock) void kb_stencil(BatchArgs a, CgScalars sc, 
   const T* inj = in + J.off;
   T* outj = out + J.off;
   double dot[1] = {0.0};
-  if (live) {
+  if constexpr (NC == 1 && D > 0) {
+    (void)op;
+    __shared__ __align__(16) double lds_site[kBlock * kScalarSiteStride];
+    march_scalar<Op, D>(g, P, logB, j, si, live, o0, o1, inj, outj, lds_site, dot[0]);
+  } else if (live) {
     const uint32_t TS = (uint32_t)(kBlock >> logB);
     const MarchOrder mo(g, TS);
     const int last = g.ndim - 1;
@@ -225,8 +406,6 @@ __global__ __launch_bounds__(kBlock) void kb_stencil(BatchArgs a, CgScalars sc, 
     auto nbr = [&](int mu, bool fwd) { return w.nbr(mu, fwd, g); };
     while (o < o1) {
       T xs[NC], y[NC];
-      // scalar operators: every load of the site first (the covariant one
-      // would need about twice the registers that way and keeps the plain form)
       if constexpr (NC == 1)
         stencil_site_gather(op, g, logB, w.s, j, P.mass_field, P.mass, P.coupling, inj, nbr, xs, y);
       else
@@ -677,7 +856,20 @@ hipError_t launch_batch_iteration(const BatchArgs& a, const BatchGroup& gr, cons
     using Op = decltype(op);
     using T = typename Op::T;
     if (ev0) (void)hipEventRecord(ev0, st);
-    kb_stencil<Op><<<gr.nitems, kBlock, 0, st>>>(a, sc, (const T*)p, (T*)w, partial);
+    auto stencil = [&](auto dim) {
+      kb_stencil<Op, decltype(dim)::value><<<gr.nitems, kBlock, 0, st>>>(a, sc, (const T*)p, (T*)w, partial);
+    };
+    if constexpr (Op::NC == 1) {
+      switch (gr.ndim) {
+        case 1: stencil(std::integral_constant<int, 1>{}); break;
+        case 2: stencil(std::integral_constant<int, 2>{}); break;
+        case 3: stencil(std::integral_constant<int, 3>{}); break;
+        case 4: stencil(std::integral_constant<int, 4>{}); break;
+        default: stencil(std::integral_constant<int, 0>{}); break;
+      }
+    } else {
+      stencil(std::integral_constant<int, 0>{});
+    }
     if (ev1) (void)hipEventRecord(ev1, st);
     kb_reduce_alpha<<<lane_grid(gr), kBlock, 0, st>>>(a, sc, gr.lane_base, gr.nlanes, partial,
                                                          gr.prec == Prec::kF32 ? 1 : 0);
