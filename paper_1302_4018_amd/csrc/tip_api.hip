@@ -1668,6 +1668,11 @@ tip_status run_batch(const tip_operator* ops, const tip_params* params, int32_t 
     args.lane_job = (const int32_t*)(tb + t_lanes);
     args.item_sites = item_sites;
     args.PI = PI;
+    // kb_stencil: slices in bands of item_sites / TS and each job's items in
+    // one contiguous part per XCD; together they halve the stencil's fetched
+    // bytes on the 64 uneven tori (its time falls by about 2%)
+    args.march = 3;
+    if (const char* e = std::getenv("TIP_BATCH_MARCH")) args.march = std::atoi(e) & 3;   // experiments
     args.bytes = g_profiling ? (unsigned long long*)(tb + t_bytes) : nullptr;
     CgScalars sc{};
     double* d = (double*)scal.p;

@@ -51,6 +51,7 @@ struct BatchArgs {
   uint32_t item_base;          // first item of the launch's group
   int32_t item_sites;          // sites per work item (a power of two >= 256)
   size_t PI;                   // partials per lane row (the most items of any job)
+  int32_t march;               // kb_stencil: bit 0 slices in bands of item_sites / TS, bit 1 job items split per XCD
   unsigned long long* bytes;   // when profiling: algorithmic bytes the stencil launches moved, or null
 };
 

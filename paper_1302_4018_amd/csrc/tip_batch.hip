@@ -188,6 +188,16 @@ struct MarchOrder {
   }
 };
 
+// Work item of a job of n items taken by the job's bl-th workgroup when the
+// items are dealt to the 8 XCDs in contiguous parts: workgroups go round
+// robin to the XCDs, so those with the same bl mod 8 share one XCD, and that
+// XCD gets the part x = bl mod 8 of the job's items (parts of n / 8 or
+// n / 8 + 1 items), in order.  A bijection of [0, n).
+__device__ __forceinline__ uint32_t xcd_part(uint32_t bl, uint32_t n) {
+  const uint32_t x = bl & 7u, k = bl >> 3, q = n >> 3, r = n & 7u;
+  return x * q + min(x, r) + k;
+}
+
 // A site of a D-dimensional lattice with its coordinates (D known at
 // compile time: the coordinate and neighbour arithmetic stays in registers
 // with no per-dimension branch).
@@ -243,14 +253,21 @@ struct WalkD {
 // and site: a step in the middle of a column loads 2D - 1 vector entries
 // instead of 2D + 1.  The arithmetic is stencil_site_gather's, in the same
 // order, so w is the same bit for bit.
+//
+// The march order is MarchOrder's with the slices cut into bands of L (the
+// last band shorter): the march runs through band h's columns (each marched
+// through the band's Lh slices), then its narrower last column, then band h +
+// 1.  With L = item_sites / TS a whole column of a band is one work item's
+// worth, so consecutive items march neighbouring columns through the same
+// slices; with L = nt it is MarchOrder's order.
 constexpr int kScalarSiteStride = 10;         // LDS doubles per site: 2 kMaxDim + 1, rounded up to pairs
 static_assert(kScalarSiteStride >= ((2 * kMaxDim + 2) & ~1), "LDS stride of the scalar march");
 
 template <class Op, int D>
 __device__ __forceinline__ void march_scalar(const Geom& g, const BatchProb& P, int logB, int j, int si, bool live,
-                                             uint32_t o0, uint32_t o1, const typename Op::T* __restrict__ inj,
-                                             typename Op::T* __restrict__ outj, double* __restrict__ lds_site,
-                                             double& dot) {
+                                             uint32_t L, uint32_t o0, uint32_t o1,
+                                             const typename Op::T* __restrict__ inj, typename Op::T* __restrict__ outj,
+                                             double* __restrict__ lds_site, double& dot) {
   using T = typename Op::T;
   constexpr int NV = 2 * D + 1;
   constexpr int NVS = (NV + 1) & ~1;                 // per-site LDS stride: pairs stay 16-byte aligned
@@ -261,20 +278,27 @@ __device__ __forceinline__ void march_scalar(const Geom& g, const BatchProb& P, 
   double* my = lds_site + si * NVS;
   const uint32_t TS = (uint32_t)(kBlock >> logB);
   const uint32_t nt = g.n[D - 1], Vp = g.stride[D - 1];
-  const uint32_t full = Vp & ~(TS - 1u), F = full * nt, wl = Vp - full;
-  uint32_t o = o0 + (uint32_t)si, t;
-  auto site_of = [&](uint32_t oo, uint32_t& tt) -> uint32_t {
-    if (oo < F) {
-      const uint32_t c = oo / (TS * nt), rem = oo - c * TS * nt;
-      tt = rem >> (8 - logB);
-      return c * TS + (rem & (TS - 1u)) + Vp * tt;
+  const uint32_t full = Vp & ~(TS - 1u), wl = Vp - full;
+  // position in the march: band of slices [t0, t0 + Lh), slice tb within it;
+  // the band's whole columns end at march index Fb
+  uint32_t o = o0 + (uint32_t)si, t0 = 0u, Lh = 1u, tb = 0u, Fb = 0u;
+  auto site_of = [&](uint32_t oo) -> uint32_t {
+    const uint32_t h = oo / (Vp * L);
+    t0 = h * L;
+    Lh = min(L, nt - t0);
+    const uint32_t ob = oo - t0 * Vp;
+    Fb = oo - ob + full * Lh;
+    if (oo < Fb) {
+      const uint32_t c = ob / (TS * Lh), rem = ob - c * TS * Lh;
+      tb = rem >> (8 - logB);
+      return c * TS + (rem & (TS - 1u)) + Vp * (t0 + tb);
     }
-    const uint32_t r = oo - F;
-    tt = r / wl;
-    return full + (r - tt * wl) + Vp * tt;
+    const uint32_t r = oo - Fb;
+    tb = r / wl;
+    return full + (r - tb * wl) + Vp * (t0 + tb);
   };
   WalkD<D> wk;
-  wk.set(site_of(o, t), g);
+  wk.set(site_of(o), g);
   bool carry = false;
   T xs = zero<T>(), xft = zero<T>();
   while (o < o1) {
@@ -339,21 +363,21 @@ __device__ __forceinline__ void march_scalar(const Geom& g, const BatchProb& P, 
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
     o += TS;
     if (o >= o1) break;
-    if (o < F) {
-      if (t + 1u < nt) {                       // next slice of the column: p there was loaded as xf[D - 1]
-        ++t;
+    if (o < Fb) {
+      if (tb + 1u < Lh) {                      // next slice of the column: p there was loaded as xf[D - 1]
+        ++tb;
         wk.s += Vp;
-        wk.x[D - 1] = t;
+        wk.x[D - 1] = t0 + tb;
         carry = true;
-      } else {                                 // first slice of the next column
-        t = 0u;
-        wk.s -= Vp * (nt - 1u);
-        wk.x[D - 1] = 0u;
+      } else {                                 // first slice of the band in the next column
+        tb = 0u;
+        wk.s -= Vp * (Lh - 1u);
+        wk.x[D - 1] = t0;
         wk.advance_plane(TS, g);
         carry = false;
       }
     } else {
-      wk.set(site_of(o, t), g);                // the last, narrower column
+      wk.set(site_of(o), g);                   // the band's narrower last column, or the next band
       carry = false;
     }
   }
@@ -386,7 +410,8 @@ __global__ __launch_bounds__(kBlock) void kb_stencil(BatchArgs a, CgScalars sc, 
   const int nlive = __syncthreads_count(live && si == 0);
   if (nlive == 0) return;
   const Op op = BatchOpOf<Op>::get(P);
-  const uint32_t o0 = (item - J.item0) * (uint32_t)a.item_sites;
+  const uint32_t local = (a.march & 2) ? xcd_part(item - J.item0, J.nitems) : item - J.item0;
+  const uint32_t o0 = local * (uint32_t)a.item_sites;
   const uint32_t o1 = min(g.V, o0 + (uint32_t)a.item_sites);
   if (a.bytes && threadIdx.x == 0)   // each link, coupling and mass read once, p read and w written per live rhs
     atomicAdd(a.bytes, (unsigned long long)(o1 - o0) * (J.site_bytes + 2ull * (unsigned)NC * (unsigned)nlive * J.esz));
@@ -396,7 +421,8 @@ __global__ __launch_bounds__(kBlock) void kb_stencil(BatchArgs a, CgScalars sc, 
   if constexpr (NC == 1 && D > 0) {
     (void)op;
     __shared__ __align__(16) double lds_site[kBlock * kScalarSiteStride];
-    march_scalar<Op, D>(g, P, logB, j, si, live, o0, o1, inj, outj, lds_site, dot[0]);
+    const uint32_t L = (a.march & 1) ? (uint32_t)a.item_sites >> (8 - logB) : g.n[D - 1];
+    march_scalar<Op, D>(g, P, logB, j, si, live, L, o0, o1, inj, outj, lds_site, dot[0]);
   } else if (live) {
     const uint32_t TS = (uint32_t)(kBlock >> logB);
     const MarchOrder mo(g, TS);
@@ -434,7 +460,7 @@ __global__ __launch_bounds__(kBlock) void kb_stencil(BatchArgs a, CgScalars sc, 
       }
     }
   }
-  store_partials<1>(dot, B, lds, partial, 0, a.PI, J.lane0, item - J.item0);
+  store_partials<1>(dot, B, lds, partial, 0, a.PI, J.lane0, local);
 }
 
 // r -= alpha w for the live lanes, partial ||r||^2.

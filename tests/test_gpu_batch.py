@@ -152,3 +152,37 @@ def test_batch_comparison_probe_kinds_against_oracle(probe, precision):
         est_o, q_o, _ = general.trace_inv_probe(orcs[i], ns[i], 1e-12, 31, MASK_Z4, probe=probe)
         assert np.max(np.abs(est - est_o) / np.abs(est_o)) <= REL, (probe, i)
         assert np.max(np.abs(st["quadratures"] - q_o) / np.abs(q_o)) <= REL, (probe, i)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+@pytest.mark.parametrize("ndim", [1, 2, 4])
+def test_batch_stencil_per_dimension(ndim, precision):
+    """Batches whose scalar problems all have the same dimension run the
+    stencil compiled for that dimension (lane k of a site reads the site's
+    coupling or mass k for the site's lanes): odd and even sides, a mass
+    field, no couplings, and blocks of fewer lanes than a site has values
+    (B = 1, 2, 4 against 2 ndim + 1), each against its own single call and
+    the oracle."""
+    tip = gpu_binding()
+    cases = {  # dims, mass, mass field, coupled, probes
+        1: [([30], 0.1, False, True, 1), ([17], 0.05, True, True, 2), ([64], 0.2, False, False, 5)],
+        2: [([6, 10], 0.1, True, True, 2), ([9, 7], 0.05, False, True, 4), ([16, 16], 0.2, False, False, 24)],
+        4: [([4, 6, 3, 5], 0.1, False, True, 3), ([6, 4, 4, 4], 0.2, True, True, 1), ([3, 5, 4, 2], 0.15, False, False, 20)],
+    }[ndim]
+    orcs, gops, ns = [], [], []
+    for k, (dims, m, field, coupled, n) in enumerate(cases):
+        w = inputs.couplings(dims, seed=740 + k) if coupled else None
+        mf = inputs.mass_field(dims, m0=m, seed=750 + k) if field else None
+        orcs.append(OracleOp(dims, 0, mass=m, mass_field=mf, coupling=w))
+        gops.append(tip.Operator(dims, tip.KIND_SCALAR, mass=m, mass_field=to_dev(mf), coupling=to_dev(w)))
+        ns.append(n)
+    prec = tip.PREC_MIXED if precision == "mixed" else tip.PREC_FP64
+    print(f"batch of {ndim}-D scalar problems, {precision}", flush=True)
+    out = tip.trace_inv_probe_batch(gops, ns, 1e-12, 57, mask=MASK_Z2, precision=prec)
+    for i, (est, st) in enumerate(out):
+        assert st["status"] == 0 and st["max_true_relres"] <= 1e-12, i
+        single, q1, _ = tip.trace_inv_probe(gops[i], ns[i], 1e-12, 57, mask=MASK_Z2, precision=prec)
+        assert np.max(np.abs(st["quadratures"] - q1) / np.abs(q1)) <= REL, (ndim, i)
+        est_o, q_o, _ = general.trace_inv_probe(orcs[i], ns[i], 1e-12, 57, MASK_Z2)
+        assert np.max(np.abs(est - est_o) / np.abs(est_o)) <= REL, (ndim, i)
+        assert np.max(np.abs(st["quadratures"] - q_o) / np.abs(q_o)) <= REL, (ndim, i)
