@@ -1548,7 +1548,7 @@ tip_status run_batch(const tip_operator* ops, const tip_params* params, int32_t 
   for (size_t oi = 0; oi < order.size();) {
     const BatchClass& c0 = classes[(size_t)order[oi]];
     BatchGroup gr{hs[(size_t)c0.prob]->kind, c0.elem, c0.prec, (uint32_t)item_job.size(), 0, (int)lane_job.size(), 0,
-                  hs[(size_t)c0.prob]->geom.ndim};
+                  hs[(size_t)c0.prob]->geom.ndim, 6};
     uint64_t off = 0;
     for (; oi < order.size() && key(classes[(size_t)order[oi]]) == key(c0); ++oi) {
       const BatchClass& c = classes[(size_t)order[oi]];
@@ -1563,6 +1563,7 @@ tip_status run_batch(const tip_operator* ops, const tip_params* params, int32_t 
       gj.cls_j3 = c.j3 >= 0 ? c.j3 : 0;
       int logB = 0;
       while ((1 << logB) < c.B) ++logB;
+      gr.min_logB = std::min(gr.min_logB, logB);
       const uint32_t nitems = (uint32_t)((gj.V + (uint32_t)item_sites - 1) / (uint32_t)item_sites);
       PI = std::max<size_t>(PI, nitems);
       const bool single = c.prec == Prec::kF32;

@@ -64,6 +64,7 @@ struct BatchGroup {
   uint32_t item_base, nitems;
   int lane_base, nlanes;
   int ndim;                    // the dimension every job of the group has, or 0 when they differ
+  int min_logB;                // log2 of the smallest block of right-hand sides among its jobs
 };
 
 hipError_t launch_batch_scalars_init(const BatchArgs& a, const CgScalars& sc, int nlanes, hipStream_t st);

@@ -260,8 +260,6 @@ struct WalkD {
 // 1.  With L = item_sites / TS a whole column of a band is one work item's
 // worth, so consecutive items march neighbouring columns through the same
 // slices; with L = nt it is MarchOrder's order.
-constexpr int kScalarSiteStride = 10;         // LDS doubles per site: 2 kMaxDim + 1, rounded up to pairs
-static_assert(kScalarSiteStride >= ((2 * kMaxDim + 2) & ~1), "LDS stride of the scalar march");
 
 template <class Op, int D>
 __device__ __forceinline__ void march_scalar(const Geom& g, const BatchProb& P, int logB, int j, int si, bool live,
@@ -279,6 +277,7 @@ __device__ __forceinline__ void march_scalar(const Geom& g, const BatchProb& P, 
   const uint32_t TS = (uint32_t)(kBlock >> logB);
   const uint32_t nt = g.n[D - 1], Vp = g.stride[D - 1];
   const uint32_t full = Vp & ~(TS - 1u), wl = Vp - full;
+  auto ld = [&](uint32_t site) { return inj[((size_t)site << logB) + j]; };
   // position in the march: band of slices [t0, t0 + Lh), slice tb within it;
   // the band's whole columns end at march index Fb
   uint32_t o = o0 + (uint32_t)si, t0 = 0u, Lh = 1u, tb = 0u, Fb = 0u;
@@ -300,7 +299,7 @@ __device__ __forceinline__ void march_scalar(const Geom& g, const BatchProb& P, 
   WalkD<D> wk;
   wk.set(site_of(o), g);
   bool carry = false;
-  T xs = zero<T>(), xft = zero<T>();
+  T xs = zero<T>(), xft = zero<T>();          // p at the site and at its forward t-neighbour, carried
   while (o < o1) {
     const uint32_t s = wk.s;
     uint32_t sb[D];
@@ -310,16 +309,16 @@ __device__ __forceinline__ void march_scalar(const Geom& g, const BatchProb& P, 
     if (live) {                                // lanes whose solve has stopped load and store nothing
 #pragma unroll
       for (int mu = 0; mu + 1 < D; ++mu) {
-        xf[mu] = inj[((size_t)wk.fwd(mu, g) << logB) + j];
-        xb[mu] = inj[((size_t)sb[mu] << logB) + j];
+        xf[mu] = ld(wk.fwd(mu, g));
+        xb[mu] = ld(sb[mu]);
       }
-      xf[D - 1] = inj[((size_t)wk.fwd(D - 1, g) << logB) + j];
+      xf[D - 1] = ld(wk.fwd(D - 1, g));
       if (carry) {
         xb[D - 1] = xs;
         xs = xft;
       } else {
-        xb[D - 1] = inj[((size_t)sb[D - 1] << logB) + j];
-        xs = inj[((size_t)s << logB) + j];
+        xb[D - 1] = ld(sb[D - 1]);
+        xs = ld(s);
       }
       xft = xf[D - 1];
     }
@@ -370,8 +369,8 @@ __device__ __forceinline__ void march_scalar(const Geom& g, const BatchProb& P, 
         wk.x[D - 1] = t0 + tb;
         carry = true;
       } else {                                 // first slice of the band in the next column
+        wk.s -= Vp * tb;
         tb = 0u;
-        wk.s -= Vp * (Lh - 1u);
         wk.x[D - 1] = t0;
         wk.advance_plane(TS, g);
         carry = false;
@@ -420,7 +419,9 @@ __global__ __launch_bounds__(kBlock) void kb_stencil(BatchArgs a, CgScalars sc, 
   double dot[1] = {0.0};
   if constexpr (NC == 1 && D > 0) {
     (void)op;
-    __shared__ __align__(16) double lds_site[kBlock * kScalarSiteStride];
+    // [256 / B of the group's narrowest job][stride]: sized at launch, so
+    // that blocks of 16 rhs take 1-1.3 KB of LDS, not the 20 KB of B = 1
+    extern __shared__ __align__(16) double lds_site[];
     const uint32_t L = (a.march & 1) ? (uint32_t)a.item_sites >> (8 - logB) : g.n[D - 1];
     march_scalar<Op, D>(g, P, logB, j, si, live, L, o0, o1, inj, outj, lds_site, dot[0]);
   } else if (live) {
@@ -883,7 +884,14 @@ hipError_t launch_batch_iteration(const BatchArgs& a, const BatchGroup& gr, cons
     using T = typename Op::T;
     if (ev0) (void)hipEventRecord(ev0, st);
     auto stencil = [&](auto dim) {
-      kb_stencil<Op, decltype(dim)::value><<<gr.nitems, kBlock, 0, st>>>(a, sc, (const T*)p, (T*)w, partial);
+      constexpr int D = decltype(dim)::value;
+      if constexpr (D > 0) {
+        constexpr int NVS = (2 * D + 2) & ~1;
+        const size_t lds = (size_t)(kBlock >> gr.min_logB) * NVS * sizeof(double);
+        kb_stencil<Op, D><<<gr.nitems, kBlock, lds, st>>>(a, sc, (const T*)p, (T*)w, partial);
+      } else {
+        kb_stencil<Op, 0><<<gr.nitems, kBlock, 0, st>>>(a, sc, (const T*)p, (T*)w, partial);
+      }
     };
     if constexpr (Op::NC == 1) {
       switch (gr.ndim) {
