@@ -198,6 +198,13 @@ __device__ __forceinline__ uint32_t xcd_part(uint32_t bl, uint32_t n) {
   return x * q + min(x, r) + k;
 }
 
+// A load through a pointer the compiler cannot place (read from a table in
+// memory) is a flat load, which also counts against the LDS wait counter;
+// the couplings and masses are in global memory.
+__device__ __forceinline__ double ld_global(const double* p) {
+  return *(const __attribute__((address_space(1))) double*)p;
+}
+
 // A site of a D-dimensional lattice with its coordinates (D known at
 // compile time: the coordinate and neighbour arithmetic stays in registers
 // with no per-dimension branch).
@@ -300,49 +307,54 @@ __device__ __forceinline__ void march_scalar(const Geom& g, const BatchProb& P, 
   wk.set(site_of(o), g);
   bool carry = false;
   T xs = zero<T>(), xft = zero<T>();          // p at the site and at its forward t-neighbour, carried
+  // scalar k of site s with backward neighbours sb: the load goes out as a
+  // global (not flat) load, which the LDS waits do not count
+  auto scalar = [&](int k, uint32_t s, const uint32_t (&sb)[D]) -> double {
+    if (k < 2 * D) {
+      uint32_t sk = s;
+      int mk = k;
+#pragma unroll
+      for (int mu = 0; mu < D; ++mu)
+        if (k == D + mu) {
+          sk = sb[mu];
+          mk = mu;
+        }
+      return w ? ld_global(w + (size_t)mk * V + sk) : 1.0;
+    }
+    return mf ? ld_global(mf + s) : P.mass;
+  };
   while (o < o1) {
     const uint32_t s = wk.s;
     uint32_t sb[D];
-    T xf[D], xb[D];
 #pragma unroll
     for (int mu = 0; mu < D; ++mu) sb[mu] = wk.bwd(mu, g);
+    // the lane's site scalar first, then the vector entries
+    double sv = 0.0;
+    if (j < NV) sv = scalar(j, s, sb);
+    T xf[D], xb[D], xfn = zero<T>();
     if (live) {                                // lanes whose solve has stopped load and store nothing
+      if (carry) {                             // values of the previous step, already waited for
+        xb[D - 1] = xs;
+        xs = xft;
+      }
 #pragma unroll
       for (int mu = 0; mu + 1 < D; ++mu) {
         xf[mu] = ld(wk.fwd(mu, g));
         xb[mu] = ld(sb[mu]);
       }
-      xf[D - 1] = ld(wk.fwd(D - 1, g));
-      if (carry) {
-        xb[D - 1] = xs;
-        xs = xft;
-      } else {
+      xfn = ld(wk.fwd(D - 1, g));
+      if (!carry) {
         xb[D - 1] = ld(sb[D - 1]);
         xs = ld(s);
       }
-      xft = xf[D - 1];
     }
-    for (int k = j; k < NV; k += B) {          // every lane of the site takes part
-      double v;
-      if (k < 2 * D) {
-        uint32_t sk = s;
-        int mk = k;
-#pragma unroll
-        for (int mu = 0; mu < D; ++mu)
-          if (k == D + mu) {
-            sk = sb[mu];
-            mk = mu;
-          }
-        v = w ? w[(size_t)mk * V + sk] : 1.0;
-      } else {
-        v = mf ? mf[s] : P.mass;
-      }
-      my[k] = v;
-    }
+    if (j < NV) my[j] = sv;
+    for (int k = j + B; k < NV; k += B) my[k] = scalar(k, s, sb);   // B < 2D + 1 only
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
     if (live) {
+      xf[D - 1] = xfn;
       double diag = my[2 * D];
       T hop = zero<T>();
 #pragma unroll
@@ -355,6 +367,7 @@ __device__ __forceinline__ void march_scalar(const Geom& g, const BatchProb& P, 
       const T y = axpy(diag, xs, axpy(-1.0, hop, zero<T>()));
       outj[((size_t)s << logB) + j] = y;
       dot += redot(xs, y);
+      xft = xfn;
     }
     // every lane has read the site's values before the next step writes them
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
@@ -575,6 +588,7 @@ __global__ __launch_bounds__(kBlock) void kb_true_residual(BatchArgs a, CgScalar
   constexpr int NC = Op::NC;
   __shared__ double lds[3 * 4 * 64];
   __shared__ SiteCode lds_code[kBlock];
+  extern __shared__ __align__(16) double lds_sv[];   // scalar operators: [256 / B of the narrowest job][stride]
   const uint32_t item = a.item_base + blockIdx.x;
   const BatchJob& J = a.jobs[a.item_job[item]];
   const int logB = J.logB, B = 1 << logB;
@@ -595,16 +609,18 @@ __global__ __launch_bounds__(kBlock) void kb_true_residual(BatchArgs a, CgScalar
   auto nbr = [&](int mu, bool fwd) { return w.nbr(mu, fwd, g); };
   for (uint32_t base = s0; base < s1; base += TS, w.advance(TS, g)) {
     const bool in = w.s < s1;
-    if (hier) {
+    if (hier || NC == 1) {
       __syncthreads();
-      if (j == 0 && in) lds_code[si] = site_code(w.s, g);
+      if (hier && j == 0 && in) lds_code[si] = site_code(w.s, g);
+      if (NC == 1 && in)
+        site_scalars_split(g, w.s, j, B, P.mass_field, P.mass, P.coupling, nbr, lds_sv + si * kSiteScalarStride);
       __syncthreads();
     }
     if (!live || !in) continue;
     const uint32_t s = w.s;
     T xs[NC], ax[NC], b[NC], rt[NC];
     if constexpr (NC == 1)
-      stencil_site_gather(op, g, logB, s, j, P.mass_field, P.mass, P.coupling, xj, nbr, xs, ax);
+      stencil_site_lds(g, logB, s, j, lds_sv + si * kSiteScalarStride, xj, nbr, xs, ax);
     else
       stencil_site_at(op, g, logB, s, j, P.mass_field, P.mass, P.coupling, xj, nbr, xs, ax);
     if (hier) rhs_coded<T, NC>(lds_code[si], lc, s, g, P.seed, P.mask, b);
@@ -663,6 +679,7 @@ __global__ __launch_bounds__(kBlock) void kb_ru_residual(BatchArgs a, CgScalars 
   if (mode == 0 && *sc.n_ru == 0) return;
   __shared__ double lds[5 * 4 * 64];
   __shared__ SiteCode lds_code[kBlock];
+  extern __shared__ __align__(16) double lds_sv[];   // scalar operators: [256 / B of the narrowest job][stride]
   const uint32_t item = a.item_base + blockIdx.x;
   const BatchJob& J = a.jobs[a.item_job[item]];
   const int logB = J.logB, B = 1 << logB;
@@ -682,12 +699,15 @@ __global__ __launch_bounds__(kBlock) void kb_ru_residual(BatchArgs a, CgScalars 
   double acc[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
   SiteWalk w(s0 + (uint32_t)si, g);
   auto nbr = [&](int mu, bool fwd) { return w.nbr(mu, fwd, g); };
-  // every thread takes every step (the probe codes are shared through LDS)
+  // every thread takes every step (the probe codes and the scalar operators'
+  // site scalars are shared through LDS)
   for (uint32_t base = s0; base < s1; base += TS, w.advance(TS, g)) {
     const bool in = w.s < s1;
-    if (hier) {
+    if (hier || NC == 1) {
       __syncthreads();
-      if (j == 0 && in) lds_code[si] = site_code(w.s, g);
+      if (hier && j == 0 && in) lds_code[si] = site_code(w.s, g);
+      if (NC == 1 && in)
+        site_scalars_split(g, w.s, j, B, P.mass_field, P.mass, P.coupling, nbr, lds_sv + si * kSiteScalarStride);
       __syncthreads();
     }
     if (!live || !in) continue;
@@ -695,7 +715,7 @@ __global__ __launch_bounds__(kBlock) void kb_ru_residual(BatchArgs a, CgScalars 
     T xs[NC], ax[NC], b[NC];
     T32 r32[NC];
     if constexpr (NC == 1)
-      stencil_site_gather(op, g, logB, s, j, P.mass_field, P.mass, P.coupling, xj, nbr, xs, ax);
+      stencil_site_lds(g, logB, s, j, lds_sv + si * kSiteScalarStride, xj, nbr, xs, ax);
     else
       stencil_site_at(op, g, logB, s, j, P.mass_field, P.mass, P.coupling, xj, nbr, xs, ax);
     if (hier) rhs_coded<T, NC>(lds_code[si], lc, s, g, P.seed, P.mask, b);
@@ -923,7 +943,8 @@ hipError_t launch_batch_reliable(const BatchArgs& a, const BatchGroup& gr, const
       using Op64 = typename FP64Op<Op>::type;
       using T64 = typename Op64::T;
       kb_ru_accumulate<T64, T32><<<gr.nitems, kBlock, 0, st>>>(a, sc, mode, (T64*)x64, (T32*)xh);
-      kb_ru_residual<Op64, T32><<<gr.nitems, kBlock, 0, st>>>(a, sc, mode, (const T64*)x64, (T32*)r, (T32*)p,
+      const size_t lds = Op64::NC == 1 ? (size_t)(kBlock >> gr.min_logB) * kSiteScalarStride * sizeof(double) : 0;
+      kb_ru_residual<Op64, T32><<<gr.nitems, kBlock, lds, st>>>(a, sc, mode, (const T64*)x64, (T32*)r, (T32*)p,
                                                                 partial, rowstride);
       kb_reduce_ru<<<lane_grid(gr), kBlock, 0, st>>>(a, sc, gr.lane_base, gr.nlanes, partial, rowstride, mode);
     }
@@ -936,7 +957,8 @@ hipError_t launch_batch_true_residual(const BatchArgs& a, const BatchGroup& gr, 
     using Op = decltype(op);
     using T = typename Op::T;
     if constexpr (!is_single<T>::value) {
-      kb_true_residual<Op><<<gr.nitems, kBlock, 0, st>>>(a, sc, (const T*)x, (T*)r, (T*)p, partial, rowstride);
+      const size_t lds = Op::NC == 1 ? (size_t)(kBlock >> gr.min_logB) * kSiteScalarStride * sizeof(double) : 0;
+      kb_true_residual<Op><<<gr.nitems, kBlock, lds, st>>>(a, sc, (const T*)x, (T*)r, (T*)p, partial, rowstride);
       kb_reduce_true<<<lane_grid(gr), kBlock, 0, st>>>(a, sc, gr.lane_base, gr.nlanes, partial, rowstride);
     }
   });

@@ -287,6 +287,64 @@ __device__ __forceinline__ void stencil_site_gather(const Op& op, const Geom& g,
   for (int c = 0; c < NC; ++c) y[c] = axpy(diag, xs[c], axpy(-1.0, hop[c], zero<T>()));
 }
 
+// Scalar operators in a workgroup pass whose steps are synchronised anyway:
+// the 2 ndim + 1 scalars of site s (w_mu(s) for mu < ndim, w_mu(s - e_mu),
+// then m(s)) are read once per site, value k by lane k of the site's B lanes
+// (lanes k, k + B, ... when B < 2 ndim + 1), into sv[k]; after the barrier
+// stencil_site_lds takes them from there.  One load per site instead of one
+// per lane: with every lane loading them, the scalars took as many address
+// cycles as the vector entries.
+template <class Nbr>
+__device__ __forceinline__ void site_scalars_split(const Geom& g, uint32_t s, int j, int B,
+                                                   const double* __restrict__ mass_field, double mass,
+                                                   const double* __restrict__ w, const Nbr& nbr, double* sv) {
+  const int nd = g.ndim, nv = 2 * nd + 1;
+  for (int k = j; k < nv; k += B) {
+    double v;
+    if (k < 2 * nd) {
+      const int mu = k < nd ? k : k - nd;
+      uint32_t sk = s;
+      if (k >= nd) {
+#pragma unroll
+        for (int m = 0; m < kMaxDim; ++m)
+          if (m == mu) sk = nbr(m, false);
+      }
+      v = w ? w[(size_t)mu * g.V + sk] : 1.0;
+    } else {
+      v = mass_field ? mass_field[s] : mass;
+    }
+    sv[k] = v;
+  }
+}
+constexpr int kSiteScalarStride = 2 * kMaxDim + 2;   // doubles per site in sv
+
+// stencil_site_gather for the scalar operators with the site's scalars from
+// sv (site_scalars_split); the same arithmetic in the same order.
+template <class T, class Nbr>
+__device__ __forceinline__ void stencil_site_lds(const Geom& g, int logB, uint32_t s, int j, const double* sv,
+                                                 const T* __restrict__ in, const Nbr& nbr, T (&xs)[1], T (&y)[1]) {
+  const size_t V = g.V;
+  T xf[kMaxDim][1], xb[kMaxDim][1];
+#pragma unroll
+  for (int mu = 0; mu < kMaxDim; ++mu) {
+    if (mu >= g.ndim) break;
+    load_vec<T, 1>(in, V, logB, nbr(mu, true), j, xf[mu]);
+    load_vec<T, 1>(in, V, logB, nbr(mu, false), j, xb[mu]);
+  }
+  load_vec<T, 1>(in, V, logB, s, j, xs);
+  double diag = sv[2 * g.ndim];
+  T hop = zero<T>();
+#pragma unroll
+  for (int mu = 0; mu < kMaxDim; ++mu) {
+    if (mu >= g.ndim) break;
+    const double wf = sv[mu], wb = sv[g.ndim + mu];
+    diag += wf + wb;
+    hop = axpy(wf, xf[mu][0], hop);
+    hop = axpy(wb, xb[mu][0], hop);
+  }
+  y[0] = axpy(diag, xs[0], axpy(-1.0, hop, zero<T>()));
+}
+
 template <class Op>
 __device__ __forceinline__ void stencil_site(const Op& op, const Geom& g, int logB, uint32_t s, int j,
                                              const double* __restrict__ mass_field, double mass,
