@@ -555,17 +555,22 @@ __global__ __launch_bounds__(kBlock) void kb_direction(BatchArgs a, CgScalars sc
     T* pj = p + base;
     size_t i = threadIdx.x;
     for (; i + 3 * kBlock < n; i += 4 * kBlock) {
+      // Loads and stores for every lane, the lane's conditions applied as
+      // selects (a lane that updates nothing writes back what it read): with
+      // the conditions as branches the compiler sank loads into them and each
+      // join waited for the loads before it.  The extra bytes are in
+      // segments that the block's live lanes fetch and write anyway.
       T pp[4], xx[4], rr[4];
 #pragma unroll
       for (int u = 0; u < 4; ++u) {
         pp[u] = pj[i + u * kBlock];
-        if (xa != 0.0) xx[u] = xj[i + u * kBlock];
-        if (live) rr[u] = rj[i + u * kBlock];
+        xx[u] = xj[i + u * kBlock];
+        rr[u] = rj[i + u * kBlock];
       }
 #pragma unroll
       for (int u = 0; u < 4; ++u) {
-        if (xa != 0.0) xj[i + u * kBlock] = axpy(xa, pp[u], xx[u]);
-        if (live) pj[i + u * kBlock] = axpy(be, pp[u], rr[u]);
+        xj[i + u * kBlock] = xa != 0.0 ? axpy(xa, pp[u], xx[u]) : xx[u];
+        pj[i + u * kBlock] = live ? axpy(be, pp[u], rr[u]) : pp[u];
       }
     }
     for (; i < n; i += kBlock) {
