@@ -1723,9 +1723,27 @@ tip_status run_batch(const tip_operator* ops, const tip_params* params, int32_t 
     int64_t stencil_launches = 0;
     double stencil_seconds = 0.0;
     std::vector<hipEvent_t> evs;
-    auto enqueue_chunk = [&](int chunk, bool timed) -> tip_status {
+    // In a captured chunk each group's iterations form a chain of their own,
+    // forked from the capturing stream onto a side stream and joined back, so
+    // the groups' launches overlap: the groups share no vector, partial entry
+    // or CG scalar (lanes are disjoint), and the counters they share (active
+    // lanes, pending reliable updates) are updated atomically and only gate
+    // early exits.  Eager chunks stay on the one stream.
+    struct SideStreams {
+      std::vector<hipStream_t> s;
+      std::vector<hipEvent_t> e;               // [0] fork, then one join per side stream
+      ~SideStreams() {
+        for (hipStream_t x : s) (void)hipStreamDestroy(x);
+        for (hipEvent_t x : e) (void)hipEventDestroy(x);
+      }
+    } side;
+    auto stream_of = [&](size_t gi, bool captured) {
+      return captured && gi > 0 && !side.s.empty() ? side.s[(gi - 1) % side.s.size()] : st;
+    };
+    auto enqueue_chunk = [&](int chunk, bool timed, bool captured) -> tip_status {
       for (int it = 0; it < chunk; ++it)
         for (size_t gi = 0; gi < groups.size(); ++gi) {
+          const hipStream_t sg = stream_of(gi, captured);
           BatchArgs ga = args;
           ga.item_base = groups[gi].item_base;
           const bool mixed = groups[gi].prec == Prec::kF32;
@@ -1738,12 +1756,23 @@ tip_status run_batch(const tip_operator* ops, const tip_params* params, int32_t 
           }
           TIP_HIP(launch_batch_iteration(ga, groups[gi], sc, vb + (mixed ? gv[gi].xh : gv[gi].x), vb + gv[gi].r,
                                          vb + gv[gi].p, vb + gv[gi].w, pt, rowstride, mixed ? eps32 : 0.0,
-                                         mixed ? tau2 : 0.0, st, e0, e1));
+                                         mixed ? tau2 : 0.0, sg, e0, e1));
           if (mixed)
             TIP_HIP(launch_batch_reliable(ga, groups[gi], sc, 0, vb + gv[gi].x, vb + gv[gi].xh, vb + gv[gi].r,
-                                          vb + gv[gi].p, pt + rowstride, rowstride, st));
+                                          vb + gv[gi].p, pt + rowstride, rowstride, sg));
         }
       return TIP_OK;
+    };
+    auto enqueue_captured_chunk = [&](int chunk) -> tip_status {
+      if (side.s.empty()) return enqueue_chunk(chunk, false, false);
+      TIP_HIP(hipEventRecord(side.e[0], st));
+      for (hipStream_t x : side.s) TIP_HIP(hipStreamWaitEvent(x, side.e[0], 0));
+      const tip_status cs = enqueue_chunk(chunk, false, true);
+      for (size_t k = 0; k < side.s.size(); ++k) {  // join every side stream, also after a failed launch
+        TIP_HIP(hipEventRecord(side.e[k + 1], side.s[k]));
+        TIP_HIP(hipStreamWaitEvent(st, side.e[k + 1], 0));
+      }
+      return cs;
     };
     // chunks of iterations replayed as one HIP graph for the whole batch
     hipGraphExec_t graph = nullptr;
@@ -1754,6 +1783,26 @@ tip_status run_batch(const tip_operator* ops, const tip_params* params, int32_t 
       }
     } graph_del{&graph};
     bool use_graph = !g_profiling && !env_off("TIP_GRAPH");
+    if (use_graph && groups.size() > 1 && !env_off("TIP_BATCH_FORK")) {
+      const size_t ns = std::min<size_t>(groups.size() - 1, 3);
+      for (size_t k = 0; k < ns; ++k) {
+        hipStream_t x = nullptr;
+        if (hipStreamCreateWithFlags(&x, hipStreamNonBlocking) != hipSuccess) break;
+        side.s.push_back(x);
+      }
+      for (size_t k = 0; k <= side.s.size(); ++k) {
+        hipEvent_t x = nullptr;
+        if (hipEventCreateWithFlags(&x, hipEventDisableTiming) != hipSuccess) break;
+        side.e.push_back(x);
+      }
+      if (side.e.size() != side.s.size() + 1 || side.s.empty()) {    // fall back to one chain
+        for (hipStream_t x : side.s) (void)hipStreamDestroy(x);
+        for (hipEvent_t x : side.e) (void)hipEventDestroy(x);
+        side.s.clear();
+        side.e.clear();
+        (void)hipGetLastError();
+      }
+    }
     auto poll = [&]() -> tip_status {
       TIP_HIP(hipMemcpyAsync(h_active, sc.active, sizeof(int), hipMemcpyDeviceToHost, st));
       TIP_HIP(hipStreamSynchronize(st));
@@ -1767,7 +1816,7 @@ tip_status run_batch(const tip_operator* ops, const tip_params* params, int32_t 
             use_graph = false;
             (void)hipGetLastError();
           } else {
-            const tip_status cs = enqueue_chunk(kBatchChunk, false);
+            const tip_status cs = enqueue_captured_chunk(kBatchChunk);
             hipGraph_t gr = nullptr;
             const hipError_t e = hipStreamEndCapture(st, &gr);
             hipError_t ei = hipErrorUnknown;
@@ -1783,7 +1832,7 @@ tip_status run_batch(const tip_operator* ops, const tip_params* params, int32_t 
         if (use_graph && graph) {
           TIP_HIP(hipGraphLaunch(graph, st));
         } else {
-          tip_status cs = enqueue_chunk(kBatchChunk, g_profiling != 0);
+          tip_status cs = enqueue_chunk(kBatchChunk, g_profiling != 0, false);
           if (cs != TIP_OK) return cs;
         }
         tip_status ps = poll();
