@@ -186,3 +186,23 @@ def test_batch_stencil_per_dimension(ndim, precision):
         est_o, q_o, _ = general.trace_inv_probe(orcs[i], ns[i], 1e-12, 57, MASK_Z2)
         assert np.max(np.abs(est - est_o) / np.abs(est_o)) <= REL, (ndim, i)
         assert np.max(np.abs(st["quadratures"] - q_o) / np.abs(q_o)) <= REL, (ndim, i)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_batch_forked_chains_equal_one_chain(precision, monkeypatch):
+    """Inside the chunk graphs each group's chain of launches runs on a side
+    stream of its own; the groups share no data, so the quadratures are the
+    same bit for bit as with one chain (TIP_BATCH_FORK=0), in both
+    precisions (the mixed solver's reliable updates included)."""
+    tip = gpu_binding()
+    prec = tip.PREC_MIXED if precision == "mixed" else tip.PREC_FP64
+    _, gops = _ops(tip, SMALL)
+    ns = [n for _, _, n in SMALL]
+    print(f"forked against one chain, {precision}", flush=True)
+    a = tip.trace_inv_probe_batch(gops, ns, 1e-12, 4018, precision=prec)
+    monkeypatch.setenv("TIP_BATCH_FORK", "0")
+    b = tip.trace_inv_probe_batch(gops, ns, 1e-12, 4018, precision=prec)
+    for i, ((ea, sa), (eb, sb)) in enumerate(zip(a, b)):
+        assert np.array_equal(sa["quadratures"], sb["quadratures"]), i
+        assert np.array_equal(ea, eb), i
+        assert sa["total_iters"] == sb["total_iters"], i
