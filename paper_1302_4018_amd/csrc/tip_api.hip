@@ -1404,7 +1404,8 @@ tip_status run_probe(tip_op_handle h, const tip_params* p, double* estimates, do
 // group advance together: each CG phase is one launch over the work items
 // of every job of the group (tip_batch.hip), and one chunk of iterations for
 // the whole batch is captured once as a HIP graph and replayed.  One host
-// thread and one stream do all of it; the host polls one counter per chunk.
+// thread does all of it (each group's chain on a side stream inside the
+// captured chunk); the host polls one counter per chunk.
 // ---------------------------------------------------------------------------
 
 struct HandleDel {
@@ -1730,9 +1731,11 @@ tip_status run_batch(const tip_operator* ops, const tip_params* params, int32_t 
     // lanes, pending reliable updates) are updated atomically and only gate
     // early exits.  Eager chunks stay on the one stream.
     struct SideStreams {
-      std::vector<hipStream_t> s;
+      std::vector<hipStream_t> s;              // only ever captured into: no work runs on them
       std::vector<hipEvent_t> e;               // [0] fork, then one join per side stream
       ~SideStreams() {
+        if (s.empty() && e.empty()) return;
+        std::lock_guard<std::mutex> lk(g_device_mu);
         for (hipStream_t x : s) (void)hipStreamDestroy(x);
         for (hipEvent_t x : e) (void)hipEventDestroy(x);
       }
@@ -1784,6 +1787,7 @@ tip_status run_batch(const tip_operator* ops, const tip_params* params, int32_t 
     } graph_del{&graph};
     bool use_graph = !g_profiling && !env_off("TIP_GRAPH");
     if (use_graph && groups.size() > 1 && !env_off("TIP_BATCH_FORK")) {
+      std::lock_guard<std::mutex> lk(g_device_mu);
       const size_t ns = std::min<size_t>(groups.size() - 1, 3);
       for (size_t k = 0; k < ns; ++k) {
         hipStream_t x = nullptr;
