@@ -18,6 +18,8 @@
 // A workgroup none of whose rhs is live returns at once, so problems that
 // have converged cost a launch slot each, not memory traffic.
 
+#include <algorithm>
+#include <cstdlib>
 #include <type_traits>
 
 #include "tip_batch.h"
@@ -532,8 +534,9 @@ __global__ __launch_bounds__(kBlock) void kb_update_r(BatchArgs a, CgScalars sc,
 // for the lanes still iterating.
 template <class T>
 __global__ __launch_bounds__(kBlock) void kb_direction(BatchArgs a, CgScalars sc, T* __restrict__ x,
-                                                       const T* __restrict__ r, T* __restrict__ p) {
-  const uint32_t item = a.item_base + blockIdx.x;
+                                                       const T* __restrict__ r, T* __restrict__ p, int parts) {
+  const uint32_t item = a.item_base + blockIdx.x / (uint32_t)parts;
+  const uint32_t part = blockIdx.x % (uint32_t)parts;
   const BatchJob& J = a.jobs[a.item_job[item]];
   const Geom& gp = J.g;
   const uint32_t V = gp.V;
@@ -547,13 +550,16 @@ __global__ __launch_bounds__(kBlock) void kb_direction(BatchArgs a, CgScalars sc
   const double be = sc.beta[J.lane0 + j];
   const uint32_t s0 = (item - J.item0) * (uint32_t)a.item_sites;
   const uint32_t s1 = min(V, s0 + (uint32_t)a.item_sites);
-  const size_t n = (size_t)(s1 - s0) << logB;        // flat, as in kb_update_r
+  const size_t ni = (size_t)(s1 - s0) << logB;       // flat, as in kb_update_r
+  // this workgroup's part of the item: whole 256-element runs (lane = element mod B)
+  const size_t chunk = ((ni + parts - 1) / parts + kBlock - 1) / kBlock * kBlock;
+  const size_t e0 = part * chunk, n = min(ni, e0 + chunk);
   for (int c = 0; c < nc; ++c) {
     const size_t base = J.off + (((size_t)c * V + s0) << logB);
     T* xj = x + base;
     const T* rj = r + base;
     T* pj = p + base;
-    size_t i = threadIdx.x;
+    size_t i = e0 + threadIdx.x;
     for (; i + 3 * kBlock < n; i += 4 * kBlock) {
       // Loads and stores for every lane, the lane's conditions applied as
       // selects (a lane that updates nothing writes back what it read): with
@@ -901,6 +907,18 @@ hipError_t launch_batch_init(const BatchArgs& a, const BatchGroup& gr, void* x64
   });
 }
 
+// Workgroups per work item in the direction pass: 8 for FP64 vectors (an
+// item of 16 rhs is then 4-8 KB per vector and workgroup, and the workgroups
+// that run together stream through neighbouring memory), one for FP32.
+// Measured on the 64 uneven tori (FP64 quadratures/s): 19 020-19 120 with
+// one, 19 210-19 230 with 2, 19 300-19 330 with 4, 19 500-19 530 with 8; in
+// mixed precision 2 and 4 changed nothing and 8 lost 6%.
+template <class T>
+static int direction_parts() {
+  if (const char* e = std::getenv("TIP_BATCH_VQ")) return std::max(1, std::min(16, std::atoi(e)));   // experiments
+  return is_single<T>::value ? 1 : 8;
+}
+
 hipError_t launch_batch_iteration(const BatchArgs& a, const BatchGroup& gr, const CgScalars& sc, void* x, void* r,
                                   void* p, void* w, double* partial, size_t rowstride, double eps, double tau2,
                                   hipStream_t st, hipEvent_t ev0, hipEvent_t ev1) {
@@ -935,7 +953,8 @@ hipError_t launch_batch_iteration(const BatchArgs& a, const BatchGroup& gr, cons
     kb_update_r<T><<<gr.nitems, kBlock, 0, st>>>(a, sc, (T*)r, (const T*)w, partial + rowstride);
     kb_reduce_beta<<<lane_grid(gr), kBlock, 0, st>>>(a, sc, gr.lane_base, gr.nlanes, partial + rowstride, eps,
                                                         tau2);
-    kb_direction<T><<<gr.nitems, kBlock, 0, st>>>(a, sc, (T*)x, (const T*)r, (T*)p);
+    const int vp = direction_parts<T>();
+    kb_direction<T><<<gr.nitems * (uint32_t)vp, kBlock, 0, st>>>(a, sc, (T*)x, (const T*)r, (T*)p, vp);
   });
 }
 
